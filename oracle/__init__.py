@@ -1,0 +1,212 @@
+"""FP64 CPU oracle for the CRK-SPH pair passes and short-range gravity.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the GPU library (``paper_2310_16122_amd``)
+and never importing it.  The arithmetic lives in ``crk_oracle.cpp`` (plain C++,
+FP64, brute-force neighbour search); this module compiles it with g++ and
+wraps it with ctypes and numpy.
+
+Reading of the paper (which names the passes and cites the method without
+printing its equations): linear conservative reproducing-kernel SPH with a
+Wendland C4 kernel of support 2h, a volume-based density, an ideal-gas
+pressure and antisymmetrised corrected-kernel gradients; short-range gravity is
+Plummer-softened Newtonian attraction cut at r_c.  The header of
+``crk_oracle.cpp`` writes every formula out.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "crk_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+MOMENT_NAMES = (["m0"] + [f"m1_{a}" for a in "xyz"] +
+                [f"m2_{p}" for p in ("xx", "xy", "xz", "yy", "yz", "zz")] +
+                [f"g0_{c}" for c in "xyz"] +
+                [f"g1_{a}{c}" for a in "xyz" for c in "xyz"] +
+                [f"g2_{p}{c}" for p in ("xx", "xy", "xz", "yy", "yz", "zz") for c in "xyz"])
+
+
+def build(force=False):
+    """Compile the oracle (g++ -O3 -fopenmp).  Returns the library path."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["g++", "-std=c++17", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared",
+               "-o", tmp, _SRC]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        D = ctypes.c_double
+        lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_volume.argtypes = [I64, P, P, P, P, P, I64, P, P, P]
+        lib.oracle_moments.argtypes = [I64, P, P, P, P, P, I64, P, P, P]
+        lib.oracle_corrections.argtypes = [I64, P, P, P, P, P, I64, P, P, P, P, P]
+        lib.oracle_corrections.restype = I64
+        lib.oracle_accel.argtypes = [I64] + [P] * 15 + [D, I64, P, P, P, P, P]
+        lib.oracle_totals.argtypes = [I64] + [P] * 9
+        lib.oracle_hydro_targets.argtypes = [I64] + [P] * 9 + [D, I64, P] + [P] * 10
+        lib.oracle_hydro_targets.restype = I64
+        lib.oracle_gravity.argtypes = [I64, P, P, P, P, D, D, D, P, I64, P, P, P, P]
+        lib.oracle_count_pairs.argtypes = [I64, P, P, P, P, ctypes.c_int, D, I64, P, P]
+        lib.oracle_count_pairs.restype = I64
+        lib.oracle_kernel.argtypes = [I64, P, D, P, P]
+        _lib = lib
+    return _lib
+
+
+def _c(a, dtype=np.float64):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def threads():
+    return _load().oracle_threads()
+
+
+def kernel(r, h):
+    """Wendland C4 W(r, h) and F(r, h) with grad_i W = F x_ij."""
+    r = _c(r)
+    W = np.empty_like(r)
+    F = np.empty_like(r)
+    _load().oracle_kernel(r.size, _p(r), float(h), _p(W), _p(F))
+    return W, F
+
+
+def _targets(targets, n):
+    if targets is None:
+        return None, n
+    t = _c(targets, np.int64)
+    return t, t.size
+
+
+def volume(g, targets=None):
+    """V_i = 1/S_i and rho_i = m_i S_i (brute force)."""
+    x, y, z, h, m = (_c(g[k]) for k in ("x", "y", "z", "h", "m"))
+    t, nt = _targets(targets, x.size)
+    V = np.empty(nt)
+    rho = np.empty(nt)
+    _load().oracle_volume(x.size, _p(x), _p(y), _p(z), _p(h), _p(m), nt, _p(t), _p(V), _p(rho))
+    return V, rho
+
+
+def moments(g, V, targets=None):
+    """The 40 raw moment sums per particle and the neighbour count."""
+    x, y, z, h = (_c(g[k]) for k in ("x", "y", "z", "h"))
+    V = _c(V)
+    t, nt = _targets(targets, x.size)
+    M = np.empty((nt, 40))
+    nnb = np.empty(nt, dtype=np.int32)
+    _load().oracle_moments(x.size, _p(x), _p(y), _p(z), _p(h), _p(V), nt, _p(t), _p(M), _p(nnb))
+    return M, nnb
+
+
+def corrections(g, V, targets=None):
+    """(A, B[n,3], dA[n,3], dB[n,3,3], n_fallback); dB[i,a,c] = d_c B^a."""
+    x, y, z, h = (_c(g[k]) for k in ("x", "y", "z", "h"))
+    V = _c(V)
+    t, nt = _targets(targets, x.size)
+    A = np.empty(nt)
+    B = np.empty((nt, 3))
+    dA = np.empty((nt, 3))
+    dB = np.empty((nt, 3, 3))
+    nf = _load().oracle_corrections(x.size, _p(x), _p(y), _p(z), _p(h), _p(V), nt, _p(t),
+                                    _p(A), _p(B), _p(dA), _p(dB))
+    return A, B, dA, dB, int(nf)
+
+
+def accel(g, V, rho, corr, targets=None):
+    """Accelerations a[n,3] and du/dt[n] given V, rho and corrections of all particles."""
+    keys = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "m")
+    arr = [_c(g[k]) for k in keys]
+    V, rho = _c(V), _c(rho)
+    A, B, dA, dB = (_c(c) for c in corr[:4])
+    t, nt = _targets(targets, arr[0].size)
+    a = np.empty((3, nt))
+    du = np.empty(nt)
+    _load().oracle_accel(arr[0].size, *[_p(v) for v in arr], _p(V), _p(rho), _p(A), _p(B),
+                         _p(dA), _p(dB), float(g["gamma"]), nt, _p(t), _p(a[0]), _p(a[1]),
+                         _p(a[2]), _p(du))
+    return a.T.copy(), du
+
+
+def totals(g, a, dudt):
+    """[sum m a (3), sum m (v.a + du/dt), sum m |a|, sum m (|v.a| + |du/dt|),
+    sum m du/dt, sum m v.a] over all particles."""
+    m, vx, vy, vz = (_c(g[k]) for k in ("m", "vx", "vy", "vz"))
+    a = _c(a)
+    ax, ay, az = (_c(a[:, c]) for c in range(3))
+    du = _c(dudt)
+    out = np.empty(8)
+    _load().oracle_totals(m.size, _p(m), _p(vx), _p(vy), _p(vz), _p(ax), _p(ay), _p(az),
+                          _p(du), _p(out))
+    return out
+
+
+def hydro(g):
+    """Full brute-force forward chain over all particles."""
+    V, rho = volume(g)
+    A, B, dA, dB, nf = corrections(g, V)
+    a, du = accel(g, V, rho, (A, B, dA, dB))
+    return dict(V=V, rho=rho, A=A, B=B, dA=dA, dB=dB, a=a, dudt=du, n_fallback=nf,
+                totals=totals(g, a, du))
+
+
+def hydro_targets(g, targets):
+    """Forward chain for sampled targets, each evaluated inside its 3-hop pool."""
+    keys = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "m")
+    arr = [_c(g[k]) for k in keys]
+    t = _c(targets, np.int64)
+    nt = t.size
+    V = np.empty(nt)
+    rho = np.empty(nt)
+    A = np.empty(nt)
+    B = np.empty((nt, 3))
+    dA = np.empty((nt, 3))
+    dB = np.empty((nt, 3, 3))
+    a = np.empty((3, nt))
+    du = np.empty(nt)
+    nf = _load().oracle_hydro_targets(arr[0].size, *[_p(v) for v in arr], float(g["gamma"]), nt,
+                                      _p(t), _p(V), _p(rho), _p(A), _p(B), _p(dA), _p(dB),
+                                      _p(a[0]), _p(a[1]), _p(a[2]), _p(du))
+    return dict(V=V, rho=rho, A=A, B=B, dA=dA, dB=dB, a=a.T.copy(), dudt=du, n_fallback=int(nf))
+
+
+def gravity(g, targets=None, poly=None):
+    """Short-range Plummer-softened gravity with a hard cutoff (brute force)."""
+    x, y, z, m = (_c(g[k]) for k in ("x", "y", "z", "m"))
+    t, nt = _targets(targets, x.size)
+    pc = None if poly is None else _c(poly)
+    a = np.empty((3, nt))
+    _load().oracle_gravity(x.size, _p(x), _p(y), _p(z), _p(m), float(g["G"]), float(g["eps"]),
+                           float(g["r_cut"]), _p(pc), nt, _p(t), _p(a[0]), _p(a[1]), _p(a[2]))
+    return a.T.copy()
+
+
+def count_pairs(g, mode, targets=None, r_fixed=0.0):
+    """Ordered pairs j != i inside the pass radius: mode 0 = 2h_i, 1 = 2max(h_i,h_j), 2 = r_fixed."""
+    x, y, z = (_c(g[k]) for k in ("x", "y", "z"))
+    h = _c(g["h"]) if "h" in g else np.zeros_like(x)
+    t, nt = _targets(targets, x.size)
+    per = np.empty(nt, dtype=np.int32)
+    tot = _load().oracle_count_pairs(x.size, _p(x), _p(y), _p(z), _p(h), int(mode), float(r_fixed),
+                                     nt, _p(t), _p(per))
+    return int(tot), per

@@ -1,0 +1,591 @@
+// CPU oracle for the CRK-SPH pair passes and short-range gravity.
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct FP64
+// reference that the GPU library is checked against.  Only the tests, the
+// smoke check and the benchmark's CPU-baseline leg may load it; the product
+// path never does, and this file shares no code, header or table with the GPU
+// library.
+//
+// Everything is FP64 and every neighbour search is brute force: for a particle
+// i the candidate set is scanned in full and each candidate is tested with the
+// periodic minimum image.  No tree, no cell list, no blocking.
+//
+// What is computed (the paper names the passes -- Geometry, Corrections,
+// Acceleration, Energy, Sec. 5 -- and cites conservative reproducing-kernel
+// SPH for the method, Sec. 3.1, without printing its equations; the formulas
+// below are linear CRK-SPH written out from its mathematics):
+//
+//   geometry     x_ij = x_i - x_j, each component wrapped to [-1/2, 1/2)
+//   kernel       Wendland C4, support H = 2h:
+//                  W = 495/(32 pi H^3) (1-q)^6 (1 + 6q + 35 q^2/3),  q = r/H < 1
+//                  grad_i W = F x_ij,  F = -1155/(4 pi H^5) (1+5q)(1-q)^5
+//   volume       S_i = sum_{j: r_ij < H_i} W(r_ij, h_i)  (j = i included)
+//                V_i = 1/S_i,  rho_i = m_i S_i
+//   moments      with W_ij = W(r_ij, h_i), d_c W_ij = F(r_ij, h_i) x_ij^c, over
+//                j with r_ij < H_i (j = i included):
+//                  m0 = sum V_j W,  m1^a = sum V_j x^a W,  m2^ab = sum V_j x^a x^b W
+//                  g0^c = sum V_j d_cW,  g1^ac = sum V_j (delta^ac W + x^a d_cW)
+//                  g2^abc = sum V_j (delta^ac x^b W + delta^bc x^a W + x^a x^b d_cW)
+//   corrections  B = -m2^-1 m1,  A = 1/(m0 + B.m1)
+//                d_cB = -m2^-1 (g1[.,c] + g2[.,.,c] B)
+//                d_cA = -A^2 (g0^c + B.g1[.,c] + m1.d_cB)
+//                (these make sum_j V_j W^R_ij = 1 and sum_j V_j x_ij W^R_ij = 0
+//                 with W^R_ij = A_i (1 + B_i.x_ij) W_ij)
+//   EOS          P_i = (gamma - 1) rho_i u_i
+//   forces       j != i with r_ij < max(H_i, H_j):
+//                  G_ij^c = d_cA_i (1+B_i.x_ij) W_ij + A_i (d_cB_i.x_ij + B_i^c) W_ij
+//                           + A_i (1+B_i.x_ij) d_cW_ij
+//                  G_ji   = the same with i <-> j (x_ji = -x_ij, h_j)
+//                  F_ij   = -1/2 V_i V_j (P_i + P_j) (G_ij - G_ji)
+//                  a_i    = (1/m_i) sum_j F_ij
+//                  du_i/dt = -(1/(2 m_i)) sum_j F_ij . (v_i - v_j)
+//   gravity      j != i with r_ij < r_c (all species):
+//                  a_i = -G sum_j m_j x_ij [ (r^2 + eps^2)^(-3/2) - sum_k p_k r^(2k) ]
+//
+// Moment storage order (40 values): m0, m1[3], m2[6] (xx xy xz yy yz zz),
+// g0[3], g1[9] (g1[a][c], a-major), g2[18] (g2[ab][c], ab in the m2 order).
+// Correction layout: dA[c] = d_cA, dB[a][c] = d_cB^a (a-major).
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------- scalars
+// T is double for values; a forward-mode dual number for gradients.
+struct Dual {
+    double v, d;
+    Dual(double a = 0.0, double b = 0.0) : v(a), d(b) {}
+};
+inline Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+inline Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+inline Dual operator-(Dual a) { return {-a.v, -a.d}; }
+inline Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+inline Dual operator/(Dual a, Dual b) { return {a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)}; }
+inline Dual& operator+=(Dual& a, Dual b) { a = a + b; return a; }
+inline Dual& operator-=(Dual& a, Dual b) { a = a - b; return a; }
+inline bool operator<(Dual a, Dual b) { return a.v < b.v; }
+inline bool operator>=(Dual a, Dual b) { return a.v >= b.v; }
+inline Dual sqrt(Dual a) { double s = std::sqrt(a.v); return {s, s > 0 ? a.d / (2.0 * s) : 0.0}; }
+inline double val(double a) { return a; }
+inline double val(Dual a) { return a.v; }
+using std::sqrt;
+
+template <class T> T wrap(T d) {
+    if (val(d) >= 0.5) d = d - T(1.0);
+    else if (val(d) < -0.5) d = d + T(1.0);
+    return d;
+}
+
+// ---------------------------------------------------------------- kernel
+template <class T> T kernel_W(T r, double h) {
+    const double H = 2.0 * h;
+    T q = r / T(H);
+    if (!(val(q) < 1.0)) return T(0.0);
+    T t = T(1.0) - q;
+    T t2 = t * t;
+    T t6 = t2 * t2 * t2;
+    return T(495.0 / (32.0 * kPi * H * H * H)) * t6 *
+           (T(1.0) + T(6.0) * q + T(35.0 / 3.0) * q * q);
+}
+
+// grad_i W(|x_i - x_j|) = kernel_F * x_ij
+template <class T> T kernel_F(T r, double h) {
+    const double H = 2.0 * h;
+    T q = r / T(H);
+    if (!(val(q) < 1.0)) return T(0.0);
+    T t = T(1.0) - q;
+    T t5 = t * t * t * t * t;
+    return T(-1155.0 / (4.0 * kPi * H * H * H * H * H)) * (T(1.0) + T(5.0) * q) * t5;
+}
+
+// ---------------------------------------------------------------- data
+template <class T> struct Gas {
+    int64_t n;
+    const T *x, *y, *z, *vx, *vy, *vz, *u;
+    const double *h, *m;
+};
+
+template <class T> struct Sep {
+    T d[3];
+    T r;
+};
+
+template <class T> Sep<T> separation(const Gas<T>& g, int64_t i, int64_t j) {
+    Sep<T> s;
+    s.d[0] = wrap(g.x[i] - g.x[j]);
+    s.d[1] = wrap(g.y[i] - g.y[j]);
+    s.d[2] = wrap(g.z[i] - g.z[j]);
+    s.r = sqrt(s.d[0] * s.d[0] + s.d[1] * s.d[1] + s.d[2] * s.d[2]);
+    return s;
+}
+
+// candidate set: either all particles (cand == nullptr) or an index list
+struct Cand {
+    const int64_t* idx;
+    int64_t n;
+    int64_t at(int64_t k) const { return idx ? idx[k] : k; }
+};
+
+// ---------------------------------------------------------------- volume
+template <class T> T volume_sum(const Gas<T>& g, int64_t i, Cand c) {
+    const double H = 2.0 * g.h[i];
+    T S = kernel_W(T(0.0), g.h[i]);  // j = i
+    for (int64_t k = 0; k < c.n; ++k) {
+        const int64_t j = c.at(k);
+        if (j == i) continue;
+        Sep<T> s = separation(g, i, j);
+        if (val(s.r) < H) S += kernel_W(s.r, g.h[i]);
+    }
+    return S;
+}
+
+// ---------------------------------------------------------------- moments
+constexpr int kSym[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};  // (a,b) -> xx xy xz yy yz zz
+
+template <class T> struct Moments {
+    T m0, m1[3], m2[6], g0[3], g1[3][3], g2[6][3];
+    int nnb;  // neighbours j != i inside the support
+};
+
+template <class T> void moments_one(const Gas<T>& g, const T* V, int64_t i, Cand c, Moments<T>& M) {
+    const double H = 2.0 * g.h[i];
+    M.m0 = T(0.0);
+    for (int a = 0; a < 3; ++a) { M.m1[a] = T(0.0); M.g0[a] = T(0.0); }
+    for (int p = 0; p < 6; ++p) { M.m2[p] = T(0.0); for (int cc = 0; cc < 3; ++cc) M.g2[p][cc] = T(0.0); }
+    for (int a = 0; a < 3; ++a) for (int cc = 0; cc < 3; ++cc) M.g1[a][cc] = T(0.0);
+    M.nnb = 0;
+    auto add = [&](int64_t j, const T x[3], T W, T Fv) {
+        const T Vj = V[j];
+        T dW[3] = {Fv * x[0], Fv * x[1], Fv * x[2]};
+        M.m0 += Vj * W;
+        for (int a = 0; a < 3; ++a) {
+            M.m1[a] += Vj * x[a] * W;
+            M.g0[a] += Vj * dW[a];
+        }
+        for (int a = 0; a < 3; ++a)
+            for (int b = a; b < 3; ++b) M.m2[kSym[a][b]] += Vj * x[a] * x[b] * W;
+        for (int a = 0; a < 3; ++a)
+            for (int cc = 0; cc < 3; ++cc)
+                M.g1[a][cc] += Vj * ((a == cc ? W : T(0.0)) + x[a] * dW[cc]);
+        for (int a = 0; a < 3; ++a)
+            for (int b = a; b < 3; ++b)
+                for (int cc = 0; cc < 3; ++cc)
+                    M.g2[kSym[a][b]][cc] += Vj * ((a == cc ? x[b] * W : T(0.0)) +
+                                                  (b == cc ? x[a] * W : T(0.0)) +
+                                                  x[a] * x[b] * dW[cc]);
+    };
+    {   // j = i: x_ii = 0
+        const T zero[3] = {T(0.0), T(0.0), T(0.0)};
+        add(i, zero, kernel_W(T(0.0), g.h[i]), kernel_F(T(0.0), g.h[i]));
+    }
+    for (int64_t k = 0; k < c.n; ++k) {
+        const int64_t j = c.at(k);
+        if (j == i) continue;
+        Sep<T> s = separation(g, i, j);
+        if (!(val(s.r) < H)) continue;
+        M.nnb += 1;
+        add(j, s.d, kernel_W(s.r, g.h[i]), kernel_F(s.r, g.h[i]));
+    }
+}
+
+// ---------------------------------------------------------------- corrections
+template <class T> struct Corr {
+    T A, B[3], dA[3], dB[3][3];  // dB[a][c] = d_c B^a
+};
+
+// Inverse of a symmetric 3x3 matrix by its adjugate; returns the determinant.
+template <class T> T inverse_sym3(const T s[6], T inv[3][3]) {
+    const T a = s[0], b = s[1], c = s[2], d = s[3], e = s[4], f = s[5];
+    // matrix [[a b c][b d e][c e f]]
+    T c00 = d * f - e * e, c01 = c * e - b * f, c02 = b * e - c * d;
+    T c11 = a * f - c * c, c12 = b * c - a * e, c22 = a * d - b * b;
+    T det = a * c00 + b * c01 + c * c02;
+    T r = T(1.0) / det;
+    inv[0][0] = c00 * r; inv[0][1] = c01 * r; inv[0][2] = c02 * r;
+    inv[1][0] = c01 * r; inv[1][1] = c11 * r; inv[1][2] = c12 * r;
+    inv[2][0] = c02 * r; inv[2][1] = c12 * r; inv[2][2] = c22 * r;
+    return det;
+}
+
+// Returns 1 when the zeroth-order fallback was taken (fewer than 4 neighbours
+// or a near-singular second moment), 0 otherwise.
+template <class T> int solve_corrections(const Moments<T>& M, Corr<T>& C) {
+    T inv[3][3];
+    T det = inverse_sym3(M.m2, inv);
+    T tr3 = (M.m2[0] + M.m2[3] + M.m2[5]) / T(3.0);
+    const bool singular = M.nnb < 4 || !(val(det) > 1e-12 * val(tr3) * val(tr3) * val(tr3));
+    if (singular) {
+        C.A = T(1.0) / M.m0;
+        for (int cc = 0; cc < 3; ++cc) {
+            C.B[cc] = T(0.0);
+            C.dA[cc] = -M.g0[cc] / (M.m0 * M.m0);
+            for (int a = 0; a < 3; ++a) C.dB[a][cc] = T(0.0);
+        }
+        return 1;
+    }
+    for (int a = 0; a < 3; ++a) {
+        T s = T(0.0);
+        for (int b = 0; b < 3; ++b) s += inv[a][b] * M.m1[b];
+        C.B[a] = -s;
+    }
+    T BM1 = C.B[0] * M.m1[0] + C.B[1] * M.m1[1] + C.B[2] * M.m1[2];
+    C.A = T(1.0) / (M.m0 + BM1);
+    for (int cc = 0; cc < 3; ++cc) {
+        // rhs^a = g1[a][c] + sum_b g2[ab][c] B^b
+        T rhs[3];
+        for (int a = 0; a < 3; ++a) {
+            T s = M.g1[a][cc];
+            for (int b = 0; b < 3; ++b) s += M.g2[kSym[a][b]][cc] * C.B[b];
+            rhs[a] = s;
+        }
+        for (int a = 0; a < 3; ++a) {
+            T s = T(0.0);
+            for (int b = 0; b < 3; ++b) s += inv[a][b] * rhs[b];
+            C.dB[a][cc] = -s;
+        }
+        T s = M.g0[cc];
+        for (int a = 0; a < 3; ++a) s += C.B[a] * M.g1[a][cc] + M.m1[a] * C.dB[a][cc];
+        C.dA[cc] = -(C.A * C.A) * s;
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------- forces
+// gradient of the corrected kernel of particle `s` seen from separation x = x_s - x_o
+template <class T> void corrected_gradient(const Corr<T>& C, const T x[3], T W, T Fv, T G[3]) {
+    T lin = T(1.0) + C.B[0] * x[0] + C.B[1] * x[1] + C.B[2] * x[2];
+    for (int cc = 0; cc < 3; ++cc) {
+        T dBx = C.dB[0][cc] * x[0] + C.dB[1][cc] * x[1] + C.dB[2][cc] * x[2];
+        G[cc] = C.dA[cc] * lin * W + C.A * (dBx + C.B[cc]) * W + C.A * lin * (Fv * x[cc]);
+    }
+}
+
+template <class T> void accel_one(const Gas<T>& g, const T* V, const T* rho, const Corr<T>* C,
+                                  double gamma, int64_t i, Cand c, T a[3], T& dudt) {
+    const T Pi = T(gamma - 1.0) * rho[i] * g.u[i];
+    a[0] = a[1] = a[2] = T(0.0);
+    dudt = T(0.0);
+    for (int64_t k = 0; k < c.n; ++k) {
+        const int64_t j = c.at(k);
+        if (j == i) continue;
+        Sep<T> s = separation(g, i, j);
+        const double Hi = 2.0 * g.h[i], Hj = 2.0 * g.h[j];
+        if (!(val(s.r) < std::max(Hi, Hj))) continue;
+        const T Pj = T(gamma - 1.0) * rho[j] * g.u[j];
+        T xji[3] = {-s.d[0], -s.d[1], -s.d[2]};
+        T Gij[3], Gji[3];
+        corrected_gradient(C[i], s.d, kernel_W(s.r, g.h[i]), kernel_F(s.r, g.h[i]), Gij);
+        corrected_gradient(C[j], xji, kernel_W(s.r, g.h[j]), kernel_F(s.r, g.h[j]), Gji);
+        const T coef = T(-0.5) * V[i] * V[j] * (Pi + Pj);
+        T vij[3] = {g.vx[i] - g.vx[j], g.vy[i] - g.vy[j], g.vz[i] - g.vz[j]};
+        T Fdotv = T(0.0);
+        for (int cc = 0; cc < 3; ++cc) {
+            T Fc = coef * (Gij[cc] - Gji[cc]);
+            a[cc] += Fc;
+            Fdotv += Fc * vij[cc];
+        }
+        dudt += Fdotv;
+    }
+    const T mi = T(g.m[i]);
+    for (int cc = 0; cc < 3; ++cc) a[cc] = a[cc] / mi;
+    dudt = T(-0.5) * dudt / mi;
+}
+
+// ---------------------------------------------------------------- closure
+// Everything the forces of a target particle t depend on lies within three
+// support radii of t: the forces need corrections of t's neighbours (one hop),
+// the corrections need volumes of their neighbours (two hops) and those
+// volumes need the positions of their neighbours (three hops).  A brute-force
+// scan collects that pool; the chain is then evaluated by brute force inside it.
+struct Closure {
+    std::vector<int64_t> pool;   // global indices within 3 H_max of the target
+};
+
+template <class T> void gather_pool(const Gas<T>& g, int64_t t, double R, std::vector<int64_t>& pool) {
+    pool.clear();
+    for (int64_t j = 0; j < g.n; ++j) {
+        Sep<T> s = separation(g, t, j);
+        if (val(s.r) < R) pool.push_back(j);
+    }
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+int oracle_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+static Gas<double> make_gas(int64_t n, const double* x, const double* y, const double* z,
+                            const double* vx, const double* vy, const double* vz,
+                            const double* u, const double* h, const double* m) {
+    Gas<double> g;
+    g.n = n; g.x = x; g.y = y; g.z = z; g.vx = vx; g.vy = vy; g.vz = vz; g.u = u; g.h = h; g.m = m;
+    return g;
+}
+
+// V_i, rho_i for i in targets (all when targets == NULL); outputs have nt entries.
+int oracle_volume(int64_t n, const double* x, const double* y, const double* z, const double* h,
+                  const double* m, int64_t nt, const int64_t* targets, double* V, double* rho) {
+    Gas<double> g = make_gas(n, x, y, z, nullptr, nullptr, nullptr, nullptr, h, m);
+    const int64_t cnt = targets ? nt : n;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < cnt; ++k) {
+        const int64_t i = targets ? targets[k] : k;
+        double S = volume_sum(g, i, Cand{nullptr, n});
+        V[k] = 1.0 / S;
+        rho[k] = m[i] * S;
+    }
+    return 0;
+}
+
+// Raw moments (40 per target, storage order above) and neighbour counts.
+int oracle_moments(int64_t n, const double* x, const double* y, const double* z, const double* h,
+                   const double* V, int64_t nt, const int64_t* targets, double* M40, int32_t* nnb) {
+    Gas<double> g = make_gas(n, x, y, z, nullptr, nullptr, nullptr, nullptr, h, nullptr);
+    const int64_t cnt = targets ? nt : n;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < cnt; ++k) {
+        const int64_t i = targets ? targets[k] : k;
+        Moments<double> M;
+        moments_one(g, V, i, Cand{nullptr, n}, M);
+        double* o = M40 + 40 * k;
+        o[0] = M.m0;
+        for (int a = 0; a < 3; ++a) o[1 + a] = M.m1[a];
+        for (int p = 0; p < 6; ++p) o[4 + p] = M.m2[p];
+        for (int a = 0; a < 3; ++a) o[10 + a] = M.g0[a];
+        for (int a = 0; a < 3; ++a) for (int c = 0; c < 3; ++c) o[13 + 3 * a + c] = M.g1[a][c];
+        for (int p = 0; p < 6; ++p) for (int c = 0; c < 3; ++c) o[22 + 3 * p + c] = M.g2[p][c];
+        if (nnb) nnb[k] = M.nnb;
+    }
+    return 0;
+}
+
+// A (nt), B (3 nt), dA (3 nt), dB (9 nt); returns the number of fallbacks.
+int64_t oracle_corrections(int64_t n, const double* x, const double* y, const double* z,
+                           const double* h, const double* V, int64_t nt, const int64_t* targets,
+                           double* A, double* B, double* dA, double* dB) {
+    Gas<double> g = make_gas(n, x, y, z, nullptr, nullptr, nullptr, nullptr, h, nullptr);
+    const int64_t cnt = targets ? nt : n;
+    int64_t fallbacks = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : fallbacks)
+    for (int64_t k = 0; k < cnt; ++k) {
+        const int64_t i = targets ? targets[k] : k;
+        Moments<double> M;
+        moments_one(g, V, i, Cand{nullptr, n}, M);
+        Corr<double> C;
+        fallbacks += solve_corrections(M, C);
+        A[k] = C.A;
+        for (int a = 0; a < 3; ++a) {
+            B[3 * k + a] = C.B[a];
+            dA[3 * k + a] = C.dA[a];
+            for (int c = 0; c < 3; ++c) dB[9 * k + 3 * a + c] = C.dB[a][c];
+        }
+    }
+    return fallbacks;
+}
+
+// Accelerations and du/dt for targets; V, rho and corrections for ALL particles.
+int oracle_accel(int64_t n, const double* x, const double* y, const double* z, const double* vx,
+                 const double* vy, const double* vz, const double* u, const double* h,
+                 const double* m, const double* V, const double* rho, const double* A,
+                 const double* B, const double* dA, const double* dB, double gamma, int64_t nt,
+                 const int64_t* targets, double* ax, double* ay, double* az, double* dudt) {
+    Gas<double> g = make_gas(n, x, y, z, vx, vy, vz, u, h, m);
+    std::vector<Corr<double>> C(n);
+    for (int64_t i = 0; i < n; ++i) {
+        C[i].A = A[i];
+        for (int a = 0; a < 3; ++a) {
+            C[i].B[a] = B[3 * i + a];
+            C[i].dA[a] = dA[3 * i + a];
+            for (int c = 0; c < 3; ++c) C[i].dB[a][c] = dB[9 * i + 3 * a + c];
+        }
+    }
+    const int64_t cnt = targets ? nt : n;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < cnt; ++k) {
+        const int64_t i = targets ? targets[k] : k;
+        double a[3], du;
+        accel_one(g, V, rho, C.data(), gamma, i, Cand{nullptr, n}, a, du);
+        ax[k] = a[0]; ay[k] = a[1]; az[k] = a[2]; dudt[k] = du;
+    }
+    return 0;
+}
+
+// Momentum and energy totals over all particles:
+// [sum m a_x, sum m a_y, sum m a_z, sum m (v.a + du/dt), sum m |a|,
+//  sum m (|v.a| + |du/dt|), sum m du/dt, sum m v.a]
+int oracle_totals(int64_t n, const double* m, const double* vx, const double* vy, const double* vz,
+                  const double* ax, const double* ay, const double* az, const double* dudt,
+                  double* totals) {
+    for (int k = 0; k < 8; ++k) totals[k] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double va = vx[i] * ax[i] + vy[i] * ay[i] + vz[i] * az[i];
+        totals[0] += m[i] * ax[i];
+        totals[1] += m[i] * ay[i];
+        totals[2] += m[i] * az[i];
+        totals[3] += m[i] * (va + dudt[i]);
+        totals[4] += m[i] * std::sqrt(ax[i] * ax[i] + ay[i] * ay[i] + az[i] * az[i]);
+        totals[5] += m[i] * (std::fabs(va) + std::fabs(dudt[i]));
+        totals[6] += m[i] * dudt[i];
+        totals[7] += m[i] * va;
+    }
+    return 0;
+}
+
+// Full chain V -> corrections -> forces for target particles, each evaluated
+// by brute force inside its own three-hop pool (see Closure above).  Outputs
+// per target: V, rho, A, B[3], dA[3], dB[9], a[3], du/dt.
+int64_t oracle_hydro_targets(int64_t n, const double* x, const double* y, const double* z,
+                             const double* vx, const double* vy, const double* vz, const double* u,
+                             const double* h, const double* m, double gamma, int64_t nt,
+                             const int64_t* targets, double* V_o, double* rho_o, double* A_o,
+                             double* B_o, double* dA_o, double* dB_o, double* ax, double* ay,
+                             double* az, double* dudt) {
+    Gas<double> g = make_gas(n, x, y, z, vx, vy, vz, u, h, m);
+    double Hmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) Hmax = std::max(Hmax, 2.0 * h[i]);
+    const double R = 3.0 * Hmax * (1.0 + 1e-12);
+    int64_t fallbacks = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : fallbacks)
+    for (int64_t k = 0; k < nt; ++k) {
+        const int64_t t = targets[k];
+        std::vector<int64_t> pool;
+        gather_pool(g, t, R, pool);
+        const int64_t np = (int64_t)pool.size();
+        // local copy of the pool's particles (pool-local indices)
+        std::vector<double> lx(np), ly(np), lz(np), lvx(np), lvy(np), lvz(np), lu(np), lh(np), lm(np);
+        int64_t lt = -1;
+        for (int64_t p = 0; p < np; ++p) {
+            const int64_t j = pool[p];
+            lx[p] = x[j]; ly[p] = y[j]; lz[p] = z[j]; lvx[p] = vx[j]; lvy[p] = vy[j]; lvz[p] = vz[j];
+            lu[p] = u[j]; lh[p] = h[j]; lm[p] = m[j];
+            if (j == t) lt = p;
+        }
+        Gas<double> lg = make_gas(np, lx.data(), ly.data(), lz.data(), lvx.data(), lvy.data(),
+                                  lvz.data(), lu.data(), lh.data(), lm.data());
+        const Cand all{nullptr, np};
+        // S1: the target and its force neighbours; S2: S1 and their gather neighbours
+        std::vector<char> in1(np, 0), in2(np, 0);
+        in1[lt] = 1;
+        for (int64_t p = 0; p < np; ++p) {
+            if (p == lt) continue;
+            Sep<double> s = separation(lg, lt, p);
+            if (s.r < std::max(2.0 * lh[lt], 2.0 * lh[p])) in1[p] = 1;
+        }
+        for (int64_t p = 0; p < np; ++p) {
+            if (!in1[p]) continue;
+            in2[p] = 1;
+            for (int64_t q = 0; q < np; ++q) {
+                Sep<double> s = separation(lg, p, q);
+                if (s.r < 2.0 * lh[p]) in2[q] = 1;
+            }
+        }
+        std::vector<double> lV(np, 0.0), lrho(np, 0.0);
+        for (int64_t p = 0; p < np; ++p) {
+            if (!in2[p]) continue;
+            double S = volume_sum(lg, p, all);
+            lV[p] = 1.0 / S;
+            lrho[p] = lm[p] * S;
+        }
+        std::vector<Corr<double>> lC(np);
+        for (int64_t p = 0; p < np; ++p) {
+            if (!in1[p]) continue;
+            Moments<double> M;
+            moments_one(lg, lV.data(), p, all, M);
+            int fb = solve_corrections(M, lC[p]);
+            if (p == lt) fallbacks += fb;
+        }
+        double a[3], du;
+        accel_one(lg, lV.data(), lrho.data(), lC.data(), gamma, lt, all, a, du);
+        V_o[k] = lV[lt];
+        rho_o[k] = lrho[lt];
+        const Corr<double>& C = lC[lt];
+        A_o[k] = C.A;
+        for (int q = 0; q < 3; ++q) {
+            B_o[3 * k + q] = C.B[q];
+            dA_o[3 * k + q] = C.dA[q];
+            for (int c = 0; c < 3; ++c) dB_o[9 * k + 3 * q + c] = C.dB[q][c];
+        }
+        ax[k] = a[0]; ay[k] = a[1]; az[k] = a[2]; dudt[k] = du;
+    }
+    return fallbacks;
+}
+
+// Short-range gravity for targets (all when targets == NULL).  poly may be NULL.
+int oracle_gravity(int64_t n, const double* x, const double* y, const double* z, const double* m,
+                   double G, double eps, double r_cut, const double* poly, int64_t nt,
+                   const int64_t* targets, double* ax, double* ay, double* az) {
+    Gas<double> g = make_gas(n, x, y, z, nullptr, nullptr, nullptr, nullptr, nullptr, m);
+    const int64_t cnt = targets ? nt : n;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < cnt; ++k) {
+        const int64_t i = targets ? targets[k] : k;
+        double a[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            Sep<double> s = separation(g, i, j);
+            if (!(s.r < r_cut)) continue;
+            const double r2 = s.r * s.r;
+            double f = 1.0 / ((r2 + eps * eps) * std::sqrt(r2 + eps * eps));
+            if (poly) {
+                double rk = 1.0;
+                for (int p = 0; p < 6; ++p) { f -= poly[p] * rk; rk *= r2; }
+            }
+            for (int c = 0; c < 3; ++c) a[c] -= G * m[j] * s.d[c] * f;
+        }
+        ax[k] = a[0]; ay[k] = a[1]; az[k] = a[2];
+    }
+    return 0;
+}
+
+// Ordered-pair interaction counts (j != i) for targets (all when NULL):
+// mode 0: r < 2 h_i (volume, moments); 1: r < 2 max(h_i, h_j) (forces);
+// 2: r < r_fixed (gravity; h unused).
+int64_t oracle_count_pairs(int64_t n, const double* x, const double* y, const double* z,
+                           const double* h, int mode, double r_fixed, int64_t nt,
+                           const int64_t* targets, int32_t* per_target) {
+    Gas<double> g = make_gas(n, x, y, z, nullptr, nullptr, nullptr, nullptr, h, nullptr);
+    const int64_t cnt = targets ? nt : n;
+    int64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : total)
+    for (int64_t k = 0; k < cnt; ++k) {
+        const int64_t i = targets ? targets[k] : k;
+        int32_t c = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            Sep<double> s = separation(g, i, j);
+            double R = mode == 0 ? 2.0 * h[i] : mode == 1 ? 2.0 * std::max(h[i], h[j]) : r_fixed;
+            if (s.r < R) ++c;
+        }
+        if (per_target) per_target[k] = c;
+        total += c;
+    }
+    return total;
+}
+
+// Kernel values for pinning: W(r, h) and F(r, h) at n radii.
+void oracle_kernel(int64_t n, const double* r, double h, double* W, double* F) {
+    for (int64_t k = 0; k < n; ++k) {
+        W[k] = kernel_W(r[k], h);
+        F[k] = kernel_F(r[k], h);
+    }
+}
+
+}  // extern "C"

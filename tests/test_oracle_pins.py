@@ -1,0 +1,269 @@
+"""Pins of the FP64 oracle against what the mathematics fixes (no GPU).
+
+Each test checks the oracle against something other than itself: closed forms
+of the Wendland C4 kernel, the exact reproducing conditions of the CRK
+corrections (which determine A, B, dA, dB uniquely), the conservation laws of
+the antisymmetric pair forces, the symmetry of a perfect lattice, a dense
+NumPy re-implementation for tiny N, and special cases that reduce to textbook
+SPH or two-body gravity.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from tests import dense_crk
+
+
+def tiny_gas(n=400, nbr=24, seed=5):
+    """Random (unclustered) gas with ~nbr neighbours, small enough for dense N^2 arrays."""
+    rng = np.random.default_rng(seed)
+    x, y, z = (synth.grid_round(rng.random(n)) for _ in range(3))
+    nt = rng.integers(nbr - 4, nbr + 5, n)
+    H = synth.knn_support(x, y, z, nt)
+    g = dict(n=n, x=x, y=y, z=z, h=synth.f32(0.5 * H), m=synth.f32(np.full(n, 1.0 / n)),
+             vx=synth.f32(rng.normal(0, 0.05, n)), vy=synth.f32(rng.normal(0, 0.05, n)),
+             vz=synth.f32(rng.normal(0, 0.05, n)), u=synth.f32(np.exp(0.5 * rng.normal(size=n))),
+             gamma=5.0 / 3.0)
+    synth.check_support(g)
+    return g
+
+
+@pytest.fixture(scope="module")
+def tiny(oracle_lib):
+    g = tiny_gas()
+    return g, oracle_lib.hydro(g), dense_crk.chain(g)
+
+
+# ---------------------------------------------------------------- kernel
+def test_kernel_normalisation(oracle_lib):
+    # 4 pi int_0^H r^2 W(r) dr = 1, Gauss-Legendre on 64 nodes (exact for the degree-10 polynomial)
+    h = 0.37
+    xg, wg = np.polynomial.legendre.leggauss(64)
+    r = (xg + 1.0) * h  # [0, 2h]
+    W, _ = oracle_lib.kernel(r, h)
+    integral = np.sum(wg * h * 4.0 * np.pi * r * r * W)
+    assert abs(integral - 1.0) < 1e-14
+
+
+def test_kernel_closed_forms(oracle_lib):
+    h = 0.21
+    H = 2 * h
+    W0, F0 = oracle_lib.kernel(np.array([0.0]), h)
+    assert W0[0] == pytest.approx(495.0 / (32.0 * math.pi * H ** 3), rel=1e-15)
+    assert F0[0] == pytest.approx(-1155.0 / (4.0 * math.pi * H ** 5), rel=1e-15)
+    Wb, Fb = oracle_lib.kernel(np.array([H, 1.5 * H]), h)
+    assert np.all(Wb == 0.0) and np.all(Fb == 0.0)
+
+
+def test_kernel_derivative_fd(oracle_lib):
+    # dW/dr = F r, checked by 4th-order central differences
+    h = 0.3
+    r = np.linspace(0.01, 2 * h - 0.01, 37)
+    eps = 1e-4
+    Wp2, _ = oracle_lib.kernel(r + 2 * eps, h)
+    Wp1, _ = oracle_lib.kernel(r + eps, h)
+    Wm1, _ = oracle_lib.kernel(r - eps, h)
+    Wm2, _ = oracle_lib.kernel(r - 2 * eps, h)
+    dW = (-Wp2 + 8 * Wp1 - 8 * Wm1 + Wm2) / (12 * eps)
+    _, F = oracle_lib.kernel(r, h)
+    scale = np.abs(F * r).max()
+    assert np.abs(dW - F * r).max() < 1e-9 * scale
+
+
+# ---------------------------------------------------------------- volume
+def test_lattice_volume_direct_sum(oracle_lib):
+    """Unjittered lattice: S = sum over lattice vectors |n| s < 2h of W(|n| s), no neighbour search."""
+    g = synth.make_lattice(n_side=16, jitter=0.0)
+    s = 1.0 / 16
+    h = g["h"][0]
+    k = np.arange(-4, 5)
+    nv = np.stack(np.meshgrid(k, k, k, indexing="ij"), -1).reshape(-1, 3)
+    rr = np.sqrt((nv.astype(float) ** 2).sum(1)) * s
+    W, _ = oracle_lib.kernel(rr[rr < 2 * h], h)
+    S = W.sum()
+    V, rho = oracle_lib.volume(g)
+    assert np.allclose(V, 1.0 / S, rtol=1e-13, atol=0)
+    assert np.allclose(rho, g["m"] * S, rtol=1e-13, atol=0)
+    # a fill factor close to 1 (the kernel estimate of the number density is ~N)
+    assert abs(V.sum() - 1.0) < 0.03
+
+
+# ---------------------------------------------------------------- corrections
+def test_reproducing_conditions(tiny, oracle_lib):
+    """sum_j V_j W^R_ij = 1 and sum_j V_j x_ij W^R_ij = 0 (these fix A and B uniquely)."""
+    g, o, _ = tiny
+    d, r = dense_crk.separations(g)
+    W, _ = dense_crk.wendland(r, 2.0 * g["h"][:, None])
+    WR = o["A"][:, None] * (1.0 + np.einsum("ia,ija->ij", o["B"], d)) * W
+    c0 = (WR * o["V"][None, :]).sum(1)
+    c1 = np.einsum("ij,ija->ia", WR * o["V"][None, :], d)
+    assert np.abs(c0 - 1.0).max() < 1e-13
+    scale = np.einsum("ij,ija->ia", np.abs(WR) * o["V"][None, :], np.abs(d)).max()
+    assert np.abs(c1).max() < 1e-13 * scale
+
+
+def test_gradient_reproducing_conditions(tiny):
+    """sum_j V_j G_ij = 0 and sum_j V_j x_ij^a G_ij^c = -delta^ac (these fix dA and dB)."""
+    g, o, _ = tiny
+    d, r = dense_crk.separations(g)
+    H = 2.0 * g["h"][:, None]
+    W, F = dense_crk.wendland(r, H)
+    lin = 1.0 + np.einsum("ia,ija->ij", o["B"], d)
+    G = (o["dA"][:, None, :] * (lin * W)[:, :, None]
+         + o["A"][:, None, None] * (np.einsum("iac,ija->ijc", o["dB"], d) + o["B"][:, None, :]) * W[:, :, None]
+         + (o["A"][:, None] * lin * F)[:, :, None] * d)
+    Vj = o["V"][None, :, None]
+    c0 = (Vj * G).sum(1)
+    c1 = np.einsum("ija,ijc->iac", Vj * d, G)
+    scale = np.abs(Vj * G).sum(1).max()
+    assert np.abs(c0).max() < 1e-12 * scale
+    assert np.abs(c1 + np.eye(3)[None]).max() < 1e-12
+
+
+def test_dense_cross_implementation(tiny):
+    """The dense NumPy chain agrees with the C++ oracle to roundoff on every output."""
+    _, o, dn = tiny
+    for k in ("V", "rho", "A", "B", "dA", "dB", "a", "dudt"):
+        ref = np.abs(dn[k]).max()
+        err = np.abs(o[k] - dn[k]).max()
+        assert err <= 1e-12 * ref, (k, err, ref)
+
+
+def test_raw_moments_against_dense(tiny, oracle_lib):
+    g, o, dn = tiny
+    M, nnb = oracle_lib.moments(g, o["V"])
+    sym = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    ref = np.concatenate([dn["m0"][:, None], dn["m1"],
+                          np.stack([dn["m2"][:, a, b] for a, b in sym], 1),
+                          dn["g0"], dn["g1"].reshape(-1, 9),
+                          np.concatenate([dn["g2"][:, a, b, :] for a, b in sym], 1)], axis=1)
+    for k in range(40):
+        s = np.abs(ref[:, k]).max() + 1e-300
+        assert np.abs(M[:, k] - ref[:, k]).max() <= 1e-12 * max(s, np.abs(ref).max() * 1e-6), k
+    cnt, _ = oracle_lib.count_pairs(g, 0)
+    assert nnb.sum() == cnt
+
+
+# ---------------------------------------------------------------- forces
+def test_momentum_and_energy_conservation(tiny, oracle_lib):
+    g, o, _ = tiny
+    T = o["totals"]
+    assert np.abs(T[:3]).max() < 1e-13 * T[4]
+    assert abs(T[3]) < 1e-13 * T[5]
+
+
+def test_lattice_zero_acceleration(oracle_lib):
+    """A perfect lattice with uniform h, m, u feels no pressure force."""
+    g = synth.make_lattice(n_side=16, jitter=0.0)  # dyadic: exact on the grid
+    o = oracle_lib.hydro(g)
+    # pair-force scale: |F_ij| ~ V^2 P |grad W| / m
+    V = o["V"][0]
+    P = (g["gamma"] - 1) * o["rho"][0] * g["u"][0]
+    _, F = oracle_lib.kernel(np.array([0.5 * 2 * g["h"][0]]), g["h"][0])
+    scale = V * V * P * abs(F[0]) * g["h"][0] / g["m"][0]
+    assert np.abs(o["a"]).max() < 1e-12 * scale
+    assert o["n_fallback"] == 0
+
+
+def test_uncorrected_limit_is_textbook_sph(tiny, oracle_lib):
+    """A=1, B=dA=dB=0 gives -(1/2m_i) sum_j V_iV_j(P_i+P_j)(F(r,h_i)+F(r,h_j)) x_ij."""
+    g, o, _ = tiny
+    n = g["n"]
+    corr = (np.ones(n), np.zeros((n, 3)), np.zeros((n, 3)), np.zeros((n, 3, 3)))
+    a, du = oracle_lib.accel(g, o["V"], o["rho"], corr)
+    d, r = dense_crk.separations(g)
+    _, Fi = dense_crk.wendland(r, 2.0 * g["h"][:, None])
+    _, Fj = dense_crk.wendland(r, 2.0 * g["h"][None, :])
+    P = (g["gamma"] - 1) * o["rho"] * g["u"]
+    np.fill_diagonal(Fi, 0.0)
+    np.fill_diagonal(Fj, 0.0)
+    pref = -0.5 * o["V"][:, None] * o["V"][None, :] * (P[:, None] + P[None, :]) * (Fi + Fj)
+    ref = np.einsum("ij,ija->ia", pref, d) / g["m"][:, None]
+    assert np.abs(a - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_galilean_and_scaling_invariance(tiny, oracle_lib):
+    g, o, _ = tiny
+    g2 = dict(g)
+    for k in ("vx", "vy", "vz"):
+        g2[k] = g[k] + 0.375
+    o2 = oracle_lib.hydro(g2)
+    assert np.abs(o2["a"] - o["a"]).max() < 1e-12 * np.abs(o["a"]).max()
+    assert np.abs(o2["dudt"] - o["dudt"]).max() < 1e-11 * np.abs(o["dudt"]).max()
+    g3 = dict(g)
+    g3["u"] = 4.0 * g["u"]
+    o3 = oracle_lib.hydro(g3)
+    assert np.abs(o3["a"] - 4.0 * o["a"]).max() < 1e-13 * np.abs(o["a"]).max()
+    g4 = dict(g)
+    for k in ("vx", "vy", "vz"):
+        g4[k] = np.zeros(g["n"])
+    o4 = oracle_lib.hydro(g4)
+    assert np.abs(o4["dudt"]).max() == 0.0
+
+
+def test_translation_and_permutation_invariance(tiny, oracle_lib):
+    g, o, _ = tiny
+    shift = np.array([0.25, 0.5, 0.125])  # exact on the 2^-32 grid
+    g2 = dict(g)
+    for c, k in enumerate("xyz"):
+        g2[k] = np.mod(g[k] + shift[c], 1.0)
+    o2 = oracle_lib.hydro(g2)
+    for k in ("V", "A", "dB", "a", "dudt"):
+        assert np.abs(o2[k] - o[k]).max() <= 1e-12 * np.abs(o[k]).max(), k
+    perm = np.random.default_rng(3).permutation(g["n"])
+    g3 = {k: (v[perm] if isinstance(v, np.ndarray) and v.shape == (g["n"],) else v) for k, v in g.items()}
+    o3 = oracle_lib.hydro(g3)
+    for k in ("V", "A", "B", "a", "dudt"):
+        assert np.abs(o3[k] - o[k][perm]).max() <= 1e-12 * np.abs(o[k]).max(), k
+
+
+# ---------------------------------------------------------------- closures
+def test_closure_targets_equal_full_chain(oracle_lib):
+    g = synth.make_config("C2", n_side=16)
+    full = oracle_lib.hydro(g)
+    t = synth.sample_targets(g["n"], 24)
+    cl = oracle_lib.hydro_targets(g, t)
+    for k in ("V", "rho", "A", "B", "dA", "dB", "a", "dudt"):
+        err = np.abs(cl[k] - full[k][t]).max()
+        assert err <= 1e-13 * np.abs(full[k]).max(), (k, err)
+
+
+# ---------------------------------------------------------------- gravity
+def test_gravity_two_body_closed_form(oracle_lib):
+    x = synth.grid_round(np.array([0.25, 0.25 + 0.01]))
+    g = dict(x=x, y=np.full(2, 0.5), z=np.full(2, 0.5), m=np.array([2.0, 3.0]),
+             G=1.0, eps=0.002, r_cut=0.05)
+    a = oracle_lib.gravity(g)
+    r = x[1] - x[0]
+    f = 1.0 / (r * r + 0.002 ** 2) ** 1.5
+    assert a[0, 0] == pytest.approx(3.0 * r * f, rel=1e-14)
+    assert a[1, 0] == pytest.approx(-2.0 * r * f, rel=1e-14)
+    assert np.all(a[:, 1:] == 0.0)
+    g["r_cut"] = 0.009  # outside the cutoff: no force
+    assert np.all(oracle_lib.gravity(g) == 0.0)
+
+
+def test_gravity_polynomial_term(oracle_lib):
+    x = synth.grid_round(np.array([0.25, 0.25 + 0.01]))
+    p = np.array([3.0, -2.0, 0.5, 0.25, -0.125, 1.0])
+    g = dict(x=x, y=np.full(2, 0.5), z=np.full(2, 0.5), m=np.array([1.0, 1.0]),
+             G=2.0, eps=0.002, r_cut=0.05)
+    a = oracle_lib.gravity(g, poly=p)
+    r = x[1] - x[0]
+    f = 1.0 / (r * r + 0.002 ** 2) ** 1.5 - sum(p[k] * r ** (2 * k) for k in range(6))
+    assert a[0, 0] == pytest.approx(2.0 * r * f, rel=1e-13)
+
+
+def test_gravity_momentum_and_lattice(oracle_lib):
+    g = synth.make_gravity(n_side=8)
+    a = oracle_lib.gravity(g)
+    Pm = (g["m"][:, None] * a).sum(0)
+    assert np.abs(Pm).max() < 1e-13 * (g["m"][:, None] * np.abs(a)).sum()
+    lat = synth.make_lattice(n_side=16, jitter=0.0)
+    gl = dict(x=lat["x"], y=lat["y"], z=lat["z"], m=lat["m"], G=1.0, eps=0.001, r_cut=0.2)
+    al = oracle_lib.gravity(gl)
+    one = lat["m"][0] / 0.01 ** 2
+    assert np.abs(al).max() < 1e-12 * one
