@@ -1,0 +1,195 @@
+/*
+ * crk.h -- C ABI of the MI355X (gfx950) library for the CRK-SPH particle-pair
+ * passes and short-range particle-particle gravity.
+ *
+ * The paper (Rangel et al., "A Performance-Portable SYCL Implementation of
+ * CRK-HACC for Exascale") names the hot GPU kernels of CRK-HACC's adiabatic
+ * hydrodynamics -- Geometry (particle volumes), Corrections (reproducing-kernel
+ * coefficients), Acceleration (momentum derivative) and Energy (internal
+ * energy derivative) -- in Sec. 5, and the short-range gravity evaluated by
+ * direct particle-particle interaction after the particle-mesh force split in
+ * Sec. 3.1.  Interactions are evaluated between leaves of a recursive
+ * coordinate bisection (RCB) tree (Sec. 3.1; Sec. 5.3, Figs. 3-4).  Two
+ * species exist: gas feels hydrodynamic and gravitational forces, dark matter
+ * gravity only (Sec. 3.1).  The paper does not print the equations; the ones
+ * implemented here are linear conservative reproducing-kernel SPH (the method
+ * it cites) with a Wendland C4 kernel of support H = 2h, spelled out per call.
+ *
+ * Conventions for every call
+ *  - Particle indices are int32 (n < 2^31).  Pair counts are int64.
+ *  - Positions x, y, z are FP64 device arrays in the unit periodic box.  They
+ *    are wrapped into [0, 1) and rounded to the 2^-32 grid on entry; inputs on
+ *    that grid are used exactly.  Separations use the minimum image.
+ *  - Every other particle field, and every output, is a device array of the
+ *    precision `prec`: float for CRK_F32, double for CRK_F64.  Vector fields
+ *    are row-major per particle: a[3*i + c], B[3*i + a], dB[9*i + 3*a + c].
+ *  - Inputs and outputs are in the caller's particle order; the library
+ *    reorders internally along the tree.
+ *  - All device buffers passed in are owned by the caller and must not alias
+ *    each other.  The library owns the memory behind a crk_leaves handle
+ *    (tree order, interaction lists and per-pass scratch) until
+ *    crk_leaves_free.
+ *  - Work is enqueued on `stream` (a hipStream_t); only crk_build_leaf_pairs
+ *    and crk_leaves_stats synchronise with the host.  Calls that use the same
+ *    handle share its scratch and must not run concurrently.
+ *  - Return value: CRK_OK (0) or a negative code; crk_last_error() then
+ *    returns a message (thread-local).  Asynchronous device errors surface at
+ *    a later call.
+ *
+ * Precision modes
+ *  - CRK_F32: pair arithmetic in FP32 with compensated (Kahan-type) FP32
+ *    accumulation; the per-particle 3x3 correction solve and the global
+ *    momentum/energy totals in FP64.
+ *  - CRK_F64: the same kernels instantiated in FP64 with plain sums.
+ */
+#ifndef CRK_H
+#define CRK_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CRK_OK = 0,
+    CRK_EINVAL = -1, /* invalid argument (null pointer, size, radius >= half the box, ...) */
+    CRK_ENOMEM = -2, /* device or host allocation failed */
+    CRK_EHIP = -3,   /* a HIP runtime or launch error */
+    CRK_ESTATE = -4  /* handle built in the wrong mode for this call */
+};
+
+typedef enum { CRK_F32 = 0, CRK_F64 = 1 } crk_prec;
+
+/* Gas particles.  x, y, z: FP64 device arrays of n.  vx..m: device arrays of n
+ * in the precision of the call.  Fields a call does not use may be NULL. */
+typedef struct {
+    int64_t n;
+    const double *x, *y, *z;
+    const void *vx, *vy, *vz; /* velocity */
+    const void *u;            /* specific internal energy */
+    const void *h;            /* smoothing length; kernel support H = 2h */
+    const void *m;            /* mass */
+} crk_gas;
+
+/* Reproducing-kernel corrections (device, precision of the call):
+ * A[n], B[3n], dA[3n] (dA[3i+c] = d_c A), dB[9n] (dB[9i+3a+c] = d_c B^a). */
+typedef struct {
+    void *A, *B, *dA, *dB;
+} crk_corr;
+
+/* Opaque handle: tree order, leaf and tile interaction lists, scratch. */
+typedef struct crk_leaves crk_leaves;
+
+/* Launch and tiling choices (the autotuner's search space). */
+typedef struct {
+    int persistent;      /* 1: persistent grid draining an atomic work queue; 0: one tile per wave */
+    int waves_per_cu;    /* persistent grid size = CUs * waves_per_cu waves */
+    int kahan_chunk;     /* FP32 moments: plain sums over this many pairs, compensated across chunks (1 = every pair) */
+    int block_waves;     /* waves per workgroup for the list-driven pair passes (1, 2, 4) */
+} crk_tuning;
+
+/*
+ * Build the tree and interaction lists (Sec. 3.1 RCB tree; Sec. 5.3 leaf-pair
+ * interaction).  Copies positions (and h) to the host, bisects recursively
+ * along the longest axis at the median until a node holds at most leaf_max
+ * particles (and, when split_extent > 0, until its longest side is at most
+ * split_extent, never producing leaves below leaf_min), then forms tiles of
+ * 64 consecutive particles in tree order and, per tile, the list of leaves
+ * whose boxes come within the interaction radius of the tile's box.
+ *
+ *  h != NULL (hydro mode): radius max(2h_i, 2h_j); a per-particle neighbour
+ *    list (j != i, |x_ij| < max(2h_i, 2h_j)) is built on the GPU for the CRK
+ *    passes.  Requires 2 max(h) < 1/2.
+ *  h == NULL (fixed-radius mode): radius r_fixed (< 1/2), for sr_gravity.
+ *
+ * prec gives the precision of h.  leaf_max in [1, 1<<20].  On success *out
+ * owns device memory until crk_leaves_free.  Synchronises `stream`.
+ */
+int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const double* z,
+                         const void* h, double r_fixed, int leaf_max, int leaf_min,
+                         double split_extent, crk_prec prec, crk_leaves** out,
+                         hipStream_t stream);
+
+/*
+ * Geometry pass (Sec. 5, "Geometry": particle volumes).
+ *   S_i = sum_{j: |x_ij| < 2h_i} W(|x_ij|, h_i)   (j = i included)
+ *   V_i = 1 / S_i,  rho_i = m_i S_i
+ * Reads gas x, y, z, h, m.  Writes V[n], rho[n].
+ */
+int crk_volume(crk_leaves* leaves, const crk_gas* gas, crk_prec prec, void* V, void* rho,
+               hipStream_t stream);
+
+/*
+ * Corrections pass (Sec. 5, "Corrections": reproducing-kernel coefficients).
+ * Over j with |x_ij| < 2h_i (j = i included), with W_ij = W(r_ij, h_i) and
+ * d_c W_ij its x_i^c derivative, the 40 moments
+ *   m0 = sum V_j W, m1^a = sum V_j x^a W, m2^ab = sum V_j x^a x^b W,
+ *   g0^c = sum V_j d_cW, g1^ac = d_c m1^a, g2^abc = d_c m2^ab
+ * give, per particle in FP64,
+ *   B = -m2^-1 m1,  A = 1/(m0 + B.m1),
+ *   d_cB = -m2^-1 (g1[.,c] + g2[.,.,c] B),  d_cA = -A^2 (g0^c + B.g1[.,c] + m1.d_cB),
+ * so that sum_j V_j A_i(1 + B_i.x_ij) W_ij reproduces constant and linear fields.
+ * If particle i has fewer than 4 neighbours or det m2 <= 1e-12 (tr m2 / 3)^3 the
+ * zeroth-order form A = 1/m0, B = 0, dA = -g0/m0^2, dB = 0 is used and counted.
+ * Reads gas x, y, z, h and V[n].  Writes *out.  If n_fallback (device int64)
+ * is not NULL the number of fallbacks is added to it.
+ */
+int crk_corrections(crk_leaves* leaves, const crk_gas* gas, const void* V, crk_prec prec,
+                    const crk_corr* out, int64_t* n_fallback, hipStream_t stream);
+
+/*
+ * Acceleration and Energy passes, fused (Sec. 5, "Acceleration", "Energy").
+ * With P_i = (gamma - 1) rho_i u_i and, for j != i with r_ij < max(2h_i, 2h_j),
+ *   G_ij = grad of the corrected kernel of i (A_i, B_i, dA_i, dB_i, h_i) at x_ij,
+ *   G_ji = the same for j at x_ji = -x_ij,
+ *   F_ij = -1/2 V_i V_j (P_i + P_j) (G_ij - G_ji)          (= -F_ji),
+ *   a_i = (1/m_i) sum_j F_ij,   du_i/dt = -(1/(2 m_i)) sum_j F_ij . (v_i - v_j).
+ * Reads gas x, y, z, vx, vy, vz, u, h, m, V, rho and the corrections.
+ * Writes a[3n] and dudt[n].  If totals (device double[8]) is not NULL it
+ * receives, in FP64, [sum m a_x, sum m a_y, sum m a_z, sum m (v.a + du/dt),
+ * sum m |a|, sum m (|v.a| + |du/dt|), sum m du/dt, sum m v.a].
+ */
+int crk_accel_energy(crk_leaves* leaves, const crk_gas* gas, const void* V, const void* rho,
+                     const crk_corr* corr, double gamma, crk_prec prec, void* a, void* dudt,
+                     double* totals, hipStream_t stream);
+
+/*
+ * Short-range particle-particle gravity (Sec. 3.1 force split; all species).
+ *   a_i = -G sum_{j != i, r_ij < r_cut} m_j x_ij [ (r^2 + eps^2)^(-3/2) - sum_k p_k r^(2k) ]
+ * poly: host array of 6 coefficients p_0..p_5 or NULL (no polynomial term).
+ * Needs a handle built in fixed-radius mode with r_fixed >= r_cut.
+ * Reads x, y, z and m[n] (precision prec).  Writes a[3n].
+ */
+int sr_gravity(crk_leaves* leaves, int64_t n, const double* x, const double* y, const double* z,
+               const void* m, double G, double eps, double r_cut, const double* poly,
+               crk_prec prec, void* a, hipStream_t stream);
+
+/*
+ * Statistics of a handle (host int64[8]):
+ *   [0] leaves, [1] tiles, [2] candidate pairs scanned by the list build
+ *   (tile particles x candidate-leaf particles), [3] neighbour-list entries,
+ *   [4] ordered pairs j != i with r < 2h_i, [5] with r < max(2h_i, 2h_j)
+ *   ([4], [5] counted in FP64 on the device; hydro mode only, else 0),
+ *   [6] padded list slots, [7] host build time in microseconds.
+ * Synchronises the device.
+ */
+int crk_leaves_stats(crk_leaves* leaves, int64_t* host_out);
+
+/* Read or set the launch/tiling choices of a handle (set validates them). */
+int crk_get_tuning(const crk_leaves* leaves, crk_tuning* out);
+int crk_set_tuning(crk_leaves* leaves, const crk_tuning* in);
+
+/* Release a handle (NULL is ignored).  Synchronises the device. */
+void crk_leaves_free(crk_leaves* leaves);
+
+/* Message for the last non-zero return on this thread ("" if none). */
+const char* crk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CRK_H */

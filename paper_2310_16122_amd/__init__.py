@@ -1,0 +1,261 @@
+"""Python binding of ``libcrk.so``: the CRK-SPH pair passes and short-range
+gravity for MI355X (gfx950).
+
+Argument marshalling only.  Every step runs in the HIP library; PyTorch
+supplies device memory and the current stream.  The functions have the names
+of the C entry points declared in ``include/crk.h`` and follow its
+conventions (caller particle order; FP64 positions; other fields and outputs
+in the precision of the call, ``"f32"`` or ``"f64"``).
+
+There is no CPU fallback: if the library is missing or no GPU is present the
+calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcrk.so")
+
+CRK_F32, CRK_F64 = 0, 1
+_PREC = {"f32": CRK_F32, "f64": CRK_F64}
+_DTYPE = {"f32": torch.float32, "f64": torch.float64}
+_STATUS = {0: "CRK_OK", -1: "CRK_EINVAL", -2: "CRK_ENOMEM", -3: "CRK_EHIP", -4: "CRK_ESTATE"}
+
+# the C symbols declared in include/crk.h
+EXPORTS = ("crk_build_leaf_pairs", "crk_volume", "crk_corrections", "crk_accel_energy",
+           "sr_gravity", "crk_leaves_stats", "crk_get_tuning", "crk_set_tuning",
+           "crk_leaves_free", "crk_last_error")
+
+
+class CrkError(RuntimeError):
+    def __init__(self, fn, code, msg):
+        super().__init__(f"{fn} failed with {_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Gas(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64)] + [(k, ctypes.c_void_p) for k in
+                                          ("x", "y", "z", "vx", "vy", "vz", "u", "h", "m")]
+
+
+class _Corr(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("A", "B", "dA", "dB")]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("persistent", ctypes.c_int), ("waves_per_cu", ctypes.c_int),
+                ("kahan_chunk", ctypes.c_int), ("block_waves", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path=None):
+    """Load libcrk.so (built by ``paper_2310_16122_amd.build``); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    P, I64, D, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    lib.crk_build_leaf_pairs.argtypes = [I64, P, P, P, P, D, I, I, D, I, ctypes.POINTER(P), P]
+    lib.crk_volume.argtypes = [P, ctypes.POINTER(_Gas), I, P, P, P]
+    lib.crk_corrections.argtypes = [P, ctypes.POINTER(_Gas), P, I, ctypes.POINTER(_Corr), P, P]
+    lib.crk_accel_energy.argtypes = [P, ctypes.POINTER(_Gas), P, P, ctypes.POINTER(_Corr), D, I,
+                                     P, P, P, P]
+    lib.sr_gravity.argtypes = [P, I64, P, P, P, P, D, D, D, P, I, P, P]
+    lib.crk_leaves_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+    lib.crk_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    lib.crk_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    lib.crk_leaves_free.argtypes = [P]
+    lib.crk_leaves_free.restype = None
+    lib.crk_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("crk_leaves_free", "crk_last_error"):
+            getattr(lib, name).restype = I
+    _lib = lib
+    return lib
+
+
+def _check(fn, code):
+    if code != 0:
+        raise CrkError(fn, code, load_library().crk_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t
+
+
+def _gas(gas, prec, keys):
+    dt = _DTYPE[prec]
+    g = _Gas()
+    g.n = int(gas["x"].numel())
+    for k in ("x", "y", "z"):
+        setattr(g, k, _dev(gas[k], torch.float64).data_ptr())
+    for k in keys:
+        setattr(g, k, _dev(gas[k], dt).data_ptr())
+    return g
+
+
+class Leaves:
+    """Owner of a ``crk_leaves`` handle (tree, interaction lists, scratch)."""
+
+    def __init__(self, handle, n, hydro, prec):
+        self._h = handle
+        self.n = n
+        self.hydro = hydro
+        self.prec = prec
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("handle already freed")
+        return self._h
+
+    def stats(self):
+        out = (ctypes.c_int64 * 8)()
+        _check("crk_leaves_stats", load_library().crk_leaves_stats(self.handle, out))
+        keys = ("leaves", "tiles", "candidate_pairs", "list_entries", "pairs_gather",
+                "pairs_force", "padded_slots", "build_us")
+        return dict(zip(keys, list(out)))
+
+    def get_tuning(self):
+        t = Tuning()
+        _check("crk_get_tuning", load_library().crk_get_tuning(self.handle, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        t = Tuning(**{**self.get_tuning(), **kw})
+        _check("crk_set_tuning", load_library().crk_set_tuning(self.handle, ctypes.byref(t)))
+
+    def free(self):
+        if self._h is not None:
+            load_library().crk_leaves_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def crk_build_leaf_pairs(x, y, z, h=None, r_fixed=0.0, leaf_max=128, leaf_min=1,
+                         split_extent=0.0, prec="f32"):
+    """Tree + interaction lists (hydro mode when h is given, else radius r_fixed)."""
+    lib = load_library()
+    for t in (x, y, z):
+        _dev(t, torch.float64)
+    if h is not None:
+        _dev(h, _DTYPE[prec])
+    out = ctypes.c_void_p()
+    _check("crk_build_leaf_pairs",
+           lib.crk_build_leaf_pairs(int(x.numel()), _ptr(x), _ptr(y), _ptr(z), _ptr(h),
+                                    float(r_fixed), int(leaf_max), int(leaf_min),
+                                    float(split_extent), _PREC[prec], ctypes.byref(out), _stream()))
+    return Leaves(out, int(x.numel()), h is not None, prec)
+
+
+def crk_volume(leaves, gas, prec="f32"):
+    g = _gas(gas, prec, ("h", "m"))
+    V = torch.empty(g.n, dtype=_DTYPE[prec], device=gas["x"].device)
+    rho = torch.empty_like(V)
+    _check("crk_volume", load_library().crk_volume(leaves.handle, ctypes.byref(g), _PREC[prec],
+                                                   _ptr(V), _ptr(rho), _stream()))
+    return V, rho
+
+
+def crk_corrections(leaves, gas, V, prec="f32", n_fallback=None):
+    g = _gas(gas, prec, ("h",))
+    dt, dev = _DTYPE[prec], gas["x"].device
+    _dev(V, dt)
+    A = torch.empty(g.n, dtype=dt, device=dev)
+    B = torch.empty(g.n, 3, dtype=dt, device=dev)
+    dA = torch.empty(g.n, 3, dtype=dt, device=dev)
+    dB = torch.empty(g.n, 3, 3, dtype=dt, device=dev)
+    c = _Corr(A.data_ptr(), B.data_ptr(), dA.data_ptr(), dB.data_ptr())
+    if n_fallback is not None:
+        _dev(n_fallback, torch.int64)
+    _check("crk_corrections",
+           load_library().crk_corrections(leaves.handle, ctypes.byref(g), _ptr(V), _PREC[prec],
+                                          ctypes.byref(c), _ptr(n_fallback), _stream()))
+    return A, B, dA, dB
+
+
+def crk_accel_energy(leaves, gas, V, rho, corr, gamma=5.0 / 3.0, prec="f32", totals=True):
+    g = _gas(gas, prec, ("vx", "vy", "vz", "u", "h", "m"))
+    dt, dev = _DTYPE[prec], gas["x"].device
+    for t in (V, rho, *corr):
+        _dev(t, dt)
+    c = _Corr(*(t.data_ptr() for t in corr))
+    a = torch.empty(g.n, 3, dtype=dt, device=dev)
+    du = torch.empty(g.n, dtype=dt, device=dev)
+    tot = torch.empty(8, dtype=torch.float64, device=dev) if totals else None
+    _check("crk_accel_energy",
+           load_library().crk_accel_energy(leaves.handle, ctypes.byref(g), _ptr(V), _ptr(rho),
+                                           ctypes.byref(c), float(gamma), _PREC[prec], _ptr(a),
+                                           _ptr(du), _ptr(tot), _stream()))
+    return a, du, tot
+
+
+def sr_gravity(leaves, x, y, z, m, G=1.0, eps=0.0, r_cut=None, poly=None, prec="f32"):
+    dt = _DTYPE[prec]
+    for t in (x, y, z):
+        _dev(t, torch.float64)
+    _dev(m, dt)
+    n = int(x.numel())
+    a = torch.empty(n, 3, dtype=dt, device=x.device)
+    pc = None
+    if poly is not None:
+        pc = (ctypes.c_double * 6)(*[float(p) for p in poly])
+    _check("sr_gravity",
+           load_library().sr_gravity(leaves.handle, n, _ptr(x), _ptr(y), _ptr(z), _ptr(m),
+                                     float(G), float(eps), float(r_cut), pc, _PREC[prec], _ptr(a),
+                                     _stream()))
+    return a
+
+
+def forward(leaves, gas, gamma=5.0 / 3.0, prec="f32"):
+    """volume -> corrections -> accel/energy; returns a dict of device tensors."""
+    V, rho = crk_volume(leaves, gas, prec)
+    nf = torch.zeros(1, dtype=torch.int64, device=gas["x"].device)
+    corr = crk_corrections(leaves, gas, V, prec, n_fallback=nf)
+    a, du, tot = crk_accel_energy(leaves, gas, V, rho, corr, gamma, prec)
+    return dict(V=V, rho=rho, A=corr[0], B=corr[1], dA=corr[2], dB=corr[3], a=a, dudt=du,
+                totals=tot, n_fallback=nf)
+
+
+def gas_to_device(cfg, prec="f32", device="cuda"):
+    """Copy a synthetic configuration's arrays to the device in the call's precision."""
+    dt = _DTYPE[prec]
+    g = {}
+    for k in ("x", "y", "z"):
+        g[k] = torch.as_tensor(cfg[k], dtype=torch.float64).to(device)
+    for k in ("vx", "vy", "vz", "u", "h", "m"):
+        if k in cfg:
+            g[k] = torch.as_tensor(cfg[k]).to(dt).to(device)
+    return g

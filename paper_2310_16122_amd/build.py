@@ -1,0 +1,50 @@
+"""Compile the gfx950 HIP library ``libcrk.so`` in-tree.
+
+hipcc builds the kernels and the C ABI (``csrc/crk.hip``); g++ builds the
+host tree (``csrc/tree.cpp``, OpenMP).  Packed FP32 instructions are switched
+off for all device code.
+"""
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB = os.path.join(HERE, "libcrk.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+
+HIP_FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I", INCLUDE, "-I", CSRC,
+]
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+
+
+def build(verbose=False):
+    bdir = os.path.join(HERE, "_build")
+    os.makedirs(bdir, exist_ok=True)
+    obj_hip = os.path.join(bdir, "crk.o")
+    obj_tree = os.path.join(bdir, "tree.o")
+    _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "crk.hip"), "-o", obj_hip], verbose)
+    _run(["g++", "-std=c++17", "-O3", "-fopenmp", "-fPIC", "-I", CSRC, "-c",
+          os.path.join(CSRC, "tree.cpp"), "-o", obj_tree], verbose)
+    tmp = LIB + ".tmp%d" % os.getpid()
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, obj_hip, obj_tree,
+          "-lgomp"], verbose)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)
+    print(LIB)

@@ -1,0 +1,1199 @@
+// CRK-SPH pair passes and short-range gravity for MI355X (gfx950).
+//
+// Layout.  Particles are reordered along the RCB tree (tree.cpp).  Tree order
+// is cut into tiles of 64 consecutive particles; a tile is the unit of work of
+// one wavefront, one particle per lane.  Positions are 32-bit fixed point in
+// the unit periodic box, so a separation is an exact signed 32-bit difference
+// that wraps to the minimum image by itself.
+//
+// Interaction lists.  For the CRK passes every tile owns a wave-interleaved
+// neighbour list: entry k of lane l lives at off[tile] + 64 k + l, so the 64
+// lanes of a wave read their k-th neighbours with one coalesced load.  The
+// list is built once per tree by streaming the tile's candidate leaves through
+// LDS and testing every pair (count pass, host prefix sum, fill pass); all
+// three forward passes reuse it.  Short-range gravity has no list: each tile
+// streams its candidate leaves through LDS and evaluates every candidate pair
+// branch-free with a cutoff mask.
+//
+// Work distribution.  Tiles are issued in decreasing-cost order (longest
+// processing time first) either one per wave or through a persistent grid in
+// which every wave pulls the next tile from an atomic counter.
+//
+// Precision.  Each pass is a template on the real type R.  R = float: pair
+// arithmetic in FP32 with compensated (Kahan) FP32 sums; the 3x3 correction
+// solve and the momentum/energy totals in FP64.  R = double: the same kernels
+// in FP64 with plain sums.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "crk.h"
+#include "tree.h"
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kInvGrid = 2.3283064365386962890625e-10;  // 2^-32
+constexpr float kCullMargin = 1.0f + 1.0e-5f;                // list radius^2 factor
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) return fail(CRK_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define LAUNCH_CHECK(name)                                                             \
+    do {                                                                               \
+        hipError_t e_ = hipGetLastError();                                             \
+        if (e_ != hipSuccess) return fail(CRK_EHIP, "launch %s: %s", name, hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------------ device helpers
+
+template <class R> __device__ __forceinline__ R sep(uint32_t a, uint32_t b) {
+    return R(int32_t(a - b)) * R(kInvGrid);
+}
+
+template <class R> __device__ __forceinline__ R dsqrt(R x);
+template <> __device__ __forceinline__ float dsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <> __device__ __forceinline__ double dsqrt<double>(double x) { return sqrt(x); }
+
+template <class R> __device__ __forceinline__ R drsqrt(R x);
+template <> __device__ __forceinline__ float drsqrt<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <> __device__ __forceinline__ double drsqrt<double>(double x) { return 1.0 / sqrt(x); }
+
+// Wendland C4 shape with support H: W = cW w(q), grad_i W = cF f(q) x_ij,
+// cW = 495/(32 pi H^3), cF = -1155/(4 pi H^5), q = r/H; zero for q >= 1.
+template <class R> __device__ __forceinline__ void wendland(R q, R& w, R& f) {
+    const R t = fmax(R(1) - q, R(0));
+    const R t2 = t * t;
+    const R t4 = t2 * t2;
+    const R t5 = t4 * t;
+    const R t6 = t5 * t;
+    w = t6 * (R(1) + q * (R(6) + q * R(35.0 / 3.0)));
+    f = t5 * (R(1) + R(5) * q);
+}
+
+template <class R> __host__ __device__ __forceinline__ R norm_W(R H) {
+    return R(495.0 / (32.0 * kPi)) / (H * H * H);
+}
+template <class R> __host__ __device__ __forceinline__ R norm_F(R H) {
+    return R(-1155.0 / (4.0 * kPi)) / (H * H * H * H * H);
+}
+
+// compensated accumulation: the sum is s - c
+template <class R> __device__ __forceinline__ void kadd(R& s, R& c, R t) {
+    const R y = t - c;
+    const R u = s + y;
+    c = (u - s) - y;
+    s = u;
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+// Work queue: tiles in decreasing-cost order, one per wave or pulled from an
+// atomic counter by a persistent grid.
+struct Queue {
+    const int32_t* order;
+    int32_t* counter;
+    int32_t n_items;
+    int32_t persistent;
+};
+
+__device__ __forceinline__ int first_item(const Queue& q, int wave_global) {
+    if (!q.persistent) return wave_global;
+    int it = 0;
+    if (lane_id() == 0) it = atomicAdd(q.counter, 1);
+    return __builtin_amdgcn_readfirstlane(it);
+}
+__device__ __forceinline__ int next_item(const Queue& q, int cur, int n_waves_grid) {
+    if (!q.persistent) return q.n_items;  // one tile per wave
+    int it = 0;
+    if (lane_id() == 0) it = atomicAdd(q.counter, 1);
+    return __builtin_amdgcn_readfirstlane(it);
+}
+
+__global__ void k_reset(int32_t* c) {
+    if (threadIdx.x < 4) c[threadIdx.x] = 0;
+}
+
+// ------------------------------------------------------------------ packing (tree order)
+
+__device__ __forceinline__ uint32_t quantize(double x) {
+    double t = x - floor(x);
+    double v = floor(t * 4294967296.0 + 0.5);
+    return v >= 4294967296.0 ? 0u : uint32_t(v);
+}
+
+// positions to fixed point (+ support radius bits for the list build)
+template <class R>
+__global__ void k_pack_quant(int n, const int32_t* perm, const double* x, const double* y,
+                             const double* z, const R* h, uint4* quant) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int i = perm[s];
+    uint4 q;
+    q.x = quantize(x[i]);
+    q.y = quantize(y[i]);
+    q.z = quantize(z[i]);
+    q.w = h ? __float_as_uint(float(2.0 * double(h[i]))) : 0u;
+    quant[s] = q;
+}
+
+template <class R> __global__ void k_gather(int n, const int32_t* perm, const R* src, R* dst) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) dst[s] = src[perm[s]];
+}
+
+// Per-particle record for the force pass: everything a neighbour contributes,
+// with the kernel normalisation folded into the correction terms:
+//   P1 = cW dA, P2[a][c] = cW A dB[a][c], P3 = cW A B, P4 = cF A.
+template <class R> struct alignas(16) RecAcc {
+    uint32_t q[4];
+    R invH, V, P, P4;
+    R B[3], P1[3], P3[3], v[3];
+    R P2[9];
+    R pad[sizeof(R) == 4 ? 3 : 5];
+};
+static_assert(sizeof(RecAcc<float>) == 128, "f32 record is one 128-byte line");
+static_assert(sizeof(RecAcc<double>) == 256, "f64 record is two 128-byte lines");
+
+template <class R>
+__global__ void k_pack_acc(int n, const int32_t* perm, const uint4* quant, const R* h, const R* u,
+                           const R* vx, const R* vy, const R* vz, const R* V, const R* rho,
+                           const R* A, const R* B, const R* dA, const R* dB, R gm1,
+                           RecAcc<R>* rec) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int i = perm[s];
+    RecAcc<R> r;
+    const uint4 q = quant[s];
+    r.q[0] = q.x; r.q[1] = q.y; r.q[2] = q.z; r.q[3] = 0;
+    const R H = R(2) * h[i];
+    const R cW = norm_W(H), cF = norm_F(H);
+    const R Ai = A[i];
+    r.invH = R(1) / H;
+    r.V = V[i];
+    r.P = gm1 * rho[i] * u[i];
+    r.P4 = cF * Ai;
+    for (int a = 0; a < 3; ++a) {
+        r.B[a] = B[3 * i + a];
+        r.P1[a] = cW * dA[3 * i + a];
+        r.P3[a] = cW * Ai * B[3 * i + a];
+        for (int c = 0; c < 3; ++c) r.P2[3 * a + c] = cW * Ai * dB[9 * i + 3 * a + c];
+    }
+    r.v[0] = vx[i]; r.v[1] = vy[i]; r.v[2] = vz[i];
+    for (int k = 0; k < int(sizeof(r.pad) / sizeof(R)); ++k) r.pad[k] = R(0);
+    rec[s] = r;
+}
+
+// ------------------------------------------------------------------ list build
+
+// One wave per tile: candidate particles are staged 64 at a time in LDS and
+// every (lane, candidate) pair is tested against max(H_i, H_j)^2 (with a tiny
+// margin so that no pair inside either support is missed in FP32).
+template <bool FILL>
+__global__ __launch_bounds__(64) void k_cull(Queue qu, int n, const uint4* __restrict__ quant,
+                                             const int32_t* __restrict__ rng_off,
+                                             const int2* __restrict__ rng, int32_t* cnt_out,
+                                             const int64_t* __restrict__ ell_off,
+                                             uint32_t* __restrict__ nbr) {
+    __shared__ uint4 sj[kWave];
+    const int lane = lane_id();
+    for (int it = first_item(qu, blockIdx.x); it < qu.n_items; it = next_item(qu, it, gridDim.x)) {
+        const int w = qu.order[it];
+        const int s = w * kWave + lane;
+        const bool valid = s < n;
+        const uint4 qi = valid ? quant[s] : make_uint4(0, 0, 0, 0);
+        const float Hi = __uint_as_float(qi.w);
+        const float Hi2 = Hi * Hi;
+        int c = 0;
+        const int64_t base_off = FILL ? ell_off[w] : 0;
+        const int cap = (FILL && valid) ? cnt_out[s] : 0;
+        for (int r = rng_off[w]; r < rng_off[w + 1]; ++r) {
+            const int2 R = rng[r];
+            for (int b = R.x; b < R.y; b += kWave) {
+                const int m = min(kWave, R.y - b);
+                __syncthreads();
+                if (lane < m) sj[lane] = quant[b + lane];
+                __syncthreads();
+                for (int jj = 0; jj < m; ++jj) {
+                    const uint4 qj = sj[jj];
+                    const float dx = sep<float>(qi.x, qj.x);
+                    const float dy = sep<float>(qi.y, qj.y);
+                    const float dz = sep<float>(qi.z, qj.z);
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    const float Hj = __uint_as_float(qj.w);
+                    const float R2 = fmaxf(Hi2, Hj * Hj) * kCullMargin;
+                    if (valid && r2 < R2 && (b + jj) != s) {
+                        // the fill pass repeats the count pass exactly; the bound
+                        // check keeps every store inside the tile's list
+                        if (FILL && c < cap) nbr[base_off + int64_t(c) * kWave + lane] = uint32_t(b + jj);
+                        ++c;
+                    }
+                }
+            }
+        }
+        if (!FILL && valid) cnt_out[s] = c;
+    }
+}
+
+// Exact FP64 interaction counts over the lists: r < H_i and r < max(H_i, H_j).
+__global__ __launch_bounds__(256) void k_count_lists(int n, const uint4* __restrict__ quant,
+                                                     const double* __restrict__ Hd,
+                                                     const int32_t* __restrict__ cnt,
+                                                     const int64_t* __restrict__ ell_off,
+                                                     const uint32_t* __restrict__ nbr,
+                                                     unsigned long long* out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long c0 = 0, c1 = 0;
+    if (s < n) {
+        const int w = s / kWave, lane = s % kWave;
+        const uint4 qi = quant[s];
+        const double Hi = Hd[s];
+        for (int k = 0; k < cnt[s]; ++k) {
+            const uint32_t j = nbr[ell_off[w] + int64_t(k) * kWave + lane];
+            const uint4 qj = quant[j];
+            const double dx = sep<double>(qi.x, qj.x), dy = sep<double>(qi.y, qj.y),
+                         dz = sep<double>(qi.z, qj.z);
+            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            c0 += r < Hi;
+            c1 += r < fmax(Hi, Hd[j]);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        c0 += __shfl_xor(c0, o);
+        c1 += __shfl_xor(c1, o);
+    }
+    if (lane_id() == 0) {
+        atomicAdd(out, c0);
+        atomicAdd(out + 1, c1);
+    }
+}
+
+// FP64 pair counts r < r_fixed over the tiles' candidate ranges.
+__global__ __launch_bounds__(64) void k_count_fixed(int n_tiles, int n, const uint4* __restrict__ quant,
+                                                    const int32_t* __restrict__ rng_off,
+                                                    const int2* __restrict__ rng, double rc,
+                                                    unsigned long long* out) {
+    const int w = blockIdx.x;
+    if (w >= n_tiles) return;
+    const int s = w * kWave + lane_id();
+    unsigned long long c = 0;
+    if (s < n) {
+        const uint4 qi = quant[s];
+        for (int r = rng_off[w]; r < rng_off[w + 1]; ++r) {
+            const int2 R = rng[r];
+            for (int j = R.x; j < R.y; ++j) {
+                if (j == s) continue;
+                const uint4 qj = quant[j];
+                const double dx = sep<double>(qi.x, qj.x), dy = sep<double>(qi.y, qj.y),
+                             dz = sep<double>(qi.z, qj.z);
+                c += sqrt(dx * dx + dy * dy + dz * dz) < rc;
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if (lane_id() == 0) atomicAdd(out, c);
+}
+
+// ------------------------------------------------------------------ list access
+
+struct Lists {
+    const int32_t* cnt;
+    const int64_t* off;
+    const int32_t* len;
+    const uint32_t* nbr;
+};
+
+// ------------------------------------------------------------------ volume
+
+template <class R>
+__global__ __launch_bounds__(256) void k_volume(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
+                                                const uint4* __restrict__ quant, const R* __restrict__ h,
+                                                const R* __restrict__ m, R* __restrict__ V_out,
+                                                R* __restrict__ rho_out) {
+    const int lane = lane_id();
+    const int wave = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    for (int it = first_item(qu, wave); it < qu.n_items; it = next_item(qu, it, 0)) {
+        const int w = qu.order[it];
+        const int s = w * kWave + lane;
+        const bool valid = s < n;
+        const int i = valid ? perm[s] : 0;
+        const uint4 qi = valid ? quant[s] : make_uint4(0, 0, 0, 0);
+        const R H = valid ? R(2) * h[i] : R(1);
+        const R invH = R(1) / H;
+        const int cnt = valid ? L.cnt[s] : 0;
+        const int len = L.len[w];
+        const uint32_t* lst = L.nbr + L.off[w] + lane;
+        R S = R(1), c = R(0);  // self term: w(0) = 1
+        for (int k = 0; k < len; ++k) {
+            if (k < cnt) {
+                const uint4 qj = quant[lst[int64_t(k) * kWave]];
+                const R dx = sep<R>(qi.x, qj.x), dy = sep<R>(qi.y, qj.y), dz = sep<R>(qi.z, qj.z);
+                const R r = dsqrt(dx * dx + dy * dy + dz * dz);
+                R wq, fq;
+                wendland(r * invH, wq, fq);
+                if (sizeof(R) == 4) kadd(S, c, wq);
+                else S += wq;
+            }
+        }
+        if (valid) {
+            const R Ssum = (S - c) * norm_W(H);
+            V_out[i] = R(1) / Ssum;
+            rho_out[i] = m[i] * Ssum;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ corrections
+
+// FP64 per-particle solve of the reproducing conditions from the 40 moments
+// (m0, m1[3], m2[6] (xx xy xz yy yz zz), g0[3], g1[9] (a-major), g2[18]
+// ((ab) in m2 order, c fastest)).  Returns 1 for the zeroth-order fallback.
+__device__ int solve_moments(const double* M, int nnb, double& A, double B[3], double dA[3],
+                             double dB[9]) {
+    const double m0 = M[0];
+    const double* m1 = M + 1;
+    const double* s = M + 4;
+    const double* g0 = M + 10;
+    const double* g1 = M + 13;
+    const double* g2 = M + 22;
+    // symmetric m2 and its adjugate
+    const double a11 = s[0], a12 = s[1], a13 = s[2], a22 = s[3], a23 = s[4], a33 = s[5];
+    const double i11 = a22 * a33 - a23 * a23;
+    const double i12 = a13 * a23 - a12 * a33;
+    const double i13 = a12 * a23 - a13 * a22;
+    const double i22 = a11 * a33 - a13 * a13;
+    const double i23 = a12 * a13 - a11 * a23;
+    const double i33 = a11 * a22 - a12 * a12;
+    const double det = a11 * i11 + a12 * i12 + a13 * i13;
+    const double tr = (a11 + a22 + a33) / 3.0;
+    if (nnb < 4 || !(det > 1e-12 * tr * tr * tr)) {
+        A = 1.0 / m0;
+        for (int c = 0; c < 3; ++c) {
+            B[c] = 0.0;
+            dA[c] = -g0[c] / (m0 * m0);
+        }
+        for (int k = 0; k < 9; ++k) dB[k] = 0.0;
+        return 1;
+    }
+    const double rd = 1.0 / det;
+    const double inv[3][3] = {{i11 * rd, i12 * rd, i13 * rd},
+                              {i12 * rd, i22 * rd, i23 * rd},
+                              {i13 * rd, i23 * rd, i33 * rd}};
+    for (int a = 0; a < 3; ++a)
+        B[a] = -(inv[a][0] * m1[0] + inv[a][1] * m1[1] + inv[a][2] * m1[2]);
+    A = 1.0 / (m0 + B[0] * m1[0] + B[1] * m1[1] + B[2] * m1[2]);
+    const int sym[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+    for (int c = 0; c < 3; ++c) {
+        double rhs[3];
+        for (int a = 0; a < 3; ++a) {
+            double t = g1[3 * a + c];
+            for (int b = 0; b < 3; ++b) t += g2[3 * sym[a][b] + c] * B[b];
+            rhs[a] = t;
+        }
+        double gA = g0[c];
+        for (int a = 0; a < 3; ++a) {
+            const double d = -(inv[a][0] * rhs[0] + inv[a][1] * rhs[1] + inv[a][2] * rhs[2]);
+            dB[3 * a + c] = d;
+            gA += B[a] * g1[3 * a + c] + m1[a] * d;
+        }
+        dA[c] = -A * A * gA;
+    }
+    return 0;
+}
+
+// Moments over the neighbour list (j = i added analytically), then the FP64
+// solve.  Accumulated per pair (w = cW w(q) V_j, f = cF f(q) V_j, x = x_ij):
+//   m0 += w, m1^a += x^a w, m2^ab += x^a x^b w, g0^c += f x^c,
+//   t1^ac += x^a f x^c, t2^abc += x^a x^b f x^c
+// and at the end g1^ac = delta^ac m0 + t1^ac, g2^abc = delta^ac m1^b + delta^bc m1^a + t2^abc.
+// FP32: plain sums over `chunk` pairs, folded into compensated sums.
+template <class R>
+__global__ __launch_bounds__(256) void k_moments(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
+                                                 const uint4* __restrict__ quant, const R* __restrict__ Vs,
+                                                 const R* __restrict__ h, int chunk, R* __restrict__ A_out,
+                                                 R* __restrict__ B_out, R* __restrict__ dA_out,
+                                                 R* __restrict__ dB_out,
+                                                 unsigned long long* __restrict__ n_fallback) {
+    constexpr bool kComp = sizeof(R) == 4;
+    const int lane = lane_id();
+    const int wave = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    for (int it = first_item(qu, wave); it < qu.n_items; it = next_item(qu, it, 0)) {
+        const int w = qu.order[it];
+        const int s = w * kWave + lane;
+        const bool valid = s < n;
+        const int i = valid ? perm[s] : 0;
+        const uint4 qi = valid ? quant[s] : make_uint4(0, 0, 0, 0);
+        const R H = valid ? R(2) * h[i] : R(1);
+        const R invH = R(1) / H;
+        const R cW = norm_W(H), cF = norm_F(H);
+        const int cnt = valid ? L.cnt[s] : 0;
+        const int len = L.len[w];
+        const uint32_t* lst = L.nbr + L.off[w] + lane;
+        R p[40], sm[40], cm[40];
+#pragma unroll
+        for (int e = 0; e < 40; ++e) { p[e] = R(0); sm[e] = R(0); cm[e] = R(0); }
+        int nnb = 0, kk = 0;
+        for (int k = 0; k < len; ++k) {
+            if (k < cnt) {
+                const uint32_t j = lst[int64_t(k) * kWave];
+                const uint4 qj = quant[j];
+                const R Vj = Vs[j];
+                const R x[3] = {sep<R>(qi.x, qj.x), sep<R>(qi.y, qj.y), sep<R>(qi.z, qj.z)};
+                const R r = dsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+                const R q = r * invH;
+                R wq, fq;
+                wendland(q, wq, fq);
+                nnb += q < R(1);
+                const R wv = cW * wq * Vj;
+                const R fv = cF * fq * Vj;
+                const R fx[3] = {fv * x[0], fv * x[1], fv * x[2]};
+                R xx[6];
+                xx[0] = x[0] * x[0]; xx[1] = x[0] * x[1]; xx[2] = x[0] * x[2];
+                xx[3] = x[1] * x[1]; xx[4] = x[1] * x[2]; xx[5] = x[2] * x[2];
+                p[0] += wv;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) p[1 + a] += x[a] * wv;
+#pragma unroll
+                for (int e = 0; e < 6; ++e) p[4 + e] += xx[e] * wv;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) p[10 + c] += fx[c];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) p[13 + 3 * a + c] += x[a] * fx[c];
+#pragma unroll
+                for (int e = 0; e < 6; ++e)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) p[22 + 3 * e + c] += xx[e] * fx[c];
+            }
+            if (kComp && ++kk == chunk) {
+#pragma unroll
+                for (int e = 0; e < 40; ++e) { kadd(sm[e], cm[e], p[e]); p[e] = R(0); }
+                kk = 0;
+            }
+        }
+        if (valid) {
+        double M[40];
+        const R Vi = Vs[s];
+#pragma unroll
+        for (int e = 0; e < 40; ++e) {
+            if (kComp) {
+                kadd(sm[e], cm[e], p[e]);
+                M[e] = double(sm[e]) - double(cm[e]);
+            } else {
+                M[e] = double(p[e]);
+            }
+        }
+        M[0] += double(cW) * double(Vi);  // j = i
+        const int sym[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+        for (int a = 0; a < 3; ++a) M[13 + 3 * a + a] += M[0];
+        for (int a = 0; a < 3; ++a)
+            for (int b = a; b < 3; ++b)
+                for (int c = 0; c < 3; ++c) {
+                    double t = 0.0;
+                    if (a == c) t += M[1 + b];
+                    if (b == c) t += M[1 + a];
+                    M[22 + 3 * sym[a][b] + c] += t;
+                }
+        double Ad, Bd[3], dAd[3], dBd[9];
+        const int fb = solve_moments(M, nnb, Ad, Bd, dAd, dBd);
+        A_out[i] = R(Ad);
+        for (int a = 0; a < 3; ++a) {
+            B_out[3 * i + a] = R(Bd[a]);
+            dA_out[3 * i + a] = R(dAd[a]);
+        }
+        for (int k = 0; k < 9; ++k) dB_out[9 * i + k] = R(dBd[k]);
+        if (n_fallback && fb) atomicAdd(n_fallback, 1ull);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ forces
+
+// gradient of a particle's corrected kernel at separation x (from that particle)
+template <class R>
+__device__ __forceinline__ void corrected_grad(const RecAcc<R>& r, R wq, R fq, const R x[3], R G[3]) {
+    const R lin = R(1) + r.B[0] * x[0] + r.B[1] * x[1] + r.B[2] * x[2];
+    const R fl = fq * r.P4 * lin;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const R t = r.P3[c] + r.P2[c] * x[0] + r.P2[3 + c] * x[1] + r.P2[6 + c] * x[2] + r.P1[c] * lin;
+        G[c] = wq * t + fl * x[c];
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
+                                               const RecAcc<R>* __restrict__ rec, const R* __restrict__ m,
+                                               R* __restrict__ a_out, R* __restrict__ du_out,
+                                               double* __restrict__ partials) {
+    constexpr bool kComp = sizeof(R) == 4;
+    const int lane = lane_id();
+    const int wave = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    for (int it = first_item(qu, wave); it < qu.n_items; it = next_item(qu, it, 0)) {
+        const int w = qu.order[it];
+        const int s = w * kWave + lane;
+        const bool valid = s < n;
+        const RecAcc<R> ri = rec[valid ? s : 0];
+        const int cnt = valid ? L.cnt[s] : 0;
+        const int len = L.len[w];
+        const uint32_t* lst = L.nbr + L.off[w] + lane;
+        R acc[4] = {R(0), R(0), R(0), R(0)}, cmp[4] = {R(0), R(0), R(0), R(0)};
+        for (int k = 0; k < len; ++k) {
+            if (k < cnt) {
+                const RecAcc<R> rj = rec[lst[int64_t(k) * kWave]];
+                const R x[3] = {sep<R>(ri.q[0], rj.q[0]), sep<R>(ri.q[1], rj.q[1]),
+                                sep<R>(ri.q[2], rj.q[2])};
+                const R xo[3] = {-x[0], -x[1], -x[2]};
+                const R r = dsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+                R wi, fi, wj, fj;
+                wendland(r * ri.invH, wi, fi);
+                wendland(r * rj.invH, wj, fj);
+                R Gi[3], Gj[3];
+                corrected_grad(ri, wi, fi, x, Gi);
+                corrected_grad(rj, wj, fj, xo, Gj);
+                const R coef = R(-0.5) * ((ri.V * rj.V) * (ri.P + rj.P));
+                R Fv = R(0);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const R F = coef * (Gi[c] - Gj[c]);
+                    Fv += F * (ri.v[c] - rj.v[c]);
+                    if (kComp) kadd(acc[c], cmp[c], F);
+                    else acc[c] += F;
+                }
+                if (kComp) kadd(acc[3], cmp[3], Fv);
+                else acc[3] += Fv;
+            }
+        }
+        double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (valid) {
+            const int i = perm[s];
+            const R mi = m[i];
+            R av[3];
+            for (int c = 0; c < 3; ++c) {
+                av[c] = (acc[c] - cmp[c]) / mi;
+                a_out[3 * i + c] = av[c];
+            }
+            const R du = R(-0.5) * (acc[3] - cmp[3]) / mi;
+            du_out[i] = du;
+            const double md = double(mi);
+            const double ax = av[0], ay = av[1], az = av[2], dd = du;
+            const double va = double(ri.v[0]) * ax + double(ri.v[1]) * ay + double(ri.v[2]) * az;
+            t[0] = md * ax; t[1] = md * ay; t[2] = md * az;
+            t[3] = md * (va + dd);
+            t[4] = md * sqrt(ax * ax + ay * ay + az * az);
+            t[5] = md * (fabs(va) + fabs(dd));
+            t[6] = md * dd;
+            t[7] = md * va;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            for (int o = 32; o > 0; o >>= 1) t[k] += __shfl_xor(t[k], o);
+        if (lane == 0)
+            for (int k = 0; k < 8; ++k) partials[8 * w + k] = t[k];
+    }
+}
+
+// fixed-order FP64 reduction of the per-tile totals
+__global__ __launch_bounds__(256) void k_totals(int n_tiles, const double* __restrict__ partials,
+                                                double* __restrict__ totals) {
+    __shared__ double red[256][8];
+    double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int w = threadIdx.x; w < n_tiles; w += 256)
+        for (int k = 0; k < 8; ++k) t[k] += partials[8 * w + k];
+    for (int k = 0; k < 8; ++k) red[threadIdx.x][k] = t[k];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st)
+            for (int k = 0; k < 8; ++k) red[threadIdx.x][k] += red[threadIdx.x + st][k];
+        __syncthreads();
+    }
+    if (threadIdx.x < 8) totals[threadIdx.x] = red[0][threadIdx.x];
+}
+
+// ------------------------------------------------------------------ gravity
+
+struct GravParams {
+    double G, eps2, rc2;
+    double poly[6];
+    int use_poly;
+};
+
+// One wave per tile; candidate particles staged 64 at a time in LDS; every
+// candidate pair evaluated branch-free, masked by 0 < r^2 < r_c^2.
+template <class R>
+__global__ __launch_bounds__(64) void k_gravity(Queue qu, int n, const int32_t* __restrict__ perm,
+                                                const uint4* __restrict__ quant, const R* __restrict__ ms,
+                                                const int32_t* __restrict__ rng_off,
+                                                const int2* __restrict__ rng, GravParams gp,
+                                                R* __restrict__ a_out) {
+    constexpr bool kComp = sizeof(R) == 4;
+    __shared__ uint4 sq[kWave];
+    __shared__ R smass[kWave];
+    const int lane = lane_id();
+    const R rc2 = R(gp.rc2), eps2 = R(gp.eps2);
+    R pc[6];
+    for (int k = 0; k < 6; ++k) pc[k] = R(gp.poly[k]);
+    for (int it = first_item(qu, blockIdx.x); it < qu.n_items; it = next_item(qu, it, gridDim.x)) {
+        const int w = qu.order[it];
+        const int s = w * kWave + lane;
+        const bool valid = s < n;
+        const uint4 qi = valid ? quant[s] : make_uint4(0, 0, 0, 0);
+        R acc[3] = {R(0), R(0), R(0)}, cmp[3] = {R(0), R(0), R(0)}, part[3] = {R(0), R(0), R(0)};
+        for (int r = rng_off[w]; r < rng_off[w + 1]; ++r) {
+            const int2 Rg = rng[r];
+            for (int b = Rg.x; b < Rg.y; b += kWave) {
+                const int mcnt = min(kWave, Rg.y - b);
+                __syncthreads();
+                if (lane < mcnt) {
+                    sq[lane] = quant[b + lane];
+                    smass[lane] = ms[b + lane];
+                }
+                __syncthreads();
+                for (int jj = 0; jj < mcnt; ++jj) {
+                    const uint4 qj = sq[jj];
+                    const R dx = sep<R>(qi.x, qj.x), dy = sep<R>(qi.y, qj.y), dz = sep<R>(qi.z, qj.z);
+                    const R r2 = dx * dx + dy * dy + dz * dz;
+                    const R ir = drsqrt(r2 + eps2);
+                    R f = ir * ir * ir;
+                    if (gp.use_poly) {
+                        R pv = pc[5];
+                        for (int k = 4; k >= 0; --k) pv = pv * r2 + pc[k];
+                        f -= pv;
+                    }
+                    f = (r2 < rc2 && r2 > R(0)) ? smass[jj] * f : R(0);
+                    part[0] += f * dx;
+                    part[1] += f * dy;
+                    part[2] += f * dz;
+                    if (kComp && (jj & 7) == 7) {
+                        for (int c = 0; c < 3; ++c) { kadd(acc[c], cmp[c], part[c]); part[c] = R(0); }
+                    }
+                }
+                if (kComp) {
+                    for (int c = 0; c < 3; ++c) { kadd(acc[c], cmp[c], part[c]); part[c] = R(0); }
+                }
+            }
+        }
+        if (valid) {
+            const int i = perm[s];
+            for (int c = 0; c < 3; ++c) {
+                const R tot = kComp ? (acc[c] - cmp[c]) : part[c];
+                a_out[3 * i + c] = R(-gp.G) * tot;
+            }
+        }
+    }
+}
+
+}  // namespace
+
+// ====================================================================== handle
+
+struct crk_leaves {
+    int64_t n = 0;
+    int hydro = 0;
+    crk_prec prec = CRK_F32;
+    double r_fixed = 0.0;
+    int64_t n_tiles = 0, n_leaves = 0;
+    int n_cu = 1;
+    crk_tuning tune{1, 32, 4, 4};
+    int32_t* perm = nullptr;
+    uint4* quant = nullptr;
+    double* Hd = nullptr;
+    int32_t* rng_off = nullptr;
+    int2* rng = nullptr;
+    int32_t* order_cull = nullptr;
+    int32_t* order_pair = nullptr;
+    int32_t* counter = nullptr;
+    int32_t* cnt = nullptr;
+    int64_t* ell_off = nullptr;
+    int32_t* ell_len = nullptr;
+    uint32_t* nbr = nullptr;
+    double* partials = nullptr;
+    unsigned long long* counts = nullptr;
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    int64_t stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    bool counted = false;
+};
+
+namespace {
+
+template <class T> int dalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+    if (e != hipSuccess) return fail(CRK_ENOMEM, "hipMalloc(%zu bytes): %s", count * sizeof(T), hipGetErrorString(e));
+    return CRK_OK;
+}
+
+void release(crk_leaves* L) {
+    void* ptrs[] = {L->perm, L->quant, L->Hd, L->rng_off, L->rng, L->order_cull, L->order_pair,
+                    L->counter, L->cnt, L->ell_off, L->ell_len, L->nbr, L->partials, L->counts,
+                    L->scratch};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+int ensure_scratch(crk_leaves* L, size_t bytes) {
+    if (bytes <= L->scratch_bytes) return CRK_OK;
+    if (L->scratch) {
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipFree(L->scratch));
+        L->scratch = nullptr;
+        L->scratch_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&L->scratch, bytes);
+    if (e != hipSuccess) return fail(CRK_ENOMEM, "scratch hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    L->scratch_bytes = bytes;
+    return CRK_OK;
+}
+
+Queue make_queue(const crk_leaves* L, const int32_t* order) {
+    return Queue{order, L->counter, int32_t(L->n_tiles), L->tune.persistent};
+}
+
+// grid for one-wave workgroups (LDS-staged kernels)
+int grid_1wave(const crk_leaves* L) {
+    if (!L->tune.persistent) return int(L->n_tiles);
+    return int(std::min<int64_t>(L->n_tiles, int64_t(L->n_cu) * L->tune.waves_per_cu));
+}
+// grid for block_waves-wave workgroups (list-driven passes)
+int grid_nwave(const crk_leaves* L) {
+    const int bw = L->tune.block_waves;
+    const int64_t waves = L->tune.persistent
+                              ? std::min<int64_t>(L->n_tiles, int64_t(L->n_cu) * L->tune.waves_per_cu)
+                              : L->n_tiles;
+    return int((waves + bw - 1) / bw);
+}
+
+int check_gas(const crk_leaves* L, const crk_gas* g, bool need_v) {
+    if (!L || !g) return fail(CRK_EINVAL, "null handle or gas");
+    if (L->n == 0 && g->n == 0) return CRK_OK;  // nothing to do in either mode
+    if (!L->hydro) return fail(CRK_ESTATE, "handle was built in fixed-radius mode; CRK passes need h");
+    if (g->n != L->n) return fail(CRK_EINVAL, "gas.n = %lld does not match the handle (%lld)",
+                                  (long long)g->n, (long long)L->n);
+    if (L->n == 0) return CRK_OK;
+    if (!g->x || !g->y || !g->z || !g->h) return fail(CRK_EINVAL, "gas positions and h are required");
+    if (need_v && (!g->vx || !g->vy || !g->vz || !g->u || !g->m))
+        return fail(CRK_EINVAL, "gas velocities, u and m are required");
+    return CRK_OK;
+}
+
+template <class R>
+int pack_positions(crk_leaves* L, const double* x, const double* y, const double* z, const R* h,
+                   hipStream_t st) {
+    const int n = int(L->n);
+    hipLaunchKernelGGL(k_pack_quant<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, x, y,
+                       z, h, L->quant);
+    LAUNCH_CHECK("pack_quant");
+    return CRK_OK;
+}
+
+void reset_queue(crk_leaves* L, hipStream_t st) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, L->counter);
+}
+
+Lists lists(const crk_leaves* L) { return Lists{L->cnt, L->ell_off, L->ell_len, L->nbr}; }
+
+template <class R> int volume_impl(crk_leaves* L, const crk_gas* g, R* V, R* rho, hipStream_t st) {
+    int rc = pack_positions<R>(L, g->x, g->y, g->z, static_cast<const R*>(g->h), st);
+    if (rc) return rc;
+    reset_queue(L, st);
+    hipLaunchKernelGGL(k_volume<R>, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves), 0, st,
+                       make_queue(L, L->order_pair), int(L->n), lists(L), L->perm, L->quant,
+                       static_cast<const R*>(g->h), static_cast<const R*>(g->m), V, rho);
+    LAUNCH_CHECK("volume");
+    return CRK_OK;
+}
+
+template <class R>
+int corrections_impl(crk_leaves* L, const crk_gas* g, const R* V, const crk_corr* out,
+                     int64_t* n_fallback, hipStream_t st) {
+    const int n = int(L->n);
+    int rc = pack_positions<R>(L, g->x, g->y, g->z, static_cast<const R*>(g->h), st);
+    if (rc) return rc;
+    if ((rc = ensure_scratch(L, sizeof(R) * size_t(n)))) return rc;
+    R* Vs = static_cast<R*>(L->scratch);
+    hipLaunchKernelGGL(k_gather<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, V, Vs);
+    LAUNCH_CHECK("gather V");
+    reset_queue(L, st);
+    hipLaunchKernelGGL(k_moments<R>, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves), 0, st,
+                       make_queue(L, L->order_pair), n, lists(L), L->perm, L->quant, Vs,
+                       static_cast<const R*>(g->h), L->tune.kahan_chunk, static_cast<R*>(out->A),
+                       static_cast<R*>(out->B), static_cast<R*>(out->dA), static_cast<R*>(out->dB),
+                       reinterpret_cast<unsigned long long*>(n_fallback));
+    LAUNCH_CHECK("moments");
+    return CRK_OK;
+}
+
+template <class R>
+int accel_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const crk_corr* C,
+               double gamma, R* a, R* dudt, double* totals, hipStream_t st) {
+    const int n = int(L->n);
+    int rc = pack_positions<R>(L, g->x, g->y, g->z, static_cast<const R*>(g->h), st);
+    if (rc) return rc;
+    if ((rc = ensure_scratch(L, sizeof(RecAcc<R>) * size_t(n)))) return rc;
+    RecAcc<R>* rec = static_cast<RecAcc<R>*>(L->scratch);
+    hipLaunchKernelGGL(k_pack_acc<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, L->quant,
+                       static_cast<const R*>(g->h), static_cast<const R*>(g->u),
+                       static_cast<const R*>(g->vx), static_cast<const R*>(g->vy),
+                       static_cast<const R*>(g->vz), V, rho, static_cast<const R*>(C->A),
+                       static_cast<const R*>(C->B), static_cast<const R*>(C->dA),
+                       static_cast<const R*>(C->dB), R(gamma - 1.0), rec);
+    LAUNCH_CHECK("pack_acc");
+    reset_queue(L, st);
+    hipLaunchKernelGGL(k_accel<R>, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves), 0, st,
+                       make_queue(L, L->order_pair), n, lists(L), L->perm, rec,
+                       static_cast<const R*>(g->m), a, dudt, L->partials);
+    LAUNCH_CHECK("accel");
+    if (totals) {
+        hipLaunchKernelGGL(k_totals, dim3(1), dim3(256), 0, st, int(L->n_tiles), L->partials, totals);
+        LAUNCH_CHECK("totals");
+    }
+    return CRK_OK;
+}
+
+template <class R>
+int gravity_impl(crk_leaves* L, const double* x, const double* y, const double* z, const R* m,
+                 const GravParams& gp, R* a, hipStream_t st) {
+    const int n = int(L->n);
+    int rc = pack_positions<R>(L, x, y, z, nullptr, st);
+    if (rc) return rc;
+    if ((rc = ensure_scratch(L, sizeof(R) * size_t(n)))) return rc;
+    R* ms = static_cast<R*>(L->scratch);
+    hipLaunchKernelGGL(k_gather<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, m, ms);
+    LAUNCH_CHECK("gather m");
+    reset_queue(L, st);
+    hipLaunchKernelGGL(k_gravity<R>, dim3(grid_1wave(L)), dim3(kWave), 0, st,
+                       make_queue(L, L->order_cull), n, L->perm, L->quant, ms, L->rng_off, L->rng,
+                       gp, a);
+    LAUNCH_CHECK("gravity");
+    return CRK_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+const char* crk_last_error(void) { return g_err.c_str(); }
+
+void crk_leaves_free(crk_leaves* L) {
+    if (!L) return;
+    (void)hipDeviceSynchronize();
+    release(L);
+    delete L;
+}
+
+int crk_get_tuning(const crk_leaves* L, crk_tuning* out) {
+    if (!L || !out) return fail(CRK_EINVAL, "null argument");
+    *out = L->tune;
+    return CRK_OK;
+}
+
+int crk_set_tuning(crk_leaves* L, const crk_tuning* in) {
+    if (!L || !in) return fail(CRK_EINVAL, "null argument");
+    if (in->persistent != 0 && in->persistent != 1) return fail(CRK_EINVAL, "persistent must be 0 or 1");
+    if (in->waves_per_cu < 1 || in->waves_per_cu > 64) return fail(CRK_EINVAL, "waves_per_cu in [1, 64]");
+    if (in->kahan_chunk < 1 || in->kahan_chunk > 64) return fail(CRK_EINVAL, "kahan_chunk in [1, 64]");
+    if (in->block_waves != 1 && in->block_waves != 2 && in->block_waves != 4)
+        return fail(CRK_EINVAL, "block_waves must be 1, 2 or 4");
+    L->tune = *in;
+    return CRK_OK;
+}
+
+int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const double* z,
+                         const void* h, double r_fixed, int leaf_max, int leaf_min,
+                         double split_extent, crk_prec prec, crk_leaves** out, hipStream_t stream) {
+    if (!out) return fail(CRK_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 0 || n >= (int64_t(1) << 31)) return fail(CRK_EINVAL, "n = %lld out of range [0, 2^31)", (long long)n);
+    if (prec != CRK_F32 && prec != CRK_F64) return fail(CRK_EINVAL, "unknown precision");
+    if (leaf_max < 1 || leaf_max > (1 << 20)) return fail(CRK_EINVAL, "leaf_max out of range [1, 2^20]");
+    if (leaf_min < 1) return fail(CRK_EINVAL, "leaf_min must be >= 1");
+    if (n > 0 && !h && !(r_fixed > 0.0 && r_fixed < 0.5))
+        return fail(CRK_EINVAL, "fixed radius must be in (0, 1/2) of the box");
+    if (n > 0 && (!x || !y || !z)) return fail(CRK_EINVAL, "positions are NULL");
+    const auto t0 = std::chrono::steady_clock::now();
+
+    crk_leaves* L = new crk_leaves();
+    L->n = n;
+    L->hydro = h != nullptr;
+    L->prec = prec;
+    L->r_fixed = r_fixed;
+    int dev = 0;
+    int rc = CRK_OK;
+    auto bail = [&](int code) {
+        release(L);
+        delete L;
+        return code;
+    };
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&L->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return bail(fail(CRK_EHIP, "cannot query the device"));
+    if ((rc = dalloc(&L->counter, 4)) || (rc = dalloc(&L->counts, 4))) return bail(rc);
+    if (n == 0) {
+        *out = L;
+        return CRK_OK;
+    }
+
+    // positions (and h) to the host
+    std::vector<double> hx(n), hy(n), hz(n), H;
+    if (hipMemcpyAsync(hx.data(), x, n * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipMemcpyAsync(hy.data(), y, n * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipMemcpyAsync(hz.data(), z, n * 8, hipMemcpyDeviceToHost, stream) != hipSuccess)
+        return bail(fail(CRK_EHIP, "copying positions to the host failed"));
+    if (L->hydro) {
+        H.resize(n);
+        if (prec == CRK_F32) {
+            std::vector<float> hf(n);
+            if (hipMemcpyAsync(hf.data(), h, n * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+                hipStreamSynchronize(stream) != hipSuccess)
+                return bail(fail(CRK_EHIP, "copying h to the host failed"));
+            for (int64_t i = 0; i < n; ++i) H[i] = 2.0 * double(hf[i]);
+        } else {
+            if (hipMemcpyAsync(H.data(), h, n * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+                hipStreamSynchronize(stream) != hipSuccess)
+                return bail(fail(CRK_EHIP, "copying h to the host failed"));
+            for (int64_t i = 0; i < n; ++i) H[i] = 2.0 * H[i];
+        }
+    }
+    if (hipStreamSynchronize(stream) != hipSuccess) return bail(fail(CRK_EHIP, "stream sync failed"));
+    std::vector<uint32_t> q[3];
+    for (int a = 0; a < 3; ++a) q[a].resize(n);
+    double Hmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double p[3] = {hx[i], hy[i], hz[i]};
+        for (int a = 0; a < 3; ++a) {
+            if (!std::isfinite(p[a])) return bail(fail(CRK_EINVAL, "non-finite position at %lld", (long long)i));
+            const double t = p[a] - std::floor(p[a]);
+            const double v = std::floor(t * 4294967296.0 + 0.5);
+            q[a][i] = v >= 4294967296.0 ? 0u : uint32_t(v);
+        }
+        if (L->hydro) {
+            if (!(H[i] > 0.0) || !std::isfinite(H[i]))
+                return bail(fail(CRK_EINVAL, "h must be positive and finite (particle %lld)", (long long)i));
+            Hmax = std::max(Hmax, H[i]);
+        }
+    }
+    if (L->hydro && !(Hmax < 0.5))
+        return bail(fail(CRK_EINVAL, "2 max(h) = %g must be below half the box", Hmax));
+
+    crk::TreeInput tin;
+    tin.n = n;
+    for (int a = 0; a < 3; ++a) tin.q[a] = q[a].data();
+    tin.H = L->hydro ? H.data() : nullptr;
+    tin.r_fixed = r_fixed;
+    tin.leaf_max = leaf_max;
+    tin.leaf_min = leaf_min;
+    tin.split_extent = split_extent;
+    crk::TreeOutput tout;
+    const char* terr = nullptr;
+    if (!crk::build_tree(tin, tout, &terr)) return bail(fail(CRK_EINVAL, "tree: %s", terr));
+    L->n_leaves = int64_t(tout.leaf_begin.size());
+    L->n_tiles = (n + kWave - 1) / kWave;
+    const int64_t nt = L->n_tiles;
+
+    // tree-order fixed-point positions and support radii
+    std::vector<uint4> hq(n);
+    std::vector<double> hH(L->hydro ? n : 0);
+    for (int64_t s = 0; s < n; ++s) {
+        const int32_t i = tout.perm[s];
+        hq[s] = make_uint4(q[0][i], q[1][i], q[2][i],
+                           L->hydro ? [](float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }(float(H[i])) : 0u);
+        if (L->hydro) hH[s] = H[i];
+    }
+    // longest-processing-time-first order of tiles for the candidate scan
+    std::vector<int32_t> order(nt);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return tout.tile_cand[a] > tout.tile_cand[b]; });
+
+    if ((rc = dalloc(&L->perm, n)) || (rc = dalloc(&L->quant, n)) ||
+        (rc = dalloc(&L->rng_off, nt + 1)) || (rc = dalloc(&L->rng, tout.rng.size() / 2)) ||
+        (rc = dalloc(&L->order_cull, nt)) || (rc = dalloc(&L->order_pair, nt)) ||
+        (rc = dalloc(&L->partials, 8 * nt)))
+        return bail(rc);
+    if (hipMemcpyAsync(L->perm, tout.perm.data(), n * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(L->quant, hq.data(), n * 16, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(L->rng_off, tout.rng_off.data(), (nt + 1) * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        (tout.rng.size() && hipMemcpyAsync(L->rng, tout.rng.data(), tout.rng.size() * 4,
+                                           hipMemcpyHostToDevice, stream) != hipSuccess) ||
+        hipMemcpyAsync(L->order_cull, order.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(L->order_pair, order.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
+        return bail(fail(CRK_EHIP, "uploading the tree failed"));
+
+    L->stats[0] = L->n_leaves;
+    L->stats[1] = nt;
+    L->stats[2] = tout.cand_pairs;
+
+    if (L->hydro) {
+        if ((rc = dalloc(&L->Hd, n)) || (rc = dalloc(&L->cnt, n)) || (rc = dalloc(&L->ell_off, nt)) ||
+            (rc = dalloc(&L->ell_len, nt)))
+            return bail(rc);
+        if (hipMemcpyAsync(L->Hd, hH.data(), n * 8, hipMemcpyHostToDevice, stream) != hipSuccess)
+            return bail(fail(CRK_EHIP, "uploading H failed"));
+        // count pass
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, L->counter);
+        hipLaunchKernelGGL(k_cull<false>, dim3(grid_1wave(L)), dim3(kWave), 0, stream,
+                           make_queue(L, L->order_cull), int(n), L->quant, L->rng_off, L->rng, L->cnt,
+                           nullptr, nullptr);
+        if (hipGetLastError() != hipSuccess) return bail(fail(CRK_EHIP, "launch cull count failed"));
+        std::vector<int32_t> hc(n);
+        if (hipMemcpyAsync(hc.data(), L->cnt, n * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+            return bail(fail(CRK_EHIP, "cull count failed"));
+        std::vector<int32_t> len(nt, 0);
+        std::vector<int64_t> off(nt, 0);
+        int64_t total = 0, entries = 0;
+        for (int64_t t = 0; t < nt; ++t) {
+            int32_t mx = 0;
+            for (int64_t s = t * kWave; s < std::min<int64_t>(n, (t + 1) * kWave); ++s) {
+                mx = std::max(mx, hc[s]);
+                entries += hc[s];
+            }
+            len[t] = mx;
+            off[t] = total;
+            total += int64_t(mx) * kWave;
+        }
+        if ((rc = dalloc(&L->nbr, size_t(total)))) return bail(rc);
+        if (hipMemcpyAsync(L->ell_off, off.data(), nt * 8, hipMemcpyHostToDevice, stream) != hipSuccess ||
+            hipMemcpyAsync(L->ell_len, len.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
+            return bail(fail(CRK_EHIP, "uploading list offsets failed"));
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, L->counter);
+        hipLaunchKernelGGL(k_cull<true>, dim3(grid_1wave(L)), dim3(kWave), 0, stream,
+                           make_queue(L, L->order_cull), int(n), L->quant, L->rng_off, L->rng, L->cnt,
+                           L->ell_off, L->nbr);
+        if (hipGetLastError() != hipSuccess) return bail(fail(CRK_EHIP, "launch cull fill failed"));
+        // pair passes: tiles with the longest lists first
+        std::vector<int32_t> po(nt);
+        std::iota(po.begin(), po.end(), 0);
+        std::stable_sort(po.begin(), po.end(), [&](int32_t a, int32_t b) { return len[a] > len[b]; });
+        if (hipMemcpyAsync(L->order_pair, po.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+            return bail(fail(CRK_EHIP, "list build failed"));
+        L->stats[3] = entries;
+        L->stats[6] = total - entries;
+    }
+    if (hipStreamSynchronize(stream) != hipSuccess) return bail(fail(CRK_EHIP, "build sync failed"));
+    L->stats[7] = std::chrono::duration_cast<std::chrono::microseconds>(
+                      std::chrono::steady_clock::now() - t0).count();
+    *out = L;
+    return CRK_OK;
+}
+
+int crk_leaves_stats(crk_leaves* L, int64_t* host_out) {
+    if (!L || !host_out) return fail(CRK_EINVAL, "null argument");
+    if (!L->counted && L->n > 0) {
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipMemset(L->counts, 0, 4 * sizeof(unsigned long long)));
+        if (L->hydro) {
+            hipLaunchKernelGGL(k_count_lists, dim3((L->n + 255) / 256), dim3(256), 0, 0, int(L->n),
+                               L->quant, L->Hd, L->cnt, L->ell_off, L->nbr, L->counts);
+        } else {
+            hipLaunchKernelGGL(k_count_fixed, dim3(L->n_tiles), dim3(64), 0, 0, int(L->n_tiles),
+                               int(L->n), L->quant, L->rng_off, L->rng, L->r_fixed, L->counts);
+        }
+        LAUNCH_CHECK("count");
+        unsigned long long c[4];
+        HIP_TRY(hipMemcpy(c, L->counts, sizeof c, hipMemcpyDeviceToHost));
+        L->stats[4] = int64_t(c[0]);
+        L->stats[5] = int64_t(L->hydro ? c[1] : c[0]);
+        L->counted = true;
+    }
+    for (int k = 0; k < 8; ++k) host_out[k] = L->stats[k];
+    return CRK_OK;
+}
+
+int crk_volume(crk_leaves* L, const crk_gas* g, crk_prec prec, void* V, void* rho, hipStream_t st) {
+    int rc = check_gas(L, g, false);
+    if (rc) return rc;
+    if (L->n == 0) return CRK_OK;
+    if (!g->m || !V || !rho) return fail(CRK_EINVAL, "m, V and rho are required");
+    if (prec == CRK_F32) return volume_impl<float>(L, g, (float*)V, (float*)rho, st);
+    if (prec == CRK_F64) return volume_impl<double>(L, g, (double*)V, (double*)rho, st);
+    return fail(CRK_EINVAL, "unknown precision");
+}
+
+int crk_corrections(crk_leaves* L, const crk_gas* g, const void* V, crk_prec prec,
+                    const crk_corr* out, int64_t* n_fallback, hipStream_t st) {
+    int rc = check_gas(L, g, false);
+    if (rc) return rc;
+    if (L->n == 0) return CRK_OK;
+    if (!V || !out || !out->A || !out->B || !out->dA || !out->dB)
+        return fail(CRK_EINVAL, "V and all correction outputs are required");
+    if (prec == CRK_F32) return corrections_impl<float>(L, g, (const float*)V, out, n_fallback, st);
+    if (prec == CRK_F64) return corrections_impl<double>(L, g, (const double*)V, out, n_fallback, st);
+    return fail(CRK_EINVAL, "unknown precision");
+}
+
+int crk_accel_energy(crk_leaves* L, const crk_gas* g, const void* V, const void* rho,
+                     const crk_corr* C, double gamma, crk_prec prec, void* a, void* dudt,
+                     double* totals, hipStream_t st) {
+    int rc = check_gas(L, g, true);
+    if (rc) return rc;
+    if (L->n == 0) {
+        if (totals) HIP_TRY(hipMemsetAsync(totals, 0, 8 * sizeof(double), st));
+        return CRK_OK;
+    }
+    if (!V || !rho || !C || !C->A || !C->B || !C->dA || !C->dB || !a || !dudt)
+        return fail(CRK_EINVAL, "V, rho, corrections, a and dudt are required");
+    if (prec == CRK_F32)
+        return accel_impl<float>(L, g, (const float*)V, (const float*)rho, C, gamma, (float*)a,
+                                 (float*)dudt, totals, st);
+    if (prec == CRK_F64)
+        return accel_impl<double>(L, g, (const double*)V, (const double*)rho, C, gamma, (double*)a,
+                                  (double*)dudt, totals, st);
+    return fail(CRK_EINVAL, "unknown precision");
+}
+
+int sr_gravity(crk_leaves* L, int64_t n, const double* x, const double* y, const double* z,
+               const void* m, double G, double eps, double r_cut, const double* poly, crk_prec prec,
+               void* a, hipStream_t st) {
+    if (!L) return fail(CRK_EINVAL, "null handle");
+    if (n != L->n) return fail(CRK_EINVAL, "n does not match the handle");
+    if (n == 0) return CRK_OK;
+    if (L->hydro) return fail(CRK_ESTATE, "sr_gravity needs a handle built in fixed-radius mode");
+    if (!(r_cut > 0.0) || r_cut > L->r_fixed)
+        return fail(CRK_EINVAL, "r_cut must be in (0, r_fixed of the handle]");
+    if (!(eps >= 0.0)) return fail(CRK_EINVAL, "eps must be >= 0");
+    if (n == 0) return CRK_OK;
+    if (!x || !y || !z || !m || !a) return fail(CRK_EINVAL, "x, y, z, m and a are required");
+    GravParams gp;
+    gp.G = G;
+    gp.eps2 = eps * eps;
+    gp.rc2 = r_cut * r_cut;
+    gp.use_poly = poly != nullptr;
+    for (int k = 0; k < 6; ++k) gp.poly[k] = poly ? poly[k] : 0.0;
+    if (prec == CRK_F32) return gravity_impl<float>(L, x, y, z, (const float*)m, gp, (float*)a, st);
+    if (prec == CRK_F64) return gravity_impl<double>(L, x, y, z, (const double*)m, gp, (double*)a, st);
+    return fail(CRK_EINVAL, "unknown precision");
+}
+
+}  // extern "C"

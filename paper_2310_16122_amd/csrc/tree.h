@@ -1,0 +1,35 @@
+// Host-side recursive coordinate bisection and tile interaction lists.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace crk {
+
+constexpr int kTile = 64;  // particles per tile = lanes per wavefront
+
+struct TreeInput {
+    int64_t n;
+    const uint32_t* q[3];   // fixed-point positions (2^-32 box units)
+    const double* H;        // support radius per particle (box units), or nullptr
+    double r_fixed;         // interaction radius when H == nullptr
+    int leaf_max;
+    int leaf_min;
+    double split_extent;    // box units; <= 0 disables the extent rule
+};
+
+struct TreeOutput {
+    std::vector<int32_t> perm;         // tree order -> input index
+    std::vector<int32_t> leaf_begin;   // leaves as ranges of tree order
+    std::vector<int32_t> leaf_end;
+    std::vector<int32_t> rng_off;      // per tile: CSR offsets into rng (n_tiles + 1)
+    std::vector<int32_t> rng;          // (begin, end) pairs of candidate particle ranges
+    std::vector<int64_t> tile_cand;    // candidate particles per tile
+    int64_t cand_pairs = 0;            // sum over tiles of (valid lanes * candidates)
+};
+
+// Builds the tree and the per-tile candidate ranges.  Returns false with a
+// message on invalid input.
+bool build_tree(const TreeInput& in, TreeOutput& out, const char** err);
+
+}  // namespace crk

@@ -1,0 +1,40 @@
+"""The C ABI library loads and exports every symbol include/crk.h declares (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "crk.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_entry_points():
+    syms = declared_symbols()
+    for name in ("crk_build_leaf_pairs", "crk_volume", "crk_corrections", "crk_accel_energy",
+                 "sr_gravity", "crk_leaves_free", "crk_last_error"):
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2310_16122_amd as crk
+
+    if not os.path.exists(crk.LIB_PATH):
+        pytest.fail("libcrk.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(crk.LIB_PATH)
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    assert set(crk.EXPORTS) == set(declared_symbols())
+
+
+def test_last_error_is_empty_string_initially():
+    import paper_2310_16122_amd as crk
+
+    lib = crk.load_library()
+    assert lib.crk_last_error() == b""

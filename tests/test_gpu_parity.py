@@ -1,0 +1,242 @@
+"""Parity of the HIP passes with the FP64 oracle, through the C ABI (GPU only).
+
+Error metric per output array (normwise): max_i |y_i - y_ref_i| / max_i |y_ref_i|.
+Bars: FP64 path <= 1e-12, FP32 path (FP32 pairs + compensated sums, FP64
+solve and totals) <= 1e-5.  Small configurations are compared element by
+element with the full brute-force oracle; the full-size configuration is
+compared on sampled particles, each evaluated by the oracle inside its
+three-hop closure.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+KEYS = ("V", "rho", "A", "B", "dA", "dB", "a", "dudt")
+
+
+@pytest.fixture(scope="module")
+def crk():
+    import paper_2310_16122_amd as crk
+
+    crk.load_library()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return crk
+
+
+def normwise(y, ref):
+    y = np.asarray(y, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.abs(y - ref).max() / np.abs(ref).max())
+
+
+def run_gpu(crk, cfg, prec, leaf_max=64, tuning=None):
+    g = crk.gas_to_device(cfg, prec)
+    L = crk.crk_build_leaf_pairs(g["x"], g["y"], g["z"], g["h"], leaf_max=leaf_max, prec=prec)
+    if tuning:
+        L.set_tuning(**tuning)
+    out = crk.forward(L, g, cfg["gamma"], prec)
+    torch.cuda.synchronize()
+    host = {k: v.double().cpu().numpy() for k, v in out.items()}
+    return host, L
+
+
+_cache = {}
+
+
+def oracle_full(name, n_side):
+    key = (name, n_side)
+    if key not in _cache:
+        cfg = synth.make_config(name, n_side)
+        _cache[key] = (cfg, oracle.hydro(cfg))
+    return _cache[key]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("name,n_side", [("C1", None), ("C2", 21), ("C5", 24)])
+def test_forward_chain_parity(crk, name, n_side, prec):
+    cfg, ref = oracle_full(name, n_side)
+    print(f"case {name} n_side={n_side} prec={prec} n={cfg['n']}", flush=True)
+    got, L = run_gpu(crk, cfg, prec)
+    errs = {k: normwise(got[k], ref[k]) for k in KEYS}
+    print(errs, flush=True)
+    for k in KEYS:
+        assert errs[k] <= TOL[prec], (k, errs[k])
+    assert int(got["n_fallback"][0]) == 0 == ref["n_fallback"]
+    # FP64 totals: momentum and energy conserved to the precision of the path
+    T = got["totals"]
+    lim = 1e-13 if prec == "f64" else 2e-6
+    assert np.abs(T[:3]).max() <= lim * T[4]
+    assert abs(T[3]) <= lim * T[5]
+    assert np.allclose(T[4], ref["totals"][4], rtol=1e-5)
+
+
+def test_interaction_counts_exact(crk):
+    cfg, _ = oracle_full("C2", 21)
+    got, L = run_gpu(crk, cfg, "f64")
+    st = L.stats()
+    assert st["pairs_gather"] == oracle.count_pairs(cfg, 0)[0]
+    assert st["pairs_force"] == oracle.count_pairs(cfg, 1)[0]
+    assert st["list_entries"] >= st["pairs_force"]
+
+
+@pytest.mark.parametrize("leaf_max", [16, 128, 512])
+def test_leaf_size_and_scheduling_do_not_change_results(crk, leaf_max):
+    cfg, _ = oracle_full("C2", 21)
+    base, _ = run_gpu(crk, cfg, "f32", leaf_max=64)
+    for tun in ({"persistent": 0}, {"persistent": 1, "waves_per_cu": 3, "block_waves": 1}):
+        got, _ = run_gpu(crk, cfg, "f32", leaf_max=leaf_max, tuning=tun)
+        for k in KEYS:
+            # the per-particle arithmetic does not depend on tree or schedule,
+            # only the neighbour order does (compensated sums: tiny differences)
+            assert normwise(got[k], base[k]) <= 2e-6, k
+
+
+def test_bitwise_reproducible(crk):
+    cfg, _ = oracle_full("C2", 21)
+    a, _ = run_gpu(crk, cfg, "f32")
+    b, _ = run_gpu(crk, cfg, "f32", tuning={"persistent": 0})
+    for k in KEYS:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_kahan_chunk_within_tolerance(crk):
+    cfg, ref = oracle_full("C2", 21)
+    for chunk in (1, 8, 32):
+        got, _ = run_gpu(crk, cfg, "f32", tuning={"kahan_chunk": chunk})
+        for k in ("A", "B", "dA", "dB"):
+            assert normwise(got[k], ref[k]) <= TOL["f32"], (chunk, k)
+
+
+def test_lattice_zero_acceleration_gpu(crk):
+    cfg = synth.make_lattice(n_side=16, jitter=0.0)
+    ref = oracle.hydro(cfg)
+    for prec, lim in (("f64", 1e-12), ("f32", 1e-5)):
+        got, _ = run_gpu(crk, cfg, prec)
+        scale = np.abs(oracle.hydro(synth.make_lattice())["a"]).max()
+        assert np.abs(got["a"]).max() <= lim * scale, prec
+        assert normwise(got["V"], ref["V"]) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_full_size_sampled_closure(crk, prec):
+    """C2 at 128^3: 48 sampled particles against the oracle's per-target closure."""
+    cfg = synth.make_config("C2")
+    print(f"case C2 full n={cfg['n']} prec={prec}", flush=True)
+    got, L = run_gpu(crk, cfg, prec, leaf_max=128)
+    t = synth.sample_targets(cfg["n"], 48, seed=11)
+    ref = oracle.hydro_targets(cfg, t)
+    for k in KEYS:
+        # normalised by the full GPU array's max (the oracle sees only the sample)
+        scale = np.abs(got[k]).max()
+        err = np.abs(got[k][t] - ref[k]).max() / scale
+        assert err <= TOL[prec], (k, err)
+    T = got["totals"]
+    lim = 1e-13 if prec == "f64" else 2e-6
+    assert np.abs(T[:3]).max() <= lim * T[4]
+
+
+# ---------------------------------------------------------------- gravity
+def gravity_case(n_side):
+    cfg = synth.make_gravity(n_side=n_side)
+    return cfg
+
+
+def borderline_bound(cfg, G=1.0):
+    """Per-particle sum of |pair term| over pairs with |r^2 - rc^2| <= 2^-20 rc^2."""
+    from scipy.spatial import cKDTree
+
+    P = np.stack([cfg["x"], cfg["y"], cfg["z"]], 1)
+    tree = cKDTree(P, boxsize=1.0)
+    rc = cfg["r_cut"]
+    lo = rc * np.sqrt(1 - 2.0 ** -20)
+    hi = rc * np.sqrt(1 + 2.0 ** -20)
+    pairs = tree.query_pairs(hi, output_type="ndarray")
+    d = P[pairs[:, 0]] - P[pairs[:, 1]]
+    d -= np.floor(d + 0.5)
+    r = np.sqrt((d * d).sum(1))
+    sel = r >= lo
+    b = np.zeros(len(P))
+    f = G / (r[sel] ** 2 + cfg["eps"] ** 2) ** 1.5 * r[sel]
+    np.add.at(b, pairs[sel, 0], cfg["m"][pairs[sel, 1]] * f)
+    np.add.at(b, pairs[sel, 1], cfg["m"][pairs[sel, 0]] * f)
+    return b
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_gravity_parity(crk, prec):
+    cfg = gravity_case(24)
+    print(f"case gravity n={cfg['n']} prec={prec}", flush=True)
+    ref = oracle.gravity(cfg)
+    dt = torch.float32 if prec == "f32" else torch.float64
+    x, y, z = (torch.as_tensor(cfg[k]).cuda() for k in ("x", "y", "z"))
+    m = torch.as_tensor(cfg["m"]).to(dt).cuda()
+    L = crk.crk_build_leaf_pairs(x, y, z, None, r_fixed=cfg["r_cut"], leaf_max=512, leaf_min=16,
+                                 split_extent=cfg["r_cut"], prec=prec)
+    a = crk.sr_gravity(L, x, y, z, m, cfg["G"], cfg["eps"], cfg["r_cut"], prec=prec)
+    a = a.double().cpu().numpy()
+    bound = borderline_bound(cfg)
+    err = np.abs(a - ref).max(1)
+    scale = np.abs(ref).max()
+    assert np.all(err <= TOL[prec] * scale + bound), (err.max() / scale)
+    st = L.stats()
+    assert st["pairs_force"] == oracle.count_pairs(cfg, 2, r_fixed=cfg["r_cut"])[0]
+
+
+def test_gravity_polynomial(crk):
+    cfg = gravity_case(16)
+    poly = np.array([1.0, -2.0, 3.0, 0.5, -0.25, 0.125]) * 1e3
+    ref = oracle.gravity(cfg, poly=poly)
+    x, y, z = (torch.as_tensor(cfg[k]).cuda() for k in ("x", "y", "z"))
+    m = torch.as_tensor(cfg["m"]).cuda()
+    L = crk.crk_build_leaf_pairs(x, y, z, None, r_fixed=cfg["r_cut"], leaf_max=64, prec="f64")
+    a = crk.sr_gravity(L, x, y, z, m, cfg["G"], cfg["eps"], cfg["r_cut"], poly=poly, prec="f64")
+    assert normwise(a.cpu().numpy(), ref) <= 1e-12 + borderline_bound(cfg).max() / np.abs(ref).max()
+
+
+# ---------------------------------------------------------------- edges and errors
+def test_empty_and_tiny_inputs(crk):
+    for n in (0, 1, 5, 63, 65):
+        rng = np.random.default_rng(n)
+        cfg = dict(x=synth.grid_round(rng.random(n)), y=synth.grid_round(rng.random(n)),
+                   z=synth.grid_round(rng.random(n)), h=synth.f32(np.full(n, 0.2)),
+                   m=synth.f32(np.full(n, 1.0 / max(n, 1))), vx=np.zeros(n), vy=np.zeros(n),
+                   vz=synth.f32(rng.normal(0, 0.1, n)), u=np.ones(n), gamma=5.0 / 3.0)
+        got, L = run_gpu(crk, cfg, "f64", leaf_max=8)
+        if n == 0:
+            assert got["V"].size == 0
+            continue
+        V, rho = oracle.volume(cfg)
+        assert normwise(got["V"], V) <= 1e-12
+        if n >= 8:
+            ref = oracle.hydro(cfg)
+            assert normwise(got["a"], ref["a"]) <= 1e-12
+            assert int(got["n_fallback"][0]) == ref["n_fallback"]
+
+
+def test_invalid_arguments(crk):
+    x = torch.rand(100, dtype=torch.float64, device="cuda")
+    h = torch.full((100,), 0.3, dtype=torch.float32, device="cuda")  # 2h >= 1/2
+    with pytest.raises(crk.CrkError) as e:
+        crk.crk_build_leaf_pairs(x, x, x, h, prec="f32")
+    assert e.value.code == -1
+    with pytest.raises(crk.CrkError):
+        crk.crk_build_leaf_pairs(x, x, x, None, r_fixed=0.5, prec="f32")
+    with pytest.raises(crk.CrkError):
+        crk.crk_build_leaf_pairs(x, x, x, None, r_fixed=0.1, leaf_max=0, prec="f32")
+    L = crk.crk_build_leaf_pairs(x, x, x, None, r_fixed=0.1, prec="f32")
+    g = {"x": x, "y": x, "z": x, "h": h, "m": h}
+    with pytest.raises(crk.CrkError) as e:
+        crk.crk_volume(L, g, "f32")
+    assert e.value.code == -4
+    with pytest.raises(crk.CrkError):
+        L.set_tuning(block_waves=3)
+    m = torch.ones(100, dtype=torch.float32, device="cuda")
+    with pytest.raises(crk.CrkError):
+        crk.sr_gravity(L, x, x, x, m, 1.0, 0.0, r_cut=0.2, prec="f32")  # r_cut > r_fixed
