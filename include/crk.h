@@ -182,6 +182,25 @@ int crk_leaves_stats(crk_leaves* leaves, int64_t* host_out);
 int crk_get_tuning(const crk_leaves* leaves, crk_tuning* out);
 int crk_set_tuning(crk_leaves* leaves, const crk_tuning* in);
 
+/*
+ * Kernel timing, for measurement.  While enabled on a handle, every kernel a
+ * call launches is bracketed by HIP events recorded on the call's stream.
+ * crk_kernel_times waits for the recorded events and returns, per kernel kind,
+ * the summed milliseconds and the number of launches since timing was last
+ * enabled (ms and launches: host arrays of CRK_K_COUNT).
+ */
+enum {
+    CRK_K_CULL = 0,    /* neighbour-list build (count and fill passes) */
+    CRK_K_VOLUME = 1,  /* volume pair kernel */
+    CRK_K_MOMENTS = 2, /* correction moments + FP64 solve */
+    CRK_K_ACCEL = 3,   /* acceleration/energy pair kernel */
+    CRK_K_GRAVITY = 4, /* short-range gravity */
+    CRK_K_PACK = 5,    /* per-particle packing, gathers and the totals reduction */
+    CRK_K_COUNT = 6
+};
+int crk_timing(crk_leaves* leaves, int enable);
+int crk_kernel_times(crk_leaves* leaves, double* ms, int64_t* launches);
+
 /* Release a handle (NULL is ignored).  Synchronises the device. */
 void crk_leaves_free(crk_leaves* leaves);
 

@@ -29,7 +29,8 @@ _STATUS = {0: "CRK_OK", -1: "CRK_EINVAL", -2: "CRK_ENOMEM", -3: "CRK_EHIP", -4: 
 # the C symbols declared in include/crk.h
 EXPORTS = ("crk_build_leaf_pairs", "crk_volume", "crk_corrections", "crk_accel_energy",
            "sr_gravity", "crk_leaves_stats", "crk_get_tuning", "crk_set_tuning",
-           "crk_leaves_free", "crk_last_error")
+           "crk_timing", "crk_kernel_times", "crk_leaves_free", "crk_last_error")
+KERNEL_KINDS = ("cull", "volume", "moments", "accel", "gravity", "pack")
 
 
 class CrkError(RuntimeError):
@@ -77,6 +78,8 @@ def load_library(path=None):
     lib.crk_leaves_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
     lib.crk_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
     lib.crk_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    lib.crk_timing.argtypes = [P, I]
+    lib.crk_kernel_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.crk_leaves_free.argtypes = [P]
     lib.crk_leaves_free.restype = None
     lib.crk_last_error.restype = ctypes.c_char_p
@@ -151,6 +154,17 @@ class Leaves:
     def set_tuning(self, **kw):
         t = Tuning(**{**self.get_tuning(), **kw})
         _check("crk_set_tuning", load_library().crk_set_tuning(self.handle, ctypes.byref(t)))
+
+    def timing(self, enable=True):
+        """Start (and reset) or stop per-kernel event timing on this handle."""
+        _check("crk_timing", load_library().crk_timing(self.handle, int(bool(enable))))
+
+    def kernel_times(self):
+        """{kind: (total ms, launches)} of the kernels timed since timing was enabled."""
+        ms = (ctypes.c_double * len(KERNEL_KINDS))()
+        nl = (ctypes.c_int64 * len(KERNEL_KINDS))()
+        _check("crk_kernel_times", load_library().crk_kernel_times(self.handle, ms, nl))
+        return {k: (ms[i], nl[i]) for i, k in enumerate(KERNEL_KINDS)}
 
     def free(self):
         if self._h is not None:

@@ -739,6 +739,13 @@ struct crk_leaves {
     size_t scratch_bytes = 0;
     int64_t stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     bool counted = false;
+    // kernel timing (events on the launch stream)
+    bool timing = false;
+    struct Timed {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Timed> timed;
 };
 
 namespace {
@@ -771,6 +778,32 @@ int ensure_scratch(crk_leaves* L, size_t bytes) {
     if (e != hipSuccess) return fail(CRK_ENOMEM, "scratch hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
     L->scratch_bytes = bytes;
     return CRK_OK;
+}
+
+// Brackets one launch with events when timing is enabled.
+struct TimeScope {
+    crk_leaves* L;
+    hipStream_t st;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimeScope(crk_leaves* l, hipStream_t s, int k) : L(l), st(s), kind(k) {
+        if (!L->timing) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+        (void)hipEventRecord(a, st);
+    }
+    ~TimeScope() {
+        if (!a) return;
+        (void)hipEventRecord(b, st);
+        L->timed.push_back({kind, a, b});
+    }
+};
+
+void drop_timed(crk_leaves* L) {
+    for (auto& t : L->timed) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    L->timed.clear();
 }
 
 Queue make_queue(const crk_leaves* L, const int32_t* order) {
@@ -808,6 +841,7 @@ template <class R>
 int pack_positions(crk_leaves* L, const double* x, const double* y, const double* z, const R* h,
                    hipStream_t st) {
     const int n = int(L->n);
+    TimeScope ts(L, st, CRK_K_PACK);
     hipLaunchKernelGGL(k_pack_quant<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, x, y,
                        z, h, L->quant);
     LAUNCH_CHECK("pack_quant");
@@ -824,6 +858,7 @@ template <class R> int volume_impl(crk_leaves* L, const crk_gas* g, R* V, R* rho
     int rc = pack_positions<R>(L, g->x, g->y, g->z, static_cast<const R*>(g->h), st);
     if (rc) return rc;
     reset_queue(L, st);
+    TimeScope ts(L, st, CRK_K_VOLUME);
     hipLaunchKernelGGL(k_volume<R>, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves), 0, st,
                        make_queue(L, L->order_pair), int(L->n), lists(L), L->perm, L->quant,
                        static_cast<const R*>(g->h), static_cast<const R*>(g->m), V, rho);
@@ -839,9 +874,13 @@ int corrections_impl(crk_leaves* L, const crk_gas* g, const R* V, const crk_corr
     if (rc) return rc;
     if ((rc = ensure_scratch(L, sizeof(R) * size_t(n)))) return rc;
     R* Vs = static_cast<R*>(L->scratch);
-    hipLaunchKernelGGL(k_gather<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, V, Vs);
+    {
+        TimeScope tp(L, st, CRK_K_PACK);
+        hipLaunchKernelGGL(k_gather<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, V, Vs);
+    }
     LAUNCH_CHECK("gather V");
     reset_queue(L, st);
+    TimeScope ts(L, st, CRK_K_MOMENTS);
     hipLaunchKernelGGL(k_moments<R>, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves), 0, st,
                        make_queue(L, L->order_pair), n, lists(L), L->perm, L->quant, Vs,
                        static_cast<const R*>(g->h), L->tune.kahan_chunk, static_cast<R*>(out->A),
@@ -859,19 +898,26 @@ int accel_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const 
     if (rc) return rc;
     if ((rc = ensure_scratch(L, sizeof(RecAcc<R>) * size_t(n)))) return rc;
     RecAcc<R>* rec = static_cast<RecAcc<R>*>(L->scratch);
+    {
+    TimeScope tp(L, st, CRK_K_PACK);
     hipLaunchKernelGGL(k_pack_acc<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, L->quant,
                        static_cast<const R*>(g->h), static_cast<const R*>(g->u),
                        static_cast<const R*>(g->vx), static_cast<const R*>(g->vy),
                        static_cast<const R*>(g->vz), V, rho, static_cast<const R*>(C->A),
                        static_cast<const R*>(C->B), static_cast<const R*>(C->dA),
                        static_cast<const R*>(C->dB), R(gamma - 1.0), rec);
+    }
     LAUNCH_CHECK("pack_acc");
     reset_queue(L, st);
-    hipLaunchKernelGGL(k_accel<R>, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves), 0, st,
-                       make_queue(L, L->order_pair), n, lists(L), L->perm, rec,
-                       static_cast<const R*>(g->m), a, dudt, L->partials);
+    {
+        TimeScope ts(L, st, CRK_K_ACCEL);
+        hipLaunchKernelGGL(k_accel<R>, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves), 0, st,
+                           make_queue(L, L->order_pair), n, lists(L), L->perm, rec,
+                           static_cast<const R*>(g->m), a, dudt, L->partials);
+    }
     LAUNCH_CHECK("accel");
     if (totals) {
+        TimeScope tt(L, st, CRK_K_PACK);
         hipLaunchKernelGGL(k_totals, dim3(1), dim3(256), 0, st, int(L->n_tiles), L->partials, totals);
         LAUNCH_CHECK("totals");
     }
@@ -886,9 +932,13 @@ int gravity_impl(crk_leaves* L, const double* x, const double* y, const double* 
     if (rc) return rc;
     if ((rc = ensure_scratch(L, sizeof(R) * size_t(n)))) return rc;
     R* ms = static_cast<R*>(L->scratch);
-    hipLaunchKernelGGL(k_gather<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, m, ms);
+    {
+        TimeScope tp(L, st, CRK_K_PACK);
+        hipLaunchKernelGGL(k_gather<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, m, ms);
+    }
     LAUNCH_CHECK("gather m");
     reset_queue(L, st);
+    TimeScope ts(L, st, CRK_K_GRAVITY);
     hipLaunchKernelGGL(k_gravity<R>, dim3(grid_1wave(L)), dim3(kWave), 0, st,
                        make_queue(L, L->order_cull), n, L->perm, L->quant, ms, L->rng_off, L->rng,
                        gp, a);
@@ -904,9 +954,31 @@ extern "C" {
 
 const char* crk_last_error(void) { return g_err.c_str(); }
 
+int crk_timing(crk_leaves* L, int enable) {
+    if (!L) return fail(CRK_EINVAL, "null handle");
+    HIP_TRY(hipDeviceSynchronize());
+    drop_timed(L);
+    L->timing = enable != 0;
+    return CRK_OK;
+}
+
+int crk_kernel_times(crk_leaves* L, double* ms, int64_t* launches) {
+    if (!L || !ms || !launches) return fail(CRK_EINVAL, "null argument");
+    for (int k = 0; k < CRK_K_COUNT; ++k) { ms[k] = 0.0; launches[k] = 0; }
+    for (auto& t : L->timed) {
+        HIP_TRY(hipEventSynchronize(t.b));
+        float v = 0.f;
+        HIP_TRY(hipEventElapsedTime(&v, t.a, t.b));
+        ms[t.kind] += v;
+        launches[t.kind] += 1;
+    }
+    return CRK_OK;
+}
+
 void crk_leaves_free(crk_leaves* L) {
     if (!L) return;
     (void)hipDeviceSynchronize();
+    drop_timed(L);
     release(L);
     delete L;
 }
@@ -950,6 +1022,7 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
     int dev = 0;
     int rc = CRK_OK;
     auto bail = [&](int code) {
+        drop_timed(L);
         release(L);
         delete L;
         return code;
@@ -1061,9 +1134,13 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
             return bail(fail(CRK_EHIP, "uploading H failed"));
         // count pass
         hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, L->counter);
-        hipLaunchKernelGGL(k_cull<false>, dim3(grid_1wave(L)), dim3(kWave), 0, stream,
-                           make_queue(L, L->order_cull), int(n), L->quant, L->rng_off, L->rng, L->cnt,
-                           nullptr, nullptr);
+        L->timing = true;  // the list build is always timed (read by crk_kernel_times)
+        {
+            TimeScope ts(L, stream, CRK_K_CULL);
+            hipLaunchKernelGGL(k_cull<false>, dim3(grid_1wave(L)), dim3(kWave), 0, stream,
+                               make_queue(L, L->order_cull), int(n), L->quant, L->rng_off, L->rng,
+                               L->cnt, nullptr, nullptr);
+        }
         if (hipGetLastError() != hipSuccess) return bail(fail(CRK_EHIP, "launch cull count failed"));
         std::vector<int32_t> hc(n);
         if (hipMemcpyAsync(hc.data(), L->cnt, n * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
@@ -1087,9 +1164,13 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
             hipMemcpyAsync(L->ell_len, len.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
             return bail(fail(CRK_EHIP, "uploading list offsets failed"));
         hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, L->counter);
-        hipLaunchKernelGGL(k_cull<true>, dim3(grid_1wave(L)), dim3(kWave), 0, stream,
-                           make_queue(L, L->order_cull), int(n), L->quant, L->rng_off, L->rng, L->cnt,
-                           L->ell_off, L->nbr);
+        {
+            TimeScope ts(L, stream, CRK_K_CULL);
+            hipLaunchKernelGGL(k_cull<true>, dim3(grid_1wave(L)), dim3(kWave), 0, stream,
+                               make_queue(L, L->order_cull), int(n), L->quant, L->rng_off, L->rng,
+                               L->cnt, L->ell_off, L->nbr);
+        }
+        L->timing = false;
         if (hipGetLastError() != hipSuccess) return bail(fail(CRK_EHIP, "launch cull fill failed"));
         // pair passes: tiles with the longest lists first
         std::vector<int32_t> po(nt);
