@@ -66,6 +66,7 @@ def _load():
         lib.oracle_count_pairs.argtypes = [I64, P, P, P, P, ctypes.c_int, D, I64, P, P]
         lib.oracle_count_pairs.restype = I64
         lib.oracle_kernel.argtypes = [I64, P, D, P, P]
+        lib.oracle_grad.argtypes = [I64] + [P] * 9 + [D, P, P, I64, P, P, D, P, P, P]
         _lib = lib
     return _lib
 
@@ -210,3 +211,37 @@ def count_pairs(g, mode, targets=None, r_fixed=0.0):
     tot = _load().oracle_count_pairs(x.size, _p(x), _p(y), _p(z), _p(h), int(mode), float(r_fixed),
                                      nt, _p(t), _p(per))
     return int(tot), per
+
+
+COORD_KINDS = ("x", "y", "z", "vx", "vy", "vz", "u")
+
+
+def grad(g, parts, kinds, fd_step=1e-6):
+    """dL/dtheta of L = sum w |a|^2 + sum c du/dt for coordinates (parts[k], kinds[k]).
+
+    kinds index COORD_KINDS.  Returns (forward-mode dual-number gradient,
+    central-difference gradient, cone sizes [k, (|D1|, |D2|, |D3|)]).  Both are
+    evaluated over each coordinate's dependency cone with baseline values
+    elsewhere (see crk_oracle.cpp).
+    """
+    keys = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "m")
+    arr = [_c(g[k]) for k in keys]
+    w, cw = _c(g["w"]), _c(g["c"])
+    pt = _c(parts, np.int64)
+    kd = _c(kinds, np.int32)
+    nc = pt.size
+    gd = np.empty(nc)
+    gf = np.empty(nc)
+    cs = np.empty((nc, 3), dtype=np.int64)
+    _load().oracle_grad(arr[0].size, *[_p(v) for v in arr], float(g["gamma"]), _p(w), _p(cw), nc,
+                        _p(pt), _p(kd), float(fd_step), _p(gd), _p(gf), _p(cs))
+    return gd, gf, cs
+
+
+def grad_coordinates(n, n_pos=32, n_vel=16, n_u=16, seed=19):
+    """The seeded sample of coordinates the gradient checks use: (parts, kinds)."""
+    rng = np.random.default_rng(seed)
+    parts = rng.choice(n, size=n_pos + n_vel + n_u, replace=False).astype(np.int64)
+    kinds = np.concatenate([rng.integers(0, 3, n_pos), rng.integers(3, 6, n_vel),
+                            np.full(n_u, 6)]).astype(np.int32)
+    return parts, kinds

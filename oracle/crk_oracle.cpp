@@ -307,16 +307,112 @@ template <class T> void accel_one(const Gas<T>& g, const T* V, const T* rho, con
 // the corrections need volumes of their neighbours (two hops) and those
 // volumes need the positions of their neighbours (three hops).  A brute-force
 // scan collects that pool; the chain is then evaluated by brute force inside it.
-struct Closure {
-    std::vector<int64_t> pool;   // global indices within 3 H_max of the target
-};
-
 template <class T> void gather_pool(const Gas<T>& g, int64_t t, double R, std::vector<int64_t>& pool) {
     pool.clear();
     for (int64_t j = 0; j < g.n; ++j) {
         Sep<T> s = separation(g, t, j);
         if (val(s.r) < R) pool.push_back(j);
     }
+}
+
+// ---------------------------------------------------------------- gradients
+// L = sum_i w_i |a_i|^2 + sum_i c_i du_i/dt with h and m held fixed.  For one
+// coordinate theta (a position, velocity or u component of particle p) only
+// the particles in theta's dependency cone change:
+//   D1: volumes that depend on x_p   = {p} and every k with p inside k's support
+//   D2: corrections that depend on D1 or x_p = D1 and every k with a D1 particle inside k's support
+//   D3: forces that depend on D1, D2 or p = D1 u D2 and all their force neighbours
+// dL/dtheta is evaluated by forward-mode dual numbers over the cone and, as a
+// check, by central differences over the same cone; every other particle keeps
+// its baseline (brute-force FP64) values.  Neighbour lists are built by brute
+// force once (all j with r_ij < max(2h_i, 2h_j)).
+struct NbrLists {
+    std::vector<int64_t> off, idx;
+    Cand of(int64_t i) const { return Cand{idx.data() + off[i], off[i + 1] - off[i]}; }
+};
+
+NbrLists brute_force_lists(const Gas<double>& g) {
+    const int64_t n = g.n;
+    std::vector<std::vector<int64_t>> L(n);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            Sep<double> s = separation(g, i, j);
+            if (s.r < 2.0 * std::max(g.h[i], g.h[j])) L[i].push_back(j);
+        }
+    }
+    NbrLists out;
+    out.off.assign(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) out.off[i + 1] = out.off[i] + (int64_t)L[i].size();
+    out.idx.resize(out.off[n]);
+    for (int64_t i = 0; i < n; ++i) std::copy(L[i].begin(), L[i].end(), out.idx.begin() + out.off[i]);
+    return out;
+}
+
+struct Cone {
+    std::vector<int64_t> d1, d2, d3;
+};
+
+// gather neighbours of k (inside k's own support) are a subset of its force list
+Cone dependency_cone(const Gas<double>& g, const NbrLists& nb, int64_t p, int kind) {
+    const int64_t n = g.n;
+    std::vector<char> in1(n, 0), in2(n, 0), in3(n, 0);
+    Cone c;
+    auto add = [](std::vector<char>& m, std::vector<int64_t>& v, int64_t k) {
+        if (!m[k]) { m[k] = 1; v.push_back(k); }
+    };
+    if (kind < 3) {
+        add(in1, c.d1, p);
+        Cand cp = nb.of(p);
+        for (int64_t t = 0; t < cp.n; ++t) {
+            const int64_t k = cp.at(t);
+            if (separation(g, k, p).r < 2.0 * g.h[k]) add(in1, c.d1, k);
+        }
+        for (int64_t l : c.d1) {
+            add(in2, c.d2, l);
+            Cand cl = nb.of(l);
+            for (int64_t t = 0; t < cl.n; ++t) {
+                const int64_t k = cl.at(t);
+                if (separation(g, k, l).r < 2.0 * g.h[k]) add(in2, c.d2, k);
+            }
+        }
+        for (int64_t l : c.d2) {
+            add(in3, c.d3, l);
+            Cand cl = nb.of(l);
+            for (int64_t t = 0; t < cl.n; ++t) add(in3, c.d3, cl.at(t));
+        }
+    } else {
+        // velocity or u of p: only the force pass of p and its neighbours
+        add(in3, c.d3, p);
+        Cand cp = nb.of(p);
+        for (int64_t t = 0; t < cp.n; ++t) add(in3, c.d3, cp.at(t));
+    }
+    return c;
+}
+
+// Loss restricted to the cone's force set, with the cone's volumes and
+// corrections recomputed from the (possibly perturbed or dual) inputs.
+template <class T>
+T cone_loss(const Gas<T>& g, const NbrLists& nb, const Cone& c, double gamma, const double* w,
+            const double* cw, std::vector<T>& V, std::vector<T>& rho, std::vector<Corr<T>>& C) {
+    for (int64_t k : c.d1) {
+        T S = volume_sum(g, k, nb.of(k));
+        V[k] = T(1.0) / S;
+        rho[k] = T(g.m[k]) * S;
+    }
+    for (int64_t k : c.d2) {
+        Moments<T> M;
+        moments_one(g, V.data(), k, nb.of(k), M);
+        solve_corrections(M, C[k]);
+    }
+    T L = T(0.0);
+    for (int64_t i : c.d3) {
+        T a[3], du;
+        accel_one(g, V.data(), rho.data(), C.data(), gamma, i, nb.of(i), a, du);
+        L += T(w[i]) * (a[0] * a[0] + a[1] * a[1] + a[2] * a[2]) + T(cw[i]) * du;
+    }
+    return L;
 }
 
 }  // namespace
@@ -586,6 +682,97 @@ void oracle_kernel(int64_t n, const double* r, double h, double* W, double* F) {
         W[k] = kernel_W(r[k], h);
         F[k] = kernel_F(r[k], h);
     }
+}
+
+
+// dL/dtheta for ncoord coordinates: kind 0-2 = x, y, z; 3-5 = vx, vy, vz; 6 = u
+// of particle part[k].  g_dual: forward-mode dual numbers; g_fd: central
+// differences with step fd_step (absolute; positions in box units, velocities
+// as given, u relative: fd_step * u_p).
+int oracle_grad(int64_t n, const double* x, const double* y, const double* z, const double* vx,
+                const double* vy, const double* vz, const double* u, const double* h,
+                const double* m, double gamma, const double* w, const double* cw, int64_t ncoord,
+                const int64_t* part, const int32_t* kind, double fd_step, double* g_dual,
+                double* g_fd, int64_t* cone_sizes) {
+    Gas<double> g = make_gas(n, x, y, z, vx, vy, vz, u, h, m);
+    const NbrLists nb = brute_force_lists(g);
+    // baseline values over all particles (brute force through the exact lists)
+    std::vector<double> V0(n), rho0(n);
+    std::vector<Corr<double>> C0(n);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        double S = volume_sum(g, i, nb.of(i));
+        V0[i] = 1.0 / S;
+        rho0[i] = m[i] * S;
+    }
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        Moments<double> M;
+        moments_one(g, V0.data(), i, nb.of(i), M);
+        solve_corrections(M, C0[i]);
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < ncoord; ++k) {
+        const int64_t p = part[k];
+        const int kd = kind[k];
+        const Cone cone = dependency_cone(g, nb, p, kd);
+        cone_sizes[3 * k + 0] = (int64_t)cone.d1.size();
+        cone_sizes[3 * k + 1] = (int64_t)cone.d2.size();
+        cone_sizes[3 * k + 2] = (int64_t)cone.d3.size();
+        // dual numbers: every input as a constant except theta
+        {
+            std::vector<Dual> f[7];
+            const double* src[7] = {x, y, z, vx, vy, vz, u};
+            for (int a = 0; a < 7; ++a) {
+                f[a].resize(n);
+                for (int64_t i = 0; i < n; ++i) f[a][i] = Dual(src[a][i], 0.0);
+            }
+            f[kd][p].d = 1.0;
+            Gas<Dual> gd;
+            gd.n = n; gd.x = f[0].data(); gd.y = f[1].data(); gd.z = f[2].data();
+            gd.vx = f[3].data(); gd.vy = f[4].data(); gd.vz = f[5].data(); gd.u = f[6].data();
+            gd.h = h; gd.m = m;
+            std::vector<Dual> V(n), rho(n);
+            std::vector<Corr<Dual>> C(n);
+            for (int64_t i = 0; i < n; ++i) { V[i] = Dual(V0[i]); rho[i] = Dual(rho0[i]); }
+            for (int64_t i : cone.d3) {
+                C[i].A = Dual(C0[i].A);
+                for (int a = 0; a < 3; ++a) {
+                    C[i].B[a] = Dual(C0[i].B[a]);
+                    C[i].dA[a] = Dual(C0[i].dA[a]);
+                    for (int c = 0; c < 3; ++c) C[i].dB[a][c] = Dual(C0[i].dB[a][c]);
+                }
+                for (int64_t t = nb.off[i]; t < nb.off[i + 1]; ++t) {
+                    const int64_t j = nb.idx[t];
+                    C[j].A = Dual(C0[j].A);
+                    for (int a = 0; a < 3; ++a) {
+                        C[j].B[a] = Dual(C0[j].B[a]);
+                        C[j].dA[a] = Dual(C0[j].dA[a]);
+                        for (int c = 0; c < 3; ++c) C[j].dB[a][c] = Dual(C0[j].dB[a][c]);
+                    }
+                }
+            }
+            g_dual[k] = cone_loss(gd, nb, cone, gamma, w, cw, V, rho, C).d;
+        }
+        // central differences over the same cone
+        {
+            std::vector<double> f[7];
+            const double* src[7] = {x, y, z, vx, vy, vz, u};
+            for (int a = 0; a < 7; ++a) f[a].assign(src[a], src[a] + n);
+            const double step = kd == 6 ? fd_step * u[p] : fd_step;
+            double Lpm[2];
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                f[kd][p] = src[kd][p] + (sgn == 0 ? step : -step);
+                Gas<double> gp = make_gas(n, f[0].data(), f[1].data(), f[2].data(), f[3].data(),
+                                          f[4].data(), f[5].data(), f[6].data(), h, m);
+                std::vector<double> V(V0), rho(rho0);
+                std::vector<Corr<double>> C(C0);
+                Lpm[sgn] = cone_loss(gp, nb, cone, gamma, w, cw, V, rho, C);
+            }
+            g_fd[k] = (Lpm[0] - Lpm[1]) / (2.0 * step);
+        }
+    }
+    return 0;
 }
 
 }  // extern "C"

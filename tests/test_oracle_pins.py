@@ -267,3 +267,44 @@ def test_gravity_momentum_and_lattice(oracle_lib):
     al = oracle_lib.gravity(gl)
     one = lat["m"][0] / 0.01 ** 2
     assert np.abs(al).max() < 1e-12 * one
+
+
+# ---------------------------------------------------------------- gradients
+def dense_loss(g):
+    o = dense_crk.chain(g)
+    return np.sum(g["w"] * np.einsum("ia,ia->i", o["a"], o["a"])) + np.sum(g["c"] * o["dudt"])
+
+
+def test_gradient_dual_against_dense_finite_differences(oracle_lib):
+    """The oracle's dual-number gradient vs central differences of the independent dense chain."""
+    g = tiny_gas(n=300, nbr=20, seed=8)
+    rng = np.random.default_rng(4)
+    g["w"] = rng.random(g["n"])
+    g["c"] = rng.random(g["n"])
+    parts, kinds = oracle_lib.grad_coordinates(g["n"], 8, 4, 4, seed=2)
+    gd, gf, cs = oracle_lib.grad(g, parts, kinds)
+    keys = oracle_lib.COORD_KINDS
+    ref = np.empty(len(parts))
+    for k, (p, kd) in enumerate(zip(parts, kinds)):
+        key = keys[kd]
+        step = 1e-6 * (g["u"][p] if key == "u" else 1.0)
+        gp = dict(g); gm = dict(g)
+        gp[key] = g[key].copy(); gm[key] = g[key].copy()
+        gp[key][p] += step
+        gm[key][p] -= step
+        ref[k] = (dense_loss(gp) - dense_loss(gm)) / (2 * step)
+    scale = np.maximum(np.abs(ref), np.sqrt(np.mean(ref ** 2)))
+    assert np.all(np.abs(gd - ref) <= 1e-6 * scale), np.abs(gd - ref) / scale
+    assert np.all(np.abs(gf - ref) <= 1e-6 * scale)
+    assert np.all(cs[:, 2] > 0)
+
+
+def test_gradient_dual_matches_cone_finite_differences(oracle_lib):
+    g = synth.make_config("C4", n_side=16)
+    parts, kinds = oracle_lib.grad_coordinates(g["n"], 16, 8, 8)
+    gd, gf, cs = oracle_lib.grad(g, parts, kinds)
+    scale = np.maximum(np.abs(gd), np.sqrt(np.mean(gd ** 2)))
+    assert np.all(np.abs(gd - gf) <= 1e-6 * scale)
+    # cones of positions are nested: D1 inside D2 inside D3
+    pos = kinds < 3
+    assert np.all(cs[pos, 0] <= cs[pos, 1]) and np.all(cs[pos, 1] <= cs[pos, 2])
