@@ -168,6 +168,25 @@ int sr_gravity(crk_leaves* leaves, int64_t n, const double* x, const double* y, 
                crk_prec prec, void* a, hipStream_t stream);
 
 /*
+ * Adjoint of crk_accel_energy together with the corrections and volume passes
+ * it depends on (reverse mode of the chain x, v, u -> V, rho -> A, B, dA, dB ->
+ * a, du/dt; h and m held fixed; the interaction lists are those of the handle).
+ * Given ga = dL/da [3n] and gdudt = dL/d(du/dt) [n], writes gx = dL/dx [3n],
+ * gv = dL/dv [3n] and gu = dL/du [n].  V, rho and the corrections must be the
+ * ones the forward passes produced for this gas (they are reused, not
+ * recomputed; the 40 moments are recomputed per tile).  Pair terms are
+ * recomputed per tile and never stored; each particle's adjoints are
+ * accumulated by its own lane, so the result is bitwise reproducible.
+ * FP32: pair arithmetic in FP32 with compensated sums, the adjoint of the 3x3
+ * solve in FP64.  (The paper has no adjoint; this is the derivative of the
+ * passes defined above.)
+ */
+int crk_accel_energy_backward(crk_leaves* leaves, const crk_gas* gas, const void* V,
+                              const void* rho, const crk_corr* corr, double gamma, const void* ga,
+                              const void* gdudt, crk_prec prec, void* gx, void* gv, void* gu,
+                              hipStream_t stream);
+
+/*
  * Statistics of a handle (host int64[8]):
  *   [0] leaves, [1] tiles, [2] candidate pairs scanned by the list build
  *   (tile particles x candidate-leaf particles), [3] neighbour-list entries,
@@ -196,7 +215,10 @@ enum {
     CRK_K_ACCEL = 3,   /* acceleration/energy pair kernel */
     CRK_K_GRAVITY = 4, /* short-range gravity */
     CRK_K_PACK = 5,    /* per-particle packing, gathers and the totals reduction */
-    CRK_K_COUNT = 6
+    CRK_K_ACCEL_ADJ = 6,   /* force adjoint pair kernel */
+    CRK_K_MOMENTS_ADJ = 7, /* moments recompute + solve adjoint, and the moments adjoint pair kernel */
+    CRK_K_VOLUME_ADJ = 8,  /* volume adjoint pair kernel */
+    CRK_K_COUNT = 9
 };
 int crk_timing(crk_leaves* leaves, int enable);
 int crk_kernel_times(crk_leaves* leaves, double* ms, int64_t* launches);

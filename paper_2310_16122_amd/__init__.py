@@ -28,9 +28,10 @@ _STATUS = {0: "CRK_OK", -1: "CRK_EINVAL", -2: "CRK_ENOMEM", -3: "CRK_EHIP", -4: 
 
 # the C symbols declared in include/crk.h
 EXPORTS = ("crk_build_leaf_pairs", "crk_volume", "crk_corrections", "crk_accel_energy",
-           "sr_gravity", "crk_leaves_stats", "crk_get_tuning", "crk_set_tuning",
+           "sr_gravity", "crk_accel_energy_backward", "crk_leaves_stats", "crk_get_tuning", "crk_set_tuning",
            "crk_timing", "crk_kernel_times", "crk_leaves_free", "crk_last_error")
-KERNEL_KINDS = ("cull", "volume", "moments", "accel", "gravity", "pack")
+KERNEL_KINDS = ("cull", "volume", "moments", "accel", "gravity", "pack", "accel_adj",
+                "moments_adj", "volume_adj")
 
 
 class CrkError(RuntimeError):
@@ -75,6 +76,8 @@ def load_library(path=None):
     lib.crk_accel_energy.argtypes = [P, ctypes.POINTER(_Gas), P, P, ctypes.POINTER(_Corr), D, I,
                                      P, P, P, P]
     lib.sr_gravity.argtypes = [P, I64, P, P, P, P, D, D, D, P, I, P, P]
+    lib.crk_accel_energy_backward.argtypes = [P, ctypes.POINTER(_Gas), P, P, ctypes.POINTER(_Corr), D,
+                                              P, P, I, P, P, P, P]
     lib.crk_leaves_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
     lib.crk_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
     lib.crk_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
@@ -234,6 +237,54 @@ def crk_accel_energy(leaves, gas, V, rho, corr, gamma=5.0 / 3.0, prec="f32", tot
                                            ctypes.byref(c), float(gamma), _PREC[prec], _ptr(a),
                                            _ptr(du), _ptr(tot), _stream()))
     return a, du, tot
+
+
+def crk_accel_energy_backward(leaves, gas, V, rho, corr, ga, gdudt, gamma=5.0 / 3.0, prec="f32"):
+    """dL/dx [n,3], dL/dv [n,3], dL/du [n] from ga = dL/da [n,3] and gdudt = dL/d(du/dt) [n]."""
+    g = _gas(gas, prec, ("vx", "vy", "vz", "u", "h", "m"))
+    dt, dev = _DTYPE[prec], gas["x"].device
+    for t in (V, rho, *corr, ga, gdudt):
+        _dev(t, dt)
+    c = _Corr(*(t.data_ptr() for t in corr))
+    gx = torch.empty(g.n, 3, dtype=dt, device=dev)
+    gv = torch.empty(g.n, 3, dtype=dt, device=dev)
+    gu = torch.empty(g.n, dtype=dt, device=dev)
+    _check("crk_accel_energy_backward",
+           load_library().crk_accel_energy_backward(leaves.handle, ctypes.byref(g), _ptr(V), _ptr(rho),
+                                                    ctypes.byref(c), float(gamma), _ptr(ga),
+                                                    _ptr(gdudt), _PREC[prec], _ptr(gx), _ptr(gv),
+                                                    _ptr(gu), _stream()))
+    return gx, gv, gu
+
+
+class CRKAccelEnergy(torch.autograd.Function):
+    """(pos [n,3] f64, v [n,3], u [n]) -> (a [n,3], du/dt [n]) through the full chain
+    volume -> corrections -> accel/energy over the handle's interaction lists.
+
+    h and m are constants.  Backward calls crk_accel_energy_backward (the
+    hand-written adjoint); the position gradient is returned in FP64.
+    """
+
+    @staticmethod
+    def forward(ctx, pos, v, u, leaves, h, m, gamma=5.0 / 3.0, prec="f32"):
+        gas = {"x": pos[:, 0].contiguous(), "y": pos[:, 1].contiguous(), "z": pos[:, 2].contiguous(),
+               "vx": v[:, 0].contiguous(), "vy": v[:, 1].contiguous(), "vz": v[:, 2].contiguous(),
+               "u": u.contiguous(), "h": h, "m": m}
+        out = forward(leaves, gas, gamma, prec)
+        ctx.leaves, ctx.gamma, ctx.prec = leaves, gamma, prec
+        ctx.gas = gas
+        ctx.save_for_backward(out["V"], out["rho"], out["A"], out["B"], out["dA"], out["dB"])
+        return out["a"], out["dudt"]
+
+    @staticmethod
+    def backward(ctx, ga, gdu):
+        V, rho, A, B, dA, dB = ctx.saved_tensors
+        dt = _DTYPE[ctx.prec]
+        ga = torch.zeros_like(A.new_empty(A.shape[0], 3)) if ga is None else ga.to(dt).contiguous()
+        gdu = torch.zeros_like(A) if gdu is None else gdu.to(dt).contiguous()
+        gx, gv, gu = crk_accel_energy_backward(ctx.leaves, ctx.gas, V, rho, (A, B, dA, dB), ga, gdu,
+                                               ctx.gamma, ctx.prec)
+        return gx.double(), gv, gu, None, None, None, None, None
 
 
 def sr_gravity(leaves, x, y, z, m, G=1.0, eps=0.0, r_cut=None, poly=None, prec="f32"):

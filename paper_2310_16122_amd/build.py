@@ -1,6 +1,7 @@
 """Compile the gfx950 HIP library ``libcrk.so`` in-tree.
 
-hipcc builds the kernels and the C ABI (``csrc/crk.hip``); g++ builds the
+hipcc builds the kernels and the C ABI (``csrc/crk.hip``, ``csrc/crk_backward.hip``);
+g++ builds the
 host tree (``csrc/tree.cpp``, OpenMP).  Packed FP32 instructions are switched
 off for all device code.
 """
@@ -33,13 +34,16 @@ def _run(cmd, verbose):
 def build(verbose=False):
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    obj_hip = os.path.join(bdir, "crk.o")
+    objs = []
+    for name in ("crk", "crk_backward"):
+        obj = os.path.join(bdir, name + ".o")
+        _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, name + ".hip"), "-o", obj], verbose)
+        objs.append(obj)
     obj_tree = os.path.join(bdir, "tree.o")
-    _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "crk.hip"), "-o", obj_hip], verbose)
     _run(["g++", "-std=c++17", "-O3", "-fopenmp", "-fPIC", "-I", CSRC, "-c",
           os.path.join(CSRC, "tree.cpp"), "-o", obj_tree], verbose)
     tmp = LIB + ".tmp%d" % os.getpid()
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, obj_hip, obj_tree,
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, obj_tree,
           "-lgomp"], verbose)
     os.replace(tmp, LIB)
     return LIB

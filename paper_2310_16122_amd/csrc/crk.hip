@@ -248,68 +248,8 @@ __global__ __launch_bounds__(256) void k_volume(Queue qu, int n, Lists L, const 
 
 // ------------------------------------------------------------------ corrections
 
-// FP64 per-particle solve of the reproducing conditions from the 40 moments
-// (m0, m1[3], m2[6] (xx xy xz yy yz zz), g0[3], g1[9] (a-major), g2[18]
-// ((ab) in m2 order, c fastest)).  Returns 1 for the zeroth-order fallback.
-__device__ int solve_moments(const double* M, int nnb, double& A, double B[3], double dA[3],
-                             double dB[9]) {
-    const double m0 = M[0];
-    const double* m1 = M + 1;
-    const double* s = M + 4;
-    const double* g0 = M + 10;
-    const double* g1 = M + 13;
-    const double* g2 = M + 22;
-    // symmetric m2 and its adjugate
-    const double a11 = s[0], a12 = s[1], a13 = s[2], a22 = s[3], a23 = s[4], a33 = s[5];
-    const double i11 = a22 * a33 - a23 * a23;
-    const double i12 = a13 * a23 - a12 * a33;
-    const double i13 = a12 * a23 - a13 * a22;
-    const double i22 = a11 * a33 - a13 * a13;
-    const double i23 = a12 * a13 - a11 * a23;
-    const double i33 = a11 * a22 - a12 * a12;
-    const double det = a11 * i11 + a12 * i12 + a13 * i13;
-    const double tr = (a11 + a22 + a33) / 3.0;
-    if (nnb < 4 || !(det > 1e-12 * tr * tr * tr)) {
-        A = 1.0 / m0;
-        for (int c = 0; c < 3; ++c) {
-            B[c] = 0.0;
-            dA[c] = -g0[c] / (m0 * m0);
-        }
-        for (int k = 0; k < 9; ++k) dB[k] = 0.0;
-        return 1;
-    }
-    const double rd = 1.0 / det;
-    const double inv[3][3] = {{i11 * rd, i12 * rd, i13 * rd},
-                              {i12 * rd, i22 * rd, i23 * rd},
-                              {i13 * rd, i23 * rd, i33 * rd}};
-    for (int a = 0; a < 3; ++a)
-        B[a] = -(inv[a][0] * m1[0] + inv[a][1] * m1[1] + inv[a][2] * m1[2]);
-    A = 1.0 / (m0 + B[0] * m1[0] + B[1] * m1[1] + B[2] * m1[2]);
-    const int sym[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
-    for (int c = 0; c < 3; ++c) {
-        double rhs[3];
-        for (int a = 0; a < 3; ++a) {
-            double t = g1[3 * a + c];
-            for (int b = 0; b < 3; ++b) t += g2[3 * sym[a][b] + c] * B[b];
-            rhs[a] = t;
-        }
-        double gA = g0[c];
-        for (int a = 0; a < 3; ++a) {
-            const double d = -(inv[a][0] * rhs[0] + inv[a][1] * rhs[1] + inv[a][2] * rhs[2]);
-            dB[3 * a + c] = d;
-            gA += B[a] * g1[3 * a + c] + m1[a] * d;
-        }
-        dA[c] = -A * A * gA;
-    }
-    return 0;
-}
-
-// Moments over the neighbour list (j = i added analytically), then the FP64
-// solve.  Accumulated per pair (w = cW w(q) V_j, f = cF f(q) V_j, x = x_ij):
-//   m0 += w, m1^a += x^a w, m2^ab += x^a x^b w, g0^c += f x^c,
-//   t1^ac += x^a f x^c, t2^abc += x^a x^b f x^c
-// and at the end g1^ac = delta^ac m0 + t1^ac, g2^abc = delta^ac m1^b + delta^bc m1^a + t2^abc.
-// FP32: plain sums over `chunk` pairs, folded into compensated sums.
+// Moments over the neighbour list and the FP64 solve; corrections written in
+// caller order.
 template <class R>
 __global__ __launch_bounds__(256) void k_moments(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
                                                  const uint4* __restrict__ quant, const R* __restrict__ Vs,
@@ -317,7 +257,6 @@ __global__ __launch_bounds__(256) void k_moments(Queue qu, int n, Lists L, const
                                                  R* __restrict__ B_out, R* __restrict__ dA_out,
                                                  R* __restrict__ dB_out,
                                                  unsigned long long* __restrict__ n_fallback) {
-    constexpr bool kComp = sizeof(R) == 4;
     const int lane = lane_id();
     const int wave = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     for (int it = first_item(qu, wave); it < qu.n_items; it = next_item(qu, it, 0)) {
@@ -325,88 +264,20 @@ __global__ __launch_bounds__(256) void k_moments(Queue qu, int n, Lists L, const
         const int s = w * kWave + lane;
         const bool valid = s < n;
         const int i = valid ? perm[s] : 0;
-        const uint4 qi = valid ? quant[s] : make_uint4(0, 0, 0, 0);
         const R H = valid ? R(2) * h[i] : R(1);
-        const R invH = R(1) / H;
-        const R cW = norm_W(H), cF = norm_F(H);
-        const int cnt = valid ? L.cnt[s] : 0;
-        const int len = L.len[w];
-        const uint32_t* lst = L.nbr + L.off[w] + lane;
-        R p[40], sm[40], cm[40];
-#pragma unroll
-        for (int e = 0; e < 40; ++e) { p[e] = R(0); sm[e] = R(0); cm[e] = R(0); }
-        int nnb = 0, kk = 0;
-        for (int k = 0; k < len; ++k) {
-            if (k < cnt) {
-                const uint32_t j = lst[int64_t(k) * kWave];
-                const uint4 qj = quant[j];
-                const R Vj = Vs[j];
-                const R x[3] = {sep<R>(qi.x, qj.x), sep<R>(qi.y, qj.y), sep<R>(qi.z, qj.z)};
-                const R r = dsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
-                const R q = r * invH;
-                R wq, fq;
-                wendland(q, wq, fq);
-                nnb += q < R(1);
-                const R wv = cW * wq * Vj;
-                const R fv = cF * fq * Vj;
-                const R fx[3] = {fv * x[0], fv * x[1], fv * x[2]};
-                R xx[6];
-                xx[0] = x[0] * x[0]; xx[1] = x[0] * x[1]; xx[2] = x[0] * x[2];
-                xx[3] = x[1] * x[1]; xx[4] = x[1] * x[2]; xx[5] = x[2] * x[2];
-                p[0] += wv;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) p[1 + a] += x[a] * wv;
-#pragma unroll
-                for (int e = 0; e < 6; ++e) p[4 + e] += xx[e] * wv;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) p[10 + c] += fx[c];
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) p[13 + 3 * a + c] += x[a] * fx[c];
-#pragma unroll
-                for (int e = 0; e < 6; ++e)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) p[22 + 3 * e + c] += xx[e] * fx[c];
-            }
-            if (kComp && ++kk == chunk) {
-#pragma unroll
-                for (int e = 0; e < 40; ++e) { kadd(sm[e], cm[e], p[e]); p[e] = R(0); }
-                kk = 0;
-            }
-        }
-        if (valid) {
         double M[40];
-        const R Vi = Vs[s];
-#pragma unroll
-        for (int e = 0; e < 40; ++e) {
-            if (kComp) {
-                kadd(sm[e], cm[e], p[e]);
-                M[e] = double(sm[e]) - double(cm[e]);
-            } else {
-                M[e] = double(p[e]);
+        int nnb = 0;
+        moment_sums<R>(w, s, valid, L, quant, Vs, H, chunk, M, nnb);
+        if (valid) {
+            double Ad, Bd[3], dAd[3], dBd[9];
+            const int fb = solve_moments(M, nnb, Ad, Bd, dAd, dBd);
+            A_out[i] = R(Ad);
+            for (int a = 0; a < 3; ++a) {
+                B_out[3 * i + a] = R(Bd[a]);
+                dA_out[3 * i + a] = R(dAd[a]);
             }
-        }
-        M[0] += double(cW) * double(Vi);  // j = i
-        const int sym[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
-        for (int a = 0; a < 3; ++a) M[13 + 3 * a + a] += M[0];
-        for (int a = 0; a < 3; ++a)
-            for (int b = a; b < 3; ++b)
-                for (int c = 0; c < 3; ++c) {
-                    double t = 0.0;
-                    if (a == c) t += M[1 + b];
-                    if (b == c) t += M[1 + a];
-                    M[22 + 3 * sym[a][b] + c] += t;
-                }
-        double Ad, Bd[3], dAd[3], dBd[9];
-        const int fb = solve_moments(M, nnb, Ad, Bd, dAd, dBd);
-        A_out[i] = R(Ad);
-        for (int a = 0; a < 3; ++a) {
-            B_out[3 * i + a] = R(Bd[a]);
-            dA_out[3 * i + a] = R(dAd[a]);
-        }
-        for (int k = 0; k < 9; ++k) dB_out[9 * i + k] = R(dBd[k]);
-        if (n_fallback && fb) atomicAdd(n_fallback, 1ull);
+            for (int k = 0; k < 9; ++k) dB_out[9 * i + k] = R(dBd[k]);
+            if (n_fallback && fb) atomicAdd(n_fallback, 1ull);
         }
     }
 }

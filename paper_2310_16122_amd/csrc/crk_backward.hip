@@ -1,0 +1,640 @@
+// Adjoint of the acceleration/energy pass and of the corrections and volume
+// passes it depends on (reverse mode, gather form, per-tile recomputation).
+//
+// Given the upstream adjoints abar_i = dL/da_i and dubar_i = dL/d(du_i/dt),
+// the gradients of L with respect to positions, velocities and internal
+// energies are produced by four list-driven pair passes and two per-particle
+// steps, with no pair quantity stored:
+//
+//  1. force adjoint (pairs): recompute F_ij, then with
+//       Fbar_ij = abar_i/m_i - abar_j/m_j - (dubar_i/2m_i + dubar_j/2m_j)(v_i - v_j)
+//     accumulate, for the lane's own particle only, vbar, Vbar, Pbar, the
+//     adjoint of its corrections (A, B, dA, dB) through G_ij and xbar through
+//     both G_ij and G_ji;
+//  2. corrections adjoint (per particle, FP64): recompute the 40 moments with
+//     the forward's arithmetic, then reverse the 3x3 solve -> Mbar;
+//  3. moments adjoint (pairs): M_k = sum_j V_j phi(x_kj, h_k) gives xbar and
+//     Vbar from the lane's own moments and from every neighbour whose moments
+//     contain the lane's particle; then per particle Sbar = -Vbar V^2 + m rhobar
+//     with rhobar = (gamma-1) u Pbar, and ubar = (gamma-1) rho Pbar;
+//  4. volume adjoint (pairs): S_k = sum_j W(r_kj, h_k) gives xbar.
+//
+// Each lane accumulates only its own particle's adjoints, so no atomics are
+// used and the result is bitwise reproducible.  FP32 path: pair arithmetic in
+// FP32 with compensated sums; the solve adjoint in FP64.
+
+#include <cstdio>
+
+#include "crk_internal.h"
+
+using namespace crk;
+
+namespace {
+
+// Per-particle record of the backward passes (unnormalised corrections;
+// cW, cF, cF2 are the kernel, gradient and Hessian normalisations of h_i).
+template <class R> struct alignas(128) RecBwd {
+    uint32_t q[3];
+    R invH;
+    R V, P, A, dubar;  // dubar = (dL/d du_i) / (2 m_i)
+    R cW, cF, cF2;
+    R B[3], dA[3], dB[9], v[3];
+    R abar[3];  // (dL/d a_i) / m_i
+};
+static_assert(sizeof(RecBwd<float>) == 128, "f32 backward record is one line");
+static_assert(sizeof(RecBwd<double>) == 256, "f64 backward record is two lines");
+
+template <class R, int N> struct Sums {
+    R s[N], c[N];
+    __device__ void zero() {
+#pragma unroll
+        for (int e = 0; e < N; ++e) { s[e] = R(0); c[e] = R(0); }
+    }
+    __device__ void add(int e, R t) {
+        if (sizeof(R) == 4) kadd(s[e], c[e], t);
+        else s[e] += t;
+    }
+    __device__ R get(int e) const { return s[e] - c[e]; }
+    __device__ double getd(int e) const { return double(s[e]) - double(c[e]); }
+};
+
+// Wendland C4 shapes and the Hessian factor: W = cW w, grad W = cF f x,
+// grad (cF f) = cF2 f2 x.
+template <class R> __device__ __forceinline__ void shapes(R q, R& w, R& f, R& f2) {
+    const R t = fmax(R(1) - q, R(0));
+    const R t2 = t * t;
+    f2 = t2 * t2;
+    const R t5 = f2 * t;
+    w = t5 * t * (R(1) + q * (R(6) + q * R(35.0 / 3.0)));
+    f = t5 * (R(1) + R(5) * q);
+}
+
+// G^c = dA^c lin W + A (sum_a dB[a][c] y^a + B^c) W + A lin F y^c, lin = 1 + B.y
+template <class R>
+__device__ __forceinline__ void corr_grad(const RecBwd<R>& r, R W, R F, const R y[3], R G[3]) {
+    const R lin = R(1) + r.B[0] * y[0] + r.B[1] * y[1] + r.B[2] * y[2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const R t = r.dB[c] * y[0] + r.dB[3 + c] * y[1] + r.dB[6 + c] * y[2] + r.B[c];
+        G[c] = r.dA[c] * lin * W + r.A * t * W + r.A * lin * F * y[c];
+    }
+}
+
+// out += (dG/dy)^T g
+template <class R>
+__device__ __forceinline__ void corr_grad_dy(const RecBwd<R>& r, R W, R F, R F2, const R y[3],
+                                             const R g[3], R out[3]) {
+    const R lin = R(1) + r.B[0] * y[0] + r.B[1] * y[1] + r.B[2] * y[2];
+    const R al = g[0] * r.dA[0] + g[1] * r.dA[1] + g[2] * r.dA[2];
+    R be = R(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        be += g[c] * (r.dB[c] * y[0] + r.dB[3 + c] * y[1] + r.dB[6 + c] * y[2] + r.B[c]);
+    const R ga = g[0] * y[0] + g[1] * y[1] + g[2] * y[2];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const R dBg = r.dB[3 * e] * g[0] + r.dB[3 * e + 1] * g[1] + r.dB[3 * e + 2] * g[2];
+        out[e] += al * (r.B[e] * W + lin * F * y[e]) + r.A * dBg * W + r.A * be * F * y[e] +
+                  r.A * r.B[e] * F * ga + r.A * lin * F2 * y[e] * ga + r.A * lin * F * g[e];
+    }
+}
+
+// adjoint of G with respect to (A, B, dA, dB), given g = Gbar
+template <class R, int N>
+__device__ __forceinline__ void corr_grad_dC(const RecBwd<R>& r, R W, R F, const R y[3], const R g[3],
+                                             Sums<R, N>& acc) {
+    const R lin = R(1) + r.B[0] * y[0] + r.B[1] * y[1] + r.B[2] * y[2];
+    const R al = g[0] * r.dA[0] + g[1] * r.dA[1] + g[2] * r.dA[2];
+    R be = R(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        be += g[c] * (r.dB[c] * y[0] + r.dB[3 + c] * y[1] + r.dB[6 + c] * y[2] + r.B[c]);
+    const R ga = g[0] * y[0] + g[1] * y[1] + g[2] * y[2];
+    acc.add(0, be * W + lin * F * ga);                                    // A
+#pragma unroll
+    for (int e = 0; e < 3; ++e) acc.add(1 + e, al * y[e] * W + r.A * g[e] * W + r.A * F * ga * y[e]);  // B
+#pragma unroll
+    for (int d = 0; d < 3; ++d) acc.add(4 + d, g[d] * lin * W);          // dA
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) acc.add(7 + 3 * a + d, g[d] * r.A * y[a] * W);  // dB[a][d]
+}
+
+template <class R>
+__global__ void k_pack_bwd(int n, const int32_t* perm, const uint4* quant, const R* h, const R* u,
+                           const R* vx, const R* vy, const R* vz, const R* m, const R* V,
+                           const R* rho, const R* A, const R* B, const R* dA, const R* dB,
+                           const R* ga, const R* gdu, R gm1, RecBwd<R>* rec, R* aux) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int i = perm[s];
+    RecBwd<R> r;
+    const uint4 q = quant[s];
+    r.q[0] = q.x; r.q[1] = q.y; r.q[2] = q.z;
+    const R H = R(2) * h[i];
+    const R invH = R(1) / H;
+    r.invH = invH;
+    r.V = V[i];
+    r.P = gm1 * rho[i] * u[i];
+    r.A = A[i];
+    const R mi = m[i];
+    r.dubar = gdu[i] / (R(2) * mi);
+    r.cW = norm_W(H);
+    r.cF = norm_F(H);
+    const R i2 = invH * invH;
+    r.cF2 = R(17325.0 / (2.0 * kPi)) * i2 * i2 * i2 * invH;
+    for (int a = 0; a < 3; ++a) {
+        r.B[a] = B[3 * i + a];
+        r.dA[a] = dA[3 * i + a];
+        r.abar[a] = ga[3 * i + a] / mi;
+    }
+    for (int k = 0; k < 9; ++k) r.dB[k] = dB[9 * i + k];
+    r.v[0] = vx[i]; r.v[1] = vy[i]; r.v[2] = vz[i];
+    rec[s] = r;
+    aux[2 * s] = invH;
+    aux[2 * s + 1] = r.V;
+}
+
+// 1. force adjoint
+template <class R>
+__global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
+                                                   const RecBwd<R>* __restrict__ rec, R* __restrict__ cbar,
+                                                   R* __restrict__ vpbar, R* __restrict__ xbar,
+                                                   R* __restrict__ gv) {
+    const int lane = lane_id();
+    const int wave = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    for (int it = first_item(qu, wave); it < qu.n_items; it = next_item(qu, it, 0)) {
+        const int w = qu.order[it];
+        const int s = w * kWave + lane;
+        const bool valid = s < n;
+        const RecBwd<R> ri = rec[valid ? s : 0];
+        const int cnt = valid ? L.cnt[s] : 0;
+        const int len = L.len[w];
+        const uint32_t* lst = L.nbr + L.off[w] + lane;
+        Sums<R, 16> cb;  // A, B[3], dA[3], dB[9]
+        Sums<R, 8> ob;   // Vbar, Pbar, xbar[3], vbar[3]
+        cb.zero();
+        ob.zero();
+        for (int k = 0; k < len; ++k) {
+            if (k < cnt) {
+                const RecBwd<R> rj = rec[lst[int64_t(k) * kWave]];
+                const R x[3] = {sep<R>(ri.q[0], rj.q[0]), sep<R>(ri.q[1], rj.q[1]), sep<R>(ri.q[2], rj.q[2])};
+                const R y[3] = {-x[0], -x[1], -x[2]};
+                const R r = dsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+                R wi, fi, f2i, wj, fj, f2j;
+                shapes(r * ri.invH, wi, fi, f2i);
+                shapes(r * rj.invH, wj, fj, f2j);
+                const R Wi = ri.cW * wi, Fi = ri.cF * fi, F2i = ri.cF2 * f2i;
+                const R Wj = rj.cW * wj, Fj = rj.cF * fj, F2j = rj.cF2 * f2j;
+                R Gi[3], Gj[3];
+                corr_grad(ri, Wi, Fi, x, Gi);
+                corr_grad(rj, Wj, Fj, y, Gj);
+                const R D[3] = {Gi[0] - Gj[0], Gi[1] - Gj[1], Gi[2] - Gj[2]};
+                const R VV = ri.V * rj.V, PP = ri.P + rj.P;
+                const R coef = R(-0.5) * (VV * PP);
+                const R kap = ri.dubar + rj.dubar;
+                R Fb[3], s_ = R(0);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const R vij = ri.v[c] - rj.v[c];
+                    Fb[c] = ri.abar[c] - rj.abar[c] - kap * vij;
+                    s_ += Fb[c] * D[c];
+                    ob.add(5 + c, -kap * coef * D[c]);  // vbar_i
+                }
+                ob.add(0, R(-0.5) * rj.V * PP * s_);  // Vbar_i
+                ob.add(1, R(-0.5) * VV * s_);         // Pbar_i
+                const R g[3] = {coef * Fb[0], coef * Fb[1], coef * Fb[2]};
+                corr_grad_dC(ri, Wi, Fi, x, g, cb);
+                R xb[3] = {R(0), R(0), R(0)};
+                corr_grad_dy(ri, Wi, Fi, F2i, x, g, xb);
+                corr_grad_dy(rj, Wj, Fj, F2j, y, g, xb);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) ob.add(2 + c, xb[c]);
+            }
+        }
+        if (valid) {
+            const int i = perm[s];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) cbar[16 * s + e] = cb.get(e);
+            vpbar[2 * s] = ob.get(0);
+            vpbar[2 * s + 1] = ob.get(1);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                xbar[4 * s + c] = ob.get(2 + c);
+                gv[3 * i + c] = ob.get(5 + c);
+            }
+        }
+    }
+}
+
+// Reverse of the FP64 solve (solve_moments) for one particle: corrections
+// adjoint Cb (A, B[3], dA[3], dB[9]) -> moments adjoint Mb[40] (storage order).
+__device__ inline void solve_moments_adjoint(const double* M, int nnb, const double* Cb, double* Mb) {
+    for (int e = 0; e < 40; ++e) Mb[e] = 0.0;
+    const double m0 = M[0];
+    const double* m1 = M + 1;
+    const double* sm = M + 4;
+    const double* g0 = M + 10;
+    const double* g1 = M + 13;
+    const double* g2 = M + 22;
+    const double a11 = sm[0], a12 = sm[1], a13 = sm[2], a22 = sm[3], a23 = sm[4], a33 = sm[5];
+    const double i11 = a22 * a33 - a23 * a23;
+    const double i12 = a13 * a23 - a12 * a33;
+    const double i13 = a12 * a23 - a13 * a22;
+    const double i22 = a11 * a33 - a13 * a13;
+    const double i23 = a12 * a13 - a11 * a23;
+    const double i33 = a11 * a22 - a12 * a12;
+    const double det = a11 * i11 + a12 * i12 + a13 * i13;
+    const double tr = (a11 + a22 + a33) / 3.0;
+    if (nnb < 4 || !(det > 1e-12 * tr * tr * tr)) {
+        // A = 1/m0, dA = -g0/m0^2
+        double mb = -Cb[0] / (m0 * m0);
+        for (int c = 0; c < 3; ++c) {
+            mb += Cb[4 + c] * 2.0 * g0[c] / (m0 * m0 * m0);
+            Mb[10 + c] = -Cb[4 + c] / (m0 * m0);
+        }
+        Mb[0] = mb;
+        return;
+    }
+    const double rd = 1.0 / det;
+    const double inv[3][3] = {{i11 * rd, i12 * rd, i13 * rd},
+                              {i12 * rd, i22 * rd, i23 * rd},
+                              {i13 * rd, i23 * rd, i33 * rd}};
+    const int sym[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+    double B[3];
+    for (int a = 0; a < 3; ++a) B[a] = -(inv[a][0] * m1[0] + inv[a][1] * m1[1] + inv[a][2] * m1[2]);
+    const double A = 1.0 / (m0 + B[0] * m1[0] + B[1] * m1[1] + B[2] * m1[2]);
+    double Ab = Cb[0];
+    double Bb[3] = {Cb[1], Cb[2], Cb[3]};
+    double m0b = 0.0, m1b[3] = {0, 0, 0}, g0b[3] = {0, 0, 0};
+    double g1b[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double g2b[3][3][3];
+    double invb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            for (int c = 0; c < 3; ++c) g2b[a][b][c] = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        double rhs[3], dB[3];
+        for (int a = 0; a < 3; ++a) {
+            double t = g1[3 * a + c];
+            for (int b = 0; b < 3; ++b) t += g2[3 * sym[a][b] + c] * B[b];
+            rhs[a] = t;
+        }
+        double tc = g0[c];
+        for (int a = 0; a < 3; ++a) {
+            dB[a] = -(inv[a][0] * rhs[0] + inv[a][1] * rhs[1] + inv[a][2] * rhs[2]);
+            tc += B[a] * g1[3 * a + c] + m1[a] * dB[a];
+        }
+        // dA_c = -A^2 tc
+        const double dAb = Cb[4 + c];
+        const double tb = -A * A * dAb;
+        Ab += -2.0 * A * tc * dAb;
+        g0b[c] += tb;
+        double dBb[3];
+        for (int a = 0; a < 3; ++a) {
+            Bb[a] += tb * g1[3 * a + c];
+            g1b[a][c] += tb * B[a];
+            m1b[a] += tb * dB[a];
+            dBb[a] = Cb[7 + 3 * a + c] + tb * m1[a];
+        }
+        // dB[.,c] = -inv rhs
+        double rb[3];
+        for (int b = 0; b < 3; ++b) rb[b] = -(inv[0][b] * dBb[0] + inv[1][b] * dBb[1] + inv[2][b] * dBb[2]);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) invb[a][b] += -dBb[a] * rhs[b];
+        // rhs = g1[.,c] + g2[.,.,c] B
+        for (int a = 0; a < 3; ++a) {
+            g1b[a][c] += rb[a];
+            for (int b = 0; b < 3; ++b) {
+                g2b[a][b][c] += rb[a] * B[b];
+                Bb[b] += g2[3 * sym[a][b] + c] * rb[a];
+            }
+        }
+    }
+    // A = 1/den, den = m0 + B.m1
+    const double denb = -A * A * Ab;
+    m0b += denb;
+    for (int a = 0; a < 3; ++a) {
+        Bb[a] += denb * m1[a];
+        m1b[a] += denb * B[a];
+    }
+    // B = -inv m1
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) invb[a][b] += -Bb[a] * m1[b];
+    for (int b = 0; b < 3; ++b) m1b[b] += -(inv[0][b] * Bb[0] + inv[1][b] * Bb[1] + inv[2][b] * Bb[2]);
+    // inv = m2^-1: m2b = -inv invb inv
+    double t[3][3], m2b[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) t[a][b] = invb[a][0] * inv[0][b] + invb[a][1] * inv[1][b] + invb[a][2] * inv[2][b];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) m2b[a][b] = -(inv[a][0] * t[0][b] + inv[a][1] * t[1][b] + inv[a][2] * t[2][b]);
+    Mb[0] = m0b;
+    for (int a = 0; a < 3; ++a) {
+        Mb[1 + a] = m1b[a];
+        Mb[10 + a] = g0b[a];
+        for (int c = 0; c < 3; ++c) Mb[13 + 3 * a + c] = g1b[a][c];
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int b = a; b < 3; ++b) {
+            const int p = sym[a][b];
+            Mb[4 + p] = a == b ? m2b[a][a] : m2b[a][b] + m2b[b][a];
+            for (int c = 0; c < 3; ++c)
+                Mb[22 + 3 * p + c] = a == b ? g2b[a][a][c] : g2b[a][b][c] + g2b[b][a][c];
+        }
+}
+
+// 2. moments recomputed with the forward's arithmetic, then the solve adjoint
+template <class R>
+__global__ __launch_bounds__(256) void k_moments_bwd(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
+                                                     const uint4* __restrict__ quant, const R* __restrict__ aux,
+                                                     const R* __restrict__ Vs, const R* __restrict__ h, int chunk,
+                                                     const R* __restrict__ cbar, R* __restrict__ mbar) {
+    const int lane = lane_id();
+    const int wave = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    for (int it = first_item(qu, wave); it < qu.n_items; it = next_item(qu, it, 0)) {
+        const int w = qu.order[it];
+        const int s = w * kWave + lane;
+        const bool valid = s < n;
+        const int i = valid ? perm[s] : 0;
+        const R H = valid ? R(2) * h[i] : R(1);
+        double M[40];
+        int nnb = 0;
+        moment_sums<R>(w, s, valid, L, quant, Vs, H, chunk, M, nnb);
+        if (valid) {
+            double Cb[16], Mb[40];
+            for (int e = 0; e < 16; ++e) Cb[e] = double(cbar[16 * s + e]);
+            solve_moments_adjoint(M, nnb, Cb, Mb);
+            for (int e = 0; e < 40; ++e) mbar[40 * s + e] = R(Mb[e]);
+        }
+    }
+}
+
+// Phi(y) = Mbar . phi(y) for the 40 moment kernels phi of a particle with
+// kernel values W, F (grad W = F y) and F2 (grad F = F2 y), and its gradient:
+//   Phi = W P(y) + F Q(y),  grad Phi = W grad P + F grad Q + (P F + Q F2) y
+// with P = mu0 + tr(g1b) + (mu1 + nu).y + sum_p mu2[p] y^a y^b,
+//      Q = g0b.y + y.g1b.y + sum_{p,c} g2b[p][c] y^a y^b y^c.
+template <class R>
+__device__ __forceinline__ void moment_phi(const R* Mb, R W, R F, R F2, const R y[3], R& Phi, R grad[3]) {
+    const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {0, 1, 2, 1, 2, 2};
+    const R* mu1 = Mb + 1;
+    const R* mu2 = Mb + 4;
+    const R* c0 = Mb + 10;
+    const R* c1 = Mb + 13;
+    const R* c2 = Mb + 22;
+    R nu[3] = {R(0), R(0), R(0)};
+    R Y2[6], T[6];
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        nu[pb[p]] += c2[3 * p + pa[p]];
+        nu[pa[p]] += c2[3 * p + pb[p]];
+        Y2[p] = y[pa[p]] * y[pb[p]];
+        T[p] = c2[3 * p] * y[0] + c2[3 * p + 1] * y[1] + c2[3 * p + 2] * y[2];
+    }
+    R P = Mb[0] + c1[0] + c1[4] + c1[8];
+    R Q = R(0);
+    R gP[3], gQ[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        P += (mu1[e] + nu[e]) * y[e];
+        Q += c0[e] * y[e];
+        gP[e] = mu1[e] + nu[e];
+        gQ[e] = c0[e];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Q += c1[3 * a + c] * y[a] * y[c];
+            gQ[a] += c1[3 * a + c] * y[c];
+            gQ[c] += c1[3 * a + c] * y[a];
+        }
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        P += mu2[p] * Y2[p];
+        Q += T[p] * Y2[p];
+        gP[pa[p]] += mu2[p] * y[pb[p]];
+        gP[pb[p]] += mu2[p] * y[pa[p]];
+        gQ[pa[p]] += T[p] * y[pb[p]];
+        gQ[pb[p]] += T[p] * y[pa[p]];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) gQ[e] += c2[3 * p + e] * Y2[p];
+    }
+    Phi = W * P + F * Q;
+    const R radial = P * F + Q * F2;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) grad[e] = W * gP[e] + F * gQ[e] + radial * y[e];
+}
+
+// 3. moments adjoint, then the per-particle volume/pressure adjoints
+template <class R>
+__global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
+                                                     const uint4* __restrict__ quant, const R* __restrict__ aux,
+                                                     const R* __restrict__ mbar, const R* __restrict__ vpbar,
+                                                     const R* __restrict__ m, const R* __restrict__ u,
+                                                     const R* __restrict__ rho, R gm1, R* __restrict__ xbar,
+                                                     R* __restrict__ sbar, R* __restrict__ gu) {
+    const int lane = lane_id();
+    const int wave = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    for (int it = first_item(qu, wave); it < qu.n_items; it = next_item(qu, it, 0)) {
+        const int w = qu.order[it];
+        const int s = w * kWave + lane;
+        const bool valid = s < n;
+        const int so = valid ? s : 0;
+        const uint4 qi = quant[so];
+        const R invHi = aux[2 * so], Vi = aux[2 * so + 1];
+        const R i2 = invHi * invHi;
+        const R cWi = R(495.0 / (32.0 * kPi)) * i2 * invHi;
+        const R cFi = R(-1155.0 / (4.0 * kPi)) * i2 * i2 * invHi;
+        const R cF2i = R(17325.0 / (2.0 * kPi)) * i2 * i2 * i2 * invHi;
+        R Mi[40];
+#pragma unroll
+        for (int e = 0; e < 40; ++e) Mi[e] = mbar[40 * so + e];
+        const int cnt = valid ? L.cnt[s] : 0;
+        const int len = L.len[w];
+        const uint32_t* lst = L.nbr + L.off[w] + lane;
+        Sums<R, 4> acc;  // Vbar, xbar[3]
+        acc.zero();
+        for (int k = 0; k < len; ++k) {
+            if (k < cnt) {
+                const uint32_t j = lst[int64_t(k) * kWave];
+                const uint4 qj = quant[j];
+                const R invHj = aux[2 * j], Vj = aux[2 * j + 1];
+                R Mj[40];
+#pragma unroll
+                for (int e = 0; e < 40; ++e) Mj[e] = mbar[40 * j + e];
+                const R x[3] = {sep<R>(qi.x, qj.x), sep<R>(qi.y, qj.y), sep<R>(qi.z, qj.z)};
+                const R y[3] = {-x[0], -x[1], -x[2]};
+                const R r = dsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+                R w_, f_, f2_;
+                // own moments: M_i contains V_j phi(x_ij, h_i)
+                shapes(r * invHi, w_, f_, f2_);
+                R Phi, g[3];
+                moment_phi(Mi, cWi * w_, cFi * f_, cF2i * f2_, x, Phi, g);
+                R xb[3] = {Vj * g[0], Vj * g[1], Vj * g[2]};
+                // the neighbour's moments contain V_i phi(x_ji, h_j)
+                const R j2 = invHj * invHj;
+                shapes(r * invHj, w_, f_, f2_);
+                moment_phi(Mj, R(495.0 / (32.0 * kPi)) * j2 * invHj * w_,
+                           R(-1155.0 / (4.0 * kPi)) * j2 * j2 * invHj * f_,
+                           R(17325.0 / (2.0 * kPi)) * j2 * j2 * j2 * invHj * f2_, y, Phi, g);
+                acc.add(0, Phi);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc.add(1 + c, xb[c] - Vi * g[c]);
+            }
+        }
+        if (valid) {
+            const int i = perm[s];
+            // j = i term of the own moments: V_i phi(0) = V_i W(0) (m0 and the g1 diagonal)
+            const double Vbar = double(acc.get(0)) + double(cWi) * (double(Mi[0]) + Mi[13] + Mi[17] + Mi[21]) +
+                                double(vpbar[2 * s]);
+            const double Pbar = double(vpbar[2 * s + 1]);
+            const double rhobar = double(gm1) * double(u[i]) * Pbar;
+            const double Sbar = -Vbar * double(Vi) * double(Vi) + double(m[i]) * rhobar;
+            sbar[s] = R(Sbar);
+            gu[i] = R(double(gm1) * double(rho[i]) * Pbar);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) xbar[4 * s + c] += acc.get(1 + c);
+        }
+    }
+}
+
+// 4. volume adjoint; writes the position gradient in caller order
+template <class R>
+__global__ __launch_bounds__(256) void k_volume_adj(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
+                                                    const uint4* __restrict__ quant, const R* __restrict__ aux,
+                                                    const R* __restrict__ sbar, const R* __restrict__ xbar,
+                                                    R* __restrict__ gx) {
+    const int lane = lane_id();
+    const int wave = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    for (int it = first_item(qu, wave); it < qu.n_items; it = next_item(qu, it, 0)) {
+        const int w = qu.order[it];
+        const int s = w * kWave + lane;
+        const bool valid = s < n;
+        const int so = valid ? s : 0;
+        const uint4 qi = quant[so];
+        const R invHi = aux[2 * so];
+        const R i2 = invHi * invHi;
+        const R cFi = R(-1155.0 / (4.0 * kPi)) * i2 * i2 * invHi;
+        const R Sbi = sbar[so];
+        const int cnt = valid ? L.cnt[s] : 0;
+        const int len = L.len[w];
+        const uint32_t* lst = L.nbr + L.off[w] + lane;
+        Sums<R, 3> acc;
+        acc.zero();
+        for (int k = 0; k < len; ++k) {
+            if (k < cnt) {
+                const uint32_t j = lst[int64_t(k) * kWave];
+                const uint4 qj = quant[j];
+                const R invHj = aux[2 * j];
+                const R x[3] = {sep<R>(qi.x, qj.x), sep<R>(qi.y, qj.y), sep<R>(qi.z, qj.z)};
+                const R r = dsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+                R w_, fi, fj, f2_;
+                shapes(r * invHi, w_, fi, f2_);
+                shapes(r * invHj, w_, fj, f2_);
+                const R j2 = invHj * invHj;
+                const R cFj = R(-1155.0 / (4.0 * kPi)) * j2 * j2 * invHj;
+                const R coef = Sbi * cFi * fi + sbar[j] * cFj * fj;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc.add(c, coef * x[c]);
+            }
+        }
+        if (valid) {
+            const int i = perm[s];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gx[3 * i + c] = xbar[4 * s + c] + acc.get(c);
+        }
+    }
+}
+
+template <class T> T* carve(char*& p, size_t count) {
+    T* r = reinterpret_cast<T*>(p);
+    p += (count * sizeof(T) + 255) / 256 * 256;
+    return r;
+}
+
+template <class R>
+int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const crk_corr* C,
+                  double gamma, const R* ga, const R* gdu, R* gx, R* gv, R* gu, hipStream_t st) {
+    const int n = int(L->n);
+    int rc = pack_positions<R>(L, g->x, g->y, g->z, static_cast<const R*>(g->h), st);
+    if (rc) return rc;
+    const size_t per = sizeof(RecBwd<R>) + 256 + sizeof(R) * (16 + 2 + 4 + 40 + 1 + 2 + 1);
+    if ((rc = ensure_scratch(L, per * size_t(n) + 8 * 256))) return rc;
+    char* p = static_cast<char*>(L->scratch);
+    RecBwd<R>* rec = carve<RecBwd<R>>(p, n);
+    R* aux = carve<R>(p, 2 * size_t(n));
+    R* Vs = carve<R>(p, n);
+    R* cbar = carve<R>(p, 16 * size_t(n));
+    R* vpbar = carve<R>(p, 2 * size_t(n));
+    R* xbar = carve<R>(p, 4 * size_t(n));
+    R* mbar = carve<R>(p, 40 * size_t(n));
+    R* sbar = carve<R>(p, n);
+    const R gm1 = R(gamma - 1.0);
+    {
+        TimeScope tp(L, st, CRK_K_PACK);
+        hipLaunchKernelGGL(k_pack_bwd<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, L->quant,
+                           static_cast<const R*>(g->h), static_cast<const R*>(g->u),
+                           static_cast<const R*>(g->vx), static_cast<const R*>(g->vy),
+                           static_cast<const R*>(g->vz), static_cast<const R*>(g->m), V, rho,
+                           static_cast<const R*>(C->A), static_cast<const R*>(C->B),
+                           static_cast<const R*>(C->dA), static_cast<const R*>(C->dB), ga, gdu, gm1,
+                           rec, aux);
+        hipLaunchKernelGGL(k_gather<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, V, Vs);
+    }
+    LAUNCH_CHECK("pack backward");
+    const dim3 grid(grid_nwave(L)), block(kWave * L->tune.block_waves);
+    const Queue q = make_queue(L, L->order_pair);
+    reset_queue(L, st);
+    {
+        TimeScope ts(L, st, CRK_K_ACCEL_ADJ);
+        hipLaunchKernelGGL(k_accel_adj<R>, grid, block, 0, st, q, n, lists(L), L->perm, rec, cbar,
+                           vpbar, xbar, gv);
+    }
+    LAUNCH_CHECK("accel adjoint");
+    reset_queue(L, st);
+    {
+        TimeScope ts(L, st, CRK_K_MOMENTS_ADJ);
+        hipLaunchKernelGGL(k_moments_bwd<R>, grid, block, 0, st, q, n, lists(L), L->perm, L->quant, aux,
+                           Vs, static_cast<const R*>(g->h), L->tune.kahan_chunk, cbar, mbar);
+    }
+    LAUNCH_CHECK("moments recompute + solve adjoint");
+    reset_queue(L, st);
+    {
+        TimeScope ts(L, st, CRK_K_MOMENTS_ADJ);
+        hipLaunchKernelGGL(k_moments_adj<R>, grid, block, 0, st, q, n, lists(L), L->perm, L->quant, aux,
+                           mbar, vpbar, static_cast<const R*>(g->m), static_cast<const R*>(g->u), rho,
+                           gm1, xbar, sbar, gu);
+    }
+    LAUNCH_CHECK("moments adjoint");
+    reset_queue(L, st);
+    {
+        TimeScope ts(L, st, CRK_K_VOLUME_ADJ);
+        hipLaunchKernelGGL(k_volume_adj<R>, grid, block, 0, st, q, n, lists(L), L->perm, L->quant, aux,
+                           sbar, xbar, gx);
+    }
+    LAUNCH_CHECK("volume adjoint");
+    return CRK_OK;
+}
+
+}  // namespace
+
+extern "C" int crk_accel_energy_backward(crk_leaves* L, const crk_gas* g, const void* V,
+                                         const void* rho, const crk_corr* C, double gamma,
+                                         const void* ga, const void* gdudt, crk_prec prec, void* gx,
+                                         void* gv, void* gu, hipStream_t st) {
+    int rc = check_gas(L, g, true);
+    if (rc) return rc;
+    if (L->n == 0) return CRK_OK;
+    if (!V || !rho || !C || !C->A || !C->B || !C->dA || !C->dB || !ga || !gdudt || !gx || !gv || !gu)
+        return fail(CRK_EINVAL, "V, rho, corrections, upstream adjoints and all gradients are required");
+    if (prec == CRK_F32)
+        return backward_impl<float>(L, g, (const float*)V, (const float*)rho, C, gamma, (const float*)ga,
+                                    (const float*)gdudt, (float*)gx, (float*)gv, (float*)gu, st);
+    if (prec == CRK_F64)
+        return backward_impl<double>(L, g, (const double*)V, (const double*)rho, C, gamma,
+                                     (const double*)ga, (const double*)gdudt, (double*)gx, (double*)gv,
+                                     (double*)gu, st);
+    return fail(CRK_EINVAL, "unknown precision");
+}

@@ -1,0 +1,146 @@
+"""Backward of the force/energy chain on the GPU (crk_accel_energy_backward), GPU only.
+
+Loss L = sum_i w_i |a_i|^2 + sum_i c_i du_i/dt with seeded w, c ~ U(0,1); h and
+m constant.  Reference: the FP64 oracle's forward-mode dual-number gradient
+and its central differences, on 64 seeded coordinates (32 positions, 16
+velocities, 16 internal energies).  Error per coordinate:
+|g - g_ref| / max(|g_ref|, rms of g_ref over the 64) <= 1e-4 (FP32 path) and
+<= 1e-9 (FP64 path).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+KEYS = oracle.COORD_KINDS
+
+
+@pytest.fixture(scope="module")
+def crk():
+    import paper_2310_16122_amd as crk
+
+    crk.load_library()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return crk
+
+
+def gpu_gradients(crk, cfg, prec, leaf_max=128):
+    dt = torch.float32 if prec == "f32" else torch.float64
+    pos = torch.stack([torch.as_tensor(cfg[k]) for k in ("x", "y", "z")], 1).cuda().requires_grad_(True)
+    v = torch.stack([torch.as_tensor(cfg[k]) for k in ("vx", "vy", "vz")], 1).to(dt).cuda().requires_grad_(True)
+    u = torch.as_tensor(cfg["u"]).to(dt).cuda().requires_grad_(True)
+    h = torch.as_tensor(cfg["h"]).to(dt).cuda()
+    m = torch.as_tensor(cfg["m"]).to(dt).cuda()
+    L = crk.crk_build_leaf_pairs(pos[:, 0].detach().contiguous(), pos[:, 1].detach().contiguous(),
+                                 pos[:, 2].detach().contiguous(), h, leaf_max=leaf_max, prec=prec)
+    a, du = crk.CRKAccelEnergy.apply(pos, v, u, L, h, m, cfg["gamma"], prec)
+    w = torch.as_tensor(cfg["w"]).to(dt).cuda()
+    c = torch.as_tensor(cfg["c"]).to(dt).cuda()
+    loss = (w * (a * a).sum(1)).sum() + (c * du).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    return (pos.grad.cpu().numpy(), v.grad.double().cpu().numpy(), u.grad.double().cpu().numpy(), L)
+
+
+def pick(grads, parts, kinds):
+    gx, gv, gu = grads[:3]
+    out = np.empty(len(parts))
+    for k, (p, kd) in enumerate(zip(parts, kinds)):
+        out[k] = gx[p, kd] if kd < 3 else (gv[p, kd - 3] if kd < 6 else gu[p])
+    return out
+
+
+def rel_err(g, ref):
+    scale = np.maximum(np.abs(ref), np.sqrt(np.mean(ref ** 2)))
+    return np.abs(g - ref) / scale
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-9), ("f32", 1e-4)])
+@pytest.mark.parametrize("n_side", [24, 64])
+def test_gradients_against_oracle(crk, n_side, prec, tol):
+    cfg = synth.make_config("C4", n_side=n_side)
+    print(f"case C4 n_side={n_side} n={cfg['n']} prec={prec}", flush=True)
+    parts, kinds = oracle.grad_coordinates(cfg["n"])
+    gd, gf, _ = oracle.grad(cfg, parts, kinds)
+    g = pick(gpu_gradients(crk, cfg, prec), parts, kinds)
+    e_dual = rel_err(g, gd)
+    e_fd = rel_err(g, gf)
+    print("max err vs dual", e_dual.max(), "vs fd", e_fd.max(), flush=True)
+    assert e_dual.max() <= tol, (e_dual.max(), [KEYS[k] for k in kinds[e_dual > tol]])
+    assert e_fd.max() <= max(tol, 1e-7)
+
+
+def tiny_cfg(n=160, nbr=16, seed=3):
+    rng = np.random.default_rng(seed)
+    x, y, z = (synth.grid_round(rng.random(n)) for _ in range(3))
+    H = synth.knn_support(x, y, z, rng.integers(nbr - 3, nbr + 4, n))
+    return dict(n=n, x=x, y=y, z=z, h=synth.f32(0.5 * H), m=synth.f32(np.full(n, 1.0 / n)),
+                vx=synth.f32(rng.normal(0, 0.1, n)), vy=synth.f32(rng.normal(0, 0.1, n)),
+                vz=synth.f32(rng.normal(0, 0.1, n)), u=synth.f32(np.exp(0.5 * rng.normal(size=n))),
+                gamma=5.0 / 3.0, w=rng.random(n), c=rng.random(n))
+
+
+def test_gradcheck_fp64(crk):
+    cfg = tiny_cfg()
+    pos = torch.stack([torch.as_tensor(cfg[k]) for k in ("x", "y", "z")], 1).cuda().requires_grad_(True)
+    v = torch.stack([torch.as_tensor(cfg[k]) for k in ("vx", "vy", "vz")], 1).cuda().requires_grad_(True)
+    u = torch.as_tensor(cfg["u"]).cuda().requires_grad_(True)
+    h = torch.as_tensor(cfg["h"]).cuda()
+    m = torch.as_tensor(cfg["m"]).cuda()
+    L = crk.crk_build_leaf_pairs(pos[:, 0].detach().contiguous(), pos[:, 1].detach().contiguous(),
+                                 pos[:, 2].detach().contiguous(), h, leaf_max=16, prec="f64")
+    fn = lambda p, vv, uu: crk.CRKAccelEnergy.apply(p, vv, uu, L, h, m, cfg["gamma"], "f64")
+    # the step 2^-20 keeps perturbed positions on the 2^-32 grid
+    assert torch.autograd.gradcheck(fn, (pos, v, u), eps=2.0 ** -20, atol=1e-5, rtol=1e-4)
+
+
+def test_directional_derivative_fp64(crk):
+    cfg = synth.make_config("C4", n_side=16)
+    rng = np.random.default_rng(9)
+    n = cfg["n"]
+    dx = rng.integers(-4096, 4097, (n, 3)) * 2.0 ** -32  # on the position grid
+    dv = rng.normal(0, 1e-6, (n, 3))
+    du_ = rng.normal(0, 1e-6, n) * cfg["u"]
+
+    def loss(c):
+        g = crk.gas_to_device(c, "f64")
+        Lh = crk.crk_build_leaf_pairs(g["x"], g["y"], g["z"], g["h"], leaf_max=64, prec="f64")
+        o = crk.forward(Lh, g, c["gamma"], "f64")
+        a = o["a"].cpu().numpy()
+        return np.sum(cfg["w"] * (a * a).sum(1)) + np.sum(cfg["c"] * o["dudt"].cpu().numpy())
+
+    def shifted(sgn):
+        c = dict(cfg)
+        for k, key in enumerate("xyz"):
+            c[key] = np.mod(cfg[key] + sgn * dx[:, k], 1.0)
+        for k, key in enumerate(("vx", "vy", "vz")):
+            c[key] = cfg[key] + sgn * dv[:, k]
+        c["u"] = cfg["u"] + sgn * du_
+        return c
+
+    fd = (loss(shifted(1)) - loss(shifted(-1))) / 2.0
+    gx, gv, gu, _ = gpu_gradients(crk, cfg, "f64", leaf_max=64)
+    an = np.sum(gx * dx) + np.sum(gv * dv) + np.sum(gu * du_)
+    assert abs(an - fd) <= 1e-6 * abs(fd), (an, fd)
+
+
+def test_backward_bitwise_reproducible(crk):
+    cfg = synth.make_config("C4", n_side=20)
+    g1 = gpu_gradients(crk, cfg, "f32")
+    g2 = gpu_gradients(crk, cfg, "f32")
+    for a, b in zip(g1[:3], g2[:3]):
+        assert np.array_equal(a, b)
+
+
+def test_velocity_gradient_vanishes_without_energy_weight(crk):
+    """a does not depend on v: with c = 0 the velocity gradient is exactly zero."""
+    cfg = synth.make_config("C4", n_side=16)
+    cfg["c"] = np.zeros(cfg["n"])
+    gx, gv, gu, _ = gpu_gradients(crk, cfg, "f64", leaf_max=64)
+    assert np.all(gv == 0.0)
+    assert np.abs(gx).max() > 0
