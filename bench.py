@@ -3,10 +3,12 @@
 
 One step = one pass of the hot path over one synthetic particle set already
 resident in HBM: for the CRK workloads the position packing, the volume pass,
-the corrections pass (40 moments + FP64 solve) and the fused acceleration /
-energy pass with FP64 totals; for the gravity workload one short-range
-gravity evaluation.  The tree and the neighbour lists are built once before
-the timed region (reported separately as build time).
+the corrections pass (40 moments + FP64 solve), the fused acceleration /
+energy pass with FP64 totals, and the backward (force, moments and volume
+adjoints, with the moments recomputed); for the gravity workload one
+short-range gravity evaluation.  The tree and the neighbour lists are built
+once before the timed region (reported separately as build time); particles
+are held in tree order.  The launch/tiling choices are autotuned first.
 
 Prints ONE JSON line.  ``value`` is pair interactions per second: ordered
 pairs j != i inside each pass's radius (2h_i for volume and moments,
@@ -29,7 +31,9 @@ METRIC = "CRK-SPH pair interactions/s & % FP32 VALU peak; fwd+bwd ms vs FP64 GPU
 # Algorithmic FP32 work per ordered pair inside the pass radius (FMA = 2 FLOP,
 # square root / reciprocal square root = 1), per-particle constants hoisted;
 # compensation arithmetic excluded.  Derivation in the design doc.
-FLOP_PER_PAIR = {"volume": 21, "moments": 112, "accel": 141, "gravity": 19}
+FLOP_PER_PAIR = {"volume": 21, "moments": 112, "accel": 141, "gravity": 19,
+                 "accel_adj": 520, "moments_adj": 580, "volume_adj": 40}
+HYDRO_KERNELS = ("volume", "moments", "accel", "accel_adj", "moments_adj", "volume_adj")
 PEAK_FP32_VALU_TFLOPS = 157.3  # 256 CUs x 2.4 GHz x 256 FLOP/clk/CU
 
 WORKLOADS = {
@@ -127,50 +131,95 @@ def roofline(kind, ms_total, launches, units):
 
 
 def bench_hydro(args, torch, crk):
+    import numpy as np
+
     import synth
 
     t0 = time.perf_counter()
     cfg = synth.make_config(args.config)
     log(f"[bench] generated {args.config}: n={cfg['n']} in {time.perf_counter() - t0:.1f}s")
-    g32 = crk.gas_to_device(cfg, "f32")
+    # Particles are kept in tree order, as a simulation keeps them: build once
+    # on the generated (random) order, reorder the arrays along the tree and
+    # rebuild, which gives the identity permutation (coalesced particle I/O).
+    g_rand = crk.gas_to_device(cfg, "f32")
     torch.cuda.synchronize()
     tb = time.perf_counter()
+    L_rand = crk.crk_build_leaf_pairs(g_rand["x"], g_rand["y"], g_rand["z"], g_rand["h"],
+                                      leaf_max=args.leaf_max, prec="f32")
+    build_ms = (time.perf_counter() - tb) * 1e3
+    cull = L_rand.kernel_times()["cull"]
+    perm = L_rand.perm().cpu().numpy()
+    cfg_t = {k: (v[perm] if isinstance(v, np.ndarray) and v.shape == (cfg["n"],) else v)
+             for k, v in cfg.items()}
+    g32 = crk.gas_to_device(cfg_t, "f32")
     L = crk.crk_build_leaf_pairs(g32["x"], g32["y"], g32["z"], g32["h"], leaf_max=args.leaf_max,
                                  prec="f32")
-    build_ms = (time.perf_counter() - tb) * 1e3
+    identity = bool((L.perm().cpu().numpy() == np.arange(cfg["n"])).all())
     if args.tuning:
         L.set_tuning(**json.loads(args.tuning))
-    cull = L.kernel_times()["cull"]
+        L_rand.set_tuning(**json.loads(args.tuning))
     st = L.stats()
-    log(f"[bench] build {build_ms:.0f} ms (list build on GPU {cull[0]:.2f} ms); stats {st}")
-    inter = 2 * st["pairs_gather"] + st["pairs_force"]
+    G, F = st["pairs_gather"], st["pairs_force"]
+    log(f"[bench] build {build_ms:.0f} ms (list build on GPU {cull[0]:.2f} ms); identity order "
+        f"after rebuild: {identity}; stats {st}")
+    G, F = st["pairs_gather"], st["pairs_force"]
+    inter_fwd = 2 * G + F
+    inter = inter_fwd + (G + 3 * F if not args.no_backward else 0)
+    dev = g32["x"].device
 
-    def step32():
-        crk.forward(L, g32, cfg["gamma"], "f32")
+    def adjoints(g, prec):
+        dt = torch.float32 if prec == "f32" else torch.float64
+        w = torch.as_tensor(cfg_t["w"]).to(dt).to(dev)
+        c = torch.as_tensor(cfg_t["c"]).to(dt).to(dev)
+        o = crk.forward(L, g, cfg["gamma"], prec)
+        return (2.0 * w[:, None] * o["a"]).contiguous(), c
 
+    def make_step(Lh, g, prec, ga, gdu):
+        def step():
+            o = crk.forward(Lh, g, cfg["gamma"], prec)
+            if not args.no_backward:
+                crk.crk_accel_energy_backward(Lh, g, o["V"], o["rho"], (o["A"], o["B"], o["dA"], o["dB"]),
+                                              ga, gdu, cfg["gamma"], prec)
+        return step
+
+    ga32, gdu32 = adjoints(g32, "f32")
+    step32 = make_step(L, g32, "f32", ga32, gdu32)
+    tuned = None
+    if not args.no_autotune and not args.tuning:
+        from paper_2310_16122_amd import tune
+
+        best, best_ms, tried = tune.autotune(L, step32, repeats=2)
+        L_rand.set_tuning(**best)
+        tuned = {"tried": len(tried), "best_ms": round(best_ms, 3)}
+        log(f"[bench] autotuned over {len(tried)} settings: {best} ({best_ms:.3f} ms)")
     L.timing(False)
-    ms32 = timed_steps(step32, 2, args.warmup, torch)  # warm-up outside the timed region
+    timed_steps(step32, 2, args.warmup, torch)
     L.timing(True)
     ms32 = timed_steps(step32, args.steps, 0, torch)
     kt = L.kernel_times()
+    L.timing(False)
     log(f"[bench] f32 step {ms32:.3f} ms; kernels {kt}")
-    units = {"volume": st["pairs_gather"], "moments": st["pairs_gather"], "accel": st["pairs_force"]}
-    dom = max(("volume", "moments", "accel"), key=lambda k: kt[k][0])
+    units = {"volume": G, "moments": G, "accel": F, "accel_adj": F, "moments_adj": F, "volume_adj": F}
+    ran = [k for k in HYDRO_KERNELS if kt[k][1] > 0]
+    dom = max(ran, key=lambda k: kt[k][0])
     rl = roofline(dom, kt[dom][0], kt[dom][1], units[dom])
-    per_kernel = {k: {"avg_ms": round(kt[k][0] / max(kt[k][1], 1), 4),
-                      "tflops": round(FLOP_PER_PAIR[k] * units[k] / (kt[k][0] / max(kt[k][1], 1)) * 1e-9, 3)}
-                  for k in ("volume", "moments", "accel")}
+    per_kernel = {k: {"avg_ms": round(kt[k][0] / kt[k][1], 4), "launches_per_step": kt[k][1] / args.steps,
+                      "tflops": round(FLOP_PER_PAIR[k] * units[k] / (kt[k][0] / kt[k][1]) * 1e-9, 3)}
+                  for k in ran}
     per_kernel["pack_ms_per_step"] = round(kt["pack"][0] / args.steps, 4)
+    flop_step = sum(FLOP_PER_PAIR[k] * units[k] * kt[k][1] / args.steps for k in ran)
+
+    # the same step with particle arrays in the generated (random) order
+    inv = torch.as_tensor(np.argsort(perm)).to(dev)  # tree position of each generated particle
+    ms_rand = timed_steps(make_step(L_rand, g_rand, "f32", ga32[inv].contiguous(), gdu32[inv].contiguous()),
+                          max(2, args.steps // 4), 1, torch)
+    log(f"[bench] f32 step, random particle order: {ms_rand:.3f} ms")
 
     ms64 = None
     if not args.no_f64:
-        g64 = crk.gas_to_device(cfg, "f64")
-
-        def step64():
-            crk.forward(L, g64, cfg["gamma"], "f64")
-
-        L.timing(False)
-        ms64 = timed_steps(step64, max(2, args.steps // 4), 1, torch)
+        g64 = crk.gas_to_device(cfg_t, "f64")
+        ga64, gdu64 = adjoints(g64, "f64")
+        ms64 = timed_steps(make_step(L, g64, "f64", ga64, gdu64), max(2, args.steps // 4), 1, torch)
         log(f"[bench] f64 step {ms64:.3f} ms")
         del g64
 
@@ -180,18 +229,19 @@ def bench_hydro(args, torch, crk):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "n": cfg["n"],
-                   "leaf_max": args.leaf_max, "passes": "pack+volume+corrections+accel_energy",
-                   "interactions_per_step": inter, "pairs_gather": st["pairs_gather"],
-                   "pairs_force": st["pairs_force"], "list_entries": st["list_entries"],
-                   "tuning": L.get_tuning()},
+                   "leaf_max": args.leaf_max,
+                   "passes": "volume+corrections+accel_energy" +
+                             ("" if args.no_backward else "+backward(accel,moments,volume adjoints)"),
+                   "particle_order": "tree order (identity permutation)" if identity else "tree-built",
+                   "interactions_per_step": inter, "pairs_gather": G, "pairs_force": F,
+                   "list_entries": st["list_entries"], "tuning": L.get_tuning(), "autotune": tuned},
         "roofline": rl,
         "kernels": per_kernel,
-        "fp32_frac_step": round(sum(FLOP_PER_PAIR[k] * units[k] for k in units) /
-                                (ms32 * 1e-3) / 1e12 / PEAK_FP32_VALU_TFLOPS, 4),
+        "fp32_frac_step": round(flop_step / (ms32 * 1e-3) / 1e12 / PEAK_FP32_VALU_TFLOPS, 4),
         "fp64_gpu_ms_per_step": None if ms64 is None else round(ms64, 4),
         "fp64_over_fp32_time": None if ms64 is None else round(ms64 / ms32, 3),
+        "random_order_ms_per_step": round(ms_rand, 4),
         "build_ms": round(build_ms, 1), "list_build_gpu_ms": round(cull[0], 3),
-        "backward": "not built yet",
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_hydro(cfg, args.cpu_budget)
@@ -244,7 +294,9 @@ def main():
     ap.add_argument("--config", default="C2", choices=("C2", "C5", "C3"))
     ap.add_argument("--leaf-max", type=int, default=128)
     ap.add_argument("--tuning", default=None, help="JSON dict of crk_tuning fields")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tuning")
     ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--no-backward", action="store_true", help="forward passes only")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     args = ap.parse_args()

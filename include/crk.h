@@ -89,6 +89,8 @@ typedef struct {
     int waves_per_cu;    /* persistent grid size = CUs * waves_per_cu waves */
     int kahan_chunk;     /* FP32 moments: plain sums over this many pairs, compensated across chunks (1 = every pair) */
     int block_waves;     /* waves per workgroup for the list-driven pair passes (1, 2, 4) */
+    int xcd_groups;      /* tile order is cut into this many contiguous chunks, one per XCD (1..16) */
+    int tile_order;      /* 0: tree order (locality); 1: longest tiles first */
 } crk_tuning;
 
 /*
@@ -197,6 +199,15 @@ int crk_accel_energy_backward(crk_leaves* leaves, const crk_gas* gas, const void
  */
 int crk_leaves_stats(crk_leaves* leaves, int64_t* host_out);
 
+/*
+ * Tree order of a handle: perm[s] = caller index of the particle at position s
+ * of tree order (device int32[n], written on `stream`).  Callers that keep
+ * their particle arrays in this order (x_tree[s] = x[perm[s]]) and rebuild get
+ * the identity permutation -- the median splits keep the existing order -- and
+ * every pass then reads and writes particle fields with coalesced accesses.
+ */
+int crk_leaves_perm(const crk_leaves* leaves, int32_t* perm, hipStream_t stream);
+
 /* Read or set the launch/tiling choices of a handle (set validates them). */
 int crk_get_tuning(const crk_leaves* leaves, crk_tuning* out);
 int crk_set_tuning(crk_leaves* leaves, const crk_tuning* in);
@@ -211,12 +222,12 @@ int crk_set_tuning(crk_leaves* leaves, const crk_tuning* in);
 enum {
     CRK_K_CULL = 0,    /* neighbour-list build (count and fill passes) */
     CRK_K_VOLUME = 1,  /* volume pair kernel */
-    CRK_K_MOMENTS = 2, /* correction moments + FP64 solve */
+    CRK_K_MOMENTS = 2, /* correction moments + FP64 solve (and their recomputation in the backward) */
     CRK_K_ACCEL = 3,   /* acceleration/energy pair kernel */
     CRK_K_GRAVITY = 4, /* short-range gravity */
     CRK_K_PACK = 5,    /* per-particle packing, gathers and the totals reduction */
     CRK_K_ACCEL_ADJ = 6,   /* force adjoint pair kernel */
-    CRK_K_MOMENTS_ADJ = 7, /* moments recompute + solve adjoint, and the moments adjoint pair kernel */
+    CRK_K_MOMENTS_ADJ = 7, /* moments adjoint pair kernel */
     CRK_K_VOLUME_ADJ = 8,  /* volume adjoint pair kernel */
     CRK_K_COUNT = 9
 };

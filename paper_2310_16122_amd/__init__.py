@@ -28,7 +28,7 @@ _STATUS = {0: "CRK_OK", -1: "CRK_EINVAL", -2: "CRK_ENOMEM", -3: "CRK_EHIP", -4: 
 
 # the C symbols declared in include/crk.h
 EXPORTS = ("crk_build_leaf_pairs", "crk_volume", "crk_corrections", "crk_accel_energy",
-           "sr_gravity", "crk_accel_energy_backward", "crk_leaves_stats", "crk_get_tuning", "crk_set_tuning",
+           "sr_gravity", "crk_accel_energy_backward", "crk_leaves_stats", "crk_leaves_perm", "crk_get_tuning", "crk_set_tuning",
            "crk_timing", "crk_kernel_times", "crk_leaves_free", "crk_last_error")
 KERNEL_KINDS = ("cull", "volume", "moments", "accel", "gravity", "pack", "accel_adj",
                 "moments_adj", "volume_adj")
@@ -51,7 +51,8 @@ class _Corr(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("persistent", ctypes.c_int), ("waves_per_cu", ctypes.c_int),
-                ("kahan_chunk", ctypes.c_int), ("block_waves", ctypes.c_int)]
+                ("kahan_chunk", ctypes.c_int), ("block_waves", ctypes.c_int),
+                ("xcd_groups", ctypes.c_int), ("tile_order", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -79,6 +80,7 @@ def load_library(path=None):
     lib.crk_accel_energy_backward.argtypes = [P, ctypes.POINTER(_Gas), P, P, ctypes.POINTER(_Corr), D,
                                               P, P, I, P, P, P, P]
     lib.crk_leaves_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+    lib.crk_leaves_perm.argtypes = [P, P, P]
     lib.crk_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
     lib.crk_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
     lib.crk_timing.argtypes = [P, I]
@@ -148,6 +150,12 @@ class Leaves:
         keys = ("leaves", "tiles", "candidate_pairs", "list_entries", "pairs_gather",
                 "pairs_force", "padded_slots", "build_us")
         return dict(zip(keys, list(out)))
+
+    def perm(self, device="cuda"):
+        """Tree order: perm[s] = caller index of the s-th particle in tree order."""
+        out = torch.empty(self.n, dtype=torch.int32, device=device)
+        _check("crk_leaves_perm", load_library().crk_leaves_perm(self.handle, _ptr(out), _stream()))
+        return out
 
     def get_tuning(self):
         t = Tuning()

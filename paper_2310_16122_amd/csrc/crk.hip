@@ -109,8 +109,8 @@ __global__ __launch_bounds__(64) void k_cull(Queue qu, int n, const uint4* __res
                                              uint32_t* __restrict__ nbr) {
     __shared__ uint4 sj[kWave];
     const int lane = lane_id();
-    for (int it = first_item(qu, blockIdx.x); it < qu.n_items; it = next_item(qu, it, gridDim.x)) {
-        const int w = qu.order[it];
+    QState qs;
+    for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
         const int s = w * kWave + lane;
         const bool valid = s < n;
         const uint4 qi = valid ? quant[s] : make_uint4(0, 0, 0, 0);
@@ -214,9 +214,8 @@ __global__ __launch_bounds__(256) void k_volume(Queue qu, int n, Lists L, const 
                                                 const R* __restrict__ m, R* __restrict__ V_out,
                                                 R* __restrict__ rho_out) {
     const int lane = lane_id();
-    const int wave = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    for (int it = first_item(qu, wave); it < qu.n_items; it = next_item(qu, it, 0)) {
-        const int w = qu.order[it];
+    QState qs;
+    for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
         const int s = w * kWave + lane;
         const bool valid = s < n;
         const int i = valid ? perm[s] : 0;
@@ -258,9 +257,8 @@ __global__ __launch_bounds__(256) void k_moments(Queue qu, int n, Lists L, const
                                                  R* __restrict__ dB_out,
                                                  unsigned long long* __restrict__ n_fallback) {
     const int lane = lane_id();
-    const int wave = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    for (int it = first_item(qu, wave); it < qu.n_items; it = next_item(qu, it, 0)) {
-        const int w = qu.order[it];
+    QState qs;
+    for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
         const int s = w * kWave + lane;
         const bool valid = s < n;
         const int i = valid ? perm[s] : 0;
@@ -303,9 +301,8 @@ __global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const i
                                                double* __restrict__ partials) {
     constexpr bool kComp = sizeof(R) == 4;
     const int lane = lane_id();
-    const int wave = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    for (int it = first_item(qu, wave); it < qu.n_items; it = next_item(qu, it, 0)) {
-        const int w = qu.order[it];
+    QState qs;
+    for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
         const int s = w * kWave + lane;
         const bool valid = s < n;
         const RecAcc<R> ri = rec[valid ? s : 0];
@@ -408,8 +405,8 @@ __global__ __launch_bounds__(64) void k_gravity(Queue qu, int n, const int32_t* 
     const R rc2 = R(gp.rc2), eps2 = R(gp.eps2);
     R pc[6];
     for (int k = 0; k < 6; ++k) pc[k] = R(gp.poly[k]);
-    for (int it = first_item(qu, blockIdx.x); it < qu.n_items; it = next_item(qu, it, gridDim.x)) {
-        const int w = qu.order[it];
+    QState qs;
+    for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
         const int s = w * kWave + lane;
         const bool valid = s < n;
         const uint4 qi = valid ? quant[s] : make_uint4(0, 0, 0, 0);
@@ -464,7 +461,7 @@ namespace crk {
 
 
 void release(crk_leaves* L) {
-    void* ptrs[] = {L->perm, L->quant, L->Hd, L->rng_off, L->rng, L->order_cull, L->order_pair,
+    void* ptrs[] = {L->perm, L->quant, L->Hd, L->rng_off, L->rng, L->order_cull, L->order_pair, L->order_tree,
                     L->counter, L->cnt, L->ell_off, L->ell_len, L->nbr, L->partials, L->counts,
                     L->scratch};
     for (void* p : ptrs)
@@ -494,22 +491,29 @@ void drop_timed(crk_leaves* L) {
 }
 
 Queue make_queue(const crk_leaves* L, const int32_t* order) {
-    return Queue{order, L->counter, int32_t(L->n_tiles), L->tune.persistent};
+    // tree order keeps spatially adjacent tiles together (L2 reuse); the
+    // longest-first order balances uneven tiles
+    const int32_t* ord = L->tune.tile_order == 0 ? L->order_tree : order;
+    const int g = L->tune.xcd_groups;
+    const int32_t per = int32_t((L->n_tiles + g - 1) / g);
+    return Queue{ord, L->counter, int32_t(L->n_tiles), L->tune.persistent, g, per};
+}
+
+static int grid_for(const crk_leaves* L, int bw) {
+    const int g = L->tune.xcd_groups;
+    const int64_t per = (L->n_tiles + g - 1) / g;
+    int64_t blocks = g * ((per + bw - 1) / bw);  // one wave per tile
+    if (L->tune.persistent) {
+        const int64_t cap = int64_t(L->n_cu) * L->tune.waves_per_cu / bw;
+        blocks = std::min(blocks, std::max<int64_t>(g, cap / g * g));
+    }
+    return int(std::max<int64_t>(blocks, 1));
 }
 
 // grid for one-wave workgroups (LDS-staged kernels)
-int grid_1wave(const crk_leaves* L) {
-    if (!L->tune.persistent) return int(L->n_tiles);
-    return int(std::min<int64_t>(L->n_tiles, int64_t(L->n_cu) * L->tune.waves_per_cu));
-}
+int grid_1wave(const crk_leaves* L) { return grid_for(L, 1); }
 // grid for block_waves-wave workgroups (list-driven passes)
-int grid_nwave(const crk_leaves* L) {
-    const int bw = L->tune.block_waves;
-    const int64_t waves = L->tune.persistent
-                              ? std::min<int64_t>(L->n_tiles, int64_t(L->n_cu) * L->tune.waves_per_cu)
-                              : L->n_tiles;
-    return int((waves + bw - 1) / bw);
-}
+int grid_nwave(const crk_leaves* L) { return grid_for(L, L->tune.block_waves); }
 
 int check_gas(const crk_leaves* L, const crk_gas* g, bool need_v) {
     if (!L || !g) return fail(CRK_EINVAL, "null handle or gas");
@@ -664,6 +668,13 @@ void crk_leaves_free(crk_leaves* L) {
     delete L;
 }
 
+int crk_leaves_perm(const crk_leaves* L, int32_t* perm, hipStream_t st) {
+    if (!L || (!perm && L->n > 0)) return fail(CRK_EINVAL, "null argument");
+    if (L->n == 0) return CRK_OK;
+    HIP_TRY(hipMemcpyAsync(perm, L->perm, size_t(L->n) * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    return CRK_OK;
+}
+
 int crk_get_tuning(const crk_leaves* L, crk_tuning* out) {
     if (!L || !out) return fail(CRK_EINVAL, "null argument");
     *out = L->tune;
@@ -677,6 +688,8 @@ int crk_set_tuning(crk_leaves* L, const crk_tuning* in) {
     if (in->kahan_chunk < 1 || in->kahan_chunk > 64) return fail(CRK_EINVAL, "kahan_chunk in [1, 64]");
     if (in->block_waves != 1 && in->block_waves != 2 && in->block_waves != 4)
         return fail(CRK_EINVAL, "block_waves must be 1, 2 or 4");
+    if (in->xcd_groups < 1 || in->xcd_groups > kMaxGroups) return fail(CRK_EINVAL, "xcd_groups in [1, 16]");
+    if (in->tile_order != 0 && in->tile_order != 1) return fail(CRK_EINVAL, "tile_order must be 0 or 1");
     L->tune = *in;
     return CRK_OK;
 }
@@ -711,7 +724,7 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&L->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return bail(fail(CRK_EHIP, "cannot query the device"));
-    if ((rc = dalloc(&L->counter, 4)) || (rc = dalloc(&L->counts, 4))) return bail(rc);
+    if ((rc = dalloc(&L->counter, kMaxGroups)) || (rc = dalloc(&L->counts, 4))) return bail(rc);
     if (n == 0) {
         *out = L;
         return CRK_OK;
@@ -784,14 +797,16 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
         if (L->hydro) hH[s] = H[i];
     }
     // longest-processing-time-first order of tiles for the candidate scan
-    std::vector<int32_t> order(nt);
+    std::vector<int32_t> order(nt), tree_order(nt);
     std::iota(order.begin(), order.end(), 0);
+    std::iota(tree_order.begin(), tree_order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t b) { return tout.tile_cand[a] > tout.tile_cand[b]; });
 
     if ((rc = dalloc(&L->perm, n)) || (rc = dalloc(&L->quant, n)) ||
         (rc = dalloc(&L->rng_off, nt + 1)) || (rc = dalloc(&L->rng, tout.rng.size() / 2)) ||
         (rc = dalloc(&L->order_cull, nt)) || (rc = dalloc(&L->order_pair, nt)) ||
+        (rc = dalloc(&L->order_tree, nt)) ||
         (rc = dalloc(&L->partials, 8 * nt)))
         return bail(rc);
     if (hipMemcpyAsync(L->perm, tout.perm.data(), n * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
@@ -800,7 +815,8 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
         (tout.rng.size() && hipMemcpyAsync(L->rng, tout.rng.data(), tout.rng.size() * 4,
                                            hipMemcpyHostToDevice, stream) != hipSuccess) ||
         hipMemcpyAsync(L->order_cull, order.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(L->order_pair, order.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
+        hipMemcpyAsync(L->order_pair, order.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(L->order_tree, tree_order.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
         return bail(fail(CRK_EHIP, "uploading the tree failed"));
 
     L->stats[0] = L->n_leaves;

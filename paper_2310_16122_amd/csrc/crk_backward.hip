@@ -163,9 +163,8 @@ __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, con
                                                    R* __restrict__ vpbar, R* __restrict__ xbar,
                                                    R* __restrict__ gv) {
     const int lane = lane_id();
-    const int wave = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    for (int it = first_item(qu, wave); it < qu.n_items; it = next_item(qu, it, 0)) {
-        const int w = qu.order[it];
+    QState qs;
+    for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
         const int s = w * kWave + lane;
         const bool valid = s < n;
         const RecBwd<R> ri = rec[valid ? s : 0];
@@ -351,9 +350,8 @@ __global__ __launch_bounds__(256) void k_moments_bwd(Queue qu, int n, Lists L, c
                                                      const R* __restrict__ Vs, const R* __restrict__ h, int chunk,
                                                      const R* __restrict__ cbar, R* __restrict__ mbar) {
     const int lane = lane_id();
-    const int wave = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    for (int it = first_item(qu, wave); it < qu.n_items; it = next_item(qu, it, 0)) {
-        const int w = qu.order[it];
+    QState qs;
+    for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
         const int s = w * kWave + lane;
         const bool valid = s < n;
         const int i = valid ? perm[s] : 0;
@@ -436,9 +434,8 @@ __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, c
                                                      const R* __restrict__ rho, R gm1, R* __restrict__ xbar,
                                                      R* __restrict__ sbar, R* __restrict__ gu) {
     const int lane = lane_id();
-    const int wave = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    for (int it = first_item(qu, wave); it < qu.n_items; it = next_item(qu, it, 0)) {
-        const int w = qu.order[it];
+    QState qs;
+    for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
         const int s = w * kWave + lane;
         const bool valid = s < n;
         const int so = valid ? s : 0;
@@ -507,9 +504,8 @@ __global__ __launch_bounds__(256) void k_volume_adj(Queue qu, int n, Lists L, co
                                                     const R* __restrict__ sbar, const R* __restrict__ xbar,
                                                     R* __restrict__ gx) {
     const int lane = lane_id();
-    const int wave = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    for (int it = first_item(qu, wave); it < qu.n_items; it = next_item(qu, it, 0)) {
-        const int w = qu.order[it];
+    QState qs;
+    for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
         const int s = w * kWave + lane;
         const bool valid = s < n;
         const int so = valid ? s : 0;
@@ -595,7 +591,7 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
     LAUNCH_CHECK("accel adjoint");
     reset_queue(L, st);
     {
-        TimeScope ts(L, st, CRK_K_MOMENTS_ADJ);
+        TimeScope ts(L, st, CRK_K_MOMENTS);  // the forward moments, recomputed
         hipLaunchKernelGGL(k_moments_bwd<R>, grid, block, 0, st, q, n, lists(L), L->perm, L->quant, aux,
                            Vs, static_cast<const R*>(g->h), L->tune.kahan_chunk, cbar, mbar);
     }

@@ -17,6 +17,7 @@ namespace crk {
 constexpr int kWave = 64;
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kInvGrid = 2.3283064365386962890625e-10;  // 2^-32
+constexpr int kMaxGroups = 16;                                // work-queue chunks (counters)
 constexpr float kCullMargin = 1.0f + 1.0e-5f;                // list radius^2 factor
 
 // Records a message for crk_last_error and returns `code`.
@@ -82,30 +83,56 @@ template <class R> __device__ __forceinline__ void kadd(R& s, R& c, R t) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
-// Work queue: tiles in decreasing-cost order, one per wave or pulled from an
-// atomic counter by a persistent grid.
+// Work distribution over tiles.  `order` lists the tiles; it is cut into
+// `groups` contiguous chunks, and workgroup b works on chunk b % groups first,
+// so that with groups = 8 each XCD (workgroups are dispatched round-robin over
+// the 8 XCDs) walks its own contiguous stretch of tree order and its L2 holds
+// the neighbours those tiles share.  Non-persistent: one tile per wave.
+// Persistent: every wave pulls tiles from its chunk's atomic counter and, when
+// that chunk is drained, from the next chunks in turn; every wave exits once
+// all chunks are drained.
 struct Queue {
     const int32_t* order;
-    int32_t* counter;
+    int32_t* counter;  // one counter per group, zeroed before each launch
     int32_t n_items;
     int32_t persistent;
+    int32_t groups;
+    int32_t per_group;  // ceil(n_items / groups)
 };
 
-__device__ __forceinline__ int first_item(const Queue& q, int wave_global) {
-    if (!q.persistent) return wave_global;
-    int it = 0;
-    if (lane_id() == 0) it = atomicAdd(q.counter, 1);
-    return __builtin_amdgcn_readfirstlane(it);
+struct QState {
+    int g, tries;
+};
+
+__device__ __forceinline__ int queue_next(const Queue& q, QState& st) {
+    if (!q.persistent) return -1;
+    while (st.tries < q.groups) {
+        int it = 0;
+        if ((threadIdx.x & 63) == 0) it = atomicAdd(q.counter + st.g, 1);
+        it = __builtin_amdgcn_readfirstlane(it);
+        const int idx = st.g * q.per_group + it;
+        if (it < q.per_group && idx < q.n_items) return q.order[idx];
+        st.g = st.g + 1 == q.groups ? 0 : st.g + 1;
+        st.tries += 1;
+    }
+    return -1;
 }
-__device__ __forceinline__ int next_item(const Queue& q, int cur, int n_waves_grid) {
-    if (!q.persistent) return q.n_items;  // one tile per wave
-    int it = 0;
-    if (lane_id() == 0) it = atomicAdd(q.counter, 1);
-    return __builtin_amdgcn_readfirstlane(it);
+
+__device__ __forceinline__ int queue_start(const Queue& q, QState& st) {
+    const int g = int(blockIdx.x % unsigned(q.groups));
+    if (!q.persistent) {
+        const int bw = int(blockDim.x >> 6);
+        const int slot = int(blockIdx.x / unsigned(q.groups)) * bw + int(threadIdx.x >> 6);
+        const int idx = g * q.per_group + slot;
+        return (slot < q.per_group && idx < q.n_items) ? q.order[idx] : -1;
+    }
+    st.g = g;
+    st.tries = 0;
+    return queue_next(q, st);
 }
 
 static __global__ void k_reset(int32_t* c) {
-    if (threadIdx.x < 4) c[threadIdx.x] = 0;
+    if (threadIdx.x < kMaxGroups) c[threadIdx.x] = 0;
 }
 
 // ------------------------------------------------------------------ packing (tree order)
@@ -305,7 +332,7 @@ struct crk_leaves {
     double r_fixed = 0.0;
     int64_t n_tiles = 0, n_leaves = 0;
     int n_cu = 1;
-    crk_tuning tune{1, 32, 4, 4};
+    crk_tuning tune{0, 16, 4, 4, 8, 0};  // measured best on the C2 workload
     int32_t* perm = nullptr;
     uint4* quant = nullptr;
     double* Hd = nullptr;
@@ -313,6 +340,7 @@ struct crk_leaves {
     int2* rng = nullptr;
     int32_t* order_cull = nullptr;
     int32_t* order_pair = nullptr;
+    int32_t* order_tree = nullptr;
     int32_t* counter = nullptr;
     int32_t* cnt = nullptr;
     int64_t* ell_off = nullptr;

@@ -66,11 +66,28 @@ struct Builder {
         if (!split && in.split_extent > 0.0 && count >= 2 * in.leaf_min && count >= 2)
             split = double(ext) / kGrid > in.split_extent;
         if (split && count >= 2) {
+            // Median split that keeps the current order inside each half: the
+            // left half takes the keys below the median and, among keys equal
+            // to it, the first ones in the current order.  Rebuilding on
+            // particles already in tree order therefore reproduces that order.
             const int32_t mid = b + count / 2;
             const uint32_t* key = in.q[axis];
-            std::nth_element(idx + b, idx + mid, idx + e, [key](int32_t u, int32_t v) {
-                return key[u] < key[v] || (key[u] == key[v] && u < v);
-            });
+            std::vector<uint32_t> tmp(count);
+            for (int32_t k = 0; k < count; ++k) tmp[k] = key[idx[b + k]];
+            std::nth_element(tmp.begin(), tmp.begin() + (mid - b), tmp.end());
+            const uint32_t med = tmp[mid - b];
+            int32_t need_eq = mid - b;
+            for (int32_t k = b; k < e; ++k) need_eq -= key[idx[k]] < med;
+            std::vector<int32_t> right;
+            right.reserve(e - mid);
+            int32_t w = b;
+            for (int32_t k = b; k < e; ++k) {
+                const int32_t p = idx[k];
+                const uint32_t v = key[p];
+                if (v < med || (v == med && need_eq-- > 0)) idx[w++] = p;
+                else right.push_back(p);
+            }
+            std::copy(right.begin(), right.end(), idx + w);
             int32_t l = -1, r = -1;
             if (count > 65536) {
 #pragma omp task shared(l)

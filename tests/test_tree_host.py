@@ -114,3 +114,18 @@ def test_tiny_and_ragged_inputs():
         assert sorted(perm.tolist()) == list(range(n))
         need = brute_pairs(cfg, lambda: np.maximum(H[:, None], H[None, :]))
         assert covered(perm, off, rng, need)
+
+
+def test_rebuild_on_tree_order_is_identity():
+    """Median splits keep the current order, so particles already in tree order stay put."""
+    cfg = synth.make_config("C2", n_side=16)
+    H = 2.0 * cfg["h"]
+    perm, *_ = build(cfg, H=H, leaf_max=32)
+    cfg2 = {k: cfg[k][perm] for k in ("x", "y", "z")}
+    perm2, *_ = build(cfg2, H=H[perm], leaf_max=32)
+    assert np.array_equal(perm2, np.arange(cfg["n"]))
+    lat = synth.make_lattice(n_side=16, jitter=0.0)  # many equal keys
+    p, *_ = build(lat, H=2.0 * lat["h"], leaf_max=64)
+    lat2 = {k: lat[k][p] for k in ("x", "y", "z")}
+    p2, *_ = build(lat2, H=2.0 * lat["h"], leaf_max=64)
+    assert np.array_equal(p2, np.arange(lat["n"]))
