@@ -32,7 +32,7 @@ METRIC = "CRK-SPH pair interactions/s & % FP32 VALU peak; fwd+bwd ms vs FP64 GPU
 # square root / reciprocal square root = 1), per-particle constants hoisted;
 # compensation arithmetic excluded.  Derivation in the design doc.
 FLOP_PER_PAIR = {"volume": 21, "moments": 112, "accel": 141, "gravity": 19,
-                 "accel_adj": 520, "moments_adj": 580, "volume_adj": 40}
+                 "accel_adj": 520, "moments_adj": 365, "volume_adj": 40}
 HYDRO_KERNELS = ("volume", "moments", "accel", "accel_adj", "moments_adj", "volume_adj")
 PEAK_FP32_VALU_TFLOPS = 157.3  # 256 CUs x 2.4 GHz x 256 FLOP/clk/CU
 
@@ -162,7 +162,6 @@ def bench_hydro(args, torch, crk):
     G, F = st["pairs_gather"], st["pairs_force"]
     log(f"[bench] build {build_ms:.0f} ms (list build on GPU {cull[0]:.2f} ms); identity order "
         f"after rebuild: {identity}; stats {st}")
-    G, F = st["pairs_gather"], st["pairs_force"]
     inter_fwd = 2 * G + F
     inter = inter_fwd + (G + 3 * F if not args.no_backward else 0)
     dev = g32["x"].device

@@ -226,17 +226,16 @@ __global__ __launch_bounds__(256) void k_volume(Queue qu, int n, Lists L, const 
         const int len = L.len[w];
         const uint32_t* lst = L.nbr + L.off[w] + lane;
         R S = R(1), c = R(0);  // self term: w(0) = 1
-        for (int k = 0; k < len; ++k) {
-            if (k < cnt) {
-                const uint4 qj = quant[lst[int64_t(k) * kWave]];
+        pipelined_list<uint4>(
+            lst, cnt, len, [&](uint32_t j) __attribute__((always_inline)) { return quant[j]; },
+            [&](const uint4& qj, int) __attribute__((always_inline)) {
                 const R dx = sep<R>(qi.x, qj.x), dy = sep<R>(qi.y, qj.y), dz = sep<R>(qi.z, qj.z);
                 const R r = dsqrt(dx * dx + dy * dy + dz * dz);
                 R wq, fq;
                 wendland(r * invH, wq, fq);
                 if (sizeof(R) == 4) kadd(S, c, wq);
                 else S += wq;
-            }
-        }
+            });
         if (valid) {
             const R Ssum = (S - c) * norm_W(H);
             V_out[i] = R(1) / Ssum;
@@ -310,9 +309,9 @@ __global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const i
         const int len = L.len[w];
         const uint32_t* lst = L.nbr + L.off[w] + lane;
         R acc[4] = {R(0), R(0), R(0), R(0)}, cmp[4] = {R(0), R(0), R(0), R(0)};
-        for (int k = 0; k < len; ++k) {
-            if (k < cnt) {
-                const RecAcc<R> rj = rec[lst[int64_t(k) * kWave]];
+        pipelined_list<RecAcc<R>>(
+            lst, cnt, len, [&](uint32_t j) __attribute__((always_inline)) { return rec[j]; },
+            [&](const RecAcc<R>& rj, int) __attribute__((always_inline)) {
                 const R x[3] = {sep<R>(ri.q[0], rj.q[0]), sep<R>(ri.q[1], rj.q[1]),
                                 sep<R>(ri.q[2], rj.q[2])};
                 const R xo[3] = {-x[0], -x[1], -x[2]};
@@ -334,8 +333,7 @@ __global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const i
                 }
                 if (kComp) kadd(acc[3], cmp[3], Fv);
                 else acc[3] += Fv;
-            }
-        }
+            });
         double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (valid) {
             const int i = perm[s];

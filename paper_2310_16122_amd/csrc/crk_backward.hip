@@ -175,9 +175,9 @@ __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, con
         Sums<R, 8> ob;   // Vbar, Pbar, xbar[3], vbar[3]
         cb.zero();
         ob.zero();
-        for (int k = 0; k < len; ++k) {
-            if (k < cnt) {
-                const RecBwd<R> rj = rec[lst[int64_t(k) * kWave]];
+        pipelined_list<RecBwd<R>>(
+            lst, cnt, len, [&](uint32_t j) __attribute__((always_inline)) { return rec[j]; },
+            [&](const RecBwd<R>& rj, int) __attribute__((always_inline)) {
                 const R x[3] = {sep<R>(ri.q[0], rj.q[0]), sep<R>(ri.q[1], rj.q[1]), sep<R>(ri.q[2], rj.q[2])};
                 const R y[3] = {-x[0], -x[1], -x[2]};
                 const R r = dsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
@@ -210,8 +210,7 @@ __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, con
                 corr_grad_dy(rj, Wj, Fj, F2j, y, g, xb);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) ob.add(2 + c, xb[c]);
-            }
-        }
+            });
         if (valid) {
             const int i = perm[s];
 #pragma unroll
@@ -343,12 +342,106 @@ __device__ inline void solve_moments_adjoint(const double* M, int nnb, const dou
         }
 }
 
+// Record of the moments adjoint: Mbar . phi(y) for the 40 moment kernels phi
+// of a particle (support radius 1/invH) is
+//   Phi(y) = W(r) P(y) + F(r) Q(y),   grad W = F y,  grad F = F2 y,
+// with P = P0 + P1.y + y.P2.y and Q = Q1.y + y.Q2.y + Q3(y, y, y).  The 40
+// adjoints collapse to 29 coefficients: c[0] P0, c[1..3] P1, c[4..9] P2,
+// c[10..12] Q1, c[13..18] Q2 (monomials xx xy xz yy yz zz), c[19..28] Q3
+// (monomials xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz).
+template <class R> struct alignas(16) RecMom {
+    uint32_t q[3];
+    R invH;
+    R V;
+    R c[29];
+};
+
+// 40 moment adjoints (storage order) -> 29 polynomial coefficients
+__device__ inline void moment_poly(const double* Mb, double* c) {
+    const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {0, 1, 2, 1, 2, 2};
+    const double* mu1 = Mb + 1;
+    const double* mu2 = Mb + 4;
+    const double* g0 = Mb + 10;
+    const double* g1 = Mb + 13;
+    const double* g2 = Mb + 22;
+    for (int e = 0; e < 29; ++e) c[e] = 0.0;
+    c[0] = Mb[0] + g1[0] + g1[4] + g1[8];
+    for (int e = 0; e < 3; ++e) {
+        c[1 + e] = mu1[e];
+        c[10 + e] = g0[e];
+    }
+    // cubic monomial index of sorted (a <= b <= c)
+    auto cub = [](int a, int b, int cc) {
+        int t;
+        if (a > b) { t = a; a = b; b = t; }
+        if (b > cc) { t = b; b = cc; cc = t; }
+        if (a > b) { t = a; a = b; b = t; }
+        const int base[3] = {0, 6, 9};  // monomials starting with x, y, z
+        const int off2[3][3] = {{0, 1, 2}, {0, 3, 4}, {0, 0, 5}};  // (b, c) within x-block
+        if (a == 0) return off2[b][cc];
+        if (a == 1) return base[1] + (b == 1 ? (cc == 1 ? 0 : cc == 2 ? 1 : 0) : 2);
+        return base[2];
+    };
+    for (int p = 0; p < 6; ++p) {
+        c[4 + p] = mu2[p];
+        // delta terms of g2: delta^ac x^b W + delta^bc x^a W
+        c[1 + pb[p]] += g2[3 * p + pa[p]];
+        c[1 + pa[p]] += g2[3 * p + pb[p]];
+        for (int cc = 0; cc < 3; ++cc) c[19 + cub(pa[p], pb[p], cc)] += g2[3 * p + cc];
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            const int lo = a < b ? a : b, hi = a < b ? b : a;
+            const int p = lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
+            c[13 + p] += g1[3 * a + b];
+        }
+}
+
+// grad of the symmetric quadratic form with monomial coefficients k[6] (value = y.grad / 2)
+template <class R> __device__ __forceinline__ void quad_grad(const R* k, const R y[3], R g[3]) {
+    g[0] = R(2) * k[0] * y[0] + k[1] * y[1] + k[2] * y[2];
+    g[1] = k[1] * y[0] + R(2) * k[3] * y[1] + k[4] * y[2];
+    g[2] = k[2] * y[0] + k[4] * y[1] + R(2) * k[5] * y[2];
+}
+
+// grad of the symmetric cubic form with monomial coefficients k[10] (value = y.grad / 3)
+template <class R> __device__ __forceinline__ void cubic_grad(const R* k, const R Y2[6], R g[3]) {
+    g[0] = R(3) * k[0] * Y2[0] + R(2) * k[1] * Y2[1] + R(2) * k[2] * Y2[2] + k[3] * Y2[3] + k[4] * Y2[4] +
+           k[5] * Y2[5];
+    g[1] = k[1] * Y2[0] + R(2) * k[3] * Y2[1] + k[4] * Y2[2] + R(3) * k[6] * Y2[3] + R(2) * k[7] * Y2[4] +
+           k[8] * Y2[5];
+    g[2] = k[2] * Y2[0] + k[4] * Y2[1] + R(2) * k[5] * Y2[2] + k[7] * Y2[3] + R(2) * k[8] * Y2[4] +
+           R(3) * k[9] * Y2[5];
+}
+
+// Phi(y) and grad Phi(y) from the 29 coefficients
+template <class R>
+__device__ __forceinline__ void moment_phi(const R* c, R W, R F, R F2, const R y[3], R& Phi, R grad[3]) {
+    R Y2[6];
+    Y2[0] = y[0] * y[0]; Y2[1] = y[0] * y[1]; Y2[2] = y[0] * y[2];
+    Y2[3] = y[1] * y[1]; Y2[4] = y[1] * y[2]; Y2[5] = y[2] * y[2];
+    R gP2[3], gQ2[3], gQ3[3];
+    quad_grad(c + 4, y, gP2);
+    quad_grad(c + 13, y, gQ2);
+    cubic_grad(c + 19, Y2, gQ3);
+    const R yP2 = y[0] * gP2[0] + y[1] * gP2[1] + y[2] * gP2[2];
+    const R yQ2 = y[0] * gQ2[0] + y[1] * gQ2[1] + y[2] * gQ2[2];
+    const R yQ3 = y[0] * gQ3[0] + y[1] * gQ3[1] + y[2] * gQ3[2];
+    const R P = c[0] + c[1] * y[0] + c[2] * y[1] + c[3] * y[2] + R(0.5) * yP2;
+    const R Q = c[10] * y[0] + c[11] * y[1] + c[12] * y[2] + R(0.5) * yQ2 + yQ3 * R(1.0 / 3.0);
+    Phi = W * P + F * Q;
+    const R radial = P * F + Q * F2;
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+        grad[e] = W * (c[1 + e] + gP2[e]) + F * (c[10 + e] + gQ2[e] + gQ3[e]) + radial * y[e];
+}
+
 // 2. moments recomputed with the forward's arithmetic, then the solve adjoint
 template <class R>
 __global__ __launch_bounds__(256) void k_moments_bwd(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
                                                      const uint4* __restrict__ quant, const R* __restrict__ aux,
                                                      const R* __restrict__ Vs, const R* __restrict__ h, int chunk,
-                                                     const R* __restrict__ cbar, R* __restrict__ mbar) {
+                                                     const R* __restrict__ cbar, RecMom<R>* __restrict__ mrec) {
     const int lane = lane_id();
     QState qs;
     for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
@@ -360,132 +453,72 @@ __global__ __launch_bounds__(256) void k_moments_bwd(Queue qu, int n, Lists L, c
         int nnb = 0;
         moment_sums<R>(w, s, valid, L, quant, Vs, H, chunk, M, nnb);
         if (valid) {
-            double Cb[16], Mb[40];
+            double Cb[16], Mb[40], c[29];
             for (int e = 0; e < 16; ++e) Cb[e] = double(cbar[16 * s + e]);
             solve_moments_adjoint(M, nnb, Cb, Mb);
-            for (int e = 0; e < 40; ++e) mbar[40 * s + e] = R(Mb[e]);
+            moment_poly(Mb, c);
+            RecMom<R> r;
+            const uint4 q = quant[s];
+            r.q[0] = q.x; r.q[1] = q.y; r.q[2] = q.z;
+            r.invH = aux[2 * s];
+            r.V = aux[2 * s + 1];
+            for (int e = 0; e < 29; ++e) r.c[e] = R(c[e]);
+            mrec[s] = r;
         }
     }
-}
-
-// Phi(y) = Mbar . phi(y) for the 40 moment kernels phi of a particle with
-// kernel values W, F (grad W = F y) and F2 (grad F = F2 y), and its gradient:
-//   Phi = W P(y) + F Q(y),  grad Phi = W grad P + F grad Q + (P F + Q F2) y
-// with P = mu0 + tr(g1b) + (mu1 + nu).y + sum_p mu2[p] y^a y^b,
-//      Q = g0b.y + y.g1b.y + sum_{p,c} g2b[p][c] y^a y^b y^c.
-template <class R>
-__device__ __forceinline__ void moment_phi(const R* Mb, R W, R F, R F2, const R y[3], R& Phi, R grad[3]) {
-    const int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {0, 1, 2, 1, 2, 2};
-    const R* mu1 = Mb + 1;
-    const R* mu2 = Mb + 4;
-    const R* c0 = Mb + 10;
-    const R* c1 = Mb + 13;
-    const R* c2 = Mb + 22;
-    R nu[3] = {R(0), R(0), R(0)};
-    R Y2[6], T[6];
-#pragma unroll
-    for (int p = 0; p < 6; ++p) {
-        nu[pb[p]] += c2[3 * p + pa[p]];
-        nu[pa[p]] += c2[3 * p + pb[p]];
-        Y2[p] = y[pa[p]] * y[pb[p]];
-        T[p] = c2[3 * p] * y[0] + c2[3 * p + 1] * y[1] + c2[3 * p + 2] * y[2];
-    }
-    R P = Mb[0] + c1[0] + c1[4] + c1[8];
-    R Q = R(0);
-    R gP[3], gQ[3];
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-        P += (mu1[e] + nu[e]) * y[e];
-        Q += c0[e] * y[e];
-        gP[e] = mu1[e] + nu[e];
-        gQ[e] = c0[e];
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            Q += c1[3 * a + c] * y[a] * y[c];
-            gQ[a] += c1[3 * a + c] * y[c];
-            gQ[c] += c1[3 * a + c] * y[a];
-        }
-#pragma unroll
-    for (int p = 0; p < 6; ++p) {
-        P += mu2[p] * Y2[p];
-        Q += T[p] * Y2[p];
-        gP[pa[p]] += mu2[p] * y[pb[p]];
-        gP[pb[p]] += mu2[p] * y[pa[p]];
-        gQ[pa[p]] += T[p] * y[pb[p]];
-        gQ[pb[p]] += T[p] * y[pa[p]];
-#pragma unroll
-        for (int e = 0; e < 3; ++e) gQ[e] += c2[3 * p + e] * Y2[p];
-    }
-    Phi = W * P + F * Q;
-    const R radial = P * F + Q * F2;
-#pragma unroll
-    for (int e = 0; e < 3; ++e) grad[e] = W * gP[e] + F * gQ[e] + radial * y[e];
 }
 
 // 3. moments adjoint, then the per-particle volume/pressure adjoints
 template <class R>
 __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
-                                                     const uint4* __restrict__ quant, const R* __restrict__ aux,
-                                                     const R* __restrict__ mbar, const R* __restrict__ vpbar,
-                                                     const R* __restrict__ m, const R* __restrict__ u,
-                                                     const R* __restrict__ rho, R gm1, R* __restrict__ xbar,
-                                                     R* __restrict__ sbar, R* __restrict__ gu) {
+                                                     const RecMom<R>* __restrict__ mrec,
+                                                     const R* __restrict__ vpbar, const R* __restrict__ m,
+                                                     const R* __restrict__ u, const R* __restrict__ rho, R gm1,
+                                                     R* __restrict__ xbar, R* __restrict__ sbar,
+                                                     R* __restrict__ gu) {
     const int lane = lane_id();
     QState qs;
     for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
         const int s = w * kWave + lane;
         const bool valid = s < n;
-        const int so = valid ? s : 0;
-        const uint4 qi = quant[so];
-        const R invHi = aux[2 * so], Vi = aux[2 * so + 1];
+        const RecMom<R> ri = mrec[valid ? s : 0];
+        const R invHi = ri.invH, Vi = ri.V;
         const R i2 = invHi * invHi;
         const R cWi = R(495.0 / (32.0 * kPi)) * i2 * invHi;
         const R cFi = R(-1155.0 / (4.0 * kPi)) * i2 * i2 * invHi;
         const R cF2i = R(17325.0 / (2.0 * kPi)) * i2 * i2 * i2 * invHi;
-        R Mi[40];
-#pragma unroll
-        for (int e = 0; e < 40; ++e) Mi[e] = mbar[40 * so + e];
         const int cnt = valid ? L.cnt[s] : 0;
         const int len = L.len[w];
         const uint32_t* lst = L.nbr + L.off[w] + lane;
         Sums<R, 4> acc;  // Vbar, xbar[3]
         acc.zero();
-        for (int k = 0; k < len; ++k) {
-            if (k < cnt) {
-                const uint32_t j = lst[int64_t(k) * kWave];
-                const uint4 qj = quant[j];
-                const R invHj = aux[2 * j], Vj = aux[2 * j + 1];
-                R Mj[40];
-#pragma unroll
-                for (int e = 0; e < 40; ++e) Mj[e] = mbar[40 * j + e];
-                const R x[3] = {sep<R>(qi.x, qj.x), sep<R>(qi.y, qj.y), sep<R>(qi.z, qj.z)};
+        pipelined_list<RecMom<R>>(
+            lst, cnt, len, [&](uint32_t j) __attribute__((always_inline)) { return mrec[j]; },
+            [&](const RecMom<R>& rj, int) __attribute__((always_inline)) {
+                const R x[3] = {sep<R>(ri.q[0], rj.q[0]), sep<R>(ri.q[1], rj.q[1]), sep<R>(ri.q[2], rj.q[2])};
                 const R y[3] = {-x[0], -x[1], -x[2]};
                 const R r = dsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
                 R w_, f_, f2_;
                 // own moments: M_i contains V_j phi(x_ij, h_i)
                 shapes(r * invHi, w_, f_, f2_);
                 R Phi, g[3];
-                moment_phi(Mi, cWi * w_, cFi * f_, cF2i * f2_, x, Phi, g);
-                R xb[3] = {Vj * g[0], Vj * g[1], Vj * g[2]};
+                moment_phi(ri.c, cWi * w_, cFi * f_, cF2i * f2_, x, Phi, g);
+                const R xb[3] = {rj.V * g[0], rj.V * g[1], rj.V * g[2]};
                 // the neighbour's moments contain V_i phi(x_ji, h_j)
+                const R invHj = rj.invH;
                 const R j2 = invHj * invHj;
                 shapes(r * invHj, w_, f_, f2_);
-                moment_phi(Mj, R(495.0 / (32.0 * kPi)) * j2 * invHj * w_,
+                moment_phi(rj.c, R(495.0 / (32.0 * kPi)) * j2 * invHj * w_,
                            R(-1155.0 / (4.0 * kPi)) * j2 * j2 * invHj * f_,
                            R(17325.0 / (2.0 * kPi)) * j2 * j2 * j2 * invHj * f2_, y, Phi, g);
                 acc.add(0, Phi);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) acc.add(1 + c, xb[c] - Vi * g[c]);
-            }
-        }
+            });
         if (valid) {
             const int i = perm[s];
-            // j = i term of the own moments: V_i phi(0) = V_i W(0) (m0 and the g1 diagonal)
-            const double Vbar = double(acc.get(0)) + double(cWi) * (double(Mi[0]) + Mi[13] + Mi[17] + Mi[21]) +
-                                double(vpbar[2 * s]);
+            // j = i term of the own moments: V_i phi(0) = V_i W(0) P0
+            const double Vbar = double(acc.get(0)) + double(cWi) * double(ri.c[0]) + double(vpbar[2 * s]);
             const double Pbar = double(vpbar[2 * s + 1]);
             const double rhobar = double(gm1) * double(u[i]) * Pbar;
             const double Sbar = -Vbar * double(Vi) * double(Vi) + double(m[i]) * rhobar;
@@ -519,11 +552,16 @@ __global__ __launch_bounds__(256) void k_volume_adj(Queue qu, int n, Lists L, co
         const uint32_t* lst = L.nbr + L.off[w] + lane;
         Sums<R, 3> acc;
         acc.zero();
-        for (int k = 0; k < len; ++k) {
-            if (k < cnt) {
-                const uint32_t j = lst[int64_t(k) * kWave];
-                const uint4 qj = quant[j];
-                const R invHj = aux[2 * j];
+        struct QS {
+            uint4 q;
+            R invH, sb;
+        };
+        pipelined_list<QS>(
+            lst, cnt, len,
+            [&](uint32_t j) __attribute__((always_inline)) { return QS{quant[j], aux[2 * j], sbar[j]}; },
+            [&](const QS& d, int) __attribute__((always_inline)) {
+                const uint4 qj = d.q;
+                const R invHj = d.invH;
                 const R x[3] = {sep<R>(qi.x, qj.x), sep<R>(qi.y, qj.y), sep<R>(qi.z, qj.z)};
                 const R r = dsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
                 R w_, fi, fj, f2_;
@@ -531,11 +569,10 @@ __global__ __launch_bounds__(256) void k_volume_adj(Queue qu, int n, Lists L, co
                 shapes(r * invHj, w_, fj, f2_);
                 const R j2 = invHj * invHj;
                 const R cFj = R(-1155.0 / (4.0 * kPi)) * j2 * j2 * invHj;
-                const R coef = Sbi * cFi * fi + sbar[j] * cFj * fj;
+                const R coef = Sbi * cFi * fi + d.sb * cFj * fj;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) acc.add(c, coef * x[c]);
-            }
-        }
+            });
         if (valid) {
             const int i = perm[s];
 #pragma unroll
@@ -546,7 +583,7 @@ __global__ __launch_bounds__(256) void k_volume_adj(Queue qu, int n, Lists L, co
 
 template <class T> T* carve(char*& p, size_t count) {
     T* r = reinterpret_cast<T*>(p);
-    p += (count * sizeof(T) + 255) / 256 * 256;
+    p += (count * sizeof(T) + 255) / 256 * 256;  // keep every array 256-byte aligned
     return r;
 }
 
@@ -556,7 +593,7 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
     const int n = int(L->n);
     int rc = pack_positions<R>(L, g->x, g->y, g->z, static_cast<const R*>(g->h), st);
     if (rc) return rc;
-    const size_t per = sizeof(RecBwd<R>) + 256 + sizeof(R) * (16 + 2 + 4 + 40 + 1 + 2 + 1);
+    const size_t per = sizeof(RecBwd<R>) + sizeof(RecMom<R>) + sizeof(R) * (16 + 2 + 4 + 1 + 2 + 1);
     if ((rc = ensure_scratch(L, per * size_t(n) + 8 * 256))) return rc;
     char* p = static_cast<char*>(L->scratch);
     RecBwd<R>* rec = carve<RecBwd<R>>(p, n);
@@ -565,7 +602,7 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
     R* cbar = carve<R>(p, 16 * size_t(n));
     R* vpbar = carve<R>(p, 2 * size_t(n));
     R* xbar = carve<R>(p, 4 * size_t(n));
-    R* mbar = carve<R>(p, 40 * size_t(n));
+    RecMom<R>* mrec = carve<RecMom<R>>(p, n);
     R* sbar = carve<R>(p, n);
     const R gm1 = R(gamma - 1.0);
     {
@@ -593,15 +630,15 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
     {
         TimeScope ts(L, st, CRK_K_MOMENTS);  // the forward moments, recomputed
         hipLaunchKernelGGL(k_moments_bwd<R>, grid, block, 0, st, q, n, lists(L), L->perm, L->quant, aux,
-                           Vs, static_cast<const R*>(g->h), L->tune.kahan_chunk, cbar, mbar);
+                           Vs, static_cast<const R*>(g->h), L->tune.kahan_chunk, cbar, mrec);
     }
     LAUNCH_CHECK("moments recompute + solve adjoint");
     reset_queue(L, st);
     {
         TimeScope ts(L, st, CRK_K_MOMENTS_ADJ);
-        hipLaunchKernelGGL(k_moments_adj<R>, grid, block, 0, st, q, n, lists(L), L->perm, L->quant, aux,
-                           mbar, vpbar, static_cast<const R*>(g->m), static_cast<const R*>(g->u), rho,
-                           gm1, xbar, sbar, gu);
+        hipLaunchKernelGGL(k_moments_adj<R>, grid, block, 0, st, q, n, lists(L), L->perm, mrec, vpbar,
+                           static_cast<const R*>(g->m), static_cast<const R*>(g->u), rho, gm1, xbar,
+                           sbar, gu);
     }
     LAUNCH_CHECK("moments adjoint");
     reset_queue(L, st);

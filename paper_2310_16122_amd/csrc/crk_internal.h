@@ -174,6 +174,29 @@ struct Lists {
 
 
 
+// Neighbour-list loop of one lane with software-pipelined loads: the list
+// index of entry k+2 and the data of entry k+1 are requested before entry k is
+// processed, so the two dependent memory round trips per neighbour overlap the
+// arithmetic.  lst points at the lane's entry 0 (entry k at lst[64 k]);
+// load(j) fetches neighbour j's data; body(d, k) runs for k < cnt.  Every lane
+// of the wave runs `len` (the tile's longest list) iterations.
+template <class D, class Load, class Body>
+__device__ __forceinline__ void pipelined_list(const uint32_t* __restrict__ lst, int cnt, int len,
+                                               Load load, Body body) {
+    uint32_t j2 = 0;
+    D d1;
+    if (cnt > 0) d1 = load(lst[0]);
+    if (cnt > 1) j2 = lst[kWave];
+    for (int k = 0; k < len; ++k) {
+        const D dc = d1;
+        uint32_t jn = 0;
+        if (k + 2 < cnt) jn = lst[int64_t(k + 2) * kWave];
+        if (k + 1 < cnt) d1 = load(j2);
+        j2 = jn;
+        if (k < cnt) body(dc, k);
+    }
+}
+
 // ------------------------------------------------------------------ moments
 
 // The 40 correction moments of the lane's particle in FP64 (storage order:
@@ -203,11 +226,15 @@ __device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, con
     for (int e = 0; e < 40; ++e) { p[e] = R(0); sm[e] = R(0); cm[e] = R(0); }
     nnb = 0;
     int kk = 0;
-    for (int k = 0; k < len; ++k) {
-        if (k < cnt) {
-            const uint32_t j = lst[int64_t(k) * kWave];
-            const uint4 qj = quant[j];
-            const R Vj = Vs[j];
+    struct QV {
+        uint4 q;
+        R V;
+    };
+    pipelined_list<QV>(
+        lst, cnt, len, [&](uint32_t j) __attribute__((always_inline)) { return QV{quant[j], Vs[j]}; },
+        [&](const QV& d, int) __attribute__((always_inline)) {
+            const uint4 qj = d.q;
+            const R Vj = d.V;
             const R x[3] = {sep<R>(qi.x, qj.x), sep<R>(qi.y, qj.y), sep<R>(qi.z, qj.z)};
             const R r = dsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
             const R q = r * invH;
@@ -235,13 +262,12 @@ __device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, con
             for (int e = 0; e < 6; ++e)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) p[22 + 3 * e + c] += xx[e] * fx[c];
-        }
-        if (kComp && ++kk == chunk) {
+            if (kComp && ++kk == chunk) {
 #pragma unroll
-            for (int e = 0; e < 40; ++e) { kadd(sm[e], cm[e], p[e]); p[e] = R(0); }
-            kk = 0;
-        }
-    }
+                for (int e = 0; e < 40; ++e) { kadd(sm[e], cm[e], p[e]); p[e] = R(0); }
+                kk = 0;
+            }
+        });
 #pragma unroll
     for (int e = 0; e < 40; ++e) {
         if (kComp) {

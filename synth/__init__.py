@@ -114,15 +114,18 @@ def knn_support(x, y, z, n_target, chunk=1 << 18, workers=-1):
     pts = np.stack([x, y, z], axis=1)
     tree = cKDTree(pts, boxsize=1.0)
     n_target = np.asarray(n_target, dtype=np.int64)
-    kmax = int(n_target.max()) + 2  # self + (n+1) neighbours
     H = np.empty(len(x))
-    for s in range(0, len(x), chunk):
-        e = min(s + chunk, len(x))
-        d, _ = tree.query(pts[s:e], k=kmax, workers=workers)
-        nt = n_target[s:e]
-        rows = np.arange(e - s)
-        # d[:, 0] is the particle itself; d[:, n] is the n-th neighbour
-        H[s:e] = 0.5 * (d[rows, nt] + d[rows, nt + 1])
+    # particles with similar targets are queried together with k = group max + 2
+    kq = (n_target + 2 + 15) // 16 * 16
+    for k in np.unique(kq):
+        sel = np.nonzero(kq == k)[0]
+        for s in range(0, len(sel), max(1, chunk * 64 // int(k))):
+            idx = sel[s:s + max(1, chunk * 64 // int(k))]
+            d, _ = tree.query(pts[idx], k=int(k), workers=workers)
+            nt = n_target[idx]
+            rows = np.arange(len(idx))
+            # d[:, 0] is the particle itself; d[:, n] is the n-th neighbour
+            H[idx] = 0.5 * (d[rows, nt] + d[rows, nt + 1])
     return H
 
 
