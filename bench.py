@@ -298,6 +298,8 @@ def main():
     ap.add_argument("--no-backward", action="store_true", help="forward passes only")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the run, copy a buffer of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this library has no multi-GPU path "
@@ -313,6 +315,16 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     out = bench_gravity(args, torch, crk) if args.config == "C3" else bench_hydro(args, torch, crk)
+    if args.calibrate_copy:
+        # a plain device copy of known size: its FETCH_SIZE / WRITE_SIZE counter
+        # readings calibrate the counters of the pair kernels
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = nbytes
     print(json.dumps(out), flush=True)
 
 

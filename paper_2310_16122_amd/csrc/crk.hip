@@ -106,6 +106,7 @@ __global__ __launch_bounds__(64) void k_cull(Queue qu, int n, const uint4* __res
                                              const int32_t* __restrict__ rng_off,
                                              const int2* __restrict__ rng, int32_t* cnt_out,
                                              const int64_t* __restrict__ ell_off,
+                                             const int32_t* __restrict__ ell_len,
                                              uint32_t* __restrict__ nbr) {
     __shared__ uint4 sj[kWave];
     const int lane = lane_id();
@@ -144,6 +145,12 @@ __global__ __launch_bounds__(64) void k_cull(Queue qu, int n, const uint4* __res
             }
         }
         if (!FILL && valid) cnt_out[s] = c;
+        if (FILL) {
+            // pad the unused slots of the tile's list with a valid index (the
+            // lane's own particle, or the tile's first one for lanes past n)
+            const uint32_t self = uint32_t(valid ? s : w * kWave);
+            for (int k = cap; k < ell_len[w]; ++k) nbr[base_off + int64_t(k) * kWave + lane] = self;
+        }
     }
 }
 
@@ -250,11 +257,13 @@ __global__ __launch_bounds__(256) void k_volume(Queue qu, int n, Lists L, const 
 // caller order.
 template <class R>
 __global__ __launch_bounds__(256) void k_moments(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
-                                                 const uint4* __restrict__ quant, const R* __restrict__ Vs,
+                                                 const RecQV<R>* __restrict__ qv,
                                                  const R* __restrict__ h, int chunk, R* __restrict__ A_out,
                                                  R* __restrict__ B_out, R* __restrict__ dA_out,
                                                  R* __restrict__ dB_out,
                                                  unsigned long long* __restrict__ n_fallback) {
+    constexpr int kStage = sizeof(RecQV<R>) > 16 ? int(sizeof(RecQV<R>) / 16) * kWave : 1;
+    __shared__ uint4 stage_buf[4 * kStage];
     const int lane = lane_id();
     QState qs;
     for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
@@ -264,7 +273,7 @@ __global__ __launch_bounds__(256) void k_moments(Queue qu, int n, Lists L, const
         const R H = valid ? R(2) * h[i] : R(1);
         double M[40];
         int nnb = 0;
-        moment_sums<R>(w, s, valid, L, quant, Vs, H, chunk, M, nnb);
+        moment_sums<R>(w, s, valid, L, qv, stage_buf + (threadIdx.x >> 6) * kStage, H, chunk, M, nnb);
         if (valid) {
             double Ad, Bd[3], dAd[3], dBd[9];
             const int fb = solve_moments(M, nnb, Ad, Bd, dAd, dBd);
@@ -299,6 +308,8 @@ __global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const i
                                                R* __restrict__ a_out, R* __restrict__ du_out,
                                                double* __restrict__ partials) {
     constexpr bool kComp = sizeof(R) == 4;
+    constexpr int kStage = int(sizeof(RecAcc<R>) / 16) * kWave;
+    __shared__ uint4 stage_buf[4 * kStage];
     const int lane = lane_id();
     QState qs;
     for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
@@ -309,8 +320,8 @@ __global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const i
         const int len = L.len[w];
         const uint32_t* lst = L.nbr + L.off[w] + lane;
         R acc[4] = {R(0), R(0), R(0), R(0)}, cmp[4] = {R(0), R(0), R(0), R(0)};
-        pipelined_list<RecAcc<R>>(
-            lst, cnt, len, [&](uint32_t j) __attribute__((always_inline)) { return rec[j]; },
+        staged_list<RecAcc<R>>(
+            lst, cnt, len, rec, stage_buf + (threadIdx.x >> 6) * kStage,
             [&](const RecAcc<R>& rj, int) __attribute__((always_inline)) {
                 const R x[3] = {sep<R>(ri.q[0], rj.q[0]), sep<R>(ri.q[1], rj.q[1]),
                                 sep<R>(ri.q[2], rj.q[2])};
@@ -554,17 +565,17 @@ int corrections_impl(crk_leaves* L, const crk_gas* g, const R* V, const crk_corr
     const int n = int(L->n);
     int rc = pack_positions<R>(L, g->x, g->y, g->z, static_cast<const R*>(g->h), st);
     if (rc) return rc;
-    if ((rc = ensure_scratch(L, sizeof(R) * size_t(n)))) return rc;
-    R* Vs = static_cast<R*>(L->scratch);
+    if ((rc = ensure_scratch(L, sizeof(RecQV<R>) * size_t(n)))) return rc;
+    RecQV<R>* qv = static_cast<RecQV<R>*>(L->scratch);
     {
         TimeScope tp(L, st, CRK_K_PACK);
-        hipLaunchKernelGGL(k_gather<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, V, Vs);
+        hipLaunchKernelGGL(k_pack_qv<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, L->quant, V, qv);
     }
-    LAUNCH_CHECK("gather V");
+    LAUNCH_CHECK("pack position/volume");
     reset_queue(L, st);
     TimeScope ts(L, st, CRK_K_MOMENTS);
     hipLaunchKernelGGL(k_moments<R>, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves), 0, st,
-                       make_queue(L, L->order_pair), n, lists(L), L->perm, L->quant, Vs,
+                       make_queue(L, L->order_pair), n, lists(L), L->perm, qv,
                        static_cast<const R*>(g->h), L->tune.kahan_chunk, static_cast<R*>(out->A),
                        static_cast<R*>(out->B), static_cast<R*>(out->dA), static_cast<R*>(out->dB),
                        reinterpret_cast<unsigned long long*>(n_fallback));
@@ -834,7 +845,7 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
             TimeScope ts(L, stream, CRK_K_CULL);
             hipLaunchKernelGGL(k_cull<false>, dim3(grid_1wave(L)), dim3(kWave), 0, stream,
                                make_queue(L, L->order_cull), int(n), L->quant, L->rng_off, L->rng,
-                               L->cnt, nullptr, nullptr);
+                               L->cnt, nullptr, nullptr, nullptr);
         }
         if (hipGetLastError() != hipSuccess) return bail(fail(CRK_EHIP, "launch cull count failed"));
         std::vector<int32_t> hc(n);
@@ -863,7 +874,7 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
             TimeScope ts(L, stream, CRK_K_CULL);
             hipLaunchKernelGGL(k_cull<true>, dim3(grid_1wave(L)), dim3(kWave), 0, stream,
                                make_queue(L, L->order_cull), int(n), L->quant, L->rng_off, L->rng,
-                               L->cnt, L->ell_off, L->nbr);
+                               L->cnt, L->ell_off, L->ell_len, L->nbr);
         }
         L->timing = false;
         if (hipGetLastError() != hipSuccess) return bail(fail(CRK_EHIP, "launch cull fill failed"));

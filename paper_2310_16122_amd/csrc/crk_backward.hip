@@ -162,6 +162,8 @@ __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, con
                                                    const RecBwd<R>* __restrict__ rec, R* __restrict__ cbar,
                                                    R* __restrict__ vpbar, R* __restrict__ xbar,
                                                    R* __restrict__ gv) {
+    constexpr int kStage = int(sizeof(RecBwd<R>) / 16) * kWave;
+    __shared__ uint4 stage_buf[4 * kStage];
     const int lane = lane_id();
     QState qs;
     for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
@@ -175,8 +177,8 @@ __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, con
         Sums<R, 8> ob;   // Vbar, Pbar, xbar[3], vbar[3]
         cb.zero();
         ob.zero();
-        pipelined_list<RecBwd<R>>(
-            lst, cnt, len, [&](uint32_t j) __attribute__((always_inline)) { return rec[j]; },
+        staged_list<RecBwd<R>>(
+            lst, cnt, len, rec, stage_buf + (threadIdx.x >> 6) * kStage,
             [&](const RecBwd<R>& rj, int) __attribute__((always_inline)) {
                 const R x[3] = {sep<R>(ri.q[0], rj.q[0]), sep<R>(ri.q[1], rj.q[1]), sep<R>(ri.q[2], rj.q[2])};
                 const R y[3] = {-x[0], -x[1], -x[2]};
@@ -436,12 +438,22 @@ __device__ __forceinline__ void moment_phi(const R* c, R W, R F, R F2, const R y
         grad[e] = W * (c[1 + e] + gP2[e]) + F * (c[10 + e] + gQ2[e] + gQ3[e]) + radial * y[e];
 }
 
+// Record of the volume adjoint: position, 1/H and Sbar of a neighbour.
+template <class R> struct alignas(16) RecVA {
+    uint32_t q[3];
+    R invH;
+    R Sbar;
+};
+
 // 2. moments recomputed with the forward's arithmetic, then the solve adjoint
 template <class R>
 __global__ __launch_bounds__(256) void k_moments_bwd(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
                                                      const uint4* __restrict__ quant, const R* __restrict__ aux,
-                                                     const R* __restrict__ Vs, const R* __restrict__ h, int chunk,
-                                                     const R* __restrict__ cbar, RecMom<R>* __restrict__ mrec) {
+                                                     const RecQV<R>* __restrict__ qv, const R* __restrict__ h,
+                                                     int chunk, const R* __restrict__ cbar,
+                                                     RecMom<R>* __restrict__ mrec) {
+    constexpr int kStage = sizeof(RecQV<R>) > 16 ? int(sizeof(RecQV<R>) / 16) * kWave : 1;
+    __shared__ uint4 stage_buf[4 * kStage];
     const int lane = lane_id();
     QState qs;
     for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
@@ -451,7 +463,7 @@ __global__ __launch_bounds__(256) void k_moments_bwd(Queue qu, int n, Lists L, c
         const R H = valid ? R(2) * h[i] : R(1);
         double M[40];
         int nnb = 0;
-        moment_sums<R>(w, s, valid, L, quant, Vs, H, chunk, M, nnb);
+        moment_sums<R>(w, s, valid, L, qv, stage_buf + (threadIdx.x >> 6) * kStage, H, chunk, M, nnb);
         if (valid) {
             double Cb[16], Mb[40], c[29];
             for (int e = 0; e < 16; ++e) Cb[e] = double(cbar[16 * s + e]);
@@ -474,8 +486,10 @@ __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, c
                                                      const RecMom<R>* __restrict__ mrec,
                                                      const R* __restrict__ vpbar, const R* __restrict__ m,
                                                      const R* __restrict__ u, const R* __restrict__ rho, R gm1,
-                                                     R* __restrict__ xbar, R* __restrict__ sbar,
+                                                     R* __restrict__ xbar, RecVA<R>* __restrict__ varec,
                                                      R* __restrict__ gu) {
+    constexpr int kStage = int(sizeof(RecMom<R>) / 16) * kWave;
+    __shared__ uint4 stage_buf[4 * kStage];
     const int lane = lane_id();
     QState qs;
     for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
@@ -492,8 +506,8 @@ __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, c
         const uint32_t* lst = L.nbr + L.off[w] + lane;
         Sums<R, 4> acc;  // Vbar, xbar[3]
         acc.zero();
-        pipelined_list<RecMom<R>>(
-            lst, cnt, len, [&](uint32_t j) __attribute__((always_inline)) { return mrec[j]; },
+        staged_list<RecMom<R>>(
+            lst, cnt, len, mrec, stage_buf + (threadIdx.x >> 6) * kStage,
             [&](const RecMom<R>& rj, int) __attribute__((always_inline)) {
                 const R x[3] = {sep<R>(ri.q[0], rj.q[0]), sep<R>(ri.q[1], rj.q[1]), sep<R>(ri.q[2], rj.q[2])};
                 const R y[3] = {-x[0], -x[1], -x[2]};
@@ -522,7 +536,11 @@ __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, c
             const double Pbar = double(vpbar[2 * s + 1]);
             const double rhobar = double(gm1) * double(u[i]) * Pbar;
             const double Sbar = -Vbar * double(Vi) * double(Vi) + double(m[i]) * rhobar;
-            sbar[s] = R(Sbar);
+            RecVA<R> va{};
+            va.q[0] = ri.q[0]; va.q[1] = ri.q[1]; va.q[2] = ri.q[2];
+            va.invH = invHi;
+            va.Sbar = R(Sbar);
+            varec[s] = va;
             gu[i] = R(double(gm1) * double(rho[i]) * Pbar);
 #pragma unroll
             for (int c = 0; c < 3; ++c) xbar[4 * s + c] += acc.get(1 + c);
@@ -533,43 +551,37 @@ __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, c
 // 4. volume adjoint; writes the position gradient in caller order
 template <class R>
 __global__ __launch_bounds__(256) void k_volume_adj(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
-                                                    const uint4* __restrict__ quant, const R* __restrict__ aux,
-                                                    const R* __restrict__ sbar, const R* __restrict__ xbar,
-                                                    R* __restrict__ gx) {
+                                                    const RecVA<R>* __restrict__ varec,
+                                                    const R* __restrict__ xbar, R* __restrict__ gx) {
+    constexpr int kStage = int(sizeof(RecVA<R>) / 16) * kWave;
+    __shared__ uint4 stage_buf[4 * kStage];
     const int lane = lane_id();
     QState qs;
     for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
         const int s = w * kWave + lane;
         const bool valid = s < n;
-        const int so = valid ? s : 0;
-        const uint4 qi = quant[so];
-        const R invHi = aux[2 * so];
+        const RecVA<R> ri = varec[valid ? s : 0];
+        const R invHi = ri.invH;
         const R i2 = invHi * invHi;
         const R cFi = R(-1155.0 / (4.0 * kPi)) * i2 * i2 * invHi;
-        const R Sbi = sbar[so];
+        const R Sbi = ri.Sbar;
         const int cnt = valid ? L.cnt[s] : 0;
         const int len = L.len[w];
         const uint32_t* lst = L.nbr + L.off[w] + lane;
         Sums<R, 3> acc;
         acc.zero();
-        struct QS {
-            uint4 q;
-            R invH, sb;
-        };
-        pipelined_list<QS>(
-            lst, cnt, len,
-            [&](uint32_t j) __attribute__((always_inline)) { return QS{quant[j], aux[2 * j], sbar[j]}; },
-            [&](const QS& d, int) __attribute__((always_inline)) {
-                const uint4 qj = d.q;
+        list_loop<RecVA<R>>(
+            lst, cnt, len, varec, stage_buf + (threadIdx.x >> 6) * kStage,
+            [&](const RecVA<R>& d, int) __attribute__((always_inline)) {
                 const R invHj = d.invH;
-                const R x[3] = {sep<R>(qi.x, qj.x), sep<R>(qi.y, qj.y), sep<R>(qi.z, qj.z)};
+                const R x[3] = {sep<R>(ri.q[0], d.q[0]), sep<R>(ri.q[1], d.q[1]), sep<R>(ri.q[2], d.q[2])};
                 const R r = dsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
                 R w_, fi, fj, f2_;
                 shapes(r * invHi, w_, fi, f2_);
                 shapes(r * invHj, w_, fj, f2_);
                 const R j2 = invHj * invHj;
                 const R cFj = R(-1155.0 / (4.0 * kPi)) * j2 * j2 * invHj;
-                const R coef = Sbi * cFi * fi + d.sb * cFj * fj;
+                const R coef = Sbi * cFi * fi + d.Sbar * cFj * fj;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) acc.add(c, coef * x[c]);
             });
@@ -593,17 +605,18 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
     const int n = int(L->n);
     int rc = pack_positions<R>(L, g->x, g->y, g->z, static_cast<const R*>(g->h), st);
     if (rc) return rc;
-    const size_t per = sizeof(RecBwd<R>) + sizeof(RecMom<R>) + sizeof(R) * (16 + 2 + 4 + 1 + 2 + 1);
+    const size_t per = sizeof(RecBwd<R>) + sizeof(RecMom<R>) + sizeof(RecQV<R>) + sizeof(RecVA<R>) +
+                       sizeof(R) * (16 + 2 + 4 + 2);
     if ((rc = ensure_scratch(L, per * size_t(n) + 8 * 256))) return rc;
     char* p = static_cast<char*>(L->scratch);
     RecBwd<R>* rec = carve<RecBwd<R>>(p, n);
     R* aux = carve<R>(p, 2 * size_t(n));
-    R* Vs = carve<R>(p, n);
+    RecQV<R>* qv = carve<RecQV<R>>(p, n);
     R* cbar = carve<R>(p, 16 * size_t(n));
     R* vpbar = carve<R>(p, 2 * size_t(n));
     R* xbar = carve<R>(p, 4 * size_t(n));
     RecMom<R>* mrec = carve<RecMom<R>>(p, n);
-    R* sbar = carve<R>(p, n);
+    RecVA<R>* varec = carve<RecVA<R>>(p, n);
     const R gm1 = R(gamma - 1.0);
     {
         TimeScope tp(L, st, CRK_K_PACK);
@@ -614,7 +627,7 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
                            static_cast<const R*>(C->A), static_cast<const R*>(C->B),
                            static_cast<const R*>(C->dA), static_cast<const R*>(C->dB), ga, gdu, gm1,
                            rec, aux);
-        hipLaunchKernelGGL(k_gather<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, V, Vs);
+        hipLaunchKernelGGL(k_pack_qv<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, L->quant, V, qv);
     }
     LAUNCH_CHECK("pack backward");
     const dim3 grid(grid_nwave(L)), block(kWave * L->tune.block_waves);
@@ -630,7 +643,7 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
     {
         TimeScope ts(L, st, CRK_K_MOMENTS);  // the forward moments, recomputed
         hipLaunchKernelGGL(k_moments_bwd<R>, grid, block, 0, st, q, n, lists(L), L->perm, L->quant, aux,
-                           Vs, static_cast<const R*>(g->h), L->tune.kahan_chunk, cbar, mrec);
+                           qv, static_cast<const R*>(g->h), L->tune.kahan_chunk, cbar, mrec);
     }
     LAUNCH_CHECK("moments recompute + solve adjoint");
     reset_queue(L, st);
@@ -638,14 +651,13 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
         TimeScope ts(L, st, CRK_K_MOMENTS_ADJ);
         hipLaunchKernelGGL(k_moments_adj<R>, grid, block, 0, st, q, n, lists(L), L->perm, mrec, vpbar,
                            static_cast<const R*>(g->m), static_cast<const R*>(g->u), rho, gm1, xbar,
-                           sbar, gu);
+                           varec, gu);
     }
     LAUNCH_CHECK("moments adjoint");
     reset_queue(L, st);
     {
         TimeScope ts(L, st, CRK_K_VOLUME_ADJ);
-        hipLaunchKernelGGL(k_volume_adj<R>, grid, block, 0, st, q, n, lists(L), L->perm, L->quant, aux,
-                           sbar, xbar, gx);
+        hipLaunchKernelGGL(k_volume_adj<R>, grid, block, 0, st, q, n, lists(L), L->perm, varec, xbar, gx);
     }
     LAUNCH_CHECK("volume adjoint");
     return CRK_OK;

@@ -174,26 +174,129 @@ struct Lists {
 
 
 
-// Neighbour-list loop of one lane with software-pipelined loads: the list
-// index of entry k+2 and the data of entry k+1 are requested before entry k is
-// processed, so the two dependent memory round trips per neighbour overlap the
-// arithmetic.  lst points at the lane's entry 0 (entry k at lst[64 k]);
-// load(j) fetches neighbour j's data; body(d, k) runs for k < cnt.  Every lane
-// of the wave runs `len` (the tile's longest list) iterations.
+// Neighbour-list loop of one lane with software-pipelined loads: the data of
+// entry k+1 and the list indices of entries k+2, k+3 are requested before
+// entry k is processed, so the two dependent memory round trips per neighbour
+// overlap the arithmetic.  The loop is unrolled by two with ping-pong buffers
+// and every load is unconditional: slots past a lane's count hold a valid
+// index (the list build pads them with the lane's own particle) and slot
+// numbers are clamped to the tile's last slot, so no record is copied between
+// iterations.  lst points at the lane's slot 0 (slot k at lst[64 k]); len is
+// the tile's longest list; load(j) fetches neighbour j's data; body(d, k) runs
+// for k < cnt.
 template <class D, class Load, class Body>
 __device__ __forceinline__ void pipelined_list(const uint32_t* __restrict__ lst, int cnt, int len,
                                                Load load, Body body) {
-    uint32_t j2 = 0;
-    D d1;
-    if (cnt > 0) d1 = load(lst[0]);
-    if (cnt > 1) j2 = lst[kWave];
+    if (len <= 0) return;
+    const int last = len - 1;
+    auto slot = [&](int k) __attribute__((always_inline)) {
+        return lst[int64_t(k < last ? k : last) * kWave];
+    };
+    D dA = load(slot(0));
+    uint32_t jB = slot(1);
+    for (int k = 0; k < len; k += 2) {
+        const uint32_t jC = slot(k + 2);
+        const D dB = load(jB);
+        if (k < cnt) body(dA, k);
+        jB = slot(k + 3);
+        dA = load(jC);
+        if (k + 1 < cnt) body(dB, k + 1);
+    }
+}
+
+// Neighbour-list loop for large per-particle records (NCH 16-byte chunks),
+// staged through LDS.  A per-lane gather of a record touches one cache line
+// per lane per 16-byte load, and the L1 resolves about one line per clock, so
+// gathering records lane by lane costs NCH x 64 line lookups per wave and slot.
+// Here the wave loads the 64 records of a slot cooperatively -- consecutive
+// lanes fetch consecutive chunks of the same record, i.e. whole lines -- with
+// direct global-to-LDS loads into a wave-private buffer, then every lane reads
+// its own record from LDS.  LDS position p (in 16-byte units) holds chunk
+// (p % NCH) ^ swz(r) of record r = p / NCH; the swizzle (power-of-two NCH
+// only) keeps the lanes' reads of one chunk on distinct banks.  The next
+// slot is staged while the current one is processed.  `lds` is this wave's
+// buffer of NCH x 64 uint4; slots past a lane's count hold valid indices.
+template <int NCH> __device__ __forceinline__ int stage_swz(int r) {
+    if ((NCH & (NCH - 1)) != 0) return 0;  // odd strides are conflict-free as they are
+    return (r ^ (r >> 3)) & (NCH - 1);
+}
+
+template <class D, class Body>
+__device__ __forceinline__ void staged_list(const uint32_t* __restrict__ lst, int cnt, int len,
+                                            const D* __restrict__ recs, uint4* __restrict__ lds,
+                                            Body body) {
+    constexpr int NCH = int(sizeof(D) / 16);
+    static_assert(sizeof(D) % 16 == 0, "records are whole 16-byte chunks");
+    if (len <= 0) return;
+    const int lane = lane_id();
+    const int last = len - 1;
+    auto slot = [&](int k) __attribute__((always_inline)) {
+        return lst[int64_t(k < last ? k : last) * kWave];
+    };
+    auto stage = [&](uint32_t j) __attribute__((always_inline)) {
+        const char* base = reinterpret_cast<const char*>(recs);
+#pragma unroll
+        for (int t = 0; t < NCH; ++t) {
+            const int g = t * kWave + lane;
+            const int r = g / NCH;
+            const int c = (g % NCH) ^ stage_swz<NCH>(r);
+            const uint32_t jr = uint32_t(__shfl(int(j), r));
+            __builtin_amdgcn_global_load_lds(base + size_t(jr) * sizeof(D) + size_t(c) * 16, lds + t * kWave,
+                                             16, 0, 0);
+        }
+    };
+    const int sw = stage_swz<NCH>(lane);
+    stage(slot(0));
+    uint32_t jn = slot(1);
     for (int k = 0; k < len; ++k) {
-        const D dc = d1;
-        uint32_t jn = 0;
-        if (k + 2 < cnt) jn = lst[int64_t(k + 2) * kWave];
-        if (k + 1 < cnt) d1 = load(j2);
-        j2 = jn;
-        if (k < cnt) body(dc, k);
+        __builtin_amdgcn_s_waitcnt(0);  // this slot's records are in LDS
+        D d;
+        uint4* dst = reinterpret_cast<uint4*>(&d);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) dst[c] = lds[lane * NCH + (c ^ sw)];
+        __builtin_amdgcn_s_waitcnt(0);  // reads done before the buffer is refilled
+        if (k + 1 < len) {
+            stage(jn);
+            jn = slot(k + 2);
+        }
+        if (k < cnt) body(d, k);
+    }
+}
+
+// Position and volume of a neighbour, the moments pass's per-pair data.
+template <class R> struct alignas(16) RecQV;
+template <> struct alignas(16) RecQV<float> {
+    uint32_t q[3];
+    float V;
+};
+template <> struct alignas(16) RecQV<double> {
+    uint32_t q[3];
+    uint32_t unused;
+    double V;
+    double unused2;
+};
+
+template <class R> __global__ void k_pack_qv(int n, const int32_t* perm, const uint4* quant, const R* V,
+                                             RecQV<R>* out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    RecQV<R> r{};
+    const uint4 q = quant[s];
+    r.q[0] = q.x; r.q[1] = q.y; r.q[2] = q.z;
+    r.V = V[perm[s]];
+    out[s] = r;
+}
+
+// One-chunk records are gathered lane by lane (a cooperative load saves
+// nothing there); larger ones are staged through LDS.
+template <class D, class Body>
+__device__ __forceinline__ void list_loop(const uint32_t* __restrict__ lst, int cnt, int len,
+                                          const D* __restrict__ recs, uint4* __restrict__ lds, Body body) {
+    if constexpr (sizeof(D) == 16) {
+        pipelined_list<D>(
+            lst, cnt, len, [&](uint32_t j) __attribute__((always_inline)) { return recs[j]; }, body);
+    } else {
+        staged_list<D>(lst, cnt, len, recs, lds, body);
     }
 }
 
@@ -211,11 +314,12 @@ __device__ __forceinline__ void pipelined_list(const uint32_t* __restrict__ lst,
 // `chunk` pairs folded into compensated sums.  Every lane of the wave must call
 // this (the loop runs over the tile's longest list).
 template <class R>
-__device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, const uint4* __restrict__ quant,
-                                   const R* __restrict__ Vs, R H, int chunk, double M[40], int& nnb) {
+__device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, const RecQV<R>* __restrict__ qv,
+                                   uint4* __restrict__ lds, R H, int chunk, double M[40], int& nnb) {
     constexpr bool kComp = sizeof(R) == 4;
     const int lane = lane_id();
-    const uint4 qi = valid ? quant[s] : make_uint4(0, 0, 0, 0);
+    const RecQV<R> self = qv[valid ? s : 0];
+    const uint4 qi = make_uint4(self.q[0], self.q[1], self.q[2], 0u);
     const R invH = R(1) / H;
     const R cW = norm_W(H), cF = norm_F(H);
     const int cnt = valid ? L.cnt[s] : 0;
@@ -226,16 +330,11 @@ __device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, con
     for (int e = 0; e < 40; ++e) { p[e] = R(0); sm[e] = R(0); cm[e] = R(0); }
     nnb = 0;
     int kk = 0;
-    struct QV {
-        uint4 q;
-        R V;
-    };
-    pipelined_list<QV>(
-        lst, cnt, len, [&](uint32_t j) __attribute__((always_inline)) { return QV{quant[j], Vs[j]}; },
-        [&](const QV& d, int) __attribute__((always_inline)) {
-            const uint4 qj = d.q;
+    list_loop<RecQV<R>>(
+        lst, cnt, len, qv, lds,
+        [&](const RecQV<R>& d, int) __attribute__((always_inline)) {
             const R Vj = d.V;
-            const R x[3] = {sep<R>(qi.x, qj.x), sep<R>(qi.y, qj.y), sep<R>(qi.z, qj.z)};
+            const R x[3] = {sep<R>(qi.x, d.q[0]), sep<R>(qi.y, d.q[1]), sep<R>(qi.z, d.q[2])};
             const R r = dsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
             const R q = r * invH;
             R wq, fq;
@@ -277,7 +376,7 @@ __device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, con
             M[e] = double(p[e]);
         }
     }
-    if (valid) M[0] += double(cW) * double(Vs[s]);  // j = i
+    if (valid) M[0] += double(cW) * double(self.V);  // j = i
     const int sym[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
     for (int a = 0; a < 3; ++a) M[13 + 3 * a + a] += M[0];
     for (int a = 0; a < 3; ++a)
