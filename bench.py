@@ -120,12 +120,37 @@ def cpu_baseline_gravity(cfg, budget_s):
                       f"brute-force gravity (all {n} particles scanned per target); {dt:.1f} s"}
 
 
-def roofline(kind, ms_total, launches, units):
+# HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, calibrated
+# against a device copy of known size (profiles/*_hbm_traffic.json, written by
+# paper_2310_16122_amd.profiling); used only while the kernel sources are the
+# ones the counters were taken on.
+TRAFFIC_FILES = {"C2": "crk_passes_C2_hbm_traffic.json", "C5": "crk_passes_C5_hbm_traffic.json",
+                 "C3": "sr_gravity_C3_hbm_traffic.json"}
+PROFILE_NAMES = {k: f"void k_{k}<float>" for k in ("volume", "moments", "accel", "accel_adj",
+                                                   "moments_adj", "volume_adj", "gravity")}
+
+
+def measured_traffic(config, kind):
+    from paper_2310_16122_amd import profiling
+
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILES.get(config, ""))
+    if not os.path.isfile(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_digest") != profiling.source_digest():
+        return None  # kernels changed since the counters were taken
+    k = rec["kernels"].get(PROFILE_NAMES[kind])
+    return None if k is None else round(k["hbm_bytes"])
+
+
+def roofline(kind, ms_total, launches, units, config):
     avg_ms = ms_total / max(launches, 1)
     achieved = FLOP_PER_PAIR[kind] * units / (avg_ms * 1e-3) / 1e12
     return {"bound": "alu", "kernel": kind, "achieved": round(achieved, 3),
             "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None,
+            "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4),
+            "traffic": measured_traffic(config, kind),
             "avg_launch_ms": round(avg_ms, 4), "flop_per_unit": FLOP_PER_PAIR[kind],
             "units_per_launch": units}
 
@@ -201,7 +226,7 @@ def bench_hydro(args, torch, crk):
     units = {"volume": G, "moments": G, "accel": F, "accel_adj": F, "moments_adj": F, "volume_adj": F}
     ran = [k for k in HYDRO_KERNELS if kt[k][1] > 0]
     dom = max(ran, key=lambda k: kt[k][0])
-    rl = roofline(dom, kt[dom][0], kt[dom][1], units[dom])
+    rl = roofline(dom, kt[dom][0], kt[dom][1], units[dom], args.config)
     per_kernel = {k: {"avg_ms": round(kt[k][0] / kt[k][1], 4), "launches_per_step": kt[k][1] / args.steps,
                       "tflops": round(FLOP_PER_PAIR[k] * units[k] / (kt[k][0] / kt[k][1]) * 1e-9, 3)}
                   for k in ran}
@@ -277,7 +302,7 @@ def bench_gravity(args, torch, crk):
         "config": {"workload": f"C3: {WORKLOADS['C3']}", "n": cfg["n"],
                    "interactions_per_step": inter, "candidate_pairs": st["candidate_pairs"],
                    "tuning": L.get_tuning()},
-        "roofline": roofline("gravity", kt["gravity"][0], kt["gravity"][1], inter),
+        "roofline": roofline("gravity", kt["gravity"][0], kt["gravity"][1], inter, "C3"),
         "build_ms": round(build_ms, 1),
     }
     if not args.no_cpu:
