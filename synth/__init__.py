@@ -36,6 +36,8 @@ Every configuration can be shrunk with ``n_side`` for tests (same recipe).
 
 from __future__ import annotations
 
+import sys
+
 import numpy as np
 
 GRID = 2.0 ** 32
@@ -117,7 +119,11 @@ def knn_support(x, y, z, n_target, chunk=1 << 18, workers=-1):
     H = np.empty(len(x))
     # particles with similar targets are queried together with k = group max + 2
     kq = (n_target + 2 + 15) // 16 * 16
+    verbose = len(x) >= (1 << 22)
     for k in np.unique(kq):
+        if verbose:
+            print(f"[synth] neighbour search k={int(k)} for {int((kq == k).sum())} particles",
+                  file=sys.stderr, flush=True)
         sel = np.nonzero(kq == k)[0]
         for s in range(0, len(sel), max(1, chunk * 64 // int(k))):
             idx = sel[s:s + max(1, chunk * 64 // int(k))]
