@@ -275,19 +275,45 @@ def bench_hydro(args, torch, crk):
 def bench_gravity(args, torch, crk):
     import synth
 
-    cfg = synth.make_config("C3")
-    x, y, z = (torch.as_tensor(cfg[k]).cuda() for k in ("x", "y", "z"))
-    m = torch.as_tensor(cfg["m"]).float().cuda()
-    tb = time.perf_counter()
-    L = crk.crk_build_leaf_pairs(x, y, z, None, r_fixed=cfg["r_cut"], leaf_max=512, leaf_min=16,
-                                 split_extent=cfg["r_cut"], prec="f32")
-    build_ms = (time.perf_counter() - tb) * 1e3
-    if args.tuning:
-        L.set_tuning(**json.loads(args.tuning))
-    st = L.stats()
+    import numpy as np
 
-    def step():
-        crk.sr_gravity(L, x, y, z, m, cfg["G"], cfg["eps"], cfg["r_cut"], prec="f32")
+    cfg = synth.make_config("C3")
+    log(f"[bench] generated C3: n={cfg['n']}")
+    x, y, z = (torch.as_tensor(cfg[k]).cuda() for k in ("x", "y", "z"))
+
+    def build(leaf_max, xx, yy, zz):
+        return crk.crk_build_leaf_pairs(xx, yy, zz, None, r_fixed=cfg["r_cut"], leaf_max=leaf_max,
+                                        leaf_min=16, split_extent=cfg["r_cut"], prec="f32")
+
+    # particles in tree order (as a simulation holds them): build, reorder, rebuild
+    tb = time.perf_counter()
+    L0 = build(512, x, y, z)
+    build_ms = (time.perf_counter() - tb) * 1e3
+    perm = L0.perm().long()
+    L0.free()
+    x, y, z = x[perm].contiguous(), y[perm].contiguous(), z[perm].contiguous()
+    m = torch.as_tensor(cfg["m"]).float().cuda()[perm].contiguous()
+
+    def make_step(Lh):
+        def step():
+            crk.sr_gravity(Lh, x, y, z, m, cfg["G"], cfg["eps"], cfg["r_cut"], prec="f32")
+        return step
+
+    tuned = None
+    if args.tuning or args.no_autotune:
+        L = build(args.leaf_max if args.leaf_max != 128 else 512, x, y, z)
+        if args.tuning:
+            L.set_tuning(**json.loads(args.tuning))
+    else:
+        from paper_2310_16122_amd import tune
+
+        leaf, L, tun, best_ms, per_leaf = tune.autotune_leaf_size(
+            lambda lm: build(lm, x, y, z), make_step, leaf_values=(128, 256, 512), log=log, repeats=2)
+        tuned = {"leaf_max": leaf, "ms_by_leaf": {str(k): round(v, 3) for k, v in per_leaf.items()},
+                 "best_ms": round(best_ms, 3)}
+        log(f"[bench] autotuned gravity: leaf {leaf}, {tun} ({best_ms:.3f} ms)")
+    st = L.stats()
+    step = make_step(L)
 
     timed_steps(step, 2, args.warmup, torch)
     L.timing(True)
@@ -301,7 +327,8 @@ def bench_gravity(args, torch, crk):
         "data": "synthetic",
         "config": {"workload": f"C3: {WORKLOADS['C3']}", "n": cfg["n"],
                    "interactions_per_step": inter, "candidate_pairs": st["candidate_pairs"],
-                   "tuning": L.get_tuning()},
+                   "leaves": st["leaves"], "particle_order": "tree order",
+                   "tuning": L.get_tuning(), "autotune": tuned},
         "roofline": roofline("gravity", kt["gravity"][0], kt["gravity"][1], inter, "C3"),
         "build_ms": round(build_ms, 1),
     }

@@ -399,8 +399,15 @@ struct GravParams {
     int use_poly;
 };
 
-// One wave per tile; candidate particles staged 64 at a time in LDS; every
-// candidate pair evaluated branch-free, masked by 0 < r^2 < r_c^2.
+// One wave per tile; candidate particles staged 64 at a time in LDS.
+// Positions are staged relative to the tile's first particle as reals, so a
+// pair's separation is three subtractions: for a compact tile (every lane
+// within 1/4 of that origin, r_c < 1/4) the relative coordinates of every pair
+// within r_c are exact minimum images and every pair beyond r_c stays beyond
+// it; other tiles use the exact fixed-point separation.  A staged neighbour
+// that no lane of the wave has within r_c skips the force arithmetic
+// (wave-uniform branch); the remaining evaluations are masked by
+// 0 < r^2 < r_c^2.
 template <class R>
 __global__ __launch_bounds__(64) void k_gravity(Queue qu, int n, const int32_t* __restrict__ perm,
                                                 const uint4* __restrict__ quant, const R* __restrict__ ms,
@@ -409,7 +416,7 @@ __global__ __launch_bounds__(64) void k_gravity(Queue qu, int n, const int32_t* 
                                                 R* __restrict__ a_out) {
     constexpr bool kComp = sizeof(R) == 4;
     __shared__ uint4 sq[kWave];
-    __shared__ R smass[kWave];
+    __shared__ R sx[kWave], sy[kWave], sz[kWave], smass[kWave];
     const int lane = lane_id();
     const R rc2 = R(gp.rc2), eps2 = R(gp.eps2);
     R pc[6];
@@ -418,33 +425,49 @@ __global__ __launch_bounds__(64) void k_gravity(Queue qu, int n, const int32_t* 
     for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
         const int s = w * kWave + lane;
         const bool valid = s < n;
-        const uint4 qi = valid ? quant[s] : make_uint4(0, 0, 0, 0);
+        const uint4 qo = quant[w * kWave];  // tile origin (wave-uniform)
+        const uint4 qi = valid ? quant[s] : qo;
+        const R xi = sep<R>(qi.x, qo.x), yi = sep<R>(qi.y, qo.y), zi = sep<R>(qi.z, qo.z);
+        const bool far = fmax(fabs(xi), fmax(fabs(yi), fabs(zi))) >= R(0.25);
+        const bool compact = __ballot(far) == 0 && gp.rc2 < 0.0625;
         R acc[3] = {R(0), R(0), R(0)}, cmp[3] = {R(0), R(0), R(0)}, part[3] = {R(0), R(0), R(0)};
+        auto pair = [&](R dx, R dy, R dz, R mj) __attribute__((always_inline)) {
+            const R r2 = dx * dx + dy * dy + dz * dz;
+            const bool in = r2 < rc2 && r2 > R(0);
+            if (__ballot(in) == 0) return;
+            const R ir = drsqrt(r2 + eps2);
+            R f = ir * ir * ir;
+            if (gp.use_poly) {
+                R pv = pc[5];
+                for (int k = 4; k >= 0; --k) pv = pv * r2 + pc[k];
+                f -= pv;
+            }
+            f = in ? mj * f : R(0);
+            part[0] += f * dx;
+            part[1] += f * dy;
+            part[2] += f * dz;
+        };
         for (int r = rng_off[w]; r < rng_off[w + 1]; ++r) {
             const int2 Rg = rng[r];
             for (int b = Rg.x; b < Rg.y; b += kWave) {
                 const int mcnt = min(kWave, Rg.y - b);
                 __syncthreads();
                 if (lane < mcnt) {
-                    sq[lane] = quant[b + lane];
+                    const uint4 qj = quant[b + lane];
+                    sq[lane] = qj;
+                    sx[lane] = sep<R>(qj.x, qo.x);
+                    sy[lane] = sep<R>(qj.y, qo.y);
+                    sz[lane] = sep<R>(qj.z, qo.z);
                     smass[lane] = ms[b + lane];
                 }
                 __syncthreads();
                 for (int jj = 0; jj < mcnt; ++jj) {
-                    const uint4 qj = sq[jj];
-                    const R dx = sep<R>(qi.x, qj.x), dy = sep<R>(qi.y, qj.y), dz = sep<R>(qi.z, qj.z);
-                    const R r2 = dx * dx + dy * dy + dz * dz;
-                    const R ir = drsqrt(r2 + eps2);
-                    R f = ir * ir * ir;
-                    if (gp.use_poly) {
-                        R pv = pc[5];
-                        for (int k = 4; k >= 0; --k) pv = pv * r2 + pc[k];
-                        f -= pv;
+                    if (compact) {
+                        pair(xi - sx[jj], yi - sy[jj], zi - sz[jj], smass[jj]);
+                    } else {
+                        const uint4 qj = sq[jj];
+                        pair(sep<R>(qi.x, qj.x), sep<R>(qi.y, qj.y), sep<R>(qi.z, qj.z), smass[jj]);
                     }
-                    f = (r2 < rc2 && r2 > R(0)) ? smass[jj] * f : R(0);
-                    part[0] += f * dx;
-                    part[1] += f * dy;
-                    part[2] += f * dz;
                     if (kComp && (jj & 7) == 7) {
                         for (int c = 0; c < 3; ++c) { kadd(acc[c], cmp[c], part[c]); part[c] = R(0); }
                     }

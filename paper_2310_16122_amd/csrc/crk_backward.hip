@@ -44,6 +44,29 @@ template <class R> struct alignas(128) RecBwd {
 static_assert(sizeof(RecBwd<float>) == 128, "f32 backward record is one line");
 static_assert(sizeof(RecBwd<double>) == 256, "f64 backward record is two lines");
 
+// Chunked compensated sums: plain partial sums over `chunk` pairs, folded into
+// (s, c) Kahan pairs (FP32); plain sums in FP64.
+template <class R, int N> struct ChunkSums {
+    R p[N], s[N], c[N];
+    int kk;
+    __device__ void zero() {
+        kk = 0;
+#pragma unroll
+        for (int e = 0; e < N; ++e) { p[e] = R(0); s[e] = R(0); c[e] = R(0); }
+    }
+    __device__ void add(int e, R t) { p[e] += t; }
+    __device__ void fold() {
+        if (sizeof(R) != 4) return;
+#pragma unroll
+        for (int e = 0; e < N; ++e) { kadd(s[e], c[e], p[e]); p[e] = R(0); }
+    }
+    __device__ void next(int chunk) {
+        if (sizeof(R) == 4 && ++kk == chunk) { fold(); kk = 0; }
+    }
+    // value after a final fold
+    __device__ R get(int e) const { return sizeof(R) == 4 ? s[e] - c[e] : p[e]; }
+};
+
 template <class R, int N> struct Sums {
     R s[N], c[N];
     __device__ void zero() {
@@ -100,9 +123,9 @@ __device__ __forceinline__ void corr_grad_dy(const RecBwd<R>& r, R W, R F, R F2,
 }
 
 // adjoint of G with respect to (A, B, dA, dB), given g = Gbar
-template <class R, int N>
+template <class R, class Acc>
 __device__ __forceinline__ void corr_grad_dC(const RecBwd<R>& r, R W, R F, const R y[3], const R g[3],
-                                             Sums<R, N>& acc) {
+                                             Acc& acc) {
     const R lin = R(1) + r.B[0] * y[0] + r.B[1] * y[1] + r.B[2] * y[2];
     const R al = g[0] * r.dA[0] + g[1] * r.dA[1] + g[2] * r.dA[2];
     R be = R(0);
@@ -159,9 +182,9 @@ __global__ void k_pack_bwd(int n, const int32_t* perm, const uint4* quant, const
 // 1. force adjoint
 template <class R>
 __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
-                                                   const RecBwd<R>* __restrict__ rec, R* __restrict__ cbar,
-                                                   R* __restrict__ vpbar, R* __restrict__ xbar,
-                                                   R* __restrict__ gv) {
+                                                   const RecBwd<R>* __restrict__ rec, int chunk,
+                                                   R* __restrict__ cbar, R* __restrict__ vpbar,
+                                                   R* __restrict__ xbar, R* __restrict__ gv) {
     constexpr int kStage = int(sizeof(RecBwd<R>) / 16) * kWave;
     __shared__ uint4 stage_buf[4 * kStage];
     const int lane = lane_id();
@@ -173,8 +196,8 @@ __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, con
         const int cnt = valid ? L.cnt[s] : 0;
         const int len = L.len[w];
         const uint32_t* lst = L.nbr + L.off[w] + lane;
-        Sums<R, 16> cb;  // A, B[3], dA[3], dB[9]
-        Sums<R, 8> ob;   // Vbar, Pbar, xbar[3], vbar[3]
+        ChunkSums<R, 16> cb;  // A, B[3], dA[3], dB[9]
+        ChunkSums<R, 8> ob;   // Vbar, Pbar, xbar[3], vbar[3]
         cb.zero();
         ob.zero();
         staged_list<RecBwd<R>>(
@@ -212,7 +235,11 @@ __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, con
                 corr_grad_dy(rj, Wj, Fj, F2j, y, g, xb);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) ob.add(2 + c, xb[c]);
+                cb.next(chunk);
+                ob.next(chunk);
             });
+        cb.fold();
+        ob.fold();
         if (valid) {
             const int i = perm[s];
 #pragma unroll
@@ -635,8 +662,8 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
     reset_queue(L, st);
     {
         TimeScope ts(L, st, CRK_K_ACCEL_ADJ);
-        hipLaunchKernelGGL(k_accel_adj<R>, grid, block, 0, st, q, n, lists(L), L->perm, rec, cbar,
-                           vpbar, xbar, gv);
+        hipLaunchKernelGGL(k_accel_adj<R>, grid, block, 0, st, q, n, lists(L), L->perm, rec,
+                           L->tune.kahan_chunk, cbar, vpbar, xbar, gv);
     }
     LAUNCH_CHECK("accel adjoint");
     reset_queue(L, st);

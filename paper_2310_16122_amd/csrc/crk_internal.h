@@ -305,18 +305,19 @@ __device__ __forceinline__ void list_loop(const uint32_t* __restrict__ lst, int 
 // The 40 correction moments of the lane's particle in FP64 (storage order:
 // m0, m1[3], m2[6] (xx xy xz yy yz zz), g0[3], g1[9] (g1[a][c], a-major),
 // g2[18] (g2[ab][c], ab in the m2 order)), and the number of neighbours inside
-// the support.  Accumulated over the list per pair (w = cW w(q) V_j,
-// f = cF f(q) V_j, x = x_ij):
+// the support.  Per pair (w = cW w(q) V_j, f = cF f(q) V_j, x = x_ij) only 29
+// independent sums are accumulated:
 //   m0 += w, m1^a += x^a w, m2^ab += x^a x^b w, g0^c += f x^c,
-//   t1^ac += x^a f x^c, t2^abc += x^a x^b f x^c;
+//   t1^ac += f x^a x^c (symmetric: 6), t3^abc += f x^a x^b x^c (fully symmetric: 10);
 // then j = i is added analytically and g1^ac = delta^ac m0 + t1^ac,
-// g2^abc = delta^ac m1^b + delta^bc m1^a + t2^abc.  FP32: plain sums over
+// g2^abc = delta^ac m1^b + delta^bc m1^a + t3^abc.  FP32: plain sums over
 // `chunk` pairs folded into compensated sums.  Every lane of the wave must call
 // this (the loop runs over the tile's longest list).
 template <class R>
 __device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, const RecQV<R>* __restrict__ qv,
                                    uint4* __restrict__ lds, R H, int chunk, double M[40], int& nnb) {
     constexpr bool kComp = sizeof(R) == 4;
+    constexpr int kN = 29;
     const int lane = lane_id();
     const RecQV<R> self = qv[valid ? s : 0];
     const uint4 qi = make_uint4(self.q[0], self.q[1], self.q[2], 0u);
@@ -325,9 +326,9 @@ __device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, con
     const int cnt = valid ? L.cnt[s] : 0;
     const int len = L.len[w];
     const uint32_t* lst = L.nbr + L.off[w] + lane;
-    R p[40], sm[40], cm[40];
+    R p[kN], sm[kN], cm[kN];
 #pragma unroll
-    for (int e = 0; e < 40; ++e) { p[e] = R(0); sm[e] = R(0); cm[e] = R(0); }
+    for (int e = 0; e < kN; ++e) { p[e] = R(0); sm[e] = R(0); cm[e] = R(0); }
     nnb = 0;
     int kk = 0;
     list_loop<RecQV<R>>(
@@ -342,50 +343,56 @@ __device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, con
             nnb += q < R(1);
             const R wv = cW * wq * Vj;
             const R fv = cF * fq * Vj;
-            const R fx[3] = {fv * x[0], fv * x[1], fv * x[2]};
-            R xx[6];
+            R xx[6], x3[10];
             xx[0] = x[0] * x[0]; xx[1] = x[0] * x[1]; xx[2] = x[0] * x[2];
             xx[3] = x[1] * x[1]; xx[4] = x[1] * x[2]; xx[5] = x[2] * x[2];
+            x3[0] = xx[0] * x[0]; x3[1] = xx[0] * x[1]; x3[2] = xx[0] * x[2];
+            x3[3] = xx[1] * x[1]; x3[4] = xx[1] * x[2]; x3[5] = xx[2] * x[2];
+            x3[6] = xx[3] * x[1]; x3[7] = xx[3] * x[2]; x3[8] = xx[4] * x[2]; x3[9] = xx[5] * x[2];
             p[0] += wv;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) p[1 + a] += x[a] * wv;
+            for (int a = 0; a < 3; ++a) {
+                p[1 + a] += x[a] * wv;
+                p[10 + a] += x[a] * fv;
+            }
 #pragma unroll
-            for (int e = 0; e < 6; ++e) p[4 + e] += xx[e] * wv;
+            for (int e = 0; e < 6; ++e) {
+                p[4 + e] += xx[e] * wv;
+                p[13 + e] += xx[e] * fv;
+            }
 #pragma unroll
-            for (int c = 0; c < 3; ++c) p[10 + c] += fx[c];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) p[13 + 3 * a + c] += x[a] * fx[c];
-#pragma unroll
-            for (int e = 0; e < 6; ++e)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) p[22 + 3 * e + c] += xx[e] * fx[c];
+            for (int e = 0; e < 10; ++e) p[19 + e] += x3[e] * fv;
             if (kComp && ++kk == chunk) {
 #pragma unroll
-                for (int e = 0; e < 40; ++e) { kadd(sm[e], cm[e], p[e]); p[e] = R(0); }
+                for (int e = 0; e < kN; ++e) { kadd(sm[e], cm[e], p[e]); p[e] = R(0); }
                 kk = 0;
             }
         });
+    double S[kN];
 #pragma unroll
-    for (int e = 0; e < 40; ++e) {
+    for (int e = 0; e < kN; ++e) {
         if (kComp) {
             kadd(sm[e], cm[e], p[e]);
-            M[e] = double(sm[e]) - double(cm[e]);
+            S[e] = double(sm[e]) - double(cm[e]);
         } else {
-            M[e] = double(p[e]);
+            S[e] = double(p[e]);
         }
     }
-    if (valid) M[0] += double(cW) * double(self.V);  // j = i
+    if (valid) S[0] += double(cW) * double(self.V);  // j = i
     const int sym[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
-    for (int a = 0; a < 3; ++a) M[13 + 3 * a + a] += M[0];
+    const int cub[3][3][3] = {{{0, 1, 2}, {1, 3, 4}, {2, 4, 5}},
+                              {{1, 3, 4}, {3, 6, 7}, {4, 7, 8}},
+                              {{2, 4, 5}, {4, 7, 8}, {5, 8, 9}}};
+    for (int e = 0; e < 13; ++e) M[e] = S[e];  // m0, m1, m2, g0
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) M[13 + 3 * a + c] = (a == c ? S[0] : 0.0) + S[13 + sym[a][c]];
     for (int a = 0; a < 3; ++a)
         for (int b = a; b < 3; ++b)
             for (int c = 0; c < 3; ++c) {
-                double t = 0.0;
-                if (a == c) t += M[1 + b];
-                if (b == c) t += M[1 + a];
-                M[22 + 3 * sym[a][b] + c] += t;
+                double t = S[19 + cub[a][b][c]];
+                if (a == c) t += S[1 + b];
+                if (b == c) t += S[1 + a];
+                M[22 + 3 * sym[a][b] + c] = t;
             }
 }
 

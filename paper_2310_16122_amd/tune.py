@@ -28,9 +28,14 @@ SPACE = {
 }
 
 
+def _sync():
+    if torch.cuda.is_available():
+        torch.cuda.synchronize()
+
+
 def _time_step(leaves, step, repeats):
     step()
-    torch.cuda.synchronize()
+    _sync()
     leaves.timing(True)
     for _ in range(repeats):
         step()
@@ -40,6 +45,8 @@ def _time_step(leaves, step, repeats):
 
 
 def cache_key(name, n, prec, leaf_max):
+    if not torch.cuda.is_available():
+        return f"cpu|{name}|n={n}|{prec}|leaf={leaf_max}"
     dev = torch.cuda.get_device_properties(0)
     arch = getattr(dev, "gcnArchName", dev.name)
     return f"{arch}|{name}|n={n}|{prec}|leaf={leaf_max}"
