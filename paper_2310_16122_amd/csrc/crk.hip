@@ -72,11 +72,12 @@ __global__ void k_pack_acc(int n, const int32_t* perm, const uint4* quant, const
                            const R* vx, const R* vy, const R* vz, const R* V, const R* rho,
                            const R* A, const R* B, const R* dA, const R* dB, R gm1,
                            RecAcc<R>* rec) {
+    __shared__ uint4 buf[256 * (sizeof(RecAcc<R>) / 16)];
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int i = perm[s];
+    const bool valid = s < n;
+    const int i = valid ? perm[s] : 0;
     RecAcc<R> r;
-    const uint4 q = quant[s];
+    const uint4 q = quant[valid ? s : 0];
     r.q[0] = q.x; r.q[1] = q.y; r.q[2] = q.z; r.q[3] = 0;
     const R H = R(2) * h[i];
     const R cW = norm_W(H), cF = norm_F(H);
@@ -93,7 +94,8 @@ __global__ void k_pack_acc(int n, const int32_t* perm, const uint4* quant, const
     }
     r.v[0] = vx[i]; r.v[1] = vy[i]; r.v[2] = vz[i];
     for (int k = 0; k < int(sizeof(r.pad) / sizeof(R)); ++k) r.pad[k] = R(0);
-    rec[s] = r;
+    const int first = blockIdx.x * blockDim.x;
+    store_records(rec, r, valid, first, min(int(blockDim.x), n - first), buf);
 }
 
 // ------------------------------------------------------------------ list build

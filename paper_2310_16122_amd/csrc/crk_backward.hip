@@ -149,11 +149,12 @@ __global__ void k_pack_bwd(int n, const int32_t* perm, const uint4* quant, const
                            const R* vx, const R* vy, const R* vz, const R* m, const R* V,
                            const R* rho, const R* A, const R* B, const R* dA, const R* dB,
                            const R* ga, const R* gdu, R gm1, RecBwd<R>* rec, R* aux) {
+    __shared__ uint4 buf[256 * (sizeof(RecBwd<R>) / 16)];
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int i = perm[s];
+    const bool valid = s < n;
+    const int i = valid ? perm[s] : 0;
     RecBwd<R> r;
-    const uint4 q = quant[s];
+    const uint4 q = quant[valid ? s : 0];
     r.q[0] = q.x; r.q[1] = q.y; r.q[2] = q.z;
     const R H = R(2) * h[i];
     const R invH = R(1) / H;
@@ -174,9 +175,12 @@ __global__ void k_pack_bwd(int n, const int32_t* perm, const uint4* quant, const
     }
     for (int k = 0; k < 9; ++k) r.dB[k] = dB[9 * i + k];
     r.v[0] = vx[i]; r.v[1] = vy[i]; r.v[2] = vz[i];
-    rec[s] = r;
-    aux[2 * s] = invH;
-    aux[2 * s + 1] = r.V;
+    const int first = blockIdx.x * blockDim.x;
+    store_records(rec, r, valid, first, min(int(blockDim.x), n - first), buf);
+    if (valid) {
+        aux[2 * s] = invH;
+        aux[2 * s + 1] = r.V;
+    }
 }
 
 // 1. force adjoint

@@ -263,6 +263,27 @@ __device__ __forceinline__ void staged_list(const uint32_t* __restrict__ lst, in
     }
 }
 
+// Block-cooperative store of one record per thread: the records pass through
+// LDS and leave as consecutive 16-byte chunks per lane (a thread storing its
+// own 128-byte record would touch one cache line per lane per store).  Every
+// thread of the block must call it; `first` is the block's first record and
+// `count` the number of valid records from there.  buf holds blockDim.x records.
+template <class Rec>
+__device__ __forceinline__ void store_records(Rec* __restrict__ out, const Rec& r, bool valid, int first,
+                                              int count, uint4* __restrict__ buf) {
+    constexpr int NCH = int(sizeof(Rec) / 16);
+    const int t = threadIdx.x;
+    const uint4* src = reinterpret_cast<const uint4*>(&r);
+    __syncthreads();
+    if (valid)
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) buf[t * NCH + c] = src[c];
+    __syncthreads();
+    uint4* dst = reinterpret_cast<uint4*>(out + first);
+    const int total = count * NCH;
+    for (int k = t; k < total; k += blockDim.x) dst[k] = buf[k];
+}
+
 // Position and volume of a neighbour, the moments pass's per-pair data.
 template <class R> struct alignas(16) RecQV;
 template <> struct alignas(16) RecQV<float> {
