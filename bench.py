@@ -1,5 +1,5 @@
 #!/usr/bin/env python3
-"""Benchmark of the CRK-SPH pair passes (and short-range gravity) on one MI355X.
+"""Benchmark of the CRK-SPH pair passes and short-range gravity on one MI355X.
 
 One step = one pass of the hot path over one synthetic particle set already
 resident in HBM: for the CRK workloads the position packing, the volume pass,
@@ -9,6 +9,10 @@ adjoints, with the moments recomputed); for the gravity workload one
 short-range gravity evaluation.  The tree and the neighbour lists are built
 once before the timed region (reported separately as build time); particles
 are held in tree order.  The launch/tiling choices are autotuned first.
+
+The default run measures the CRK step on C2 (the headline line) and then the
+gravity step on its own workload (C3, gas + dark matter), reported in the same
+JSON line under ``sr_gravity``; ``--config`` runs one workload alone.
 
 Prints ONE JSON line.  ``value`` is pair interactions per second: ordered
 pairs j != i inside each pass's radius (2h_i for volume and moments,
@@ -30,7 +34,7 @@ METRIC = "CRK-SPH pair interactions/s & % FP32 VALU peak; fwd+bwd ms vs FP64 GPU
 
 # Algorithmic FP32 work per ordered pair inside the pass radius (FMA = 2 FLOP,
 # square root / reciprocal square root = 1), per-particle constants hoisted;
-# compensation arithmetic excluded.  Derivation in the design doc.
+# compensation arithmetic excluded.
 FLOP_PER_PAIR = {"volume": 21, "moments": 112, "accel": 141, "gravity": 19,
                  "accel_adj": 520, "moments_adj": 365, "volume_adj": 40}
 HYDRO_KERNELS = ("volume", "moments", "accel", "accel_adj", "moments_adj", "volume_adj")
@@ -60,6 +64,20 @@ def timed_steps(step, steps, warmup, torch):
     return (time.perf_counter() - t0) / steps * 1e3
 
 
+def sampled(run, k0, n, budget_s):
+    """Time run(k) on a sample of k targets sized to take about budget_s seconds
+    (one small warm-up call first: library load and thread start-up)."""
+    run(min(8, k0))
+    k = k0
+    dt, inter = run(k)
+    for _ in range(3):
+        if dt >= budget_s / 2 or k >= n:
+            break
+        k = int(min(k * budget_s / max(dt, 1e-3), n))
+        dt, inter = run(k)
+    return k, dt, inter
+
+
 def cpu_baseline_hydro(cfg, budget_s):
     """The oracle (brute-force FP64 passes) on a sample of target particles of the workload."""
     import numpy as np
@@ -84,11 +102,7 @@ def cpu_baseline_hydro(cfg, budget_s):
         inter = 2 * oracle.count_pairs(cfg, 0, t)[0] + oracle.count_pairs(cfg, 1, t)[0]
         return dt, inter
 
-    k = 64
-    dt, inter = run(k)
-    if dt < budget_s / 4:
-        k = int(min(k * budget_s / max(dt, 1e-3), n))
-        dt, inter = run(k)
+    k, dt, inter = sampled(run, 64, n, budget_s)
     return {"value": inter / dt, "unit": "interactions/s", "cores": oracle.threads(),
             "kind": "oracle",
             "sample": f"{k} sampled particles of the {n}-particle workload through the oracle's "
@@ -109,11 +123,7 @@ def cpu_baseline_gravity(cfg, budget_s):
         dt = time.perf_counter() - t0
         return dt, oracle.count_pairs(cfg, 2, t, r_fixed=cfg["r_cut"])[0]
 
-    k = 256
-    dt, inter = run(k)
-    if dt < budget_s / 4:
-        k = int(min(k * budget_s / max(dt, 1e-3), n))
-        dt, inter = run(k)
+    k, dt, inter = sampled(run, 256, n, budget_s)
     return {"value": inter / dt, "unit": "interactions/s", "cores": oracle.threads(),
             "kind": "oracle",
             "sample": f"{k} sampled particles of the {n}-particle workload through the oracle's "
@@ -346,6 +356,10 @@ def main():
     ap.add_argument("--leaf-max", type=int, default=128)
     ap.add_argument("--tuning", default=None, help="JSON dict of crk_tuning fields")
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tuning")
+    ap.add_argument("--no-gravity", action="store_true", help="C2 only: skip the gravity workload")
+    ap.add_argument("--gravity-tuning", default=None, help="JSON crk_tuning for the gravity workload")
+    ap.add_argument("--gravity-leaf-max", type=int, default=512,
+                    help="gravity leaf size when its tuning is given")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-backward", action="store_true", help="forward passes only")
     ap.add_argument("--no-cpu", action="store_true")
@@ -366,7 +380,19 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
-    out = bench_gravity(args, torch, crk) if args.config == "C3" else bench_hydro(args, torch, crk)
+    if args.config == "C3":
+        out = bench_gravity(args, torch, crk)
+    else:
+        out = bench_hydro(args, torch, crk)
+        if args.config == "C2" and not args.no_gravity:
+            # the gravity pass on its own workload, in the same JSON line
+            import gc
+
+            gc.collect()
+            torch.cuda.empty_cache()
+            gargs = argparse.Namespace(**vars(args))
+            gargs.config, gargs.tuning, gargs.leaf_max = "C3", args.gravity_tuning, args.gravity_leaf_max
+            out["sr_gravity"] = bench_gravity(gargs, torch, crk)
     if args.calibrate_copy:
         # a plain device copy of known size: its FETCH_SIZE / WRITE_SIZE counter
         # readings calibrate the counters of the pair kernels

@@ -265,7 +265,7 @@ __global__ __launch_bounds__(256) void k_moments(Queue qu, int n, Lists L, const
                                                  R* __restrict__ dB_out,
                                                  unsigned long long* __restrict__ n_fallback) {
     constexpr int kStage = sizeof(RecQV<R>) > 16 ? int(sizeof(RecQV<R>) / 16) * kWave : 1;
-    __shared__ uint4 stage_buf[4 * kStage];
+    extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
     const int lane = lane_id();
     QState qs;
     for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const i
                                                double* __restrict__ partials) {
     constexpr bool kComp = sizeof(R) == 4;
     constexpr int kStage = int(sizeof(RecAcc<R>) / 16) * kWave;
-    __shared__ uint4 stage_buf[4 * kStage];
+    extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
     const int lane = lane_id();
     QState qs;
     for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
@@ -401,30 +401,43 @@ struct GravParams {
     int use_poly;
 };
 
-// One wave per tile; candidate particles staged 64 at a time in LDS.
-// Positions are staged relative to the tile's first particle as reals, so a
-// pair's separation is three subtractions: for a compact tile (every lane
-// within 1/4 of that origin, r_c < 1/4) the relative coordinates of every pair
-// within r_c are exact minimum images and every pair beyond r_c stays beyond
-// it; other tiles use the exact fixed-point separation.  A staged neighbour
-// that no lane of the wave has within r_c skips the force arithmetic
-// (wave-uniform branch); the remaining evaluations are masked by
-// 0 < r^2 < r_c^2.
-template <class R>
+// A staged candidate: position relative to the tile origin, and mass.
+template <class R> struct alignas(4 * sizeof(R)) GravRec {
+    R x, y, z, m;
+};
+
+// One wave per tile.  Candidates are streamed in blocks of 64 (the next
+// block's loads are issued before the current one is evaluated).  Positions
+// are taken relative to the tile's first particle as reals, so a pair's
+// separation is three subtractions: for a compact tile (every lane within
+// 1/4 of that origin, r_c < 1/4) the relative coordinates of every pair within
+// r_c are exact minimum images and every pair beyond r_c stays beyond it;
+// other tiles use the exact fixed-point separation.  In a compact tile a
+// candidate farther than r_c from the tile's bounding box cannot interact
+// with any lane and is dropped before it reaches LDS; the survivors are
+// compacted, padded with massless entries to whole chunks, and evaluated in
+// straight-line chunks of kChunk with the compensated fold between chunks.
+template <class R, bool kPoly, bool kSoft>
 __global__ __launch_bounds__(64) void k_gravity(Queue qu, int n, const int32_t* __restrict__ perm,
                                                 const uint4* __restrict__ quant, const R* __restrict__ ms,
                                                 const int32_t* __restrict__ rng_off,
                                                 const int2* __restrict__ rng, GravParams gp,
                                                 R* __restrict__ a_out) {
     constexpr bool kComp = sizeof(R) == 4;
+    constexpr int kChunk = 8;
+    __shared__ GravRec<R> srec[kWave];
     __shared__ uint4 sq[kWave];
-    __shared__ R sx[kWave], sy[kWave], sz[kWave], smass[kWave];
     const int lane = lane_id();
     const R rc2 = R(gp.rc2), eps2 = R(gp.eps2);
+    // the box test keeps a margin over the pair test so rounding never drops
+    // a candidate that some lane would count
+    const R keep2 = rc2 * R(1.001);
     R pc[6];
     for (int k = 0; k < 6; ++k) pc[k] = R(gp.poly[k]);
     QState qs;
-    for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
+    for (int wq = queue_start(qu, qs); wq >= 0; wq = queue_next(qu, qs)) {
+        // tile, ranges and block bounds are wave-uniform: keep them scalar
+        const int w = __builtin_amdgcn_readfirstlane(wq);
         const int s = w * kWave + lane;
         const bool valid = s < n;
         const uint4 qo = quant[w * kWave];  // tile origin (wave-uniform)
@@ -432,14 +445,23 @@ __global__ __launch_bounds__(64) void k_gravity(Queue qu, int n, const int32_t* 
         const R xi = sep<R>(qi.x, qo.x), yi = sep<R>(qi.y, qo.y), zi = sep<R>(qi.z, qo.z);
         const bool far = fmax(fabs(xi), fmax(fabs(yi), fabs(zi))) >= R(0.25);
         const bool compact = __ballot(far) == 0 && gp.rc2 < 0.0625;
+        R lo[3] = {xi, yi, zi}, hi[3] = {xi, yi, zi};
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                lo[c] = fmin(lo[c], R(__shfl_xor(lo[c], o)));
+                hi[c] = fmax(hi[c], R(__shfl_xor(hi[c], o)));
+            }
         R acc[3] = {R(0), R(0), R(0)}, cmp[3] = {R(0), R(0), R(0)}, part[3] = {R(0), R(0), R(0)};
         auto pair = [&](R dx, R dy, R dz, R mj) __attribute__((always_inline)) {
             const R r2 = dx * dx + dy * dy + dz * dz;
-            const bool in = r2 < rc2 && r2 > R(0);
-            if (__ballot(in) == 0) return;
+            // with softening a coincident pair (the self pair included) has a
+            // finite f and a zero separation, so it adds exactly zero
+            const bool in = kSoft ? r2 < rc2 : (r2 < rc2 && r2 > R(0));
             const R ir = drsqrt(r2 + eps2);
             R f = ir * ir * ir;
-            if (gp.use_poly) {
+            if (kPoly) {
                 R pv = pc[5];
                 for (int k = 4; k >= 0; --k) pv = pv * r2 + pc[k];
                 f -= pv;
@@ -449,33 +471,69 @@ __global__ __launch_bounds__(64) void k_gravity(Queue qu, int n, const int32_t* 
             part[1] += f * dy;
             part[2] += f * dz;
         };
-        for (int r = rng_off[w]; r < rng_off[w + 1]; ++r) {
-            const int2 Rg = rng[r];
-            for (int b = Rg.x; b < Rg.y; b += kWave) {
-                const int mcnt = min(kWave, Rg.y - b);
-                __syncthreads();
-                if (lane < mcnt) {
-                    const uint4 qj = quant[b + lane];
-                    sq[lane] = qj;
-                    sx[lane] = sep<R>(qj.x, qo.x);
-                    sy[lane] = sep<R>(qj.y, qo.y);
-                    sz[lane] = sep<R>(qj.z, qo.z);
-                    smass[lane] = ms[b + lane];
-                }
-                __syncthreads();
-                for (int jj = 0; jj < mcnt; ++jj) {
-                    if (compact) {
-                        pair(xi - sx[jj], yi - sy[jj], zi - sz[jj], smass[jj]);
-                    } else {
-                        const uint4 qj = sq[jj];
-                        pair(sep<R>(qi.x, qj.x), sep<R>(qi.y, qj.y), sep<R>(qi.z, qj.z), smass[jj]);
+        auto fold = [&]() __attribute__((always_inline)) {
+            if (kComp)
+                for (int c = 0; c < 3; ++c) { kadd(acc[c], cmp[c], part[c]); part[c] = R(0); }
+        };
+        // candidate blocks: range r, block [b, min(b + 64, e))
+        auto uni = [](int v) __attribute__((always_inline)) { return __builtin_amdgcn_readfirstlane(v); };
+        const int r1 = uni(rng_off[w + 1]);
+        int r = uni(rng_off[w]), b = 0, e = 0;
+        if (r < r1) { const int2 g = rng[r]; b = uni(g.x); e = uni(g.y); }
+        uint4 nq = qo;
+        R nm = R(0);
+        if (r < r1 && lane < e - b) { nq = quant[b + lane]; nm = ms[b + lane]; }
+        while (r < r1) {
+            const int mcnt = min(kWave, e - b);
+            const uint4 qj = nq;
+            const R mj = nm;
+            // advance and prefetch the next block
+            int nb = b + kWave, ne = e, nr = r;
+            if (nb >= ne) {
+                ++nr;
+                if (nr < r1) { const int2 g = rng[nr]; nb = uni(g.x); ne = uni(g.y); }
+            }
+            if (nr < r1 && lane < ne - nb) { nq = quant[nb + lane]; nm = ms[nb + lane]; }
+            r = nr; b = nb; e = ne;
+
+            const GravRec<R> g{sep<R>(qj.x, qo.x), sep<R>(qj.y, qo.y), sep<R>(qj.z, qo.z), mj};
+            bool keep = lane < mcnt;
+            if (compact && keep) {
+                const R d0 = fmax(fmax(lo[0] - g.x, g.x - hi[0]), R(0));
+                const R d1 = fmax(fmax(lo[1] - g.y, g.y - hi[1]), R(0));
+                const R d2 = fmax(fmax(lo[2] - g.z, g.z - hi[2]), R(0));
+                keep = d0 * d0 + d1 * d1 + d2 * d2 < keep2;
+            }
+            const uint64_t mask = __ballot(keep);
+            if (mask == 0) continue;
+            const int cnt = __popcll(mask);
+            const int padded = (cnt + kChunk - 1) / kChunk * kChunk;
+            const int pos = __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
+            __syncthreads();  // the previous block's entries have been read
+            if (keep) { srec[pos] = g; sq[pos] = qj; }
+            if (lane >= cnt && lane < padded) {
+                srec[lane] = GravRec<R>{R(2), R(2), R(2), R(0)};
+                sq[lane] = qo;
+            }
+            __syncthreads();
+            if (compact) {
+                for (int j0 = 0; j0 < padded; j0 += kChunk) {
+#pragma unroll
+                    for (int u = 0; u < kChunk; ++u) {
+                        const GravRec<R> c = srec[j0 + u];
+                        pair(xi - c.x, yi - c.y, zi - c.z, c.m);
                     }
-                    if (kComp && (jj & 7) == 7) {
-                        for (int c = 0; c < 3; ++c) { kadd(acc[c], cmp[c], part[c]); part[c] = R(0); }
-                    }
+                    fold();
                 }
-                if (kComp) {
-                    for (int c = 0; c < 3; ++c) { kadd(acc[c], cmp[c], part[c]); part[c] = R(0); }
+            } else {
+                for (int j0 = 0; j0 < padded; j0 += kChunk) {
+#pragma unroll
+                    for (int u = 0; u < kChunk; ++u) {
+                        const uint4 c = sq[j0 + u];
+                        pair(sep<R>(qi.x, c.x), sep<R>(qi.y, c.y), sep<R>(qi.z, c.z), srec[j0 + u].m);
+                    }
+                    fold();
                 }
             }
         }
@@ -599,7 +657,8 @@ int corrections_impl(crk_leaves* L, const crk_gas* g, const R* V, const crk_corr
     LAUNCH_CHECK("pack position/volume");
     reset_queue(L, st);
     TimeScope ts(L, st, CRK_K_MOMENTS);
-    hipLaunchKernelGGL(k_moments<R>, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves), 0, st,
+    hipLaunchKernelGGL(k_moments<R>, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves),
+                       stage_bytes<RecQV<R>>(L->tune.block_waves), st,
                        make_queue(L, L->order_pair), n, lists(L), L->perm, qv,
                        static_cast<const R*>(g->h), L->tune.kahan_chunk, static_cast<R*>(out->A),
                        static_cast<R*>(out->B), static_cast<R*>(out->dA), static_cast<R*>(out->dB),
@@ -629,7 +688,8 @@ int accel_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const 
     reset_queue(L, st);
     {
         TimeScope ts(L, st, CRK_K_ACCEL);
-        hipLaunchKernelGGL(k_accel<R>, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves), 0, st,
+        hipLaunchKernelGGL(k_accel<R>, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves),
+                           stage_bytes<RecAcc<R>>(L->tune.block_waves), st,
                            make_queue(L, L->order_pair), n, lists(L), L->perm, rec,
                            static_cast<const R*>(g->m), a, dudt, L->partials);
     }
@@ -657,7 +717,12 @@ int gravity_impl(crk_leaves* L, const double* x, const double* y, const double* 
     LAUNCH_CHECK("gather m");
     reset_queue(L, st);
     TimeScope ts(L, st, CRK_K_GRAVITY);
-    hipLaunchKernelGGL(k_gravity<R>, dim3(grid_1wave(L)), dim3(kWave), 0, st,
+    // softening large enough that a coincident pair's f = m eps^-3 is no larger
+    // than a real close pair's (eps^-3 <= 2^120 in FP32)
+    const bool soft = R(gp.eps2) >= R(0x1p-80);
+    auto kern = gp.use_poly ? (soft ? k_gravity<R, true, true> : k_gravity<R, true, false>)
+                            : (soft ? k_gravity<R, false, true> : k_gravity<R, false, false>);
+    hipLaunchKernelGGL(kern, dim3(grid_1wave(L)), dim3(kWave), 0, st,
                        make_queue(L, L->order_cull), n, L->perm, L->quant, ms, L->rng_off, L->rng,
                        gp, a);
     LAUNCH_CHECK("gravity");

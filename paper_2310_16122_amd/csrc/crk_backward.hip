@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, con
                                                    R* __restrict__ cbar, R* __restrict__ vpbar,
                                                    R* __restrict__ xbar, R* __restrict__ gv) {
     constexpr int kStage = int(sizeof(RecBwd<R>) / 16) * kWave;
-    __shared__ uint4 stage_buf[4 * kStage];
+    extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
     const int lane = lane_id();
     QState qs;
     for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
@@ -484,7 +484,7 @@ __global__ __launch_bounds__(256) void k_moments_bwd(Queue qu, int n, Lists L, c
                                                      int chunk, const R* __restrict__ cbar,
                                                      RecMom<R>* __restrict__ mrec) {
     constexpr int kStage = sizeof(RecQV<R>) > 16 ? int(sizeof(RecQV<R>) / 16) * kWave : 1;
-    __shared__ uint4 stage_buf[4 * kStage];
+    extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
     const int lane = lane_id();
     QState qs;
     for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
@@ -520,7 +520,7 @@ __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, c
                                                      R* __restrict__ xbar, RecVA<R>* __restrict__ varec,
                                                      R* __restrict__ gu) {
     constexpr int kStage = int(sizeof(RecMom<R>) / 16) * kWave;
-    __shared__ uint4 stage_buf[4 * kStage];
+    extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
     const int lane = lane_id();
     QState qs;
     for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
@@ -585,7 +585,7 @@ __global__ __launch_bounds__(256) void k_volume_adj(Queue qu, int n, Lists L, co
                                                     const RecVA<R>* __restrict__ varec,
                                                     const R* __restrict__ xbar, R* __restrict__ gx) {
     constexpr int kStage = int(sizeof(RecVA<R>) / 16) * kWave;
-    __shared__ uint4 stage_buf[4 * kStage];
+    extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
     const int lane = lane_id();
     QState qs;
     for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
@@ -661,34 +661,37 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
         hipLaunchKernelGGL(k_pack_qv<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, L->quant, V, qv);
     }
     LAUNCH_CHECK("pack backward");
-    const dim3 grid(grid_nwave(L)), block(kWave * L->tune.block_waves);
+    const int bw = L->tune.block_waves;
+    const dim3 grid(grid_nwave(L)), block(kWave * bw);
     const Queue q = make_queue(L, L->order_pair);
     reset_queue(L, st);
     {
         TimeScope ts(L, st, CRK_K_ACCEL_ADJ);
-        hipLaunchKernelGGL(k_accel_adj<R>, grid, block, 0, st, q, n, lists(L), L->perm, rec,
-                           L->tune.kahan_chunk, cbar, vpbar, xbar, gv);
+        hipLaunchKernelGGL(k_accel_adj<R>, grid, block, stage_bytes<RecBwd<R>>(bw), st, q, n, lists(L),
+                           L->perm, rec, L->tune.kahan_chunk, cbar, vpbar, xbar, gv);
     }
     LAUNCH_CHECK("accel adjoint");
     reset_queue(L, st);
     {
         TimeScope ts(L, st, CRK_K_MOMENTS);  // the forward moments, recomputed
-        hipLaunchKernelGGL(k_moments_bwd<R>, grid, block, 0, st, q, n, lists(L), L->perm, L->quant, aux,
-                           qv, static_cast<const R*>(g->h), L->tune.kahan_chunk, cbar, mrec);
+        hipLaunchKernelGGL(k_moments_bwd<R>, grid, block, stage_bytes<RecQV<R>>(bw), st, q, n, lists(L),
+                           L->perm, L->quant, aux, qv, static_cast<const R*>(g->h), L->tune.kahan_chunk,
+                           cbar, mrec);
     }
     LAUNCH_CHECK("moments recompute + solve adjoint");
     reset_queue(L, st);
     {
         TimeScope ts(L, st, CRK_K_MOMENTS_ADJ);
-        hipLaunchKernelGGL(k_moments_adj<R>, grid, block, 0, st, q, n, lists(L), L->perm, mrec, vpbar,
-                           static_cast<const R*>(g->m), static_cast<const R*>(g->u), rho, gm1, xbar,
-                           varec, gu);
+        hipLaunchKernelGGL(k_moments_adj<R>, grid, block, stage_bytes<RecMom<R>>(bw), st, q, n, lists(L),
+                           L->perm, mrec, vpbar, static_cast<const R*>(g->m), static_cast<const R*>(g->u),
+                           rho, gm1, xbar, varec, gu);
     }
     LAUNCH_CHECK("moments adjoint");
     reset_queue(L, st);
     {
         TimeScope ts(L, st, CRK_K_VOLUME_ADJ);
-        hipLaunchKernelGGL(k_volume_adj<R>, grid, block, 0, st, q, n, lists(L), L->perm, varec, xbar, gx);
+        hipLaunchKernelGGL(k_volume_adj<R>, grid, block, stage_bytes<RecVA<R>>(bw), st, q, n, lists(L),
+                           L->perm, varec, xbar, gx);
     }
     LAUNCH_CHECK("volume adjoint");
     return CRK_OK;

@@ -111,7 +111,7 @@ __device__ __forceinline__ int queue_next(const Queue& q, QState& st) {
         if ((threadIdx.x & 63) == 0) it = atomicAdd(q.counter + st.g, 1);
         it = __builtin_amdgcn_readfirstlane(it);
         const int idx = st.g * q.per_group + it;
-        if (it < q.per_group && idx < q.n_items) return q.order[idx];
+        if (it < q.per_group && idx < q.n_items) return __builtin_amdgcn_readfirstlane(q.order[idx]);
         st.g = st.g + 1 == q.groups ? 0 : st.g + 1;
         st.tries += 1;
     }
@@ -124,7 +124,8 @@ __device__ __forceinline__ int queue_start(const Queue& q, QState& st) {
         const int bw = int(blockDim.x >> 6);
         const int slot = int(blockIdx.x / unsigned(q.groups)) * bw + int(threadIdx.x >> 6);
         const int idx = g * q.per_group + slot;
-        return (slot < q.per_group && idx < q.n_items) ? q.order[idx] : -1;
+        // the item is wave-uniform: keep it in a scalar register
+        return __builtin_amdgcn_readfirstlane((slot < q.per_group && idx < q.n_items) ? q.order[idx] : -1);
     }
     st.g = g;
     st.tries = 0;
@@ -213,9 +214,10 @@ __device__ __forceinline__ void pipelined_list(const uint32_t* __restrict__ lst,
 // direct global-to-LDS loads into a wave-private buffer, then every lane reads
 // its own record from LDS.  LDS position p (in 16-byte units) holds chunk
 // (p % NCH) ^ swz(r) of record r = p / NCH; the swizzle (power-of-two NCH
-// only) keeps the lanes' reads of one chunk on distinct banks.  The next
-// slot is staged while the current one is processed.  `lds` is this wave's
-// buffer of NCH x 64 uint4; slots past a lane's count hold valid indices.
+// only) keeps the lanes' reads of one chunk on distinct banks.  The record
+// indices of the next slot are fetched one slot ahead, and that slot is
+// staged while the current one is processed.  `lds` is this wave's buffer of
+// NCH x 64 uint4; slots past a lane's count hold valid indices.
 template <int NCH> __device__ __forceinline__ int stage_swz(int r) {
     if ((NCH & (NCH - 1)) != 0) return 0;  // odd strides are conflict-free as they are
     return (r ^ (r >> 3)) & (NCH - 1);
@@ -227,27 +229,43 @@ __device__ __forceinline__ void staged_list(const uint32_t* __restrict__ lst, in
                                             Body body) {
     constexpr int NCH = int(sizeof(D) / 16);
     static_assert(sizeof(D) % 16 == 0, "records are whole 16-byte chunks");
+    // with NCH dividing 64, the records a lane loads sit at a fixed stride in
+    // the slot's row (one address, immediate offsets); otherwise each lane
+    // takes them from the lanes that own them, all exchanges issued at once
+    constexpr bool kRowLoads = kWave % NCH == 0;
     if (len <= 0) return;
     const int lane = lane_id();
     const int last = len - 1;
-    auto slot = [&](int k) __attribute__((always_inline)) {
-        return lst[int64_t(k < last ? k : last) * kWave];
+    const uint32_t* row0 = lst - lane;  // the tile's slot-major list
+    uint32_t idx[NCH];
+    uint32_t own = 0;  // kRowLoads == false: this lane's entry of the next slot
+    auto load_idx = [&](int k) __attribute__((always_inline)) {
+        const uint32_t* row = row0 + int64_t(k < last ? k : last) * kWave;
+        if (kRowLoads) {
+#pragma unroll
+            for (int t = 0; t < NCH; ++t) idx[t] = row[(t * kWave + lane) / NCH];
+        } else {
+            own = row[lane];
+        }
     };
-    auto stage = [&](uint32_t j) __attribute__((always_inline)) {
+    auto stage = [&]() __attribute__((always_inline)) {
+        if (!kRowLoads) {
+#pragma unroll
+            for (int t = 0; t < NCH; ++t) idx[t] = uint32_t(__shfl(int(own), (t * kWave + lane) / NCH));
+        }
         const char* base = reinterpret_cast<const char*>(recs);
 #pragma unroll
         for (int t = 0; t < NCH; ++t) {
             const int g = t * kWave + lane;
-            const int r = g / NCH;
-            const int c = (g % NCH) ^ stage_swz<NCH>(r);
-            const uint32_t jr = uint32_t(__shfl(int(j), r));
-            __builtin_amdgcn_global_load_lds(base + size_t(jr) * sizeof(D) + size_t(c) * 16, lds + t * kWave,
-                                             16, 0, 0);
+            const int c = (g % NCH) ^ stage_swz<NCH>(g / NCH);
+            __builtin_amdgcn_global_load_lds(base + size_t(idx[t]) * sizeof(D) + size_t(c) * 16,
+                                             lds + t * kWave, 16, 0, 0);
         }
     };
     const int sw = stage_swz<NCH>(lane);
-    stage(slot(0));
-    uint32_t jn = slot(1);
+    load_idx(0);
+    stage();
+    load_idx(1);
     for (int k = 0; k < len; ++k) {
         __builtin_amdgcn_s_waitcnt(0);  // this slot's records are in LDS
         D d;
@@ -256,8 +274,8 @@ __device__ __forceinline__ void staged_list(const uint32_t* __restrict__ lst, in
         for (int c = 0; c < NCH; ++c) dst[c] = lds[lane * NCH + (c ^ sw)];
         __builtin_amdgcn_s_waitcnt(0);  // reads done before the buffer is refilled
         if (k + 1 < len) {
-            stage(jn);
-            jn = slot(k + 2);
+            stage();
+            load_idx(k + 2);
         }
         if (k < cnt) body(d, k);
     }
@@ -306,6 +324,12 @@ template <class R> __global__ void k_pack_qv(int n, const int32_t* perm, const u
     r.q[0] = q.x; r.q[1] = q.y; r.q[2] = q.z;
     r.V = V[perm[s]];
     out[s] = r;
+}
+
+// Dynamic LDS of a list-driven launch: one wave's staging buffer for records
+// of type D per wave of the workgroup (one-chunk records need none).
+template <class D> inline size_t stage_bytes(int block_waves) {
+    return sizeof(D) > 16 ? sizeof(D) * size_t(kWave) * size_t(block_waves) : 16;
 }
 
 // One-chunk records are gathered lane by lane (a cooperative load saves

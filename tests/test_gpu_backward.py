@@ -29,7 +29,7 @@ def crk():
     return crk
 
 
-def gpu_gradients(crk, cfg, prec, leaf_max=128):
+def gpu_gradients(crk, cfg, prec, leaf_max=128, tuning=None):
     dt = torch.float32 if prec == "f32" else torch.float64
     pos = torch.stack([torch.as_tensor(cfg[k]) for k in ("x", "y", "z")], 1).cuda().requires_grad_(True)
     v = torch.stack([torch.as_tensor(cfg[k]) for k in ("vx", "vy", "vz")], 1).to(dt).cuda().requires_grad_(True)
@@ -38,6 +38,8 @@ def gpu_gradients(crk, cfg, prec, leaf_max=128):
     m = torch.as_tensor(cfg["m"]).to(dt).cuda()
     L = crk.crk_build_leaf_pairs(pos[:, 0].detach().contiguous(), pos[:, 1].detach().contiguous(),
                                  pos[:, 2].detach().contiguous(), h, leaf_max=leaf_max, prec=prec)
+    if tuning:
+        L.set_tuning(**tuning)
     a, du = crk.CRKAccelEnergy.apply(pos, v, u, L, h, m, cfg["gamma"], prec)
     w = torch.as_tensor(cfg["w"]).to(dt).cuda()
     c = torch.as_tensor(cfg["c"]).to(dt).cuda()
@@ -135,6 +137,19 @@ def test_backward_bitwise_reproducible(crk):
     g2 = gpu_gradients(crk, cfg, "f32")
     for a, b in zip(g1[:3], g2[:3]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_backward_schedule_independent(crk, prec):
+    """Workgroup shape, queue mode and tile order change only which wave runs a
+    tile, never a lane's arithmetic: gradients are bitwise identical."""
+    cfg = synth.make_config("C4", n_side=20)
+    base = gpu_gradients(crk, cfg, prec)
+    for tun in ({"block_waves": 1}, {"block_waves": 2, "persistent": 1, "waves_per_cu": 3},
+                {"block_waves": 4, "xcd_groups": 1, "tile_order": 1}):
+        got = gpu_gradients(crk, cfg, prec, tuning=tun)
+        for a, b in zip(got[:3], base[:3]):
+            assert np.array_equal(a, b), tun
 
 
 def test_velocity_gradient_vanishes_without_energy_weight(crk):

@@ -148,7 +148,16 @@ def gravity_case(n_side):
     return cfg
 
 
-def borderline_bound(cfg, G=1.0):
+def pair_term(cfg, r, poly=None, G=1.0):
+    """|force per unit neighbour mass| of a pair at separation r (with the
+    optional polynomial subtracted)."""
+    f = 1.0 / (r ** 2 + cfg["eps"] ** 2) ** 1.5
+    if poly is not None:
+        f = f - np.polyval(np.asarray(poly)[::-1], r ** 2)
+    return G * np.abs(f) * r
+
+
+def borderline_bound(cfg, G=1.0, poly=None):
     """Per-particle sum of |pair term| over pairs with |r^2 - rc^2| <= 2^-20 rc^2."""
     from scipy.spatial import cKDTree
 
@@ -163,7 +172,7 @@ def borderline_bound(cfg, G=1.0):
     r = np.sqrt((d * d).sum(1))
     sel = r >= lo
     b = np.zeros(len(P))
-    f = G / (r[sel] ** 2 + cfg["eps"] ** 2) ** 1.5 * r[sel]
+    f = pair_term(cfg, r[sel], poly, G)
     np.add.at(b, pairs[sel, 0], cfg["m"][pairs[sel, 1]] * f)
     np.add.at(b, pairs[sel, 1], cfg["m"][pairs[sel, 0]] * f)
     return b
@@ -189,15 +198,90 @@ def test_gravity_parity(crk, prec):
     assert st["pairs_force"] == oracle.count_pairs(cfg, 2, r_fixed=cfg["r_cut"])[0]
 
 
-def test_gravity_polynomial(crk):
+def borderline_bound_targets(cfg, targets, G=1.0):
+    """borderline_bound restricted to the given target particles."""
+    from scipy.spatial import cKDTree
+
+    P = np.stack([cfg["x"], cfg["y"], cfg["z"]], 1)
+    tree = cKDTree(P, boxsize=1.0)
+    rc = cfg["r_cut"]
+    lo, hi = rc * np.sqrt(1 - 2.0 ** -20), rc * np.sqrt(1 + 2.0 ** -20)
+    b = np.zeros(len(targets))
+    for k, (i, nb) in enumerate(zip(targets, tree.query_ball_point(P[targets], hi))):
+        nb = np.asarray([j for j in nb if j != i], dtype=np.int64)
+        if nb.size == 0:
+            continue
+        d = P[i] - P[nb]
+        d -= np.floor(d + 0.5)
+        r = np.sqrt((d * d).sum(1))
+        sel = r >= lo
+        b[k] = (cfg["m"][nb[sel]] * pair_term(cfg, r[sel], None, G)).sum()
+    return b
+
+
+def gravity_gpu(crk, cfg, prec, leaf_max=512, tuning=None, poly=None):
+    dt = torch.float32 if prec == "f32" else torch.float64
+    x, y, z = (torch.as_tensor(cfg[k]).cuda() for k in ("x", "y", "z"))
+    m = torch.as_tensor(cfg["m"]).to(dt).cuda()
+    L = crk.crk_build_leaf_pairs(x, y, z, None, r_fixed=cfg["r_cut"], leaf_max=leaf_max, leaf_min=16,
+                                 split_extent=cfg["r_cut"], prec=prec)
+    if tuning:
+        L.set_tuning(**tuning)
+    a = crk.sr_gravity(L, x, y, z, m, cfg["G"], cfg["eps"], cfg["r_cut"], poly=poly, prec=prec)
+    return a.double().cpu().numpy(), L
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_gravity_unsoftened(crk, prec):
+    """eps = 0: the self pair and coincident pairs must be excluded explicitly."""
+    cfg = dict(gravity_case(16), eps=0.0)
+    print(f"case gravity eps=0 n={cfg['n']} prec={prec}", flush=True)
+    ref = oracle.gravity(cfg)
+    a, _ = gravity_gpu(crk, cfg, prec, leaf_max=128)
+    err = np.abs(a - ref).max(1)
+    assert np.all(err <= TOL[prec] * np.abs(ref).max() + borderline_bound(cfg)), err.max()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_gravity_spread_tiles(crk, prec):
+    """Tiles whose particles span more than a quarter of the box take the
+    fixed-point separation path (no bounding-box cull)."""
+    rng = np.random.default_rng(5)
+    n = 300
+    cfg = dict(x=synth.grid_round(rng.random(n)), y=synth.grid_round(rng.random(n)),
+               z=synth.grid_round(rng.random(n)), m=synth.f32(rng.uniform(0.5, 1.5, n) / n),
+               G=1.0, eps=float(synth.f32(0.01)), r_cut=float(synth.f32(0.2)))
+    print(f"case gravity spread n={n} prec={prec}", flush=True)
+    ref = oracle.gravity(cfg)
+    for leaf_max in (64, 512):
+        a, _ = gravity_gpu(crk, cfg, prec, leaf_max=leaf_max)
+        err = np.abs(a - ref).max(1)
+        assert np.all(err <= TOL[prec] * np.abs(ref).max() + borderline_bound(cfg)), (leaf_max, err.max())
+
+
+@pytest.mark.parametrize("tuning", [None, {"xcd_groups": 1, "tile_order": 1},
+                                    {"persistent": 1, "waves_per_cu": 8}])
+def test_gravity_full_size_sampled(crk, tuning):
+    """C3 at 2 x 128^3, leaf 512 (the benchmarked launch), FP32: 256 sampled
+    particles against the brute-force oracle."""
+    cfg = synth.make_config("C3")
+    print(f"case C3 full n={cfg['n']} tuning={tuning}", flush=True)
+    a, L = gravity_gpu(crk, cfg, "f32", leaf_max=512, tuning=tuning)
+    t = synth.sample_targets(cfg["n"], 256, seed=13)
+    ref = oracle.gravity(cfg, t)
+    bound = borderline_bound_targets(cfg, t)
+    err = np.abs(a[t] - ref).max(1)
+    assert np.all(err <= TOL["f32"] * np.abs(a).max() + bound), err.max()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_gravity_polynomial(crk, prec):
     cfg = gravity_case(16)
     poly = np.array([1.0, -2.0, 3.0, 0.5, -0.25, 0.125]) * 1e3
     ref = oracle.gravity(cfg, poly=poly)
-    x, y, z = (torch.as_tensor(cfg[k]).cuda() for k in ("x", "y", "z"))
-    m = torch.as_tensor(cfg["m"]).cuda()
-    L = crk.crk_build_leaf_pairs(x, y, z, None, r_fixed=cfg["r_cut"], leaf_max=64, prec="f64")
-    a = crk.sr_gravity(L, x, y, z, m, cfg["G"], cfg["eps"], cfg["r_cut"], poly=poly, prec="f64")
-    assert normwise(a.cpu().numpy(), ref) <= 1e-12 + borderline_bound(cfg).max() / np.abs(ref).max()
+    a, _ = gravity_gpu(crk, cfg, prec, leaf_max=64, poly=poly)
+    err = np.abs(a - ref).max(1)
+    assert np.all(err <= TOL[prec] * np.abs(ref).max() + borderline_bound(cfg, poly=poly)), err.max()
 
 
 # ---------------------------------------------------------------- edges and errors
