@@ -102,14 +102,36 @@ __global__ void k_pack_acc(int n, const int32_t* perm, const uint4* quant, const
 
 // One wave per tile: candidate particles are staged 64 at a time in LDS and
 // every (lane, candidate) pair is tested against max(H_i, H_j)^2 (with a tiny
-// margin so that no pair inside either support is missed in FP32).
+// margin so that no pair inside either support is missed in FP32).  The fill
+// pass puts the pairs inside the lane's own support (r < H_i, same margin)
+// at the front of its list and the others at the back, so the passes that
+// gather over r < H_i only stop at the gather count.
+// Squared separation for the list membership test.  The count and fill
+// passes are separate kernels: with contraction off and a fixed order both
+// evaluate it bit for bit alike, so a pair on the boundary is either in both
+// or in neither (and lanes i and j agree, the separations being exact
+// negatives).
+__device__ __forceinline__ float cull_r2(const uint4& qi, const uint4& qj) {
+#pragma clang fp contract(off)
+    const float dx = sep<float>(qi.x, qj.x);
+    const float dy = sep<float>(qi.y, qj.y);
+    const float dz = sep<float>(qi.z, qj.z);
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+__device__ __forceinline__ float cull_scale(float a2, float b2) {
+#pragma clang fp contract(off)
+    return fmaxf(a2, b2) * kCullMargin;
+}
+
 template <bool FILL>
 __global__ __launch_bounds__(64) void k_cull(Queue qu, int n, const uint4* __restrict__ quant,
                                              const int32_t* __restrict__ rng_off,
                                              const int2* __restrict__ rng, int32_t* cnt_out,
                                              const int64_t* __restrict__ ell_off,
                                              const int32_t* __restrict__ ell_len,
-                                             uint32_t* __restrict__ nbr) {
+                                             uint32_t* __restrict__ nbr, int32_t* __restrict__ cntg_out,
+                                             int32_t* __restrict__ leng_out, int32_t* __restrict__ err) {
     __shared__ uint4 sj[kWave];
     const int lane = lane_id();
     QState qs;
@@ -122,6 +144,8 @@ __global__ __launch_bounds__(64) void k_cull(Queue qu, int n, const uint4* __res
         int c = 0;
         const int64_t base_off = FILL ? ell_off[w] : 0;
         const int cap = (FILL && valid) ? cnt_out[s] : 0;
+        int front = 0, back = cap - 1;  // fill cursors: gather pairs, other pairs
+        const float G2 = cull_scale(Hi2, Hi2);
         for (int r = rng_off[w]; r < rng_off[w + 1]; ++r) {
             const int2 R = rng[r];
             for (int b = R.x; b < R.y; b += kWave) {
@@ -131,16 +155,16 @@ __global__ __launch_bounds__(64) void k_cull(Queue qu, int n, const uint4* __res
                 __syncthreads();
                 for (int jj = 0; jj < m; ++jj) {
                     const uint4 qj = sj[jj];
-                    const float dx = sep<float>(qi.x, qj.x);
-                    const float dy = sep<float>(qi.y, qj.y);
-                    const float dz = sep<float>(qi.z, qj.z);
-                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    const float r2 = cull_r2(qi, qj);
                     const float Hj = __uint_as_float(qj.w);
-                    const float R2 = fmaxf(Hi2, Hj * Hj) * kCullMargin;
+                    const float R2 = cull_scale(Hi2, Hj * Hj);
                     if (valid && r2 < R2 && (b + jj) != s) {
                         // the fill pass repeats the count pass exactly; the bound
-                        // check keeps every store inside the tile's list
-                        if (FILL && c < cap) nbr[base_off + int64_t(c) * kWave + lane] = uint32_t(b + jj);
+                        // check keeps every store inside the lane's cnt slots
+                        if (FILL && front <= back) {
+                            const int k = r2 < G2 ? front++ : back--;
+                            nbr[base_off + int64_t(k) * kWave + lane] = uint32_t(b + jj);
+                        }
                         ++c;
                     }
                 }
@@ -152,6 +176,16 @@ __global__ __launch_bounds__(64) void k_cull(Queue qu, int n, const uint4* __res
             // lane's own particle, or the tile's first one for lanes past n)
             const uint32_t self = uint32_t(valid ? s : w * kWave);
             for (int k = cap; k < ell_len[w]; ++k) nbr[base_off + int64_t(k) * kWave + lane] = self;
+            if (c != cap) {
+                // the two passes disagreed: keep every slot a valid index and
+                // let the build report the error
+                for (int k = front; k <= back; ++k) nbr[base_off + int64_t(k) * kWave + lane] = self;
+                atomicAdd(err, 1);
+            }
+            if (valid) cntg_out[s] = front;
+            int mx = front;
+            for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o));
+            if (lane == 0) leng_out[w] = mx;
         }
     }
 }
@@ -220,7 +254,7 @@ __global__ __launch_bounds__(64) void k_count_fixed(int n_tiles, int n, const ui
 template <class R>
 __global__ __launch_bounds__(256) void k_volume(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
                                                 const uint4* __restrict__ quant, const R* __restrict__ h,
-                                                const R* __restrict__ m, R* __restrict__ V_out,
+                                                const R* __restrict__ m, int chunk, R* __restrict__ V_out,
                                                 R* __restrict__ rho_out) {
     const int lane = lane_id();
     QState qs;
@@ -234,7 +268,9 @@ __global__ __launch_bounds__(256) void k_volume(Queue qu, int n, Lists L, const 
         const int cnt = valid ? L.cnt[s] : 0;
         const int len = L.len[w];
         const uint32_t* lst = L.nbr + L.off[w] + lane;
-        R S = R(1), c = R(0);  // self term: w(0) = 1
+        ChunkSums<R, 1> S;
+        S.zero();
+        S.add(0, R(1));  // self term: w(0) = 1
         pipelined_list<uint4>(
             lst, cnt, len, [&](uint32_t j) __attribute__((always_inline)) { return quant[j]; },
             [&](const uint4& qj, int) __attribute__((always_inline)) {
@@ -242,11 +278,12 @@ __global__ __launch_bounds__(256) void k_volume(Queue qu, int n, Lists L, const 
                 const R r = dsqrt(dx * dx + dy * dy + dz * dz);
                 R wq, fq;
                 wendland(r * invH, wq, fq);
-                if (sizeof(R) == 4) kadd(S, c, wq);
-                else S += wq;
+                S.add(0, wq);
+                S.next(chunk);
             });
+        S.fold();
         if (valid) {
-            const R Ssum = (S - c) * norm_W(H);
+            const R Ssum = S.get(0) * norm_W(H);
             V_out[i] = R(1) / Ssum;
             rho_out[i] = m[i] * Ssum;
         }
@@ -307,9 +344,8 @@ __device__ __forceinline__ void corrected_grad(const RecAcc<R>& r, R wq, R fq, c
 template <class R>
 __global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
                                                const RecAcc<R>* __restrict__ rec, const R* __restrict__ m,
-                                               R* __restrict__ a_out, R* __restrict__ du_out,
+                                               int chunk, R* __restrict__ a_out, R* __restrict__ du_out,
                                                double* __restrict__ partials) {
-    constexpr bool kComp = sizeof(R) == 4;
     constexpr int kStage = int(sizeof(RecAcc<R>) / 16) * kWave;
     extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
     const int lane = lane_id();
@@ -321,7 +357,8 @@ __global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const i
         const int cnt = valid ? L.cnt[s] : 0;
         const int len = L.len[w];
         const uint32_t* lst = L.nbr + L.off[w] + lane;
-        R acc[4] = {R(0), R(0), R(0), R(0)}, cmp[4] = {R(0), R(0), R(0), R(0)};
+        ChunkSums<R, 4> acc;  // sum F (3), sum F . v_ij
+        acc.zero();
         staged_list<RecAcc<R>>(
             lst, cnt, len, rec, stage_buf + (threadIdx.x >> 6) * kStage,
             [&](const RecAcc<R>& rj, int) __attribute__((always_inline)) {
@@ -341,22 +378,22 @@ __global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const i
                 for (int c = 0; c < 3; ++c) {
                     const R F = coef * (Gi[c] - Gj[c]);
                     Fv += F * (ri.v[c] - rj.v[c]);
-                    if (kComp) kadd(acc[c], cmp[c], F);
-                    else acc[c] += F;
+                    acc.add(c, F);
                 }
-                if (kComp) kadd(acc[3], cmp[3], Fv);
-                else acc[3] += Fv;
+                acc.add(3, Fv);
+                acc.next(chunk);
             });
+        acc.fold();
         double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (valid) {
             const int i = perm[s];
             const R mi = m[i];
             R av[3];
             for (int c = 0; c < 3; ++c) {
-                av[c] = (acc[c] - cmp[c]) / mi;
+                av[c] = acc.get(c) / mi;
                 a_out[3 * i + c] = av[c];
             }
-            const R du = R(-0.5) * (acc[3] - cmp[3]) / mi;
+            const R du = R(-0.5) * acc.get(3) / mi;
             du_out[i] = du;
             const double md = double(mi);
             const double ax = av[0], ay = av[1], az = av[2], dd = du;
@@ -554,7 +591,8 @@ namespace crk {
 
 void release(crk_leaves* L) {
     void* ptrs[] = {L->perm, L->quant, L->Hd, L->rng_off, L->rng, L->order_cull, L->order_pair, L->order_tree,
-                    L->counter, L->cnt, L->ell_off, L->ell_len, L->nbr, L->partials, L->counts,
+                    L->counter, L->cnt, L->cnt_gather, L->ell_off, L->ell_len, L->ell_len_gather, L->nbr,
+                    L->build_err, L->partials, L->counts,
                     L->scratch};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -625,6 +663,9 @@ void reset_queue(crk_leaves* L, hipStream_t st) {
 }
 
 Lists lists(const crk_leaves* L) { return Lists{L->cnt, L->ell_off, L->ell_len, L->nbr}; }
+Lists lists_gather(const crk_leaves* L) {
+    return Lists{L->cnt_gather, L->ell_off, L->ell_len_gather, L->nbr};
+}
 
 }  // namespace crk
 
@@ -636,8 +677,9 @@ template <class R> int volume_impl(crk_leaves* L, const crk_gas* g, R* V, R* rho
     reset_queue(L, st);
     TimeScope ts(L, st, CRK_K_VOLUME);
     hipLaunchKernelGGL(k_volume<R>, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves), 0, st,
-                       make_queue(L, L->order_pair), int(L->n), lists(L), L->perm, L->quant,
-                       static_cast<const R*>(g->h), static_cast<const R*>(g->m), V, rho);
+                       make_queue(L, L->order_pair), int(L->n), lists_gather(L), L->perm, L->quant,
+                       static_cast<const R*>(g->h), static_cast<const R*>(g->m), L->tune.kahan_chunk, V,
+                       rho);
     LAUNCH_CHECK("volume");
     return CRK_OK;
 }
@@ -659,7 +701,7 @@ int corrections_impl(crk_leaves* L, const crk_gas* g, const R* V, const crk_corr
     TimeScope ts(L, st, CRK_K_MOMENTS);
     hipLaunchKernelGGL(k_moments<R>, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves),
                        stage_bytes<RecQV<R>>(L->tune.block_waves), st,
-                       make_queue(L, L->order_pair), n, lists(L), L->perm, qv,
+                       make_queue(L, L->order_pair), n, lists_gather(L), L->perm, qv,
                        static_cast<const R*>(g->h), L->tune.kahan_chunk, static_cast<R*>(out->A),
                        static_cast<R*>(out->B), static_cast<R*>(out->dA), static_cast<R*>(out->dB),
                        reinterpret_cast<unsigned long long*>(n_fallback));
@@ -691,7 +733,7 @@ int accel_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const 
         hipLaunchKernelGGL(k_accel<R>, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves),
                            stage_bytes<RecAcc<R>>(L->tune.block_waves), st,
                            make_queue(L, L->order_pair), n, lists(L), L->perm, rec,
-                           static_cast<const R*>(g->m), a, dudt, L->partials);
+                           static_cast<const R*>(g->m), L->tune.kahan_chunk, a, dudt, L->partials);
     }
     LAUNCH_CHECK("accel");
     if (totals) {
@@ -924,7 +966,8 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
 
     if (L->hydro) {
         if ((rc = dalloc(&L->Hd, n)) || (rc = dalloc(&L->cnt, n)) || (rc = dalloc(&L->ell_off, nt)) ||
-            (rc = dalloc(&L->ell_len, nt)))
+            (rc = dalloc(&L->ell_len, nt)) || (rc = dalloc(&L->cnt_gather, n)) ||
+            (rc = dalloc(&L->ell_len_gather, nt)) || (rc = dalloc(&L->build_err, 1)))
             return bail(rc);
         if (hipMemcpyAsync(L->Hd, hH.data(), n * 8, hipMemcpyHostToDevice, stream) != hipSuccess)
             return bail(fail(CRK_EHIP, "uploading H failed"));
@@ -935,7 +978,7 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
             TimeScope ts(L, stream, CRK_K_CULL);
             hipLaunchKernelGGL(k_cull<false>, dim3(grid_1wave(L)), dim3(kWave), 0, stream,
                                make_queue(L, L->order_cull), int(n), L->quant, L->rng_off, L->rng,
-                               L->cnt, nullptr, nullptr, nullptr);
+                               L->cnt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
         }
         if (hipGetLastError() != hipSuccess) return bail(fail(CRK_EHIP, "launch cull count failed"));
         std::vector<int32_t> hc(n);
@@ -960,11 +1003,14 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
             hipMemcpyAsync(L->ell_len, len.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
             return bail(fail(CRK_EHIP, "uploading list offsets failed"));
         hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, L->counter);
+        if (hipMemsetAsync(L->build_err, 0, sizeof(int32_t), stream) != hipSuccess)
+            return bail(fail(CRK_EHIP, "clearing the list check failed"));
         {
             TimeScope ts(L, stream, CRK_K_CULL);
             hipLaunchKernelGGL(k_cull<true>, dim3(grid_1wave(L)), dim3(kWave), 0, stream,
                                make_queue(L, L->order_cull), int(n), L->quant, L->rng_off, L->rng,
-                               L->cnt, L->ell_off, L->ell_len, L->nbr);
+                               L->cnt, L->ell_off, L->ell_len, L->nbr, L->cnt_gather, L->ell_len_gather,
+                               L->build_err);
         }
         L->timing = false;
         if (hipGetLastError() != hipSuccess) return bail(fail(CRK_EHIP, "launch cull fill failed"));
@@ -972,9 +1018,15 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
         std::vector<int32_t> po(nt);
         std::iota(po.begin(), po.end(), 0);
         std::stable_sort(po.begin(), po.end(), [&](int32_t a, int32_t b) { return len[a] > len[b]; });
+        int32_t mismatched = 0;
         if (hipMemcpyAsync(L->order_pair, po.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+            hipMemcpyAsync(&mismatched, L->build_err, sizeof(int32_t), hipMemcpyDeviceToHost, stream) !=
+                hipSuccess ||
             hipStreamSynchronize(stream) != hipSuccess)
             return bail(fail(CRK_EHIP, "list build failed"));
+        if (mismatched)
+            return bail(fail(CRK_EHIP, "neighbour lists: count and fill passes disagree on %d particles",
+                             mismatched));
         L->stats[3] = entries;
         L->stats[6] = total - entries;
     }

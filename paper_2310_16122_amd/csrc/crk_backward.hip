@@ -44,29 +44,6 @@ template <class R> struct alignas(128) RecBwd {
 static_assert(sizeof(RecBwd<float>) == 128, "f32 backward record is one line");
 static_assert(sizeof(RecBwd<double>) == 256, "f64 backward record is two lines");
 
-// Chunked compensated sums: plain partial sums over `chunk` pairs, folded into
-// (s, c) Kahan pairs (FP32); plain sums in FP64.
-template <class R, int N> struct ChunkSums {
-    R p[N], s[N], c[N];
-    int kk;
-    __device__ void zero() {
-        kk = 0;
-#pragma unroll
-        for (int e = 0; e < N; ++e) { p[e] = R(0); s[e] = R(0); c[e] = R(0); }
-    }
-    __device__ void add(int e, R t) { p[e] += t; }
-    __device__ void fold() {
-        if (sizeof(R) != 4) return;
-#pragma unroll
-        for (int e = 0; e < N; ++e) { kadd(s[e], c[e], p[e]); p[e] = R(0); }
-    }
-    __device__ void next(int chunk) {
-        if (sizeof(R) == 4 && ++kk == chunk) { fold(); kk = 0; }
-    }
-    // value after a final fold
-    __device__ R get(int e) const { return sizeof(R) == 4 ? s[e] - c[e] : p[e]; }
-};
-
 template <class R, int N> struct Sums {
     R s[N], c[N];
     __device__ void zero() {
@@ -477,12 +454,12 @@ template <class R> struct alignas(16) RecVA {
 };
 
 // 2. moments recomputed with the forward's arithmetic, then the solve adjoint
+// (three waves per SIMD: the few spilled values live outside the neighbour loop)
 template <class R>
-__global__ __launch_bounds__(256) void k_moments_bwd(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
-                                                     const uint4* __restrict__ quant, const R* __restrict__ aux,
-                                                     const RecQV<R>* __restrict__ qv, const R* __restrict__ h,
-                                                     int chunk, const R* __restrict__ cbar,
-                                                     RecMom<R>* __restrict__ mrec) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_moments_bwd(
+    Queue qu, int n, Lists L, const int32_t* __restrict__ perm, const uint4* __restrict__ quant,
+    const R* __restrict__ aux, const RecQV<R>* __restrict__ qv, const R* __restrict__ h, int chunk,
+    const R* __restrict__ cbar, RecMom<R>* __restrict__ mrec) {
     constexpr int kStage = sizeof(RecQV<R>) > 16 ? int(sizeof(RecQV<R>) / 16) * kWave : 1;
     extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
     const int lane = lane_id();
@@ -535,7 +512,7 @@ __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, c
         const int cnt = valid ? L.cnt[s] : 0;
         const int len = L.len[w];
         const uint32_t* lst = L.nbr + L.off[w] + lane;
-        Sums<R, 4> acc;  // Vbar, xbar[3]
+        Sums<R, 4> acc;  // Vbar, xbar[3]; per-pair compensation keeps the register count at 3 waves/SIMD
         acc.zero();
         staged_list<RecMom<R>>(
             lst, cnt, len, mrec, stage_buf + (threadIdx.x >> 6) * kStage,
@@ -583,7 +560,8 @@ __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, c
 template <class R>
 __global__ __launch_bounds__(256) void k_volume_adj(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
                                                     const RecVA<R>* __restrict__ varec,
-                                                    const R* __restrict__ xbar, R* __restrict__ gx) {
+                                                    const R* __restrict__ xbar, int chunk,
+                                                    R* __restrict__ gx) {
     constexpr int kStage = int(sizeof(RecVA<R>) / 16) * kWave;
     extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
     const int lane = lane_id();
@@ -599,7 +577,7 @@ __global__ __launch_bounds__(256) void k_volume_adj(Queue qu, int n, Lists L, co
         const int cnt = valid ? L.cnt[s] : 0;
         const int len = L.len[w];
         const uint32_t* lst = L.nbr + L.off[w] + lane;
-        Sums<R, 3> acc;
+        ChunkSums<R, 3> acc;
         acc.zero();
         list_loop<RecVA<R>>(
             lst, cnt, len, varec, stage_buf + (threadIdx.x >> 6) * kStage,
@@ -615,7 +593,9 @@ __global__ __launch_bounds__(256) void k_volume_adj(Queue qu, int n, Lists L, co
                 const R coef = Sbi * cFi * fi + d.Sbar * cFj * fj;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) acc.add(c, coef * x[c]);
+                acc.next(chunk);
             });
+        acc.fold();
         if (valid) {
             const int i = perm[s];
 #pragma unroll
@@ -674,9 +654,9 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
     reset_queue(L, st);
     {
         TimeScope ts(L, st, CRK_K_MOMENTS);  // the forward moments, recomputed
-        hipLaunchKernelGGL(k_moments_bwd<R>, grid, block, stage_bytes<RecQV<R>>(bw), st, q, n, lists(L),
-                           L->perm, L->quant, aux, qv, static_cast<const R*>(g->h), L->tune.kahan_chunk,
-                           cbar, mrec);
+        hipLaunchKernelGGL(k_moments_bwd<R>, grid, block, stage_bytes<RecQV<R>>(bw), st, q, n,
+                           lists_gather(L), L->perm, L->quant, aux, qv, static_cast<const R*>(g->h),
+                           L->tune.kahan_chunk, cbar, mrec);
     }
     LAUNCH_CHECK("moments recompute + solve adjoint");
     reset_queue(L, st);
@@ -691,7 +671,7 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
     {
         TimeScope ts(L, st, CRK_K_VOLUME_ADJ);
         hipLaunchKernelGGL(k_volume_adj<R>, grid, block, stage_bytes<RecVA<R>>(bw), st, q, n, lists(L),
-                           L->perm, varec, xbar, gx);
+                           L->perm, varec, xbar, L->tune.kahan_chunk, gx);
     }
     LAUNCH_CHECK("volume adjoint");
     return CRK_OK;

@@ -166,6 +166,8 @@ template <class R> __global__ void k_gather(int n, const int32_t* perm, const R*
 
 // ------------------------------------------------------------------ list access
 
+// A tile's neighbour lists: per lane `cnt` entries (the first `cnt` slots),
+// per tile `len` slots (the longest lane); slot k of lane l at off + 64 k + l.
 struct Lists {
     const int32_t* cnt;
     const int64_t* off;
@@ -345,6 +347,29 @@ __device__ __forceinline__ void list_loop(const uint32_t* __restrict__ lst, int 
     }
 }
 
+// Chunked compensated sums: plain partial sums over `chunk` pairs, folded into
+// (s, c) Kahan pairs (FP32); plain sums in FP64.
+template <class R, int N> struct ChunkSums {
+    R p[N], s[N], c[N];
+    int kk;
+    __device__ void zero() {
+        kk = 0;
+#pragma unroll
+        for (int e = 0; e < N; ++e) { p[e] = R(0); s[e] = R(0); c[e] = R(0); }
+    }
+    __device__ void add(int e, R t) { p[e] += t; }
+    __device__ void fold() {
+        if (sizeof(R) != 4) return;
+#pragma unroll
+        for (int e = 0; e < N; ++e) { kadd(s[e], c[e], p[e]); p[e] = R(0); }
+    }
+    __device__ void next(int chunk) {
+        if (sizeof(R) == 4 && ++kk == chunk) { fold(); kk = 0; }
+    }
+    // value after a final fold
+    __device__ R get(int e) const { return sizeof(R) == 4 ? s[e] - c[e] : p[e]; }
+};
+
 // ------------------------------------------------------------------ moments
 
 // The 40 correction moments of the lane's particle in FP64 (storage order:
@@ -520,8 +545,11 @@ struct crk_leaves {
     int32_t* order_tree = nullptr;
     int32_t* counter = nullptr;
     int32_t* cnt = nullptr;
+    int32_t* cnt_gather = nullptr;  // entries with r < H_i (the front of each lane's list)
     int64_t* ell_off = nullptr;
     int32_t* ell_len = nullptr;
+    int32_t* ell_len_gather = nullptr;  // per tile: longest gather part
+    int32_t* build_err = nullptr;       // lanes whose count and fill passes disagreed
     uint32_t* nbr = nullptr;
     double* partials = nullptr;
     unsigned long long* counts = nullptr;
@@ -557,7 +585,8 @@ int grid_1wave(const crk_leaves* L);
 int grid_nwave(const crk_leaves* L);
 int check_gas(const crk_leaves* L, const crk_gas* g, bool need_v);
 void reset_queue(crk_leaves* L, hipStream_t st);
-Lists lists(const crk_leaves* L);
+Lists lists(const crk_leaves* L);         // pairs r < max(H_i, H_j)
+Lists lists_gather(const crk_leaves* L);  // their front parts: r < H_i
 
 // Brackets one launch with events when timing is enabled.
 struct TimeScope {

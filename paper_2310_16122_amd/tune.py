@@ -3,7 +3,7 @@
 The search space is the ``crk_tuning`` struct of ``include/crk.h`` --
 persistent work queue or one tile per wave, persistent grid size, waves per
 workgroup, number of XCD chunks of tile order, tree order or longest-first
-order, compensation chunk of the FP32 moments -- plus the leaf size of the
+order, compensation chunk of the FP32 pair sums -- plus the leaf size of the
 tree (which needs a rebuild).  Candidates are timed with the library's own
 per-kernel HIP-event timing on the caller's step (a closure that runs the
 passes), by coordinate descent from the current setting.  Results are cached
