@@ -928,49 +928,65 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
     L->n_tiles = (n + kWave - 1) / kWave;
     const int64_t nt = L->n_tiles;
 
-    // tree-order fixed-point positions and support radii
+    if ((rc = dalloc(&L->perm, n)) || (rc = dalloc(&L->quant, n)) || (rc = dalloc(&L->rng_off, nt + 1)) ||
+        (rc = dalloc(&L->order_cull, nt)) || (rc = dalloc(&L->order_pair, nt)) ||
+        (rc = dalloc(&L->order_tree, nt)) || (rc = dalloc(&L->partials, 8 * nt)))
+        return bail(rc);
+    if (L->hydro && ((rc = dalloc(&L->Hd, n)) || (rc = dalloc(&L->cnt, n)) || (rc = dalloc(&L->ell_off, nt)) ||
+                     (rc = dalloc(&L->ell_len, nt)) || (rc = dalloc(&L->cnt_gather, n)) ||
+                     (rc = dalloc(&L->ell_len_gather, nt)) || (rc = dalloc(&L->build_err, 1))))
+        return bail(rc);
+    // tree-order fixed-point positions and support radii, candidate ranges and
+    // the tile orders of one tree order, uploaded (host buffers must outlive
+    // the asynchronous copies: they are synchronised before reuse)
     std::vector<uint4> hq(n);
     std::vector<double> hH(L->hydro ? n : 0);
-    for (int64_t s = 0; s < n; ++s) {
-        const int32_t i = tout.perm[s];
-        hq[s] = make_uint4(q[0][i], q[1][i], q[2][i],
-                           L->hydro ? [](float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }(float(H[i])) : 0u);
-        if (L->hydro) hH[s] = H[i];
-    }
-    // longest-processing-time-first order of tiles for the candidate scan
     std::vector<int32_t> order(nt), tree_order(nt);
-    std::iota(order.begin(), order.end(), 0);
     std::iota(tree_order.begin(), tree_order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int32_t a, int32_t b) { return tout.tile_cand[a] > tout.tile_cand[b]; });
-
-    if ((rc = dalloc(&L->perm, n)) || (rc = dalloc(&L->quant, n)) ||
-        (rc = dalloc(&L->rng_off, nt + 1)) || (rc = dalloc(&L->rng, tout.rng.size() / 2)) ||
-        (rc = dalloc(&L->order_cull, nt)) || (rc = dalloc(&L->order_pair, nt)) ||
-        (rc = dalloc(&L->order_tree, nt)) ||
-        (rc = dalloc(&L->partials, 8 * nt)))
-        return bail(rc);
-    if (hipMemcpyAsync(L->perm, tout.perm.data(), n * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(L->quant, hq.data(), n * 16, hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(L->rng_off, tout.rng_off.data(), (nt + 1) * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
-        (tout.rng.size() && hipMemcpyAsync(L->rng, tout.rng.data(), tout.rng.size() * 4,
-                                           hipMemcpyHostToDevice, stream) != hipSuccess) ||
-        hipMemcpyAsync(L->order_cull, order.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(L->order_pair, order.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(L->order_tree, tree_order.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
-        return bail(fail(CRK_EHIP, "uploading the tree failed"));
-
+    size_t rng_alloc = 0;
+    auto upload = [&](const crk::TreeOutput& t) -> int {
+        for (int64_t s = 0; s < n; ++s) {
+            const int32_t i = t.perm[s];
+            uint32_t hw = 0;
+            if (L->hydro) {
+                const float hf = float(H[i]);
+                std::memcpy(&hw, &hf, 4);
+                hH[s] = H[i];
+            }
+            hq[s] = make_uint4(q[0][i], q[1][i], q[2][i], hw);
+        }
+        // longest-processing-time-first order of tiles for the candidate scan
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return t.tile_cand[a] > t.tile_cand[b]; });
+        const size_t nr = t.rng.size() / 2;
+        if (nr > rng_alloc) {
+            if (L->rng && hipFree(L->rng) != hipSuccess) return fail(CRK_EHIP, "freeing candidate ranges failed");
+            L->rng = nullptr;
+            int e = dalloc(&L->rng, nr);
+            if (e) return e;
+            rng_alloc = nr;
+        }
+        if (hipMemcpyAsync(L->perm, t.perm.data(), n * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+            hipMemcpyAsync(L->quant, hq.data(), n * 16, hipMemcpyHostToDevice, stream) != hipSuccess ||
+            hipMemcpyAsync(L->rng_off, t.rng_off.data(), (nt + 1) * 4, hipMemcpyHostToDevice, stream) !=
+                hipSuccess ||
+            (nr && hipMemcpyAsync(L->rng, t.rng.data(), nr * 8, hipMemcpyHostToDevice, stream) != hipSuccess) ||
+            hipMemcpyAsync(L->order_cull, order.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+            hipMemcpyAsync(L->order_pair, order.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+            hipMemcpyAsync(L->order_tree, tree_order.data(), nt * 4, hipMemcpyHostToDevice, stream) !=
+                hipSuccess ||
+            (L->hydro && hipMemcpyAsync(L->Hd, hH.data(), n * 8, hipMemcpyHostToDevice, stream) != hipSuccess) ||
+            hipStreamSynchronize(stream) != hipSuccess)
+            return fail(CRK_EHIP, "uploading the tree failed");
+        L->stats[2] = t.cand_pairs;
+        return CRK_OK;
+    };
+    if ((rc = upload(tout))) return bail(rc);
     L->stats[0] = L->n_leaves;
     L->stats[1] = nt;
-    L->stats[2] = tout.cand_pairs;
 
     if (L->hydro) {
-        if ((rc = dalloc(&L->Hd, n)) || (rc = dalloc(&L->cnt, n)) || (rc = dalloc(&L->ell_off, nt)) ||
-            (rc = dalloc(&L->ell_len, nt)) || (rc = dalloc(&L->cnt_gather, n)) ||
-            (rc = dalloc(&L->ell_len_gather, nt)) || (rc = dalloc(&L->build_err, 1)))
-            return bail(rc);
-        if (hipMemcpyAsync(L->Hd, hH.data(), n * 8, hipMemcpyHostToDevice, stream) != hipSuccess)
-            return bail(fail(CRK_EHIP, "uploading H failed"));
         // count pass
         hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, L->counter);
         L->timing = true;  // the list build is always timed (read by crk_kernel_times)
@@ -985,6 +1001,26 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
         if (hipMemcpyAsync(hc.data(), L->cnt, n * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
             hipStreamSynchronize(stream) != hipSuccess)
             return bail(fail(CRK_EHIP, "cull count failed"));
+        // Tiles of similar list lengths: order every leaf by decreasing count
+        // (the leaves, their boxes and every particle's count stay the same;
+        // only the tiles and their candidate ranges change), so that a tile's
+        // longest list -- the slots all its lanes step through -- is closer
+        // to its average one.
+        {
+            std::vector<int32_t> work(n);
+            for (int64_t s = 0; s < n; ++s) work[tout.perm[s]] = hc[s];
+            tin.weight = work.data();
+            crk::TreeOutput tb;
+            if (!crk::build_tree(tin, tb, &terr)) return bail(fail(CRK_EINVAL, "tree: %s", terr));
+            if (int64_t(tb.leaf_begin.size()) != L->n_leaves)
+                return bail(fail(CRK_EHIP, "tree rebuild changed the leaves"));
+            tout = std::move(tb);
+            if ((rc = upload(tout))) return bail(rc);
+            for (int64_t s = 0; s < n; ++s) hc[s] = work[tout.perm[s]];
+            if (hipMemcpyAsync(L->cnt, hc.data(), n * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+                hipStreamSynchronize(stream) != hipSuccess)
+                return bail(fail(CRK_EHIP, "uploading list counts failed"));
+        }
         std::vector<int32_t> len(nt, 0);
         std::vector<int64_t> off(nt, 0);
         int64_t total = 0, entries = 0;

@@ -157,6 +157,15 @@ bool build_tree(const TreeInput& in, TreeOutput& out, const char** err) {
         out.leaf_begin.push_back(nodes[k].begin);
         out.leaf_end.push_back(nodes[k].end);
     }
+    if (in.weight) {
+        // a leaf's box and radius do not depend on the order inside it
+        int32_t* perm = out.perm.data();
+        const int32_t* wt = in.weight;
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t k = 0; k < int64_t(leaves.size()); ++k)
+            std::stable_sort(perm + nodes[leaves[k]].begin, perm + nodes[leaves[k]].end,
+                             [wt](int32_t a, int32_t b) { return wt[a] > wt[b]; });
+    }
 
     // tiles of kTile consecutive particles in tree order
     const int64_t n_tiles = (n + kTile - 1) / kTile;

@@ -16,6 +16,10 @@ struct TreeInput {
     int leaf_max;
     int leaf_min;
     double split_extent;    // box units; <= 0 disables the extent rule
+    // optional per-particle work (input index): inside every leaf, particles
+    // are ordered by decreasing work (stable), so that each tile of 64 groups
+    // lanes of similar list length
+    const int32_t* weight = nullptr;
 };
 
 struct TreeOutput {

@@ -31,7 +31,8 @@ def shim():
     return _lib
 
 
-def build(cfg, H=None, r_fixed=0.0, leaf_max=32, leaf_min=1, split_extent=0.0):
+def build(cfg, H=None, r_fixed=0.0, leaf_max=32, leaf_min=1, split_extent=0.0, weight=None,
+          leaves=False):
     n = len(cfg["x"])
     q = [np.ascontiguousarray(synth.to_u32(cfg[k])) for k in ("x", "y", "z")]
     perm = np.empty(n, np.int32)
@@ -43,12 +44,16 @@ def build(cfg, H=None, r_fixed=0.0, leaf_max=32, leaf_min=1, split_extent=0.0):
     cp = ctypes.c_longlong()
     P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
     Hc = None if H is None else np.ascontiguousarray(H, np.float64)
+    W = None if weight is None else np.ascontiguousarray(weight, np.int32)
+    lb = np.empty(n + 1, np.int32)
     rc = shim().tree_shim(ctypes.c_longlong(n), P(q[0]), P(q[1]), P(q[2]),
                           None if Hc is None else P(Hc), ctypes.c_double(r_fixed),
                           leaf_max, leaf_min, ctypes.c_double(split_extent), P(perm),
-                          ctypes.byref(nl), P(rng_off), P(rng), cap, ctypes.byref(cp))
+                          ctypes.byref(nl), P(rng_off), P(rng), cap, ctypes.byref(cp),
+                          None if W is None else P(W), P(lb))
     assert rc >= 0
-    return perm, nl.value, rng_off, rng[:rc].reshape(-1, 2), cp.value
+    res = (perm, nl.value, rng_off, rng[:rc].reshape(-1, 2), cp.value)
+    return res + (lb[:nl.value],) if leaves else res
 
 
 def brute_pairs(cfg, radius_fn):
@@ -129,3 +134,31 @@ def test_rebuild_on_tree_order_is_identity():
     lat2 = {k: lat[k][p] for k in ("x", "y", "z")}
     p2, *_ = build(lat2, H=2.0 * lat["h"], leaf_max=64)
     assert np.array_equal(p2, np.arange(lat["n"]))
+
+
+def test_weighted_leaves_keep_sets_and_sort_by_work():
+    """With a work weight, each leaf holds the same particles, ordered by
+    decreasing weight (stable), and the new tiles' candidates still cover
+    every pair; rebuilding on that order with the same weights is the identity."""
+    cfg = synth.make_config("C2", n_side=14)
+    n = cfg["n"]
+    H = 2.0 * cfg["h"]
+    w = np.random.default_rng(4).integers(40, 120, n).astype(np.int32)
+    p0, nl0, _, _, _, lb0 = build(cfg, H=H, leaf_max=128, leaves=True)
+    p1, nl1, off, rng, _, lb1 = build(cfg, H=H, leaf_max=128, weight=w, leaves=True)
+    assert nl0 == nl1 and np.array_equal(lb0, lb1)
+    ends = np.append(lb1[1:], n)
+    for b, e in zip(lb1, ends):
+        assert set(p0[b:e]) == set(p1[b:e])
+        ww = w[p1[b:e]]
+        assert np.all(ww[:-1] >= ww[1:])
+        # stable: equal weights keep the unweighted order
+        for v in np.unique(ww):
+            sel = p1[b:e][ww == v]
+            pos0 = {x: k for k, x in enumerate(p0[b:e])}
+            assert [pos0[x] for x in sel] == sorted(pos0[x] for x in sel)
+    need = brute_pairs(cfg, lambda: np.maximum(H[:, None], H[None, :]))
+    assert covered(p1, off, rng, need)
+    cfg2 = {k: cfg[k][p1] for k in ("x", "y", "z")}
+    p2, *_ = build(cfg2, H=H[p1], leaf_max=128, weight=w[p1])
+    assert np.array_equal(p2, np.arange(n))
