@@ -209,10 +209,13 @@ def bench_hydro(args, torch, crk):
         return (2.0 * w[:, None] * o["a"]).contiguous(), c
 
     def make_step(Lh, g, prec, ga, gdu):
+        # the forward keeps its per-particle moment sums for the backward
+        # (30 doubles per particle); pair terms are recomputed, never stored
         def step():
-            o = crk.forward(Lh, g, cfg["gamma"], prec)
+            o = crk.forward(Lh, g, cfg["gamma"], prec, store_sums=not args.no_backward)
             if not args.no_backward:
-                crk.crk_accel_energy_backward(Lh, g, o["V"], o["rho"], (o["A"], o["B"], o["dA"], o["dB"]),
+                crk.crk_accel_energy_backward(Lh, g, o["V"], o["rho"],
+                                              (o["A"], o["B"], o["dA"], o["dB"], o["M"]),
                                               ga, gdu, cfg["gamma"], prec)
         return step
 
@@ -241,6 +244,7 @@ def bench_hydro(args, torch, crk):
                       "tflops": round(FLOP_PER_PAIR[k] * units[k] / (kt[k][0] / kt[k][1]) * 1e-9, 3)}
                   for k in ran}
     per_kernel["pack_ms_per_step"] = round(kt["pack"][0] / args.steps, 4)
+    per_kernel["solve_adj_ms_per_step"] = round(kt["solve_adj"][0] / args.steps, 4)
     flop_step = sum(FLOP_PER_PAIR[k] * units[k] * kt[k][1] / args.steps for k in ran)
 
     # the same step with particle arrays in the generated (random) order

@@ -75,9 +75,15 @@ typedef struct {
 } crk_gas;
 
 /* Reproducing-kernel corrections (device, precision of the call):
- * A[n], B[3n], dA[3n] (dA[3i+c] = d_c A), dB[9n] (dB[9i+3a+c] = d_c B^a). */
+ * A[n], B[3n], dA[3n] (dA[3i+c] = d_c A), dB[9n] (dB[9i+3a+c] = d_c B^a).
+ * M (optional, NULL = unused): device double[30 n], caller-owned, row-major
+ * [30][n] in caller order: the 29 independent moment sums of each particle
+ * (m0 with the self term, m1[3], m2[6], g0[3], the symmetric t1[6] and t3[10]
+ * of the gradient moments) and its neighbour count.  crk_corrections fills it;
+ * crk_accel_energy_backward reads it instead of recomputing the moments. */
 typedef struct {
     void *A, *B, *dA, *dB;
+    double* M;
 } crk_corr;
 
 /* Opaque handle: tree order, leaf and tile interaction lists, scratch. */
@@ -136,8 +142,9 @@ int crk_volume(crk_leaves* leaves, const crk_gas* gas, crk_prec prec, void* V, v
  * so that sum_j V_j A_i(1 + B_i.x_ij) W_ij reproduces constant and linear fields.
  * If particle i has fewer than 4 neighbours or det m2 <= 1e-12 (tr m2 / 3)^3 the
  * zeroth-order form A = 1/m0, B = 0, dA = -g0/m0^2, dB = 0 is used and counted.
- * Reads gas x, y, z, h and V[n].  Writes *out.  If n_fallback (device int64)
- * is not NULL the number of fallbacks is added to it.
+ * Reads gas x, y, z, h and V[n].  Writes A, B, dA, dB of *out, and out->M when
+ * it is not NULL.  If n_fallback (device int64) is not NULL the number of
+ * fallbacks is added to it.
  */
 int crk_corrections(crk_leaves* leaves, const crk_gas* gas, const void* V, crk_prec prec,
                     const crk_corr* out, int64_t* n_fallback, hipStream_t stream);
@@ -176,7 +183,9 @@ int sr_gravity(crk_leaves* leaves, int64_t n, const double* x, const double* y, 
  * Given ga = dL/da [3n] and gdudt = dL/d(du/dt) [n], writes gx = dL/dx [3n],
  * gv = dL/dv [3n] and gu = dL/du [n].  V, rho and the corrections must be the
  * ones the forward passes produced for this gas (they are reused, not
- * recomputed; the 40 moments are recomputed per tile).  Pair terms are
+ * recomputed).  The moments are taken from corr->M when it is not NULL (it
+ * must then hold what crk_corrections wrote for this gas and V), else
+ * recomputed per tile over the lists.  Pair terms are
  * recomputed per tile and never stored; each particle's adjoints are
  * accumulated by its own lane, so the result is bitwise reproducible.
  * FP32: pair arithmetic in FP32 with compensated sums, the adjoint of the 3x3
@@ -229,7 +238,8 @@ enum {
     CRK_K_ACCEL_ADJ = 6,   /* force adjoint pair kernel */
     CRK_K_MOMENTS_ADJ = 7, /* moments adjoint pair kernel */
     CRK_K_VOLUME_ADJ = 8,  /* volume adjoint pair kernel */
-    CRK_K_COUNT = 9
+    CRK_K_SOLVE_ADJ = 9,   /* per-particle solve adjoint from stored moment sums (crk_corr.M) */
+    CRK_K_COUNT = 10
 };
 int crk_timing(crk_leaves* leaves, int enable);
 int crk_kernel_times(crk_leaves* leaves, double* ms, int64_t* launches);

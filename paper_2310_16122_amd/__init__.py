@@ -31,7 +31,7 @@ EXPORTS = ("crk_build_leaf_pairs", "crk_volume", "crk_corrections", "crk_accel_e
            "sr_gravity", "crk_accel_energy_backward", "crk_leaves_stats", "crk_leaves_perm", "crk_get_tuning", "crk_set_tuning",
            "crk_timing", "crk_kernel_times", "crk_leaves_free", "crk_last_error")
 KERNEL_KINDS = ("cull", "volume", "moments", "accel", "gravity", "pack", "accel_adj",
-                "moments_adj", "volume_adj")
+                "moments_adj", "volume_adj", "solve_adj")
 
 
 class CrkError(RuntimeError):
@@ -46,7 +46,16 @@ class _Gas(ctypes.Structure):
 
 
 class _Corr(ctypes.Structure):
-    _fields_ = [(k, ctypes.c_void_p) for k in ("A", "B", "dA", "dB")]
+    _fields_ = [(k, ctypes.c_void_p) for k in ("A", "B", "dA", "dB", "M")]
+
+
+def _corr(corr):
+    """(A, B, dA, dB[, M]) -> crk_corr; M (the stored moment sums) is optional."""
+    ptrs = [t.data_ptr() for t in corr[:4]]
+    M = corr[4] if len(corr) > 4 else None
+    if M is not None:
+        _dev(M, torch.float64)
+    return _Corr(*ptrs, None if M is None else M.data_ptr())
 
 
 class Tuning(ctypes.Structure):
@@ -214,7 +223,9 @@ def crk_volume(leaves, gas, prec="f32"):
     return V, rho
 
 
-def crk_corrections(leaves, gas, V, prec="f32", n_fallback=None):
+def crk_corrections(leaves, gas, V, prec="f32", n_fallback=None, store_sums=False):
+    """(A, B, dA, dB), plus M [30, n] FP64 (the moment sums the backward can reuse)
+    when store_sums is true."""
     g = _gas(gas, prec, ("h",))
     dt, dev = _DTYPE[prec], gas["x"].device
     _dev(V, dt)
@@ -222,21 +233,22 @@ def crk_corrections(leaves, gas, V, prec="f32", n_fallback=None):
     B = torch.empty(g.n, 3, dtype=dt, device=dev)
     dA = torch.empty(g.n, 3, dtype=dt, device=dev)
     dB = torch.empty(g.n, 3, 3, dtype=dt, device=dev)
-    c = _Corr(A.data_ptr(), B.data_ptr(), dA.data_ptr(), dB.data_ptr())
+    M = torch.empty(30, g.n, dtype=torch.float64, device=dev) if store_sums else None
+    c = _corr((A, B, dA, dB, M))
     if n_fallback is not None:
         _dev(n_fallback, torch.int64)
     _check("crk_corrections",
            load_library().crk_corrections(leaves.handle, ctypes.byref(g), _ptr(V), _PREC[prec],
                                           ctypes.byref(c), _ptr(n_fallback), _stream()))
-    return A, B, dA, dB
+    return (A, B, dA, dB, M) if store_sums else (A, B, dA, dB)
 
 
 def crk_accel_energy(leaves, gas, V, rho, corr, gamma=5.0 / 3.0, prec="f32", totals=True):
     g = _gas(gas, prec, ("vx", "vy", "vz", "u", "h", "m"))
     dt, dev = _DTYPE[prec], gas["x"].device
-    for t in (V, rho, *corr):
+    for t in (V, rho, *corr[:4]):
         _dev(t, dt)
-    c = _Corr(*(t.data_ptr() for t in corr))
+    c = _corr(corr)
     a = torch.empty(g.n, 3, dtype=dt, device=dev)
     du = torch.empty(g.n, dtype=dt, device=dev)
     tot = torch.empty(8, dtype=torch.float64, device=dev) if totals else None
@@ -248,12 +260,15 @@ def crk_accel_energy(leaves, gas, V, rho, corr, gamma=5.0 / 3.0, prec="f32", tot
 
 
 def crk_accel_energy_backward(leaves, gas, V, rho, corr, ga, gdudt, gamma=5.0 / 3.0, prec="f32"):
-    """dL/dx [n,3], dL/dv [n,3], dL/du [n] from ga = dL/da [n,3] and gdudt = dL/d(du/dt) [n]."""
+    """dL/dx [n,3], dL/dv [n,3], dL/du [n] from ga = dL/da [n,3] and gdudt = dL/d(du/dt) [n].
+
+    corr = (A, B, dA, dB) recomputes the moments; (A, B, dA, dB, M) with the
+    forward's stored sums M reuses them."""
     g = _gas(gas, prec, ("vx", "vy", "vz", "u", "h", "m"))
     dt, dev = _DTYPE[prec], gas["x"].device
-    for t in (V, rho, *corr, ga, gdudt):
+    for t in (V, rho, *corr[:4], ga, gdudt):
         _dev(t, dt)
-    c = _Corr(*(t.data_ptr() for t in corr))
+    c = _corr(corr)
     gx = torch.empty(g.n, 3, dtype=dt, device=dev)
     gv = torch.empty(g.n, 3, dtype=dt, device=dev)
     gu = torch.empty(g.n, dtype=dt, device=dev)
@@ -278,19 +293,19 @@ class CRKAccelEnergy(torch.autograd.Function):
         gas = {"x": pos[:, 0].contiguous(), "y": pos[:, 1].contiguous(), "z": pos[:, 2].contiguous(),
                "vx": v[:, 0].contiguous(), "vy": v[:, 1].contiguous(), "vz": v[:, 2].contiguous(),
                "u": u.contiguous(), "h": h, "m": m}
-        out = forward(leaves, gas, gamma, prec)
+        out = forward(leaves, gas, gamma, prec, store_sums=True)
         ctx.leaves, ctx.gamma, ctx.prec = leaves, gamma, prec
         ctx.gas = gas
-        ctx.save_for_backward(out["V"], out["rho"], out["A"], out["B"], out["dA"], out["dB"])
+        ctx.save_for_backward(out["V"], out["rho"], out["A"], out["B"], out["dA"], out["dB"], out["M"])
         return out["a"], out["dudt"]
 
     @staticmethod
     def backward(ctx, ga, gdu):
-        V, rho, A, B, dA, dB = ctx.saved_tensors
+        V, rho, A, B, dA, dB, M = ctx.saved_tensors
         dt = _DTYPE[ctx.prec]
         ga = torch.zeros_like(A.new_empty(A.shape[0], 3)) if ga is None else ga.to(dt).contiguous()
         gdu = torch.zeros_like(A) if gdu is None else gdu.to(dt).contiguous()
-        gx, gv, gu = crk_accel_energy_backward(ctx.leaves, ctx.gas, V, rho, (A, B, dA, dB), ga, gdu,
+        gx, gv, gu = crk_accel_energy_backward(ctx.leaves, ctx.gas, V, rho, (A, B, dA, dB, M), ga, gdu,
                                                ctx.gamma, ctx.prec)
         return gx.double(), gv, gu, None, None, None, None, None
 
@@ -312,14 +327,18 @@ def sr_gravity(leaves, x, y, z, m, G=1.0, eps=0.0, r_cut=None, poly=None, prec="
     return a
 
 
-def forward(leaves, gas, gamma=5.0 / 3.0, prec="f32"):
-    """volume -> corrections -> accel/energy; returns a dict of device tensors."""
+def forward(leaves, gas, gamma=5.0 / 3.0, prec="f32", store_sums=False):
+    """volume -> corrections -> accel/energy; returns a dict of device tensors
+    (with M, the moment sums for the backward, when store_sums is true)."""
     V, rho = crk_volume(leaves, gas, prec)
     nf = torch.zeros(1, dtype=torch.int64, device=gas["x"].device)
-    corr = crk_corrections(leaves, gas, V, prec, n_fallback=nf)
+    corr = crk_corrections(leaves, gas, V, prec, n_fallback=nf, store_sums=store_sums)
     a, du, tot = crk_accel_energy(leaves, gas, V, rho, corr, gamma, prec)
-    return dict(V=V, rho=rho, A=corr[0], B=corr[1], dA=corr[2], dB=corr[3], a=a, dudt=du,
-                totals=tot, n_fallback=nf)
+    out = dict(V=V, rho=rho, A=corr[0], B=corr[1], dA=corr[2], dB=corr[3], a=a, dudt=du,
+               totals=tot, n_fallback=nf)
+    if store_sums:
+        out["M"] = corr[4]
+    return out
 
 
 def gas_to_device(cfg, prec="f32", device="cuda"):

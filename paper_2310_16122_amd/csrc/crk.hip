@@ -300,7 +300,8 @@ __global__ __launch_bounds__(256) void k_moments(Queue qu, int n, Lists L, const
                                                  const R* __restrict__ h, int chunk, R* __restrict__ A_out,
                                                  R* __restrict__ B_out, R* __restrict__ dA_out,
                                                  R* __restrict__ dB_out,
-                                                 unsigned long long* __restrict__ n_fallback) {
+                                                 unsigned long long* __restrict__ n_fallback,
+                                                 double* __restrict__ sums_out) {
     constexpr int kStage = sizeof(RecQV<R>) > 16 ? int(sizeof(RecQV<R>) / 16) * kWave : 1;
     extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
     const int lane = lane_id();
@@ -310,9 +311,15 @@ __global__ __launch_bounds__(256) void k_moments(Queue qu, int n, Lists L, const
         const bool valid = s < n;
         const int i = valid ? perm[s] : 0;
         const R H = valid ? R(2) * h[i] : R(1);
-        double M[40];
+        double S[29], M[40];
         int nnb = 0;
-        moment_sums<R>(w, s, valid, L, qv, stage_buf + (threadIdx.x >> 6) * kStage, H, chunk, M, nnb);
+        moment_sums<R>(w, s, valid, L, qv, stage_buf + (threadIdx.x >> 6) * kStage, H, chunk, S, nnb);
+        if (valid && sums_out) {
+            // kept for the backward (caller order, one row of n per sum)
+            for (int e = 0; e < 29; ++e) sums_out[int64_t(e) * n + i] = S[e];
+            sums_out[int64_t(29) * n + i] = double(nnb);
+        }
+        moments_from_sums(S, M);
         if (valid) {
             double Ad, Bd[3], dAd[3], dBd[9];
             const int fb = solve_moments(M, nnb, Ad, Bd, dAd, dBd);
@@ -704,7 +711,7 @@ int corrections_impl(crk_leaves* L, const crk_gas* g, const R* V, const crk_corr
                        make_queue(L, L->order_pair), n, lists_gather(L), L->perm, qv,
                        static_cast<const R*>(g->h), L->tune.kahan_chunk, static_cast<R*>(out->A),
                        static_cast<R*>(out->B), static_cast<R*>(out->dA), static_cast<R*>(out->dB),
-                       reinterpret_cast<unsigned long long*>(n_fallback));
+                       reinterpret_cast<unsigned long long*>(n_fallback), static_cast<double*>(out->M));
     LAUNCH_CHECK("moments");
     return CRK_OK;
 }

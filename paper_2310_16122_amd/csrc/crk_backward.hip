@@ -453,6 +453,26 @@ template <class R> struct alignas(16) RecVA {
     R Sbar;
 };
 
+// Per particle (tree position s): the adjoint of the FP64 solve from the 40
+// moments and the correction adjoints, compressed to the 29 polynomial
+// coefficients of the moments adjoint, written with the position, 1/H and V.
+template <class R>
+__device__ inline void moments_adjoint_record(int s, const double M[40], int nnb, const uint4* __restrict__ quant,
+                                              const R* __restrict__ aux, const R* __restrict__ cbar,
+                                              RecMom<R>* __restrict__ mrec) {
+    double Cb[16], Mb[40], c[29];
+    for (int e = 0; e < 16; ++e) Cb[e] = double(cbar[16 * s + e]);
+    solve_moments_adjoint(M, nnb, Cb, Mb);
+    moment_poly(Mb, c);
+    RecMom<R> r;
+    const uint4 q = quant[s];
+    r.q[0] = q.x; r.q[1] = q.y; r.q[2] = q.z;
+    r.invH = aux[2 * s];
+    r.V = aux[2 * s + 1];
+    for (int e = 0; e < 29; ++e) r.c[e] = R(c[e]);
+    mrec[s] = r;
+}
+
 // 2. moments recomputed with the forward's arithmetic, then the solve adjoint
 // (three waves per SIMD: the few spilled values live outside the neighbour loop)
 template <class R>
@@ -469,23 +489,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         const bool valid = s < n;
         const int i = valid ? perm[s] : 0;
         const R H = valid ? R(2) * h[i] : R(1);
-        double M[40];
+        double S[29], M[40];
         int nnb = 0;
-        moment_sums<R>(w, s, valid, L, qv, stage_buf + (threadIdx.x >> 6) * kStage, H, chunk, M, nnb);
-        if (valid) {
-            double Cb[16], Mb[40], c[29];
-            for (int e = 0; e < 16; ++e) Cb[e] = double(cbar[16 * s + e]);
-            solve_moments_adjoint(M, nnb, Cb, Mb);
-            moment_poly(Mb, c);
-            RecMom<R> r;
-            const uint4 q = quant[s];
-            r.q[0] = q.x; r.q[1] = q.y; r.q[2] = q.z;
-            r.invH = aux[2 * s];
-            r.V = aux[2 * s + 1];
-            for (int e = 0; e < 29; ++e) r.c[e] = R(c[e]);
-            mrec[s] = r;
-        }
+        moment_sums<R>(w, s, valid, L, qv, stage_buf + (threadIdx.x >> 6) * kStage, H, chunk, S, nnb);
+        moments_from_sums(S, M);
+        if (valid) moments_adjoint_record(s, M, nnb, quant, aux, cbar, mrec);
     }
+}
+
+// 2'. the same from the forward's stored moment sums (one thread per particle)
+template <class R>
+__global__ __launch_bounds__(256) void k_moments_bwd_stored(int n, const int32_t* __restrict__ perm,
+                                                            const uint4* __restrict__ quant,
+                                                            const R* __restrict__ aux,
+                                                            const double* __restrict__ sums,
+                                                            const R* __restrict__ cbar,
+                                                            RecMom<R>* __restrict__ mrec) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int i = perm[s];
+    double S[29], M[40];
+    for (int e = 0; e < 29; ++e) S[e] = sums[int64_t(e) * n + i];
+    const int nnb = int(sums[int64_t(29) * n + i]);
+    moments_from_sums(S, M);
+    moments_adjoint_record(s, M, nnb, quant, aux, cbar, mrec);
 }
 
 // 3. moments adjoint, then the per-particle volume/pressure adjoints
@@ -651,14 +678,18 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
                            L->perm, rec, L->tune.kahan_chunk, cbar, vpbar, xbar, gv);
     }
     LAUNCH_CHECK("accel adjoint");
-    reset_queue(L, st);
-    {
+    if (C->M) {
+        TimeScope ts(L, st, CRK_K_SOLVE_ADJ);  // the forward's moment sums, stored
+        hipLaunchKernelGGL(k_moments_bwd_stored<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm,
+                           L->quant, aux, C->M, cbar, mrec);
+    } else {
+        reset_queue(L, st);
         TimeScope ts(L, st, CRK_K_MOMENTS);  // the forward moments, recomputed
         hipLaunchKernelGGL(k_moments_bwd<R>, grid, block, stage_bytes<RecQV<R>>(bw), st, q, n,
                            lists_gather(L), L->perm, L->quant, aux, qv, static_cast<const R*>(g->h),
                            L->tune.kahan_chunk, cbar, mrec);
     }
-    LAUNCH_CHECK("moments recompute + solve adjoint");
+    LAUNCH_CHECK("moments + solve adjoint");
     reset_queue(L, st);
     {
         TimeScope ts(L, st, CRK_K_MOMENTS_ADJ);

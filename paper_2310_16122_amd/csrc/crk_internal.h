@@ -372,20 +372,20 @@ template <class R, int N> struct ChunkSums {
 
 // ------------------------------------------------------------------ moments
 
-// The 40 correction moments of the lane's particle in FP64 (storage order:
-// m0, m1[3], m2[6] (xx xy xz yy yz zz), g0[3], g1[9] (g1[a][c], a-major),
-// g2[18] (g2[ab][c], ab in the m2 order)), and the number of neighbours inside
-// the support.  Per pair (w = cW w(q) V_j, f = cF f(q) V_j, x = x_ij) only 29
-// independent sums are accumulated:
+// The correction moments of the lane's particle, as 29 independent FP64 sums
+// S, and the number of neighbours inside the support.  The 40 moments (storage
+// order: m0, m1[3], m2[6] (xx xy xz yy yz zz), g0[3], g1[9] (g1[a][c],
+// a-major), g2[18] (g2[ab][c], ab in the m2 order)) follow from S
+// (moments_from_sums).  Per pair (w = cW w(q) V_j, f = cF f(q) V_j, x = x_ij):
 //   m0 += w, m1^a += x^a w, m2^ab += x^a x^b w, g0^c += f x^c,
 //   t1^ac += f x^a x^c (symmetric: 6), t3^abc += f x^a x^b x^c (fully symmetric: 10);
-// then j = i is added analytically and g1^ac = delta^ac m0 + t1^ac,
+// j = i is added analytically to m0; then g1^ac = delta^ac m0 + t1^ac and
 // g2^abc = delta^ac m1^b + delta^bc m1^a + t3^abc.  FP32: plain sums over
 // `chunk` pairs folded into compensated sums.  Every lane of the wave must call
 // this (the loop runs over the tile's longest list).
 template <class R>
 __device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, const RecQV<R>* __restrict__ qv,
-                                   uint4* __restrict__ lds, R H, int chunk, double M[40], int& nnb) {
+                                   uint4* __restrict__ lds, R H, int chunk, double S[29], int& nnb) {
     constexpr bool kComp = sizeof(R) == 4;
     constexpr int kN = 29;
     const int lane = lane_id();
@@ -438,7 +438,6 @@ __device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, con
                 kk = 0;
             }
         });
-    double S[kN];
 #pragma unroll
     for (int e = 0; e < kN; ++e) {
         if (kComp) {
@@ -449,6 +448,10 @@ __device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, con
         }
     }
     if (valid) S[0] += double(cW) * double(self.V);  // j = i
+}
+
+// The 40 moments from the 29 independent sums (self term included).
+__device__ inline void moments_from_sums(const double S[29], double M[40]) {
     const int sym[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
     const int cub[3][3][3] = {{{0, 1, 2}, {1, 3, 4}, {2, 4, 5}},
                               {{1, 3, 4}, {3, 6, 7}, {4, 7, 8}},

@@ -140,6 +140,24 @@ def test_backward_bitwise_reproducible(crk):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_stored_moment_sums_give_the_recomputed_backward(crk, prec):
+    """The backward from the forward's stored moment sums equals, bit for bit,
+    the backward that recomputes the moments over the lists."""
+    cfg = synth.make_config("C4", n_side=20)
+    g = crk.gas_to_device(cfg, prec)
+    L = crk.crk_build_leaf_pairs(g["x"], g["y"], g["z"], g["h"], leaf_max=64, prec=prec)
+    o = crk.forward(L, g, cfg["gamma"], prec, store_sums=True)
+    dt = o["a"].dtype
+    ga = (2.0 * torch.as_tensor(cfg["w"]).to(dt).cuda()[:, None] * o["a"]).contiguous()
+    gdu = torch.as_tensor(cfg["c"]).to(dt).cuda()
+    corr = (o["A"], o["B"], o["dA"], o["dB"])
+    stored = crk.crk_accel_energy_backward(L, g, o["V"], o["rho"], corr + (o["M"],), ga, gdu, cfg["gamma"], prec)
+    recomputed = crk.crk_accel_energy_backward(L, g, o["V"], o["rho"], corr, ga, gdu, cfg["gamma"], prec)
+    for a, b in zip(stored, recomputed):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_backward_schedule_independent(crk, prec):
     """Workgroup shape, queue mode and tile order change only which wave runs a
     tile, never a lane's arithmetic: gradients are bitwise identical."""

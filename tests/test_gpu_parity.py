@@ -77,6 +77,47 @@ def test_forward_chain_parity(crk, name, n_side, prec):
     assert np.allclose(T[4], ref["totals"][4], rtol=1e-5)
 
 
+def test_stored_moment_sums_match_oracle_moments(crk):
+    """crk_corrections' optional output: the 29 independent sums and the
+    neighbour count, rebuilt here into the 40 moments of the oracle."""
+    cfg, ref = oracle_full("C2", 21)
+    g = crk.gas_to_device(cfg, "f64")
+    L = crk.crk_build_leaf_pairs(g["x"], g["y"], g["z"], g["h"], leaf_max=64, prec="f64")
+    V, _ = crk.crk_volume(L, g, "f64")
+    A, B, dA, dB, S = crk.crk_corrections(L, g, V, "f64", store_sums=True)
+    A0, B0, dA0, dB0 = crk.crk_corrections(L, g, V, "f64")
+    for u, v in ((A, A0), (B, B0), (dA, dA0), (dB, dB0)):
+        assert torch.equal(u, v)
+    S = S.cpu().numpy()
+    M_ref, nnb_ref = oracle.moments(cfg, ref["V"])
+    sym = [[0, 1, 2], [1, 3, 4], [2, 4, 5]]
+    cub = {}
+    k = 0
+    for a in range(3):
+        for b in range(a, 3):
+            for c in range(b, 3):
+                for p in {(a, b, c), (a, c, b), (b, a, c), (b, c, a), (c, a, b), (c, b, a)}:
+                    cub[p] = k
+                k += 1
+    M = np.zeros((cfg["n"], 40))
+    M[:, :13] = S[:13].T
+    for a in range(3):
+        for c in range(3):
+            M[:, 13 + 3 * a + c] = (S[0] if a == c else 0.0) + S[13 + sym[a][c]]
+    for a in range(3):
+        for b in range(a, 3):
+            for c in range(3):
+                t = S[19 + cub[(a, b, c)]].copy()
+                if a == c:
+                    t += S[1 + b]
+                if b == c:
+                    t += S[1 + a]
+                M[:, 22 + 3 * sym[a][b] + c] = t
+    for lo, hi in ((0, 1), (1, 4), (4, 10), (10, 13), (13, 22), (22, 40)):
+        assert normwise(M[:, lo:hi], M_ref[:, lo:hi]) <= 1e-12, (lo, hi)
+    assert np.array_equal(S[29].astype(np.int64), nnb_ref)
+
+
 def test_interaction_counts_exact(crk):
     cfg, _ = oracle_full("C2", 21)
     got, L = run_gpu(crk, cfg, "f64")
