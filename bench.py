@@ -248,10 +248,12 @@ def bench_hydro(args, torch, crk):
     flop_step = sum(FLOP_PER_PAIR[k] * units[k] * kt[k][1] / args.steps for k in ran)
 
     # the same step with particle arrays in the generated (random) order
-    inv = torch.as_tensor(np.argsort(perm)).to(dev)  # tree position of each generated particle
-    ms_rand = timed_steps(make_step(L_rand, g_rand, "f32", ga32[inv].contiguous(), gdu32[inv].contiguous()),
-                          max(2, args.steps // 4), 1, torch)
-    log(f"[bench] f32 step, random particle order: {ms_rand:.3f} ms")
+    ms_rand = None
+    if not args.no_random_order:
+        inv = torch.as_tensor(np.argsort(perm)).to(dev)  # tree position of each generated particle
+        ms_rand = timed_steps(make_step(L_rand, g_rand, "f32", ga32[inv].contiguous(),
+                                        gdu32[inv].contiguous()), max(2, args.steps // 4), 1, torch)
+        log(f"[bench] f32 step, random particle order: {ms_rand:.3f} ms")
 
     ms64 = None
     if not args.no_f64:
@@ -278,7 +280,7 @@ def bench_hydro(args, torch, crk):
         "fp32_frac_step": round(flop_step / (ms32 * 1e-3) / 1e12 / PEAK_FP32_VALU_TFLOPS, 4),
         "fp64_gpu_ms_per_step": None if ms64 is None else round(ms64, 4),
         "fp64_over_fp32_time": None if ms64 is None else round(ms64 / ms32, 3),
-        "random_order_ms_per_step": round(ms_rand, 4),
+        "random_order_ms_per_step": None if ms_rand is None else round(ms_rand, 4),
         "build_ms": round(build_ms, 1), "list_build_gpu_ms": round(cull[0], 3),
     }
     if not args.no_cpu:
@@ -361,6 +363,8 @@ def main():
     ap.add_argument("--tuning", default=None, help="JSON dict of crk_tuning fields")
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tuning")
     ap.add_argument("--no-gravity", action="store_true", help="C2 only: skip the gravity workload")
+    ap.add_argument("--no-random-order", action="store_true",
+                    help="skip the comparison step on randomly ordered particle arrays")
     ap.add_argument("--gravity-tuning", default=None, help="JSON crk_tuning for the gravity workload")
     ap.add_argument("--gravity-leaf-max", type=int, default=512,
                     help="gravity leaf size when its tuning is given")

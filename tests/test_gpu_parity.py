@@ -183,6 +183,30 @@ def test_full_size_sampled_closure(crk, prec):
     assert np.abs(T[:3]).max() <= lim * T[4]
 
 
+def test_c5_full_size_sampled(crk):
+    """C5 at 256^3 (32-256 neighbours over a 16x density contrast), leaf 128, the
+    benchmarked tuning: 32 sampled particles of the FP32 and FP64 forward chains
+    against the oracle's per-target closure, and the momentum totals."""
+    cfg = synth.make_config("C5")
+    print(f"case C5 full n={cfg['n']}", flush=True)
+    t = synth.sample_targets(cfg["n"], 32, seed=17)
+    ref = oracle.hydro_targets(cfg, t)
+    assert ref["n_fallback"] == 0
+    for prec in ("f32", "f64"):
+        got, L = run_gpu(crk, cfg, prec, leaf_max=128,
+                         tuning={"persistent": 0, "block_waves": 4, "xcd_groups": 8, "kahan_chunk": 8})
+        for k in KEYS:
+            scale = np.abs(got[k]).max()
+            err = np.abs(got[k][t] - ref[k]).max() / scale
+            assert err <= TOL[prec], (prec, k, err)
+        assert int(got["n_fallback"][0]) == 0
+        T = got["totals"]
+        assert np.abs(T[:3]).max() <= (1e-13 if prec == "f64" else 2e-6) * T[4]
+        L.free()
+        del got
+        torch.cuda.empty_cache()
+
+
 # ---------------------------------------------------------------- gravity
 def gravity_case(n_side):
     cfg = synth.make_gravity(n_side=n_side)
