@@ -69,56 +69,79 @@ template <class R> __device__ __forceinline__ void shapes(R q, R& w, R& f, R& f2
     f = t5 * (R(1) + R(5) * q);
 }
 
-// G^c = dA^c lin W + A (sum_a dB[a][c] y^a + B^c) W + A lin F y^c, lin = 1 + B.y
-template <class R>
-__device__ __forceinline__ void corr_grad(const RecBwd<R>& r, R W, R F, const R y[3], R G[3]) {
-    const R lin = R(1) + r.B[0] * y[0] + r.B[1] * y[1] + r.B[2] * y[2];
+// One side of a pair: the corrected kernel gradient of a particle (record r)
+// at separation y from it, G^c = dA^c lin W + A t^c W + A lin F y^c, with
+// lin = 1 + B.y and t^c = sum_a dB[a][c] y^a + B^c, and the pieces its adjoints
+// share.  Written factored (the compiler does not reassociate): per side the
+// gradient takes 3 FMA per component after lin and t.
+template <class R> struct Side {
+    R lin, t[3];
+};
+
+template <class R> __device__ __forceinline__ Side<R> side_terms(const RecBwd<R>& r, const R y[3]) {
+    Side<R> s;
+    s.lin = R(1) + r.B[0] * y[0] + r.B[1] * y[1] + r.B[2] * y[2];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const R t = r.dB[c] * y[0] + r.dB[3 + c] * y[1] + r.dB[6 + c] * y[2] + r.B[c];
-        G[c] = r.dA[c] * lin * W + r.A * t * W + r.A * lin * F * y[c];
-    }
+    for (int c = 0; c < 3; ++c) s.t[c] = r.dB[c] * y[0] + r.dB[3 + c] * y[1] + r.dB[6 + c] * y[2] + r.B[c];
+    return s;
 }
 
-// out += (dG/dy)^T g
 template <class R>
-__device__ __forceinline__ void corr_grad_dy(const RecBwd<R>& r, R W, R F, R F2, const R y[3],
-                                             const R g[3], R out[3]) {
-    const R lin = R(1) + r.B[0] * y[0] + r.B[1] * y[1] + r.B[2] * y[2];
-    const R al = g[0] * r.dA[0] + g[1] * r.dA[1] + g[2] * r.dA[2];
-    R be = R(0);
+__device__ __forceinline__ void corr_grad(const RecBwd<R>& r, const Side<R>& s, R W, R F, const R y[3], R G[3]) {
+    const R LW = s.lin * W, AW = r.A * W, K = r.A * s.lin * F;
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-        be += g[c] * (r.dB[c] * y[0] + r.dB[3 + c] * y[1] + r.dB[6 + c] * y[2] + r.B[c]);
-    const R ga = g[0] * y[0] + g[1] * y[1] + g[2] * y[2];
+    for (int c = 0; c < 3; ++c) G[c] = LW * r.dA[c] + AW * s.t[c] + K * y[c];
+}
+
+// Contractions of the upstream adjoint g = Gbar with one side:
+// al = g.dA, be = g.t, ga = g.y.
+template <class R> struct Dots {
+    R al, be, ga;
+};
+
+template <class R>
+__device__ __forceinline__ Dots<R> side_dots(const RecBwd<R>& r, const Side<R>& s, const R y[3], const R g[3]) {
+    return Dots<R>{g[0] * r.dA[0] + g[1] * r.dA[1] + g[2] * r.dA[2],
+                   g[0] * s.t[0] + g[1] * s.t[1] + g[2] * s.t[2],
+                   g[0] * y[0] + g[1] * y[1] + g[2] * y[2]};
+}
+
+// out += (dG/dy)^T g, i.e. per component e
+//   W (al B^e + A (dB g)^e) + y^e (F (al lin + A be) + A lin F2 ga) + A F (ga B^e + lin g^e)
+// (F2: the gradient factor of F, grad F = F2 y).
+template <class R>
+__device__ __forceinline__ void corr_grad_dy(const RecBwd<R>& r, const Side<R>& s, const Dots<R>& d, R W, R F,
+                                             R F2, const R y[3], const R g[3], R out[3]) {
+    const R AW = r.A * W, AF = r.A * F;
+    const R KB = d.al * W + AF * d.ga;                                    // coefficient of B^e
+    const R KY = F * (d.al * s.lin + r.A * d.be) + r.A * F2 * s.lin * d.ga;  // of y^e
+    const R KG = AF * s.lin;                                              // of g^e
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
         const R dBg = r.dB[3 * e] * g[0] + r.dB[3 * e + 1] * g[1] + r.dB[3 * e + 2] * g[2];
-        out[e] += al * (r.B[e] * W + lin * F * y[e]) + r.A * dBg * W + r.A * be * F * y[e] +
-                  r.A * r.B[e] * F * ga + r.A * lin * F2 * y[e] * ga + r.A * lin * F * g[e];
+        out[e] += KB * r.B[e] + AW * dBg + KY * y[e] + KG * g[e];
     }
 }
 
-// adjoint of G with respect to (A, B, dA, dB), given g = Gbar
+// adjoint of G with respect to (A, B, dA, dB), given g = Gbar:
+//   A: be W + lin F ga,  B^e: y^e (al W + A F ga) + A W g^e,
+//   dA^d: lin W g^d,  dB[a][d]: A W y^a g^d
 template <class R, class Acc>
-__device__ __forceinline__ void corr_grad_dC(const RecBwd<R>& r, R W, R F, const R y[3], const R g[3],
-                                             Acc& acc) {
-    const R lin = R(1) + r.B[0] * y[0] + r.B[1] * y[1] + r.B[2] * y[2];
-    const R al = g[0] * r.dA[0] + g[1] * r.dA[1] + g[2] * r.dA[2];
-    R be = R(0);
+__device__ __forceinline__ void corr_grad_dC(const RecBwd<R>& r, const Side<R>& s, const Dots<R>& d, R W, R F,
+                                             const R y[3], const R g[3], Acc& acc) {
+    const R AW = r.A * W, LW = s.lin * W;
+    const R KB = d.al * W + r.A * F * d.ga;
+    acc.add(0, d.be * W + s.lin * F * d.ga);  // A
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-        be += g[c] * (r.dB[c] * y[0] + r.dB[3 + c] * y[1] + r.dB[6 + c] * y[2] + r.B[c]);
-    const R ga = g[0] * y[0] + g[1] * y[1] + g[2] * y[2];
-    acc.add(0, be * W + lin * F * ga);                                    // A
+    for (int e = 0; e < 3; ++e) acc.add(1 + e, KB * y[e] + AW * g[e]);  // B
 #pragma unroll
-    for (int e = 0; e < 3; ++e) acc.add(1 + e, al * y[e] * W + r.A * g[e] * W + r.A * F * ga * y[e]);  // B
+    for (int c = 0; c < 3; ++c) acc.add(4 + c, LW * g[c]);  // dA
 #pragma unroll
-    for (int d = 0; d < 3; ++d) acc.add(4 + d, g[d] * lin * W);          // dA
+    for (int a = 0; a < 3; ++a) {
+        const R AWy = AW * y[a];
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) acc.add(7 + 3 * a + d, g[d] * r.A * y[a] * W);  // dB[a][d]
+        for (int c = 0; c < 3; ++c) acc.add(7 + 3 * a + c, AWy * g[c]);  // dB[a][c]
+    }
 }
 
 template <class R>
@@ -192,9 +215,10 @@ __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, con
                 shapes(r * rj.invH, wj, fj, f2j);
                 const R Wi = ri.cW * wi, Fi = ri.cF * fi, F2i = ri.cF2 * f2i;
                 const R Wj = rj.cW * wj, Fj = rj.cF * fj, F2j = rj.cF2 * f2j;
+                const Side<R> si = side_terms(ri, x), sj = side_terms(rj, y);
                 R Gi[3], Gj[3];
-                corr_grad(ri, Wi, Fi, x, Gi);
-                corr_grad(rj, Wj, Fj, y, Gj);
+                corr_grad(ri, si, Wi, Fi, x, Gi);
+                corr_grad(rj, sj, Wj, Fj, y, Gj);
                 const R D[3] = {Gi[0] - Gj[0], Gi[1] - Gj[1], Gi[2] - Gj[2]};
                 const R VV = ri.V * rj.V, PP = ri.P + rj.P;
                 const R coef = R(-0.5) * (VV * PP);
@@ -210,10 +234,11 @@ __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, con
                 ob.add(0, R(-0.5) * rj.V * PP * s_);  // Vbar_i
                 ob.add(1, R(-0.5) * VV * s_);         // Pbar_i
                 const R g[3] = {coef * Fb[0], coef * Fb[1], coef * Fb[2]};
-                corr_grad_dC(ri, Wi, Fi, x, g, cb);
+                const Dots<R> di = side_dots(ri, si, x, g), dj = side_dots(rj, sj, y, g);
+                corr_grad_dC(ri, si, di, Wi, Fi, x, g, cb);
                 R xb[3] = {R(0), R(0), R(0)};
-                corr_grad_dy(ri, Wi, Fi, F2i, x, g, xb);
-                corr_grad_dy(rj, Wj, Fj, F2j, y, g, xb);
+                corr_grad_dy(ri, si, di, Wi, Fi, F2i, x, g, xb);
+                corr_grad_dy(rj, sj, dj, Wj, Fj, F2j, y, g, xb);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) ob.add(2 + c, xb[c]);
                 cb.next(chunk);
@@ -405,6 +430,24 @@ __device__ inline void moment_poly(const double* Mb, double* c) {
             const int p = lo == 0 ? hi : (lo == 1 ? 2 + hi : 5);
             c[13 + p] += g1[3 * a + b];
         }
+}
+
+// Gradient-ready coefficients.  The records hold the 29 coefficients with the
+// multiplicities of the derivatives folded in (scale_coefficients): for the
+// quadratic forms (monomials xx xy xz yy yz zz) the diagonal ones doubled, for
+// the cubic form (xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz) the pure cubes
+// tripled and xyz halved.  With Y2 = (y0^2, 2 y0 y1, 2 y0 y2, y1^2, 2 y1 y2,
+// y2^2) every gradient component is then a plain dot product.
+__device__ inline void scale_coefficients(double* c) {
+    for (int o : {4, 13}) {
+        c[o + 0] *= 2.0;
+        c[o + 3] *= 2.0;
+        c[o + 5] *= 2.0;
+    }
+    c[19 + 0] *= 3.0;
+    c[19 + 4] *= 0.5;
+    c[19 + 6] *= 3.0;
+    c[19 + 9] *= 3.0;
 }
 
 // grad of the symmetric quadratic form with monomial coefficients k[6] (value = y.grad / 2)
