@@ -140,7 +140,9 @@ PROFILE_NAMES = {k: f"void k_{k}<float>" for k in ("volume", "moments", "accel",
                                                    "moments_adj", "volume_adj", "gravity")}
 
 
-def measured_traffic(config, kind):
+def measured_counters(config, kind):
+    """The kernel's counter readings from the committed profile, or None when
+    there is none or the kernel sources changed since it was taken."""
     from paper_2310_16122_amd import profiling
 
     path = os.path.join(ROOT, "profiles", TRAFFIC_FILES.get(config, ""))
@@ -150,19 +152,26 @@ def measured_traffic(config, kind):
         rec = json.load(f)
     if rec.get("source_digest") != profiling.source_digest():
         return None  # kernels changed since the counters were taken
-    k = rec["kernels"].get(PROFILE_NAMES[kind])
-    return None if k is None else round(k["hbm_bytes"])
+    return rec["kernels"].get(PROFILE_NAMES[kind])
 
 
 def roofline(kind, ms_total, launches, units, config):
     avg_ms = ms_total / max(launches, 1)
     achieved = FLOP_PER_PAIR[kind] * units / (avg_ms * 1e-3) / 1e12
-    return {"bound": "alu", "kernel": kind, "achieved": round(achieved, 3),
-            "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4),
-            "traffic": measured_traffic(config, kind),
-            "avg_launch_ms": round(avg_ms, 4), "flop_per_unit": FLOP_PER_PAIR[kind],
-            "units_per_launch": units}
+    k = measured_counters(config, kind)
+    out = {"bound": "alu", "kernel": kind, "achieved": round(achieved, 3),
+           "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+           "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4),
+           "traffic": None if k is None else round(k["hbm_bytes"]),
+           "avg_launch_ms": round(avg_ms, 4), "flop_per_unit": FLOP_PER_PAIR[kind],
+           "units_per_launch": units}
+    if k is not None and "SQ_INSTS_VALU_FLOPS_FP32" in k:
+        # executed FP32 FLOP (counter: per wave instruction, FMA = 2; x 64 lanes),
+        # padding, compensation and masked lanes included
+        ex = 64.0 * k["SQ_INSTS_VALU_FLOPS_FP32"] / (avg_ms * 1e-3) / 1e12
+        out["executed_counter"] = round(ex, 3)
+        out["executed_frac"] = round(ex / PEAK_FP32_VALU_TFLOPS, 4)
+    return out
 
 
 def bench_hydro(args, torch, crk):

@@ -28,10 +28,13 @@
  *  - All device buffers passed in are owned by the caller and must not alias
  *    each other.  The library owns the memory behind a crk_leaves handle
  *    (tree order, interaction lists and per-pass scratch) until
- *    crk_leaves_free.
- *  - Work is enqueued on `stream` (a hipStream_t); only crk_build_leaf_pairs
- *    and crk_leaves_stats synchronise with the host.  Calls that use the same
- *    handle share its scratch and must not run concurrently.
+ *    crk_leaves_free.  The scratch is allocated (hipMalloc) by the first pass
+ *    that needs it and grown, after a device synchronisation, when a later
+ *    pass needs more; steady-state calls allocate nothing.
+ *  - Work is enqueued on `stream` (a hipStream_t).  crk_build_leaf_pairs,
+ *    crk_leaves_stats, crk_timing, crk_kernel_times and crk_leaves_free
+ *    synchronise with the host.  Calls that use the same handle share its
+ *    scratch and must not run concurrently.
  *  - Return value: CRK_OK (0) or a negative code; crk_last_error() then
  *    returns a message (thread-local).  Asynchronous device errors surface at
  *    a later call.
