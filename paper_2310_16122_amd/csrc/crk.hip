@@ -420,13 +420,13 @@ __global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const i
     }
 }
 
-// fixed-order FP64 reduction of the per-tile totals
-__global__ __launch_bounds__(256) void k_totals(int n_tiles, const double* __restrict__ partials,
-                                                double* __restrict__ totals) {
-    __shared__ double red[256][8];
-    double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int w = threadIdx.x; w < n_tiles; w += 256)
-        for (int k = 0; k < 8; ++k) t[k] += partials[8 * w + k];
+// Fixed-order FP64 reduction of the per-tile totals in two stages: block b
+// sums tiles [b per, (b + 1) per) (thread t takes every 256th from the start),
+// then one block sums the block results.  The order depends only on the tile
+// count, never on the schedule that produced the tiles.
+constexpr int kTotalsBlocks = 128;
+
+__device__ __forceinline__ void block_sum8(double t[8], double (*red)[8]) {
     for (int k = 0; k < 8; ++k) red[threadIdx.x][k] = t[k];
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
@@ -434,7 +434,17 @@ __global__ __launch_bounds__(256) void k_totals(int n_tiles, const double* __res
             for (int k = 0; k < 8; ++k) red[threadIdx.x][k] += red[threadIdx.x + st][k];
         __syncthreads();
     }
-    if (threadIdx.x < 8) totals[threadIdx.x] = red[0][threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_totals_blocks(int n_items, int per, const double* __restrict__ in,
+                                                       double* __restrict__ out) {
+    __shared__ double red[256][8];
+    double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int lo = blockIdx.x * per, hi = min(n_items, lo + per);
+    for (int w = lo + int(threadIdx.x); w < hi; w += 256)
+        for (int k = 0; k < 8; ++k) t[k] += in[8 * w + k];
+    block_sum8(t, red);
+    if (threadIdx.x < 8) out[8 * blockIdx.x + threadIdx.x] = red[0][threadIdx.x];
 }
 
 // ------------------------------------------------------------------ gravity
@@ -666,7 +676,8 @@ int check_gas(const crk_leaves* L, const crk_gas* g, bool need_v) {
 }
 
 void reset_queue(crk_leaves* L, hipStream_t st) {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, L->counter);
+    // only the persistent queue reads the counters
+    if (L->tune.persistent) hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, L->counter);
 }
 
 Lists lists(const crk_leaves* L) { return Lists{L->cnt, L->ell_off, L->ell_len, L->nbr}; }
@@ -745,7 +756,12 @@ int accel_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const 
     LAUNCH_CHECK("accel");
     if (totals) {
         TimeScope tt(L, st, CRK_K_PACK);
-        hipLaunchKernelGGL(k_totals, dim3(1), dim3(256), 0, st, int(L->n_tiles), L->partials, totals);
+        const int nt = int(L->n_tiles);
+        const int per = (nt + kTotalsBlocks - 1) / kTotalsBlocks;
+        double* blocks = L->partials + 8 * int64_t(nt);  // kTotalsBlocks x 8 after the tile partials
+        hipLaunchKernelGGL(k_totals_blocks, dim3(kTotalsBlocks), dim3(256), 0, st, nt, per, L->partials, blocks);
+        hipLaunchKernelGGL(k_totals_blocks, dim3(1), dim3(256), 0, st, kTotalsBlocks, kTotalsBlocks, blocks,
+                           totals);
         LAUNCH_CHECK("totals");
     }
     return CRK_OK;
@@ -937,7 +953,7 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
 
     if ((rc = dalloc(&L->perm, n)) || (rc = dalloc(&L->quant, n)) || (rc = dalloc(&L->rng_off, nt + 1)) ||
         (rc = dalloc(&L->order_cull, nt)) || (rc = dalloc(&L->order_pair, nt)) ||
-        (rc = dalloc(&L->order_tree, nt)) || (rc = dalloc(&L->partials, 8 * nt)))
+        (rc = dalloc(&L->order_tree, nt)) || (rc = dalloc(&L->partials, 8 * nt + 8 * kTotalsBlocks)))
         return bail(rc);
     if (L->hydro && ((rc = dalloc(&L->Hd, n)) || (rc = dalloc(&L->cnt, n)) || (rc = dalloc(&L->ell_off, nt)) ||
                      (rc = dalloc(&L->ell_len, nt)) || (rc = dalloc(&L->cnt_gather, n)) ||
