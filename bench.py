@@ -268,12 +268,21 @@ def bench_hydro(args, torch, crk):
         log(f"[bench] f32 step, random particle order: {ms_rand:.3f} ms")
 
     ms64 = None
+    acc = None
     if not args.no_f64:
         g64 = crk.gas_to_device(cfg_t, "f64")
         ga64, gdu64 = adjoints(g64, "f64")
         ms64 = timed_steps(make_step(L, g64, "f64", ga64, gdu64), max(2, args.steps // 4), 1, torch)
         log(f"[bench] f64 step {ms64:.3f} ms")
-        del g64
+        # the FP32 mixed path against the FP64 GPU form, every particle, per output
+        o32 = crk.forward(L, g32, cfg["gamma"], "f32")
+        o64 = crk.forward(L, g64, cfg["gamma"], "f64")
+        acc = {}
+        for k in ("V", "rho", "A", "B", "dA", "dB", "a", "dudt"):
+            d = (o32[k].double() - o64[k]).abs().max().item()
+            acc[k] = float(f"{d / o64[k].abs().max().item():.3e}")
+        log(f"[bench] FP32 vs FP64 normwise errors {acc}")
+        del g64, o32, o64
 
     out = {
         "metric": METRIC, "value": inter / (ms32 * 1e-3), "unit": "interactions/s",
@@ -292,6 +301,7 @@ def bench_hydro(args, torch, crk):
         "fp32_frac_step": round(flop_step / (ms32 * 1e-3) / 1e12 / PEAK_FP32_VALU_TFLOPS, 4),
         "fp64_gpu_ms_per_step": None if ms64 is None else round(ms64, 4),
         "fp64_over_fp32_time": None if ms64 is None else round(ms64 / ms32, 3),
+        "fp32_vs_fp64_normwise": acc,
         "random_order_ms_per_step": None if ms_rand is None else round(ms_rand, 4),
         "build_ms": round(build_ms, 1), "list_build_gpu_ms": round(cull[0], 3),
     }

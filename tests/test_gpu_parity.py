@@ -118,6 +118,17 @@ def test_stored_moment_sums_match_oracle_moments(crk):
     assert np.array_equal(S[29].astype(np.int64), nnb_ref)
 
 
+def test_fp32_against_fp64_all_particles_c2(crk):
+    """C2 at 128^3: every output of the FP32 mixed path against the FP64 GPU
+    path over all 2,097,152 particles (the oracle checks both on samples)."""
+    cfg = synth.make_config("C2")
+    print(f"case C2 full f32 vs f64 n={cfg['n']}", flush=True)
+    g64, _ = run_gpu(crk, cfg, "f64", leaf_max=128)
+    g32, _ = run_gpu(crk, cfg, "f32", leaf_max=128)
+    for k in KEYS:
+        assert normwise(g32[k], g64[k]) <= TOL["f32"], k
+
+
 def test_interaction_counts_exact(crk):
     cfg, _ = oracle_full("C2", 21)
     got, L = run_gpu(crk, cfg, "f64")
@@ -189,10 +200,11 @@ def test_c5_full_size_sampled(crk):
     against the oracle's per-target closure, and the momentum totals."""
     cfg = synth.make_config("C5")
     print(f"case C5 full n={cfg['n']}", flush=True)
-    t = synth.sample_targets(cfg["n"], 32, seed=17)
+    t = synth.sample_targets(cfg["n"], 128, seed=17)
     ref = oracle.hydro_targets(cfg, t)
     assert ref["n_fallback"] == 0
-    for prec in ("f32", "f64"):
+    res = {}
+    for prec in ("f64", "f32"):
         got, L = run_gpu(crk, cfg, prec, leaf_max=128,
                          tuning={"persistent": 0, "block_waves": 4, "xcd_groups": 8, "kahan_chunk": 8})
         for k in KEYS:
@@ -202,9 +214,13 @@ def test_c5_full_size_sampled(crk):
         assert int(got["n_fallback"][0]) == 0
         T = got["totals"]
         assert np.abs(T[:3]).max() <= (1e-13 if prec == "f64" else 2e-6) * T[4]
+        res[prec] = {k: got[k] for k in KEYS}
         L.free()
         del got
         torch.cuda.empty_cache()
+    # the FP32 mixed path against the FP64 GPU path over every particle
+    for k in KEYS:
+        assert normwise(res["f32"][k], res["f64"][k]) <= TOL["f32"], k
 
 
 # ---------------------------------------------------------------- gravity
