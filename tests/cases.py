@@ -1,0 +1,19 @@
+"""Small hand-made particle sets shared by the GPU tests."""
+
+import numpy as np
+
+import synth
+
+
+def fallback_case():
+    """240 random particles, a tenth of them with h for only 2 neighbours: the
+    singular-moment fallback (fewer than 4 neighbours) triggers for those."""
+    rng = np.random.default_rng(21)
+    n = 240
+    x, y, z = (synth.grid_round(rng.random(n)) for _ in range(3))
+    target = np.where(rng.random(n) < 0.1, 2, 18)
+    H = synth.knn_support(x, y, z, target)
+    return dict(n=n, x=x, y=y, z=z, h=synth.f32(0.5 * H), m=synth.f32(np.full(n, 1.0 / n)),
+                vx=synth.f32(rng.normal(0, 0.1, n)), vy=synth.f32(rng.normal(0, 0.1, n)),
+                vz=synth.f32(rng.normal(0, 0.1, n)), u=synth.f32(np.exp(0.5 * rng.normal(size=n))),
+                gamma=5.0 / 3.0, w=rng.random(n), c=rng.random(n))

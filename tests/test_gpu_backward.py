@@ -14,6 +14,7 @@ import torch
 
 import oracle
 import synth
+from tests.cases import fallback_case
 
 pytestmark = pytest.mark.gpu
 
@@ -168,6 +169,20 @@ def test_backward_schedule_independent(crk, prec):
         got = gpu_gradients(crk, cfg, prec, tuning=tun)
         for a, b in zip(got[:3], base[:3]):
             assert np.array_equal(a, b), tun
+
+
+def test_gradients_through_the_fallback(crk):
+    """Gradients of a set where a tenth of the particles take the zeroth-order
+    fallback, at coordinates of those particles and of their neighbours."""
+    cfg = fallback_case()
+    n = cfg["n"]
+    rng = np.random.default_rng(3)
+    parts = rng.choice(n, size=48, replace=False).astype(np.int64)
+    kinds = rng.integers(0, 7, 48).astype(np.int32)
+    gd, gf, _ = oracle.grad(cfg, parts, kinds)
+    g = pick(gpu_gradients(crk, cfg, "f64", leaf_max=32), parts, kinds)
+    assert rel_err(g, gd).max() <= 1e-9
+    assert rel_err(g, gf).max() <= 1e-6
 
 
 def test_velocity_gradient_vanishes_without_energy_weight(crk):

@@ -14,6 +14,7 @@ import torch
 
 import oracle
 import synth
+from tests.cases import fallback_case
 
 pytestmark = pytest.mark.gpu
 
@@ -383,6 +384,17 @@ def test_empty_and_tiny_inputs(crk):
             ref = oracle.hydro(cfg)
             assert normwise(got["a"], ref["a"]) <= 1e-12
             assert int(got["n_fallback"][0]) == ref["n_fallback"]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_singular_moment_fallback(crk, prec):
+    cfg = fallback_case()
+    ref = oracle.hydro(cfg)
+    assert ref["n_fallback"] > 0
+    got, _ = run_gpu(crk, cfg, prec, leaf_max=32)
+    assert int(got["n_fallback"][0]) == ref["n_fallback"]
+    for k in KEYS:
+        assert normwise(got[k], ref[k]) <= TOL[prec], k
 
 
 def test_invalid_arguments(crk):

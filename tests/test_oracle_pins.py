@@ -105,6 +105,33 @@ def test_reproducing_conditions(tiny, oracle_lib):
     assert np.abs(c1).max() < 1e-13 * scale
 
 
+def test_zeroth_order_fallback(oracle_lib):
+    """Particles with fewer than 4 neighbours take the zeroth-order form: it
+    reproduces constants (sum_j V_j A_i W_ij = 1) with a vanishing gradient
+    (sum_j V_j d_c(A_i W_ij) = 0) and B = dB = 0; exactly those particles fall
+    back, and the others still reproduce linear fields."""
+    from tests.cases import fallback_case
+
+    g = fallback_case()
+    o = oracle_lib.hydro(g)
+    d, r = dense_crk.separations(g)
+    H = 2.0 * g["h"][:, None]
+    W, F = dense_crk.wendland(r, H)
+    nnb = ((r < H).sum(1) - 1)  # neighbours inside the support, self excluded
+    fb = nnb < 4
+    assert fb.sum() > 0 and o["n_fallback"] == fb.sum()
+    Vj = o["V"][None, :]
+    c0 = (Vj * o["A"][:, None] * W).sum(1)
+    grad = (Vj[:, :, None] * (o["dA"][:, None, :] * W[:, :, None]
+                              + o["A"][:, None, None] * F[:, :, None] * d)).sum(1)
+    assert np.abs(c0[fb] - 1.0).max() < 1e-13
+    assert np.abs(grad[fb]).max() < 1e-12 * np.abs(Vj[:, :, None] * F[:, :, None] * d).sum(1)[fb].max()
+    assert np.all(o["B"][fb] == 0.0) and np.all(o["dB"][fb] == 0.0)
+    WR = o["A"][:, None] * (1.0 + np.einsum("ia,ija->ij", o["B"], d)) * W
+    c1 = np.einsum("ij,ija->ia", WR * Vj, d)
+    assert np.abs(c1[~fb]).max() < 1e-12 * np.abs(d).max()
+
+
 def test_gradient_reproducing_conditions(tiny):
     """sum_j V_j G_ij = 0 and sum_j V_j x_ij^a G_ij^c = -delta^ac (these fix dA and dB)."""
     g, o, _ = tiny
