@@ -14,7 +14,7 @@ import torch
 
 import oracle
 import synth
-from tests.cases import fallback_case
+from tests.cases import fallback_case, planar_case
 
 pytestmark = pytest.mark.gpu
 
@@ -32,9 +32,12 @@ def crk():
 
 
 def normwise(y, ref):
+    """max |y - ref| / max |ref|; the absolute error where ref is identically zero."""
     y = np.asarray(y, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
-    return float(np.abs(y - ref).max() / np.abs(ref).max())
+    scale = np.abs(ref).max()
+    err = np.abs(y - ref).max()
+    return float(err / scale) if scale > 0 else float(err)
 
 
 def run_gpu(crk, cfg, prec, leaf_max=64, tuning=None):
@@ -387,14 +390,31 @@ def test_empty_and_tiny_inputs(crk):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_singular_moment_fallback(crk, prec):
-    cfg = fallback_case()
+@pytest.mark.parametrize("case", [fallback_case, planar_case])
+def test_singular_moment_fallback(crk, prec, case):
+    """Few neighbours (fallback_case) and a singular second moment (planar_case)."""
+    cfg = case()
     ref = oracle.hydro(cfg)
     assert ref["n_fallback"] > 0
     got, _ = run_gpu(crk, cfg, prec, leaf_max=32)
     assert int(got["n_fallback"][0]) == ref["n_fallback"]
     for k in KEYS:
         assert normwise(got[k], ref[k]) <= TOL[prec], k
+
+
+def test_gravity_empty_and_tiny(crk):
+    for n in (0, 1, 2, 63, 65):
+        rng = np.random.default_rng(100 + n)
+        cfg = dict(x=synth.grid_round(rng.random(n)), y=synth.grid_round(rng.random(n)),
+                   z=synth.grid_round(rng.random(n)), m=synth.f32(rng.uniform(0.5, 1.5, n) / max(n, 1)),
+                   G=1.0, eps=float(synth.f32(0.01)), r_cut=float(synth.f32(0.3)))
+        a, _ = gravity_gpu(crk, cfg, "f64", leaf_max=16)
+        assert a.shape == (n, 3)
+        if n == 0:
+            continue
+        ref = oracle.gravity(cfg)
+        bound = borderline_bound(cfg)
+        assert np.all(np.abs(a - ref).max(1) <= 1e-12 * max(np.abs(ref).max(), 1e-300) + bound), n
 
 
 def test_invalid_arguments(crk):
