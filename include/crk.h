@@ -100,6 +100,9 @@ typedef struct {
     int block_waves;     /* waves per workgroup for the list-driven pair passes (1, 2, 4) */
     int xcd_groups;      /* tile order is cut into this many contiguous chunks, one per XCD (1..16) */
     int tile_order;      /* 0: tree order (locality); 1: longest tiles first */
+    int addr64;          /* 0: staged record loads use 32-bit offsets from the array base while the records
+                            span at most 4 GiB, 64-bit addresses beyond; 1: 64-bit addresses always
+                            (same results bit for bit; kept to exercise the wide form on small inputs) */
 } crk_tuning;
 
 /*

@@ -55,14 +55,22 @@ using namespace crk;
 namespace {
 
 // Per-particle record for the force pass: everything a neighbour contributes,
-// with the kernel normalisation folded into the correction terms:
-//   P1 = cW dA, P2[a][c] = cW A dB[a][c], P3 = cW A B, P4 = cF A.
+// with the kernel normalisations, the linear correction and the fixed-point
+// scale s = 2^-32 folded in.  For y the separation in grid units (x = s y) and
+// q = |y| invHs, the gradient of the particle's corrected kernel is
+//   G[c] = w(q) (T0[c] + sum_a Qs[a][c] y[a]) + f(q) (P4s + PBs . y) y[c]
+// with T0 = cW (A B + dA), Q[a][c] = cW (A dB[a][c] + dA[c] B[a]), P4 = cF A,
+// PB = P4 B and Qs = s Q, P4s = s P4, PBs = s^2 PB, invHs = s / H (exact
+// power-of-two scalings): the product rule on A (1 + B . x) W, expanded.
+// The record fills whole 128-byte lines (one in FP32, two in FP64): a record
+// that straddled a line boundary would cost an extra line lookup when staged.
 template <class R> struct alignas(16) RecAcc {
-    uint32_t q[4];
-    R invH, V, P, P4;
-    R B[3], P1[3], P3[3], v[3];
-    R P2[9];
-    R pad[sizeof(R) == 4 ? 3 : 5];
+    uint32_t q[3];
+    R invHs;
+    R V, P, P4s;
+    R PBs[3], T0[3], v[3];
+    R Qs[9];
+    R pad[sizeof(R) == 4 ? 6 : 8];
 };
 static_assert(sizeof(RecAcc<float>) == 128, "f32 record is one 128-byte line");
 static_assert(sizeof(RecAcc<double>) == 256, "f64 record is two 128-byte lines");
@@ -76,24 +84,31 @@ __global__ void k_pack_acc(int n, const int32_t* perm, const uint4* quant, const
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = s < n;
     const int i = valid ? perm[s] : 0;
-    RecAcc<R> r;
+    RecAcc<R> r{};
     const uint4 q = quant[valid ? s : 0];
-    r.q[0] = q.x; r.q[1] = q.y; r.q[2] = q.z; r.q[3] = 0;
-    const R H = R(2) * h[i];
-    const R cW = norm_W(H), cF = norm_F(H);
-    const R Ai = A[i];
-    r.invH = R(1) / H;
+    r.q[0] = q.x; r.q[1] = q.y; r.q[2] = q.z;
+    // the folded coefficients in FP64, rounded once
+    const double sc = kInvGrid;
+    const double H = 2.0 * double(h[i]);
+    const double cW = norm_W(H), cF = norm_F(H);
+    const double Ai = A[i];
+    const double P4 = cF * Ai;
+    double Bd[3], dAd[3];
+    for (int a = 0; a < 3; ++a) {
+        Bd[a] = B[3 * i + a];
+        dAd[a] = dA[3 * i + a];
+    }
+    r.invHs = R(sc / H);
     r.V = V[i];
     r.P = gm1 * rho[i] * u[i];
-    r.P4 = cF * Ai;
+    r.P4s = R(sc * P4);
     for (int a = 0; a < 3; ++a) {
-        r.B[a] = B[3 * i + a];
-        r.P1[a] = cW * dA[3 * i + a];
-        r.P3[a] = cW * Ai * B[3 * i + a];
-        for (int c = 0; c < 3; ++c) r.P2[3 * a + c] = cW * Ai * dB[9 * i + 3 * a + c];
+        r.PBs[a] = R(sc * sc * P4 * Bd[a]);
+        r.T0[a] = R(cW * (Ai * Bd[a] + dAd[a]));
+        for (int c = 0; c < 3; ++c)
+            r.Qs[3 * a + c] = R(sc * cW * (Ai * double(dB[9 * i + 3 * a + c]) + dAd[c] * Bd[a]));
     }
     r.v[0] = vx[i]; r.v[1] = vy[i]; r.v[2] = vz[i];
-    for (int k = 0; k < int(sizeof(r.pad) / sizeof(R)); ++k) r.pad[k] = R(0);
     const int first = blockIdx.x * blockDim.x;
     store_records(rec, r, valid, first, min(int(blockDim.x), n - first), buf);
 }
@@ -273,13 +288,13 @@ __global__ __launch_bounds__(256) void k_volume(Queue qu, int n, Lists L, const 
         S.add(0, R(1));  // self term: w(0) = 1
         pipelined_list<uint4>(
             lst, cnt, len, [&](uint32_t j) __attribute__((always_inline)) { return quant[j]; },
-            [&](const uint4& qj, int) __attribute__((always_inline)) {
+            [&](const uint4& qj, int k) __attribute__((always_inline)) {
                 const R dx = sep<R>(qi.x, qj.x), dy = sep<R>(qi.y, qj.y), dz = sep<R>(qi.z, qj.z);
                 const R r = dsqrt(dx * dx + dy * dy + dz * dz);
                 R wq, fq;
                 wendland(r * invH, wq, fq);
                 S.add(0, wq);
-                S.next(chunk);
+                S.next(k, chunk);
             });
         S.fold();
         if (valid) {
@@ -294,7 +309,7 @@ __global__ __launch_bounds__(256) void k_volume(Queue qu, int n, Lists L, const 
 
 // Moments over the neighbour list and the FP64 solve; corrections written in
 // caller order.
-template <class R>
+template <class R, bool kOff32>
 __global__ __launch_bounds__(256) void k_moments(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
                                                  const RecQV<R>* __restrict__ qv,
                                                  const R* __restrict__ h, int chunk, R* __restrict__ A_out,
@@ -313,7 +328,7 @@ __global__ __launch_bounds__(256) void k_moments(Queue qu, int n, Lists L, const
         const R H = valid ? R(2) * h[i] : R(1);
         double S[29], M[40];
         int nnb = 0;
-        moment_sums<R>(w, s, valid, L, qv, stage_buf + (threadIdx.x >> 6) * kStage, H, chunk, S, nnb);
+        moment_sums<R, kOff32>(w, s, valid, L, qv, stage_buf + wave_in_block() * kStage, H, chunk, S, nnb);
         if (valid && sums_out) {
             // kept for the backward (caller order, one row of n per sum)
             for (int e = 0; e < 29; ++e) sums_out[int64_t(e) * n + i] = S[e];
@@ -336,19 +351,20 @@ __global__ __launch_bounds__(256) void k_moments(Queue qu, int n, Lists L, const
 
 // ------------------------------------------------------------------ forces
 
-// gradient of a particle's corrected kernel at separation x (from that particle)
+// gradient of a particle's corrected kernel at separation y (grid units, from
+// that particle); the lane's own particle and its neighbour go through the same
+// expression, on exactly negated separations, so that F_ij = -F_ji bit for bit
 template <class R>
-__device__ __forceinline__ void corrected_grad(const RecAcc<R>& r, R wq, R fq, const R x[3], R G[3]) {
-    const R lin = R(1) + r.B[0] * x[0] + r.B[1] * x[1] + r.B[2] * x[2];
-    const R fl = fq * r.P4 * lin;
+__device__ __forceinline__ void corrected_grad(const RecAcc<R>& r, R wq, R fq, const R y[3], R G[3]) {
+    const R fl = fq * (r.P4s + r.PBs[0] * y[0] + r.PBs[1] * y[1] + r.PBs[2] * y[2]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const R t = r.P3[c] + r.P2[c] * x[0] + r.P2[3 + c] * x[1] + r.P2[6 + c] * x[2] + r.P1[c] * lin;
-        G[c] = wq * t + fl * x[c];
+        const R t = r.T0[c] + r.Qs[c] * y[0] + r.Qs[3 + c] * y[1] + r.Qs[6 + c] * y[2];
+        G[c] = wq * t + fl * y[c];
     }
 }
 
-template <class R>
+template <class R, bool kOff32>
 __global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
                                                const RecAcc<R>* __restrict__ rec, const R* __restrict__ m,
                                                int chunk, R* __restrict__ a_out, R* __restrict__ du_out,
@@ -363,23 +379,24 @@ __global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const i
         const RecAcc<R> ri = rec[valid ? s : 0];
         const int cnt = valid ? L.cnt[s] : 0;
         const int len = L.len[w];
-        const uint32_t* lst = L.nbr + L.off[w] + lane;
-        ChunkSums<R, 4> acc;  // sum F (3), sum F . v_ij
+        // sums over pairs of (V_i V_j)(P_i + P_j)(G_i - G_j) (3) and of its dot
+        // product with v_i - v_j; the pair force is -1/2 of the first
+        ChunkSums<R, 4> acc;
         acc.zero();
-        staged_list<RecAcc<R>>(
-            lst, cnt, len, rec, stage_buf + (threadIdx.x >> 6) * kStage,
-            [&](const RecAcc<R>& rj, int) __attribute__((always_inline)) {
-                const R x[3] = {sep<R>(ri.q[0], rj.q[0]), sep<R>(ri.q[1], rj.q[1]),
-                                sep<R>(ri.q[2], rj.q[2])};
-                const R xo[3] = {-x[0], -x[1], -x[2]};
-                const R r = dsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        staged_list<RecAcc<R>, kOff32>(
+            L.nbr + L.off[w], cnt, len, rec, stage_buf + wave_in_block() * kStage,
+            [&](const RecAcc<R>& rj, int k) __attribute__((always_inline)) {
+                const R y[3] = {grid_sep<R>(ri.q[0], rj.q[0]), grid_sep<R>(ri.q[1], rj.q[1]),
+                                grid_sep<R>(ri.q[2], rj.q[2])};
+                const R yo[3] = {-y[0], -y[1], -y[2]};
+                const R r = dsqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
                 R wi, fi, wj, fj;
-                wendland(r * ri.invH, wi, fi);
-                wendland(r * rj.invH, wj, fj);
+                wendland(r * ri.invHs, wi, fi);
+                wendland(r * rj.invHs, wj, fj);
                 R Gi[3], Gj[3];
-                corrected_grad(ri, wi, fi, x, Gi);
-                corrected_grad(rj, wj, fj, xo, Gj);
-                const R coef = R(-0.5) * ((ri.V * rj.V) * (ri.P + rj.P));
+                corrected_grad(ri, wi, fi, y, Gi);
+                corrected_grad(rj, wj, fj, yo, Gj);
+                const R coef = (ri.V * rj.V) * (ri.P + rj.P);
                 R Fv = R(0);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -388,7 +405,7 @@ __global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const i
                     acc.add(c, F);
                 }
                 acc.add(3, Fv);
-                acc.next(chunk);
+                acc.next(k, chunk);
             });
         acc.fold();
         double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -397,10 +414,10 @@ __global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const i
             const R mi = m[i];
             R av[3];
             for (int c = 0; c < 3; ++c) {
-                av[c] = acc.get(c) / mi;
+                av[c] = R(-0.5) * acc.get(c) / mi;
                 a_out[3 * i + c] = av[c];
             }
-            const R du = R(-0.5) * acc.get(3) / mi;
+            const R du = R(0.25) * acc.get(3) / mi;
             du_out[i] = du;
             const double md = double(mi);
             const double ax = av[0], ay = av[1], az = av[2], dd = du;
@@ -717,7 +734,8 @@ int corrections_impl(crk_leaves* L, const crk_gas* g, const R* V, const crk_corr
     LAUNCH_CHECK("pack position/volume");
     reset_queue(L, st);
     TimeScope ts(L, st, CRK_K_MOMENTS);
-    hipLaunchKernelGGL(k_moments<R>, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves),
+    auto kern = off32<RecQV<R>>(L) ? k_moments<R, true> : k_moments<R, false>;
+    hipLaunchKernelGGL(kern, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves),
                        stage_bytes<RecQV<R>>(L->tune.block_waves), st,
                        make_queue(L, L->order_pair), n, lists_gather(L), L->perm, qv,
                        static_cast<const R*>(g->h), L->tune.kahan_chunk, static_cast<R*>(out->A),
@@ -748,7 +766,8 @@ int accel_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const 
     reset_queue(L, st);
     {
         TimeScope ts(L, st, CRK_K_ACCEL);
-        hipLaunchKernelGGL(k_accel<R>, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves),
+        auto kern = off32<RecAcc<R>>(L) ? k_accel<R, true> : k_accel<R, false>;
+        hipLaunchKernelGGL(kern, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves),
                            stage_bytes<RecAcc<R>>(L->tune.block_waves), st,
                            make_queue(L, L->order_pair), n, lists(L), L->perm, rec,
                            static_cast<const R*>(g->m), L->tune.kahan_chunk, a, dudt, L->partials);
@@ -849,11 +868,13 @@ int crk_set_tuning(crk_leaves* L, const crk_tuning* in) {
     if (!L || !in) return fail(CRK_EINVAL, "null argument");
     if (in->persistent != 0 && in->persistent != 1) return fail(CRK_EINVAL, "persistent must be 0 or 1");
     if (in->waves_per_cu < 1 || in->waves_per_cu > 64) return fail(CRK_EINVAL, "waves_per_cu in [1, 64]");
-    if (in->kahan_chunk < 1 || in->kahan_chunk > 64) return fail(CRK_EINVAL, "kahan_chunk in [1, 64]");
+    if (in->kahan_chunk < 1 || in->kahan_chunk > 64 || (in->kahan_chunk & (in->kahan_chunk - 1)))
+        return fail(CRK_EINVAL, "kahan_chunk must be a power of two in [1, 64]");
     if (in->block_waves != 1 && in->block_waves != 2 && in->block_waves != 4)
         return fail(CRK_EINVAL, "block_waves must be 1, 2 or 4");
     if (in->xcd_groups < 1 || in->xcd_groups > kMaxGroups) return fail(CRK_EINVAL, "xcd_groups in [1, 16]");
     if (in->tile_order != 0 && in->tile_order != 1) return fail(CRK_EINVAL, "tile_order must be 0 or 1");
+    if (in->addr64 != 0 && in->addr64 != 1) return fail(CRK_EINVAL, "addr64 must be 0 or 1");
     L->tune = *in;
     return CRK_OK;
 }

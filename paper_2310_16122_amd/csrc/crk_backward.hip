@@ -184,7 +184,7 @@ __global__ void k_pack_bwd(int n, const int32_t* perm, const uint4* quant, const
 }
 
 // 1. force adjoint
-template <class R>
+template <class R, bool kOff32>
 __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
                                                    const RecBwd<R>* __restrict__ rec, int chunk,
                                                    R* __restrict__ cbar, R* __restrict__ vpbar,
@@ -199,14 +199,13 @@ __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, con
         const RecBwd<R> ri = rec[valid ? s : 0];
         const int cnt = valid ? L.cnt[s] : 0;
         const int len = L.len[w];
-        const uint32_t* lst = L.nbr + L.off[w] + lane;
         ChunkSums<R, 16> cb;  // A, B[3], dA[3], dB[9]
         ChunkSums<R, 8> ob;   // Vbar, Pbar, xbar[3], vbar[3]
         cb.zero();
         ob.zero();
-        staged_list<RecBwd<R>>(
-            lst, cnt, len, rec, stage_buf + (threadIdx.x >> 6) * kStage,
-            [&](const RecBwd<R>& rj, int) __attribute__((always_inline)) {
+        staged_list<RecBwd<R>, kOff32>(
+            L.nbr + L.off[w], cnt, len, rec, stage_buf + wave_in_block() * kStage,
+            [&](const RecBwd<R>& rj, int k) __attribute__((always_inline)) {
                 const R x[3] = {sep<R>(ri.q[0], rj.q[0]), sep<R>(ri.q[1], rj.q[1]), sep<R>(ri.q[2], rj.q[2])};
                 const R y[3] = {-x[0], -x[1], -x[2]};
                 const R r = dsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
@@ -241,8 +240,8 @@ __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, con
                 corr_grad_dy(rj, sj, dj, Wj, Fj, F2j, y, g, xb);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) ob.add(2 + c, xb[c]);
-                cb.next(chunk);
-                ob.next(chunk);
+                cb.next(k, chunk);
+                ob.next(k, chunk);
             });
         cb.fold();
         ob.fold();
@@ -518,7 +517,7 @@ __device__ inline void moments_adjoint_record(int s, const double M[40], int nnb
 
 // 2. moments recomputed with the forward's arithmetic, then the solve adjoint
 // (three waves per SIMD: the few spilled values live outside the neighbour loop)
-template <class R>
+template <class R, bool kOff32>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_moments_bwd(
     Queue qu, int n, Lists L, const int32_t* __restrict__ perm, const uint4* __restrict__ quant,
     const R* __restrict__ aux, const RecQV<R>* __restrict__ qv, const R* __restrict__ h, int chunk,
@@ -534,7 +533,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         const R H = valid ? R(2) * h[i] : R(1);
         double S[29], M[40];
         int nnb = 0;
-        moment_sums<R>(w, s, valid, L, qv, stage_buf + (threadIdx.x >> 6) * kStage, H, chunk, S, nnb);
+        moment_sums<R, kOff32>(w, s, valid, L, qv, stage_buf + wave_in_block() * kStage, H, chunk, S, nnb);
         moments_from_sums(S, M);
         if (valid) moments_adjoint_record(s, M, nnb, quant, aux, cbar, mrec);
     }
@@ -559,7 +558,7 @@ __global__ __launch_bounds__(256) void k_moments_bwd_stored(int n, const int32_t
 }
 
 // 3. moments adjoint, then the per-particle volume/pressure adjoints
-template <class R>
+template <class R, bool kOff32>
 __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
                                                      const RecMom<R>* __restrict__ mrec,
                                                      const R* __restrict__ vpbar, const R* __restrict__ m,
@@ -581,11 +580,10 @@ __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, c
         const R cF2i = R(17325.0 / (2.0 * kPi)) * i2 * i2 * i2 * invHi;
         const int cnt = valid ? L.cnt[s] : 0;
         const int len = L.len[w];
-        const uint32_t* lst = L.nbr + L.off[w] + lane;
         Sums<R, 4> acc;  // Vbar, xbar[3]; per-pair compensation keeps the register count at 3 waves/SIMD
         acc.zero();
-        staged_list<RecMom<R>>(
-            lst, cnt, len, mrec, stage_buf + (threadIdx.x >> 6) * kStage,
+        staged_list<RecMom<R>, kOff32>(
+            L.nbr + L.off[w], cnt, len, mrec, stage_buf + wave_in_block() * kStage,
             [&](const RecMom<R>& rj, int) __attribute__((always_inline)) {
                 const R x[3] = {sep<R>(ri.q[0], rj.q[0]), sep<R>(ri.q[1], rj.q[1]), sep<R>(ri.q[2], rj.q[2])};
                 const R y[3] = {-x[0], -x[1], -x[2]};
@@ -627,7 +625,7 @@ __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, c
 }
 
 // 4. volume adjoint; writes the position gradient in caller order
-template <class R>
+template <class R, bool kOff32>
 __global__ __launch_bounds__(256) void k_volume_adj(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
                                                     const RecVA<R>* __restrict__ varec,
                                                     const R* __restrict__ xbar, int chunk,
@@ -646,12 +644,11 @@ __global__ __launch_bounds__(256) void k_volume_adj(Queue qu, int n, Lists L, co
         const R Sbi = ri.Sbar;
         const int cnt = valid ? L.cnt[s] : 0;
         const int len = L.len[w];
-        const uint32_t* lst = L.nbr + L.off[w] + lane;
         ChunkSums<R, 3> acc;
         acc.zero();
-        list_loop<RecVA<R>>(
-            lst, cnt, len, varec, stage_buf + (threadIdx.x >> 6) * kStage,
-            [&](const RecVA<R>& d, int) __attribute__((always_inline)) {
+        list_loop<RecVA<R>, kOff32>(
+            L.nbr + L.off[w], cnt, len, varec, stage_buf + wave_in_block() * kStage,
+            [&](const RecVA<R>& d, int k) __attribute__((always_inline)) {
                 const R invHj = d.invH;
                 const R x[3] = {sep<R>(ri.q[0], d.q[0]), sep<R>(ri.q[1], d.q[1]), sep<R>(ri.q[2], d.q[2])};
                 const R r = dsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
@@ -663,7 +660,7 @@ __global__ __launch_bounds__(256) void k_volume_adj(Queue qu, int n, Lists L, co
                 const R coef = Sbi * cFi * fi + d.Sbar * cFj * fj;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) acc.add(c, coef * x[c]);
-                acc.next(chunk);
+                acc.next(k, chunk);
             });
         acc.fold();
         if (valid) {
@@ -717,7 +714,8 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
     reset_queue(L, st);
     {
         TimeScope ts(L, st, CRK_K_ACCEL_ADJ);
-        hipLaunchKernelGGL(k_accel_adj<R>, grid, block, stage_bytes<RecBwd<R>>(bw), st, q, n, lists(L),
+        auto kern = off32<RecBwd<R>>(L) ? k_accel_adj<R, true> : k_accel_adj<R, false>;
+        hipLaunchKernelGGL(kern, grid, block, stage_bytes<RecBwd<R>>(bw), st, q, n, lists(L),
                            L->perm, rec, L->tune.kahan_chunk, cbar, vpbar, xbar, gv);
     }
     LAUNCH_CHECK("accel adjoint");
@@ -728,7 +726,8 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
     } else {
         reset_queue(L, st);
         TimeScope ts(L, st, CRK_K_MOMENTS);  // the forward moments, recomputed
-        hipLaunchKernelGGL(k_moments_bwd<R>, grid, block, stage_bytes<RecQV<R>>(bw), st, q, n,
+        auto kern = off32<RecQV<R>>(L) ? k_moments_bwd<R, true> : k_moments_bwd<R, false>;
+        hipLaunchKernelGGL(kern, grid, block, stage_bytes<RecQV<R>>(bw), st, q, n,
                            lists_gather(L), L->perm, L->quant, aux, qv, static_cast<const R*>(g->h),
                            L->tune.kahan_chunk, cbar, mrec);
     }
@@ -736,7 +735,8 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
     reset_queue(L, st);
     {
         TimeScope ts(L, st, CRK_K_MOMENTS_ADJ);
-        hipLaunchKernelGGL(k_moments_adj<R>, grid, block, stage_bytes<RecMom<R>>(bw), st, q, n, lists(L),
+        auto kern = off32<RecMom<R>>(L) ? k_moments_adj<R, true> : k_moments_adj<R, false>;
+        hipLaunchKernelGGL(kern, grid, block, stage_bytes<RecMom<R>>(bw), st, q, n, lists(L),
                            L->perm, mrec, vpbar, static_cast<const R*>(g->m), static_cast<const R*>(g->u),
                            rho, gm1, xbar, varec, gu);
     }
@@ -744,7 +744,8 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
     reset_queue(L, st);
     {
         TimeScope ts(L, st, CRK_K_VOLUME_ADJ);
-        hipLaunchKernelGGL(k_volume_adj<R>, grid, block, stage_bytes<RecVA<R>>(bw), st, q, n, lists(L),
+        auto kern = off32<RecVA<R>>(L) ? k_volume_adj<R, true> : k_volume_adj<R, false>;
+        hipLaunchKernelGGL(kern, grid, block, stage_bytes<RecVA<R>>(bw), st, q, n, lists(L),
                            L->perm, varec, xbar, L->tune.kahan_chunk, gx);
     }
     LAUNCH_CHECK("volume adjoint");

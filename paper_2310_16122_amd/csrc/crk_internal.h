@@ -46,6 +46,11 @@ template <class R> __device__ __forceinline__ R sep(uint32_t a, uint32_t b) {
     return R(int32_t(a - b)) * R(kInvGrid);
 }
 
+// the same separation in grid units (2^32 per box length)
+template <class R> __device__ __forceinline__ R grid_sep(uint32_t a, uint32_t b) {
+    return R(int32_t(a - b));
+}
+
 template <class R> __device__ __forceinline__ R dsqrt(R x);
 template <> __device__ __forceinline__ float dsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <> __device__ __forceinline__ double dsqrt<double>(double x) { return sqrt(x); }
@@ -190,6 +195,7 @@ struct Lists {
 template <class D, class Load, class Body>
 __device__ __forceinline__ void pipelined_list(const uint32_t* __restrict__ lst, int cnt, int len,
                                                Load load, Body body) {
+    len = __builtin_amdgcn_readfirstlane(len);  // the tile's: a scalar slot loop
     if (len <= 0) return;
     const int last = len - 1;
     auto slot = [&](int k) __attribute__((always_inline)) {
@@ -218,36 +224,80 @@ __device__ __forceinline__ void pipelined_list(const uint32_t* __restrict__ lst,
 // (p % NCH) ^ swz(r) of record r = p / NCH; the swizzle (power-of-two NCH
 // only) keeps the lanes' reads of one chunk on distinct banks.  The record
 // indices of the next slot are fetched one slot ahead, and that slot is
-// staged while the current one is processed.  `lds` is this wave's buffer of
-// NCH x 64 uint4; slots past a lane's count hold valid indices.
+// staged while the current one is processed.
+//
+// `row0` is the tile's slot-major list (slot k at row0 + 64 k) and `lds` this
+// wave's buffer of NCH x 64 uint4; both are wave-uniform, so slot rows and LDS
+// destinations are scalar arithmetic.  kOff32: the records span at most
+// 4 GiB, and each load is a 32-bit offset from the scalar base (one vector
+// instruction per load); otherwise 64-bit addresses.  Slots past a lane's
+// count hold valid indices.
 template <int NCH> __device__ __forceinline__ int stage_swz(int r) {
     if ((NCH & (NCH - 1)) != 0) return 0;  // odd strides are conflict-free as they are
     return (r ^ (r >> 3)) & (NCH - 1);
 }
 
-template <class D, class Body>
-__device__ __forceinline__ void staged_list(const uint32_t* __restrict__ lst, int cnt, int len,
+// index of the calling wave within its workgroup, in a scalar register
+__device__ __forceinline__ int wave_in_block() {
+    return __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+}
+
+// a pointer the caller knows to be wave-uniform, moved to scalar registers
+template <class T> __device__ __forceinline__ const T* uniform_ptr(const T* p) {
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(a));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(a >> 32));
+    return reinterpret_cast<const T*>((uint64_t(hi) << 32) | lo);
+}
+
+// Byte offset of record j in the 32-bit form: a shift for power-of-two record
+// sizes, else one 24-bit multiply (the form is taken only for j < 2^24).
+template <class D> __device__ __forceinline__ uint32_t record_offset(uint32_t j) {
+    constexpr uint32_t kSize = uint32_t(sizeof(D));
+    if constexpr ((kSize & (kSize - 1)) == 0) return j * kSize;
+    else return uint32_t(__umul24(j, kSize));
+}
+
+template <class D, bool kOff32, class Body>
+__device__ __forceinline__ void staged_list(const uint32_t* __restrict__ row0, int cnt, int len,
                                             const D* __restrict__ recs, uint4* __restrict__ lds,
                                             Body body) {
     constexpr int NCH = int(sizeof(D) / 16);
     static_assert(sizeof(D) % 16 == 0, "records are whole 16-byte chunks");
-    // with NCH dividing 64, the records a lane loads sit at a fixed stride in
-    // the slot's row (one address, immediate offsets); otherwise each lane
-    // takes them from the lanes that own them, all exchanges issued at once
-    constexpr bool kRowLoads = kWave % NCH == 0;
+    // with NCH dividing 64 or at most 8, every lane loads the NCH record
+    // indices it stages from the slot's row (scalar row address, per-lane
+    // offsets fixed for the loop); otherwise it loads its own entry and takes
+    // the others from the lanes that own them, all exchanges issued at once
+    constexpr bool kRowLoads = kWave % NCH == 0 || NCH <= 8;
+    len = __builtin_amdgcn_readfirstlane(len);  // the tile's: slot loop and rows in scalar registers
+    row0 = uniform_ptr(row0);
     if (len <= 0) return;
     const int lane = lane_id();
     const int last = len - 1;
-    const uint32_t* row0 = lst - lane;  // the tile's slot-major list
     uint32_t idx[NCH];
+    uint32_t coff[NCH];  // byte offset of the chunk this lane loads, within its record
+    uint32_t roff[NCH];  // kRowLoads: byte offset in the row of the entry naming that record
+#pragma unroll
+    for (int t = 0; t < NCH; ++t) {
+        const int g = t * kWave + lane;
+        coff[t] = uint32_t((g % NCH) ^ stage_swz<NCH>(g / NCH)) * 16u;
+        roff[t] = uint32_t(kWave % NCH == 0 ? t * (kWave / NCH) + lane / NCH : g / NCH) * 4u;
+    }
     uint32_t own = 0;  // kRowLoads == false: this lane's entry of the next slot
+    // the tile's list as a buffer (gfx9 raw-buffer descriptor word: 32-bit
+    // elements): row loads take the slot's byte offset from a scalar register
+    // and the lane's offset from a fixed vector register; reads past the
+    // tile's slots return 0 instead of touching memory
+    const __amdgpu_buffer_rsrc_t rows = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t*>(row0), 0, len * kWave * 4, 0x00020000);
     auto load_idx = [&](int k) __attribute__((always_inline)) {
-        const uint32_t* row = row0 + int64_t(k < last ? k : last) * kWave;
+        const int sk = (k < last ? k : last) * kWave * 4;
         if (kRowLoads) {
 #pragma unroll
-            for (int t = 0; t < NCH; ++t) idx[t] = row[(t * kWave + lane) / NCH];
+            for (int t = 0; t < NCH; ++t)
+                idx[t] = uint32_t(__builtin_amdgcn_raw_buffer_load_b32(rows, int(roff[t]), sk, 0));
         } else {
-            own = row[lane];
+            own = uint32_t(__builtin_amdgcn_raw_buffer_load_b32(rows, lane * 4, sk, 0));
         }
     };
     auto stage = [&]() __attribute__((always_inline)) {
@@ -258,10 +308,9 @@ __device__ __forceinline__ void staged_list(const uint32_t* __restrict__ lst, in
         const char* base = reinterpret_cast<const char*>(recs);
 #pragma unroll
         for (int t = 0; t < NCH; ++t) {
-            const int g = t * kWave + lane;
-            const int c = (g % NCH) ^ stage_swz<NCH>(g / NCH);
-            __builtin_amdgcn_global_load_lds(base + size_t(idx[t]) * sizeof(D) + size_t(c) * 16,
-                                             lds + t * kWave, 16, 0, 0);
+            const char* src = kOff32 ? base + (record_offset<D>(idx[t]) + coff[t])
+                                     : base + size_t(idx[t]) * sizeof(D) + coff[t];
+            __builtin_amdgcn_global_load_lds(src, lds + t * kWave, 16, 0, 0);
         }
     };
     const int sw = stage_swz<NCH>(lane);
@@ -281,6 +330,15 @@ __device__ __forceinline__ void staged_list(const uint32_t* __restrict__ lst, in
         }
         if (k < cnt) body(d, k);
     }
+}
+
+// True when every record of an array of n records of type D lies within
+// 4 GiB of its base, and the index fits the 24-bit multiply where the record
+// size is not a power of two (the 32-bit offset form of staged_list).
+template <class D> inline bool records_off32(int64_t n) {
+    constexpr uint64_t kSize = sizeof(D);
+    const bool pow2 = (kSize & (kSize - 1)) == 0;
+    return uint64_t(n) * kSize <= (uint64_t(1) << 32) && (pow2 || n <= (int64_t(1) << 24));
 }
 
 // Block-cooperative store of one record per thread: the records pass through
@@ -336,24 +394,26 @@ template <class D> inline size_t stage_bytes(int block_waves) {
 
 // One-chunk records are gathered lane by lane (a cooperative load saves
 // nothing there); larger ones are staged through LDS.
-template <class D, class Body>
-__device__ __forceinline__ void list_loop(const uint32_t* __restrict__ lst, int cnt, int len,
+template <class D, bool kOff32, class Body>
+__device__ __forceinline__ void list_loop(const uint32_t* __restrict__ row0, int cnt, int len,
                                           const D* __restrict__ recs, uint4* __restrict__ lds, Body body) {
     if constexpr (sizeof(D) == 16) {
         pipelined_list<D>(
-            lst, cnt, len, [&](uint32_t j) __attribute__((always_inline)) { return recs[j]; }, body);
+            row0 + lane_id(), cnt, len, [&](uint32_t j) __attribute__((always_inline)) { return recs[j]; },
+            body);
     } else {
-        staged_list<D>(lst, cnt, len, recs, lds, body);
+        staged_list<D, kOff32>(row0, cnt, len, recs, lds, body);
     }
 }
 
 // Chunked compensated sums: plain partial sums over `chunk` pairs, folded into
 // (s, c) Kahan pairs (FP32); plain sums in FP64.
+// A lane adds the pairs of list slots 0, 1, ... in order, so after slot k it
+// holds k + 1 pairs: with a power-of-two chunk the fold test depends on the
+// wave-uniform slot number only (a scalar branch, no per-lane counter).
 template <class R, int N> struct ChunkSums {
     R p[N], s[N], c[N];
-    int kk;
     __device__ void zero() {
-        kk = 0;
 #pragma unroll
         for (int e = 0; e < N; ++e) { p[e] = R(0); s[e] = R(0); c[e] = R(0); }
     }
@@ -363,8 +423,9 @@ template <class R, int N> struct ChunkSums {
 #pragma unroll
         for (int e = 0; e < N; ++e) { kadd(s[e], c[e], p[e]); p[e] = R(0); }
     }
-    __device__ void next(int chunk) {
-        if (sizeof(R) == 4 && ++kk == chunk) { fold(); kk = 0; }
+    // after the pair of slot k; chunk is a power of two
+    __device__ void next(int k, int chunk) {
+        if (sizeof(R) == 4 && ((k + 1) & (chunk - 1)) == 0) fold();
     }
     // value after a final fold
     __device__ R get(int e) const { return sizeof(R) == 4 ? s[e] - c[e] : p[e]; }
@@ -383,7 +444,7 @@ template <class R, int N> struct ChunkSums {
 // g2^abc = delta^ac m1^b + delta^bc m1^a + t3^abc.  FP32: plain sums over
 // `chunk` pairs folded into compensated sums.  Every lane of the wave must call
 // this (the loop runs over the tile's longest list).
-template <class R>
+template <class R, bool kOff32>
 __device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, const RecQV<R>* __restrict__ qv,
                                    uint4* __restrict__ lds, R H, int chunk, double S[29], int& nnb) {
     constexpr bool kComp = sizeof(R) == 4;
@@ -395,15 +456,13 @@ __device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, con
     const R cW = norm_W(H), cF = norm_F(H);
     const int cnt = valid ? L.cnt[s] : 0;
     const int len = L.len[w];
-    const uint32_t* lst = L.nbr + L.off[w] + lane;
     R p[kN], sm[kN], cm[kN];
 #pragma unroll
     for (int e = 0; e < kN; ++e) { p[e] = R(0); sm[e] = R(0); cm[e] = R(0); }
     nnb = 0;
-    int kk = 0;
-    list_loop<RecQV<R>>(
-        lst, cnt, len, qv, lds,
-        [&](const RecQV<R>& d, int) __attribute__((always_inline)) {
+    list_loop<RecQV<R>, kOff32>(
+        L.nbr + L.off[w], cnt, len, qv, lds,
+        [&](const RecQV<R>& d, int k) __attribute__((always_inline)) {
             const R Vj = d.V;
             const R x[3] = {sep<R>(qi.x, d.q[0]), sep<R>(qi.y, d.q[1]), sep<R>(qi.z, d.q[2])};
             const R r = dsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
@@ -432,10 +491,9 @@ __device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, con
             }
 #pragma unroll
             for (int e = 0; e < 10; ++e) p[19 + e] += x3[e] * fv;
-            if (kComp && ++kk == chunk) {
+            if (kComp && ((k + 1) & (chunk - 1)) == 0) {  // see ChunkSums
 #pragma unroll
                 for (int e = 0; e < kN; ++e) { kadd(sm[e], cm[e], p[e]); p[e] = R(0); }
-                kk = 0;
             }
         });
 #pragma unroll
@@ -537,7 +595,7 @@ struct crk_leaves {
     double r_fixed = 0.0;
     int64_t n_tiles = 0, n_leaves = 0;
     int n_cu = 1;
-    crk_tuning tune{0, 16, 4, 4, 8, 0};  // measured best on the C2 workload
+    crk_tuning tune{0, 16, 4, 4, 8, 0, 0};  // measured best on the C2 workload
     int32_t* perm = nullptr;
     uint4* quant = nullptr;
     double* Hd = nullptr;
@@ -590,6 +648,11 @@ int check_gas(const crk_leaves* L, const crk_gas* g, bool need_v);
 void reset_queue(crk_leaves* L, hipStream_t st);
 Lists lists(const crk_leaves* L);         // pairs r < max(H_i, H_j)
 Lists lists_gather(const crk_leaves* L);  // their front parts: r < H_i
+
+// Whether a pass over n records of type D takes the 32-bit offset form.
+template <class D> inline bool off32(const crk_leaves* L) {
+    return !L->tune.addr64 && records_off32<D>(L->n);
+}
 
 // Brackets one launch with events when timing is enabled.
 struct TimeScope {

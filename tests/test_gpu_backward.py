@@ -160,12 +160,13 @@ def test_stored_moment_sums_give_the_recomputed_backward(crk, prec):
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_backward_schedule_independent(crk, prec):
-    """Workgroup shape, queue mode and tile order change only which wave runs a
-    tile, never a lane's arithmetic: gradients are bitwise identical."""
+    """Workgroup shape, queue mode, tile order and the record addressing form
+    change only which wave runs a tile or how a record is fetched, never a
+    lane's arithmetic: gradients are bitwise identical."""
     cfg = synth.make_config("C4", n_side=20)
     base = gpu_gradients(crk, cfg, prec)
     for tun in ({"block_waves": 1}, {"block_waves": 2, "persistent": 1, "waves_per_cu": 3},
-                {"block_waves": 4, "xcd_groups": 1, "tile_order": 1}):
+                {"block_waves": 4, "xcd_groups": 1, "tile_order": 1}, {"addr64": 1}):
         got = gpu_gradients(crk, cfg, prec, tuning=tun)
         for a, b in zip(got[:3], base[:3]):
             assert np.array_equal(a, b), tun

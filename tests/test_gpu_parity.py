@@ -162,6 +162,18 @@ def test_bitwise_reproducible(crk):
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_wide_record_addressing_is_bitwise_identical(crk, prec):
+    """Record arrays beyond 4 GiB are addressed with 64-bit pointers instead of
+    32-bit offsets; forcing that form on a small input changes no bit."""
+    cfg, _ = oracle_full("C2", 21)
+    a, _ = run_gpu(crk, cfg, prec)
+    b, L = run_gpu(crk, cfg, prec, tuning={"addr64": 1})
+    assert L.get_tuning()["addr64"] == 1
+    for k in KEYS:
+        assert np.array_equal(a[k], b[k]), k
+
+
 def test_kahan_chunk_within_tolerance(crk):
     cfg, ref = oracle_full("C2", 21)
     for chunk in (1, 8, 32, 64):
