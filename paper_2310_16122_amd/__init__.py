@@ -28,7 +28,8 @@ _STATUS = {0: "CRK_OK", -1: "CRK_EINVAL", -2: "CRK_ENOMEM", -3: "CRK_EHIP", -4: 
 
 # the C symbols declared in include/crk.h
 EXPORTS = ("crk_build_leaf_pairs", "crk_volume", "crk_corrections", "crk_accel_energy",
-           "sr_gravity", "crk_accel_energy_backward", "crk_leaves_stats", "crk_leaves_perm", "crk_get_tuning", "crk_set_tuning",
+           "sr_gravity", "crk_accel_energy_backward", "crk_leaves_stats", "crk_leaves_perm",
+           "crk_get_tuning", "crk_set_tuning",
            "crk_timing", "crk_kernel_times", "crk_leaves_free", "crk_last_error")
 KERNEL_KINDS = ("cull", "volume", "moments", "accel", "gravity", "pack", "accel_adj",
                 "moments_adj", "volume_adj", "solve_adj")

@@ -21,6 +21,10 @@ ARCH = "gfx950"
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fused within a source expression only: device code shared
+    # by several kernels (and by both sides of a pair) rounds the same way in
+    # every one of them
+    "-ffp-contract=on",
     "-I", INCLUDE, "-I", CSRC,
 ]
 

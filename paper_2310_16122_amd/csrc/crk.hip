@@ -317,7 +317,7 @@ __global__ __launch_bounds__(256) void k_moments(Queue qu, int n, Lists L, const
                                                  R* __restrict__ dB_out,
                                                  unsigned long long* __restrict__ n_fallback,
                                                  double* __restrict__ sums_out) {
-    constexpr int kStage = sizeof(RecQV<R>) > 16 ? int(sizeof(RecQV<R>) / 16) * kWave : 1;
+    constexpr int kStage = stage_stride<RecQV<R>>();
     extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
     const int lane = lane_id();
     QState qs;
@@ -364,12 +364,76 @@ __device__ __forceinline__ void corrected_grad(const RecAcc<R>& r, R wq, R fq, c
     }
 }
 
+// One pair of the force pass for lane particle i and neighbour j: adds
+// (V_i V_j)(P_i + P_j)(G_i - G_j) (the pair force is -1/2 of it) and its dot
+// product with v_i - v_j.
+template <class R>
+__device__ __forceinline__ void accel_pair(const RecAcc<R>& ri, const RecAcc<R>& rj, int k, int chunk,
+                                           ChunkSums<R, 4>& acc) {
+    const R y[3] = {grid_sep<R>(ri.q[0], rj.q[0]), grid_sep<R>(ri.q[1], rj.q[1]),
+                    grid_sep<R>(ri.q[2], rj.q[2])};
+    const R yo[3] = {-y[0], -y[1], -y[2]};
+    const R r = dsqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+    R wi, fi, wj, fj;
+    wendland(r * ri.invHs, wi, fi);
+    wendland(r * rj.invHs, wj, fj);
+    R Gi[3], Gj[3];
+    corrected_grad(ri, wi, fi, y, Gi);
+    corrected_grad(rj, wj, fj, yo, Gj);
+    const R coef = (ri.V * rj.V) * (ri.P + rj.P);
+    R Fv = R(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const R F = coef * (Gi[c] - Gj[c]);
+        Fv += F * (ri.v[c] - rj.v[c]);
+        acc.add(c, F);
+    }
+    acc.add(3, Fv);
+    acc.next(k, chunk);
+}
+
+// a_i = -1/2 sum / m_i and du_i/dt = 1/4 (dot-product sum) / m_i; the tile's
+// FP64 partial totals go to partials[8 w ...]
+template <class R>
+__device__ __forceinline__ void accel_finish(int w, int s, bool valid, const RecAcc<R>& ri,
+                                             ChunkSums<R, 4>& acc, const int32_t* __restrict__ perm,
+                                             const R* __restrict__ m, R* __restrict__ a_out,
+                                             R* __restrict__ du_out, double* __restrict__ partials) {
+    acc.fold();
+    double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (valid) {
+        const int i = perm[s];
+        const R mi = m[i];
+        R av[3];
+        for (int c = 0; c < 3; ++c) {
+            av[c] = R(-0.5) * acc.get(c) / mi;
+            a_out[3 * i + c] = av[c];
+        }
+        const R du = R(0.25) * acc.get(3) / mi;
+        du_out[i] = du;
+        const double md = double(mi);
+        const double ax = av[0], ay = av[1], az = av[2], dd = du;
+        const double va = double(ri.v[0]) * ax + double(ri.v[1]) * ay + double(ri.v[2]) * az;
+        t[0] = md * ax; t[1] = md * ay; t[2] = md * az;
+        t[3] = md * (va + dd);
+        t[4] = md * sqrt(ax * ax + ay * ay + az * az);
+        t[5] = md * (fabs(va) + fabs(dd));
+        t[6] = md * dd;
+        t[7] = md * va;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        for (int o = 32; o > 0; o >>= 1) t[k] += __shfl_xor(t[k], o);
+    if (lane_id() == 0)
+        for (int k = 0; k < 8; ++k) partials[8 * w + k] = t[k];
+}
+
 template <class R, bool kOff32>
 __global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
                                                const RecAcc<R>* __restrict__ rec, const R* __restrict__ m,
                                                int chunk, R* __restrict__ a_out, R* __restrict__ du_out,
                                                double* __restrict__ partials) {
-    constexpr int kStage = int(sizeof(RecAcc<R>) / 16) * kWave;
+    constexpr int kStage = stage_stride<RecAcc<R>>();
     extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
     const int lane = lane_id();
     QState qs;
@@ -379,61 +443,14 @@ __global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const i
         const RecAcc<R> ri = rec[valid ? s : 0];
         const int cnt = valid ? L.cnt[s] : 0;
         const int len = L.len[w];
-        // sums over pairs of (V_i V_j)(P_i + P_j)(G_i - G_j) (3) and of its dot
-        // product with v_i - v_j; the pair force is -1/2 of the first
         ChunkSums<R, 4> acc;
         acc.zero();
         staged_list<RecAcc<R>, kOff32>(
             L.nbr + L.off[w], cnt, len, rec, stage_buf + wave_in_block() * kStage,
             [&](const RecAcc<R>& rj, int k) __attribute__((always_inline)) {
-                const R y[3] = {grid_sep<R>(ri.q[0], rj.q[0]), grid_sep<R>(ri.q[1], rj.q[1]),
-                                grid_sep<R>(ri.q[2], rj.q[2])};
-                const R yo[3] = {-y[0], -y[1], -y[2]};
-                const R r = dsqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
-                R wi, fi, wj, fj;
-                wendland(r * ri.invHs, wi, fi);
-                wendland(r * rj.invHs, wj, fj);
-                R Gi[3], Gj[3];
-                corrected_grad(ri, wi, fi, y, Gi);
-                corrected_grad(rj, wj, fj, yo, Gj);
-                const R coef = (ri.V * rj.V) * (ri.P + rj.P);
-                R Fv = R(0);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const R F = coef * (Gi[c] - Gj[c]);
-                    Fv += F * (ri.v[c] - rj.v[c]);
-                    acc.add(c, F);
-                }
-                acc.add(3, Fv);
-                acc.next(k, chunk);
+                accel_pair(ri, rj, k, chunk, acc);
             });
-        acc.fold();
-        double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (valid) {
-            const int i = perm[s];
-            const R mi = m[i];
-            R av[3];
-            for (int c = 0; c < 3; ++c) {
-                av[c] = R(-0.5) * acc.get(c) / mi;
-                a_out[3 * i + c] = av[c];
-            }
-            const R du = R(0.25) * acc.get(3) / mi;
-            du_out[i] = du;
-            const double md = double(mi);
-            const double ax = av[0], ay = av[1], az = av[2], dd = du;
-            const double va = double(ri.v[0]) * ax + double(ri.v[1]) * ay + double(ri.v[2]) * az;
-            t[0] = md * ax; t[1] = md * ay; t[2] = md * az;
-            t[3] = md * (va + dd);
-            t[4] = md * sqrt(ax * ax + ay * ay + az * az);
-            t[5] = md * (fabs(va) + fabs(dd));
-            t[6] = md * dd;
-            t[7] = md * va;
-        }
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            for (int o = 32; o > 0; o >>= 1) t[k] += __shfl_xor(t[k], o);
-        if (lane == 0)
-            for (int k = 0; k < 8; ++k) partials[8 * w + k] = t[k];
+        accel_finish(w, s, valid, ri, acc, perm, m, a_out, du_out, partials);
     }
 }
 
@@ -767,8 +784,8 @@ int accel_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const 
     {
         TimeScope ts(L, st, CRK_K_ACCEL);
         auto kern = off32<RecAcc<R>>(L) ? k_accel<R, true> : k_accel<R, false>;
-        hipLaunchKernelGGL(kern, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves),
-                           stage_bytes<RecAcc<R>>(L->tune.block_waves), st,
+        const int bw = L->tune.block_waves;
+        hipLaunchKernelGGL(kern, dim3(grid_nwave(L)), dim3(kWave * bw), stage_bytes<RecAcc<R>>(bw), st,
                            make_queue(L, L->order_pair), n, lists(L), L->perm, rec,
                            static_cast<const R*>(g->m), L->tune.kahan_chunk, a, dudt, L->partials);
     }

@@ -189,7 +189,7 @@ __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, con
                                                    const RecBwd<R>* __restrict__ rec, int chunk,
                                                    R* __restrict__ cbar, R* __restrict__ vpbar,
                                                    R* __restrict__ xbar, R* __restrict__ gv) {
-    constexpr int kStage = int(sizeof(RecBwd<R>) / 16) * kWave;
+    constexpr int kStage = stage_stride<RecBwd<R>>();
     extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
     const int lane = lane_id();
     QState qs;
@@ -522,7 +522,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     Queue qu, int n, Lists L, const int32_t* __restrict__ perm, const uint4* __restrict__ quant,
     const R* __restrict__ aux, const RecQV<R>* __restrict__ qv, const R* __restrict__ h, int chunk,
     const R* __restrict__ cbar, RecMom<R>* __restrict__ mrec) {
-    constexpr int kStage = sizeof(RecQV<R>) > 16 ? int(sizeof(RecQV<R>) / 16) * kWave : 1;
+    constexpr int kStage = stage_stride<RecQV<R>>();
     extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
     const int lane = lane_id();
     QState qs;
@@ -565,7 +565,7 @@ __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, c
                                                      const R* __restrict__ u, const R* __restrict__ rho, R gm1,
                                                      R* __restrict__ xbar, RecVA<R>* __restrict__ varec,
                                                      R* __restrict__ gu) {
-    constexpr int kStage = int(sizeof(RecMom<R>) / 16) * kWave;
+    constexpr int kStage = stage_stride<RecMom<R>>();
     extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
     const int lane = lane_id();
     QState qs;
@@ -630,7 +630,7 @@ __global__ __launch_bounds__(256) void k_volume_adj(Queue qu, int n, Lists L, co
                                                     const RecVA<R>* __restrict__ varec,
                                                     const R* __restrict__ xbar, int chunk,
                                                     R* __restrict__ gx) {
-    constexpr int kStage = int(sizeof(RecVA<R>) / 16) * kWave;
+    constexpr int kStage = stage_stride<RecVA<R>>();
     extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
     const int lane = lane_id();
     QState qs;

@@ -284,20 +284,22 @@ __device__ __forceinline__ void staged_list(const uint32_t* __restrict__ row0, i
         roff[t] = uint32_t(kWave % NCH == 0 ? t * (kWave / NCH) + lane / NCH : g / NCH) * 4u;
     }
     uint32_t own = 0;  // kRowLoads == false: this lane's entry of the next slot
-    // the tile's list as a buffer (gfx9 raw-buffer descriptor word: 32-bit
-    // elements): row loads take the slot's byte offset from a scalar register
-    // and the lane's offset from a fixed vector register; reads past the
-    // tile's slots return 0 instead of touching memory
-    const __amdgpu_buffer_rsrc_t rows = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<uint32_t*>(row0), 0, len * kWave * 4, 0x00020000);
+    // kRowLoads: a slot's row of 64 indices goes to LDS with one direct load
+    // (one vector-memory request instead of NCH), and each lane reads the NCH
+    // entries it needs from there together with its record
+    uint32_t* rowbuf = reinterpret_cast<uint32_t*>(lds + NCH * kWave);
     auto load_idx = [&](int k) __attribute__((always_inline)) {
-        const int sk = (k < last ? k : last) * kWave * 4;
+        const uint32_t* row = row0 + (k < last ? k : last) * kWave;
+        if (kRowLoads) {
+            __builtin_amdgcn_global_load_lds(row + lane, rowbuf, 4, 0, 0);
+        } else {
+            own = row[lane];
+        }
+    };
+    auto read_idx = [&]() __attribute__((always_inline)) {
         if (kRowLoads) {
 #pragma unroll
-            for (int t = 0; t < NCH; ++t)
-                idx[t] = uint32_t(__builtin_amdgcn_raw_buffer_load_b32(rows, int(roff[t]), sk, 0));
-        } else {
-            own = uint32_t(__builtin_amdgcn_raw_buffer_load_b32(rows, lane * 4, sk, 0));
+            for (int t = 0; t < NCH; ++t) idx[t] = rowbuf[roff[t] / 4];
         }
     };
     auto stage = [&]() __attribute__((always_inline)) {
@@ -315,15 +317,19 @@ __device__ __forceinline__ void staged_list(const uint32_t* __restrict__ row0, i
     };
     const int sw = stage_swz<NCH>(lane);
     load_idx(0);
+    __builtin_amdgcn_s_waitcnt(0);
+    read_idx();
+    __builtin_amdgcn_s_waitcnt(0);
     stage();
     load_idx(1);
     for (int k = 0; k < len; ++k) {
-        __builtin_amdgcn_s_waitcnt(0);  // this slot's records are in LDS
+        __builtin_amdgcn_s_waitcnt(0);  // this slot's records (and the next row) are in LDS
         D d;
         uint4* dst = reinterpret_cast<uint4*>(&d);
 #pragma unroll
         for (int c = 0; c < NCH; ++c) dst[c] = lds[lane * NCH + (c ^ sw)];
-        __builtin_amdgcn_s_waitcnt(0);  // reads done before the buffer is refilled
+        if (k + 1 < len) read_idx();
+        __builtin_amdgcn_s_waitcnt(0);  // reads done before the buffers are refilled
         if (k + 1 < len) {
             stage();
             load_idx(k + 2);
@@ -386,10 +392,16 @@ template <class R> __global__ void k_pack_qv(int n, const int32_t* perm, const u
     out[s] = r;
 }
 
-// Dynamic LDS of a list-driven launch: one wave's staging buffer for records
-// of type D per wave of the workgroup (one-chunk records need none).
+// LDS of one wave in a list-driven pass, in 16-byte units: the staged records
+// of a slot and the slot's row of indices (one-chunk records need none).
+template <class D> __host__ __device__ constexpr int stage_stride() {
+    return sizeof(D) > 16 ? int(sizeof(D) / 16) * kWave + kWave / 4 : 1;
+}
+
+// Dynamic LDS of a list-driven launch: one wave's buffers per wave of the
+// workgroup.
 template <class D> inline size_t stage_bytes(int block_waves) {
-    return sizeof(D) > 16 ? sizeof(D) * size_t(kWave) * size_t(block_waves) : 16;
+    return size_t(stage_stride<D>()) * 16 * size_t(sizeof(D) > 16 ? block_waves : 1);
 }
 
 // One-chunk records are gathered lane by lane (a cooperative load saves
