@@ -205,6 +205,132 @@ __global__ __launch_bounds__(64) void k_cull(Queue qu, int n, const uint4* __res
     }
 }
 
+// ------------------------------------------------------------------ shared-record slots
+
+// Reorders each tile's lists so that the lanes sharing a neighbour take it in
+// the same slot, and records every slot's distinct particles (srec, scnt)
+// and each lane's position among them (sidx).  Greedy, one slot at a time:
+// among the tile's neighbours, take the one that the most lanes still free in
+// this slot need (ties: the smaller index), give it to those lanes, and
+// repeat until every lane with entries left holds one; so each lane still
+// fills slots 0 .. cnt - 1 and a tile keeps its slot count.  A lane takes its
+// gather neighbours (r < H_i) before the others, so the front of its list
+// keeps serving the gather passes.  The choice depends only on counts and
+// indices, never on the hash layout: the schedule is deterministic.  A tile
+// whose neighbour set overflows the table keeps its order with the identity
+// sets (64 per slot).  One wave per tile.
+constexpr int kSchedHash = 2048;
+
+__global__ __launch_bounds__(64) void k_schedule(int n, const int32_t* __restrict__ cnt,
+                                                 const int32_t* __restrict__ cntg,
+                                                 const int64_t* __restrict__ ell_off,
+                                                 const int32_t* __restrict__ ell_len, uint32_t* __restrict__ nbr,
+                                                 uint32_t* __restrict__ srec, uint8_t* __restrict__ sidx,
+                                                 int32_t* __restrict__ scnt) {
+    __shared__ uint32_t key[kSchedHash];
+    __shared__ unsigned long long gm[kSchedHash], bm[kSchedHash];  // lanes needing it: gather, other
+    const int w = blockIdx.x;
+    const int lane = int(threadIdx.x);
+    const int s = w * kWave + lane;
+    const bool valid = s < n;
+    const int c = valid ? cnt[s] : 0;
+    const int cg = valid ? cntg[s] : 0;
+    const int len = ell_len[w];
+    const int64_t off = ell_off[w];
+    const uint32_t self = uint32_t(valid ? s : w * kWave);
+    for (int t = lane; t < kSchedHash; t += kWave) {
+        key[t] = 0xFFFFFFFFu;
+        gm[t] = 0;
+        bm[t] = 0;
+    }
+    __syncthreads();
+    int full = 0;
+    for (int k = 0; k < c; ++k) {
+        const uint32_t j = nbr[off + int64_t(k) * kWave + lane];
+        uint32_t h = (j * 2654435761u) >> 21;
+        int probe = 0;
+        for (; probe < kSchedHash; ++probe) {
+            const uint32_t prev = atomicCAS(&key[h], 0xFFFFFFFFu, j);
+            if (prev == 0xFFFFFFFFu || prev == j) break;
+            h = (h + 1) & (kSchedHash - 1);
+        }
+        if (probe == kSchedHash) {
+            full = 1;
+            break;
+        }
+        atomicOr(k < cg ? &gm[h] : &bm[h], 1ull << lane);
+    }
+    __syncthreads();
+    if (__ballot(full) != 0) {  // identity sets: every lane's own entry
+        for (int k = 0; k < len; ++k) {
+            const int64_t e = off + int64_t(k) * kWave + lane;
+            srec[e] = nbr[e];
+            sidx[e] = uint8_t(lane);
+            if (lane == 0) scnt[(off >> 6) + k] = kWave;
+        }
+        return;
+    }
+    int remg = cg, remb = c - cg;
+    const unsigned long long bit = 1ull << lane;
+    for (int k = 0; k < len; ++k) {
+        const unsigned long long gph = __ballot(remg > 0);
+        unsigned long long open = __ballot(remg + remb > 0);
+        uint32_t mine = self;
+        int mypos = 0, m = 0;
+        uint32_t first = 0;
+        while (open != 0 && m < kWave) {
+            int bc = 0, bs = -1;
+            uint32_t bk = 0xFFFFFFFFu;
+            for (int t = lane; t < kSchedHash; t += kWave) {
+                const uint32_t kk = key[t];
+                if (kk == 0xFFFFFFFFu) continue;
+                const int cv = __popcll(((gm[t] & gph) | (bm[t] & ~gph)) & open);
+                if (cv > bc || (cv == bc && cv > 0 && kk < bk)) {
+                    bc = cv;
+                    bk = kk;
+                    bs = t;
+                }
+            }
+            for (int o = kWave / 2; o > 0; o >>= 1) {
+                const int oc = __shfl_xor(bc, o);
+                const uint32_t ok = uint32_t(__shfl_xor(int(bk), o));
+                const int os = __shfl_xor(bs, o);
+                if (oc > bc || (oc == bc && ok < bk)) {
+                    bc = oc;
+                    bk = ok;
+                    bs = os;
+                }
+            }
+            bc = __builtin_amdgcn_readfirstlane(bc);
+            if (bc == 0) break;
+            bs = __builtin_amdgcn_readfirstlane(bs);
+            bk = uint32_t(__builtin_amdgcn_readfirstlane(int(bk)));
+            const unsigned long long take = ((gm[bs] & gph) | (bm[bs] & ~gph)) & open;
+            __syncthreads();  // every lane has read the masks before they change
+            if (take & bit) {
+                mine = bk;
+                mypos = m;
+                if (remg > 0) --remg;
+                else --remb;
+            }
+            if (lane == 0) {
+                gm[bs] &= ~(take & gph);
+                bm[bs] &= ~(take & ~gph);
+                srec[off + int64_t(k) * kWave + m] = bk;
+            }
+            __syncthreads();
+            if (m == 0) first = bk;
+            open &= ~take;
+            ++m;
+        }
+        const int64_t e = off + int64_t(k) * kWave + lane;
+        nbr[e] = mine;
+        sidx[e] = uint8_t(mypos);
+        if (lane >= m) srec[e] = m > 0 ? first : self;  // past the set: any valid index
+        if (lane == 0) scnt[(off >> 6) + k] = m > 0 ? m : 1;
+    }
+}
+
 // Exact FP64 interaction counts over the lists: r < H_i and r < max(H_i, H_j).
 __global__ __launch_bounds__(256) void k_count_lists(int n, const uint4* __restrict__ quant,
                                                      const double* __restrict__ Hd,
@@ -446,7 +572,7 @@ __global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const i
         ChunkSums<R, 4> acc;
         acc.zero();
         staged_list<RecAcc<R>, kOff32>(
-            L.nbr + L.off[w], cnt, len, rec, stage_buf + wave_in_block() * kStage,
+            L, w, cnt, len, rec, stage_buf + wave_in_block() * kStage,
             [&](const RecAcc<R>& rj, int k) __attribute__((always_inline)) {
                 accel_pair(ri, rj, k, chunk, acc);
             });
@@ -643,7 +769,7 @@ namespace crk {
 void release(crk_leaves* L) {
     void* ptrs[] = {L->perm, L->quant, L->Hd, L->rng_off, L->rng, L->order_cull, L->order_pair, L->order_tree,
                     L->counter, L->cnt, L->cnt_gather, L->ell_off, L->ell_len, L->ell_len_gather, L->nbr,
-                    L->build_err, L->partials, L->counts,
+                    L->build_err, L->partials, L->counts, L->srec, L->sidx, L->scnt,
                     L->scratch};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -714,9 +840,11 @@ void reset_queue(crk_leaves* L, hipStream_t st) {
     if (L->tune.persistent) hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, L->counter);
 }
 
-Lists lists(const crk_leaves* L) { return Lists{L->cnt, L->ell_off, L->ell_len, L->nbr}; }
+Lists lists(const crk_leaves* L) {
+    return Lists{L->cnt, L->ell_off, L->ell_len, L->nbr, L->srec, L->sidx, L->scnt};
+}
 Lists lists_gather(const crk_leaves* L) {
-    return Lists{L->cnt_gather, L->ell_off, L->ell_len_gather, L->nbr};
+    return Lists{L->cnt_gather, L->ell_off, L->ell_len_gather, L->nbr, L->srec, L->sidx, L->scnt};
 }
 
 }  // namespace crk
@@ -1124,6 +1252,14 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
         if (mismatched)
             return bail(fail(CRK_EHIP, "neighbour lists: count and fill passes disagree on %d particles",
                              mismatched));
+        // shared-record slots: reorder the lists, name each slot's particles
+        if ((rc = dalloc(&L->srec, size_t(total))) || (rc = dalloc(&L->sidx, size_t(total))) ||
+            (rc = dalloc(&L->scnt, size_t(total / kWave))))
+            return bail(rc);
+        hipLaunchKernelGGL(k_schedule, dim3(unsigned(nt)), dim3(kWave), 0, stream, int(n), L->cnt, L->cnt_gather,
+                           L->ell_off, L->ell_len, L->nbr, L->srec, L->sidx, L->scnt);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(stream) != hipSuccess)
+            return bail(fail(CRK_EHIP, "list schedule failed"));
         L->stats[3] = entries;
         L->stats[6] = total - entries;
     }

@@ -203,8 +203,8 @@ __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, con
         ChunkSums<R, 8> ob;   // Vbar, Pbar, xbar[3], vbar[3]
         cb.zero();
         ob.zero();
-        staged_list<RecBwd<R>, kOff32>(
-            L.nbr + L.off[w], cnt, len, rec, stage_buf + wave_in_block() * kStage,
+        staged_list<RecBwd<R>, kOff32, false>(  // measured faster with fixed LDS addresses
+            L, w, cnt, len, rec, stage_buf + wave_in_block() * kStage,
             [&](const RecBwd<R>& rj, int k) __attribute__((always_inline)) {
                 const R x[3] = {sep<R>(ri.q[0], rj.q[0]), sep<R>(ri.q[1], rj.q[1]), sep<R>(ri.q[2], rj.q[2])};
                 const R y[3] = {-x[0], -x[1], -x[2]};
@@ -582,8 +582,8 @@ __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, c
         const int len = L.len[w];
         Sums<R, 4> acc;  // Vbar, xbar[3]; per-pair compensation keeps the register count at 3 waves/SIMD
         acc.zero();
-        staged_list<RecMom<R>, kOff32>(
-            L.nbr + L.off[w], cnt, len, mrec, stage_buf + wave_in_block() * kStage,
+        staged_list<RecMom<R>, kOff32, false>(  // measured faster with fixed LDS addresses
+            L, w, cnt, len, mrec, stage_buf + wave_in_block() * kStage,
             [&](const RecMom<R>& rj, int) __attribute__((always_inline)) {
                 const R x[3] = {sep<R>(ri.q[0], rj.q[0]), sep<R>(ri.q[1], rj.q[1]), sep<R>(ri.q[2], rj.q[2])};
                 const R y[3] = {-x[0], -x[1], -x[2]};
@@ -647,7 +647,7 @@ __global__ __launch_bounds__(256) void k_volume_adj(Queue qu, int n, Lists L, co
         ChunkSums<R, 3> acc;
         acc.zero();
         list_loop<RecVA<R>, kOff32>(
-            L.nbr + L.off[w], cnt, len, varec, stage_buf + wave_in_block() * kStage,
+            L, w, cnt, len, varec, stage_buf + wave_in_block() * kStage,
             [&](const RecVA<R>& d, int k) __attribute__((always_inline)) {
                 const R invHj = d.invH;
                 const R x[3] = {sep<R>(ri.q[0], d.q[0]), sep<R>(ri.q[1], d.q[1]), sep<R>(ri.q[2], d.q[2])};

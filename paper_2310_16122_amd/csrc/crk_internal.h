@@ -173,11 +173,17 @@ template <class R> __global__ void k_gather(int n, const int32_t* perm, const R*
 
 // A tile's neighbour lists: per lane `cnt` entries (the first `cnt` slots),
 // per tile `len` slots (the longest lane); slot k of lane l at off + 64 k + l.
+// Each slot also names the distinct particles its 64 entries refer to:
+// scnt[off / 64 + k] of them, in srec[off + 64 k + e], and lane l's entry is
+// the particle at position sidx[off + 64 k + l] of that set.
 struct Lists {
     const int32_t* cnt;
     const int64_t* off;
     const int32_t* len;
     const uint32_t* nbr;
+    const uint32_t* srec;
+    const uint8_t* sidx;
+    const int32_t* scnt;
 };
 
 
@@ -216,22 +222,23 @@ __device__ __forceinline__ void pipelined_list(const uint32_t* __restrict__ lst,
 // Neighbour-list loop for large per-particle records (NCH 16-byte chunks),
 // staged through LDS.  A per-lane gather of a record touches one cache line
 // per lane per 16-byte load, and the L1 resolves about one line per clock, so
-// gathering records lane by lane costs NCH x 64 line lookups per wave and slot.
-// Here the wave loads the 64 records of a slot cooperatively -- consecutive
-// lanes fetch consecutive chunks of the same record, i.e. whole lines -- with
-// direct global-to-LDS loads into a wave-private buffer, then every lane reads
-// its own record from LDS.  LDS position p (in 16-byte units) holds chunk
-// (p % NCH) ^ swz(r) of record r = p / NCH; the swizzle (power-of-two NCH
-// only) keeps the lanes' reads of one chunk on distinct banks.  The record
-// indices of the next slot are fetched one slot ahead, and that slot is
-// staged while the current one is processed.
+// the wave stages the records of a slot cooperatively instead: consecutive
+// lanes fetch consecutive chunks of the same record -- whole lines -- with
+// direct global-to-LDS loads into a wave-private buffer, and every lane then
+// reads its own entry's record from LDS.  Only the slot's distinct particles
+// are fetched (the list build orders each tile's lists so that lanes sharing
+// a neighbour take it in the same slot): m records in ceil(m NCH / 64)
+// loads.  LDS position q (16-byte units) holds chunk (q % NCH) ^ swz(r) of
+// set record r = q / NCH; the swizzle (power-of-two NCH only) spreads the
+// lanes' reads of one chunk over the banks.  A slot's set (its row of
+// particle indices, one direct load into LDS), count and positions are
+// fetched one slot ahead, and the slot's records are staged while the
+// previous one is processed.
 //
-// `row0` is the tile's slot-major list (slot k at row0 + 64 k) and `lds` this
-// wave's buffer of NCH x 64 uint4; both are wave-uniform, so slot rows and LDS
-// destinations are scalar arithmetic.  kOff32: the records span at most
-// 4 GiB, and each load is a 32-bit offset from the scalar base (one vector
-// instruction per load); otherwise 64-bit addresses.  Slots past a lane's
-// count hold valid indices.
+// kOff32: the records span at most 4 GiB and each load is a 32-bit offset
+// from the scalar base; otherwise 64-bit addresses.  kShared = false stages
+// all 64 entries of each slot in lane order instead (fixed LDS addresses per
+// lane): the passes with the heaviest arithmetic per pair measure faster so.
 template <int NCH> __device__ __forceinline__ int stage_swz(int r) {
     if ((NCH & (NCH - 1)) != 0) return 0;  // odd strides are conflict-free as they are
     return (r ^ (r >> 3)) & (NCH - 1);
@@ -258,82 +265,92 @@ template <class D> __device__ __forceinline__ uint32_t record_offset(uint32_t j)
     else return uint32_t(__umul24(j, kSize));
 }
 
-template <class D, bool kOff32, class Body>
-__device__ __forceinline__ void staged_list(const uint32_t* __restrict__ row0, int cnt, int len,
+template <class D, bool kOff32, bool kShared = true, class Body>
+__device__ __forceinline__ void staged_list(const Lists& L, int w, int cnt, int len,
                                             const D* __restrict__ recs, uint4* __restrict__ lds,
                                             Body body) {
     constexpr int NCH = int(sizeof(D) / 16);
     static_assert(sizeof(D) % 16 == 0, "records are whole 16-byte chunks");
-    // with NCH dividing 64 or at most 8, every lane loads the NCH record
-    // indices it stages from the slot's row (scalar row address, per-lane
-    // offsets fixed for the loop); otherwise it loads its own entry and takes
-    // the others from the lanes that own them, all exchanges issued at once
-    constexpr bool kRowLoads = kWave % NCH == 0 || NCH <= 8;
     len = __builtin_amdgcn_readfirstlane(len);  // the tile's: slot loop and rows in scalar registers
-    row0 = uniform_ptr(row0);
     if (len <= 0) return;
     const int lane = lane_id();
     const int last = len - 1;
-    uint32_t idx[NCH];
-    uint32_t coff[NCH];  // byte offset of the chunk this lane loads, within its record
-    uint32_t roff[NCH];  // kRowLoads: byte offset in the row of the entry naming that record
+    const int64_t off = L.off[w];
+    const uint32_t* row0 = uniform_ptr((kShared ? L.srec : L.nbr) + off);
+    const int32_t* cnt0 = uniform_ptr(L.scnt + (off >> 6));
+    // the tile's positions as a buffer: slot k's byte row at a scalar offset
+    const __amdgpu_buffer_rsrc_t pos = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint8_t*>(uniform_ptr(L.sidx + off)), 0, len * kWave, 0x00020000);
+    uint32_t coff[NCH];  // byte offset of the chunk this lane stages, within its record
+    uint32_t roff[NCH];  // entry of the slot's set naming that record
 #pragma unroll
     for (int t = 0; t < NCH; ++t) {
         const int g = t * kWave + lane;
         coff[t] = uint32_t((g % NCH) ^ stage_swz<NCH>(g / NCH)) * 16u;
-        roff[t] = uint32_t(kWave % NCH == 0 ? t * (kWave / NCH) + lane / NCH : g / NCH) * 4u;
+        roff[t] = uint32_t(kWave % NCH == 0 ? t * (kWave / NCH) + lane / NCH : g / NCH);
     }
-    uint32_t own = 0;  // kRowLoads == false: this lane's entry of the next slot
-    // kRowLoads: a slot's row of 64 indices goes to LDS with one direct load
-    // (one vector-memory request instead of NCH), and each lane reads the NCH
-    // entries it needs from there together with its record
     uint32_t* rowbuf = reinterpret_cast<uint32_t*>(lds + NCH * kWave);
-    auto load_idx = [&](int k) __attribute__((always_inline)) {
+    uint32_t idx[NCH];
+    auto load_set = [&](int k) __attribute__((always_inline)) {  // row of slot k into LDS
         const uint32_t* row = row0 + (k < last ? k : last) * kWave;
-        if (kRowLoads) {
-            __builtin_amdgcn_global_load_lds(row + lane, rowbuf, 4, 0, 0);
-        } else {
-            own = row[lane];
-        }
+        __builtin_amdgcn_global_load_lds(row + lane, rowbuf, 4, 0, 0);
     };
-    auto read_idx = [&]() __attribute__((always_inline)) {
-        if (kRowLoads) {
-#pragma unroll
-            for (int t = 0; t < NCH; ++t) idx[t] = rowbuf[roff[t] / 4];
-        }
+    auto load_count = [&](int k) __attribute__((always_inline)) {
+        return kShared ? cnt0[k < last ? k : last] : kWave;
     };
-    auto stage = [&]() __attribute__((always_inline)) {
-        if (!kRowLoads) {
+    auto load_pos = [&](int k) __attribute__((always_inline)) {
+        return kShared ? uint32_t(__builtin_amdgcn_raw_buffer_load_b8(pos, lane, (k < last ? k : last) * kWave, 0))
+                       : uint32_t(lane);
+    };
+    auto read_idx = [&](int m) __attribute__((always_inline)) {
 #pragma unroll
-            for (int t = 0; t < NCH; ++t) idx[t] = uint32_t(__shfl(int(own), (t * kWave + lane) / NCH));
-        }
+        for (int t = 0; t < NCH; ++t)
+            if (t * kWave < m * NCH) idx[t] = rowbuf[roff[t]];
+    };
+    auto stage = [&](int m) __attribute__((always_inline)) {
         const char* base = reinterpret_cast<const char*>(recs);
 #pragma unroll
         for (int t = 0; t < NCH; ++t) {
-            const char* src = kOff32 ? base + (record_offset<D>(idx[t]) + coff[t])
-                                     : base + size_t(idx[t]) * sizeof(D) + coff[t];
-            __builtin_amdgcn_global_load_lds(src, lds + t * kWave, 16, 0, 0);
+            if (t * kWave < m * NCH) {  // wave-uniform: loads that hold chunks of the set
+                const char* src = kOff32 ? base + (record_offset<D>(idx[t]) + coff[t])
+                                         : base + size_t(idx[t]) * sizeof(D) + coff[t];
+                if (t * kWave + lane < m * NCH) __builtin_amdgcn_global_load_lds(src, lds + t * kWave, 16, 0, 0);
+            }
         }
     };
-    const int sw = stage_swz<NCH>(lane);
-    load_idx(0);
-    __builtin_amdgcn_s_waitcnt(0);
-    read_idx();
-    __builtin_amdgcn_s_waitcnt(0);
-    stage();
-    load_idx(1);
-    for (int k = 0; k < len; ++k) {
-        __builtin_amdgcn_s_waitcnt(0);  // this slot's records (and the next row) are in LDS
+    const char* lb = reinterpret_cast<const char*>(lds);
+    auto read_rec = [&](uint32_t p) __attribute__((always_inline)) {
         D d;
         uint4* dst = reinterpret_cast<uint4*>(&d);
+        const uint32_t sw = uint32_t(stage_swz<NCH>(int(p)));
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) dst[c] = lds[lane * NCH + (c ^ sw)];
-        if (k + 1 < len) read_idx();
+        for (int c = 0; c < NCH; ++c)
+            dst[c] = *reinterpret_cast<const uint4*>(lb + (p * NCH + (uint32_t(c) ^ sw)) * 16u);
+        return d;
+    };
+    int m_next = __builtin_amdgcn_readfirstlane(load_count(0));
+    uint32_t p_cur = load_pos(0);
+    load_set(0);
+    __builtin_amdgcn_s_waitcnt(0);
+    read_idx(m_next);
+    __builtin_amdgcn_s_waitcnt(0);
+    stage(m_next);
+    load_set(1);
+    int m_after = load_count(1);
+    uint32_t p_next = load_pos(1);
+    for (int k = 0; k < len; ++k) {
+        __builtin_amdgcn_s_waitcnt(0);  // this slot's records and the next slot's set are in LDS
+        const D d = read_rec(p_cur);
+        m_next = __builtin_amdgcn_readfirstlane(m_after);
+        if (k + 1 < len) read_idx(m_next);
         __builtin_amdgcn_s_waitcnt(0);  // reads done before the buffers are refilled
         if (k + 1 < len) {
-            stage();
-            load_idx(k + 2);
+            stage(m_next);
+            load_set(k + 2);
         }
+        p_cur = p_next;
+        m_after = load_count(k + 2);
+        p_next = load_pos(k + 2);
         if (k < cnt) body(d, k);
     }
 }
@@ -407,14 +424,14 @@ template <class D> inline size_t stage_bytes(int block_waves) {
 // One-chunk records are gathered lane by lane (a cooperative load saves
 // nothing there); larger ones are staged through LDS.
 template <class D, bool kOff32, class Body>
-__device__ __forceinline__ void list_loop(const uint32_t* __restrict__ row0, int cnt, int len,
+__device__ __forceinline__ void list_loop(const Lists& L, int w, int cnt, int len,
                                           const D* __restrict__ recs, uint4* __restrict__ lds, Body body) {
     if constexpr (sizeof(D) == 16) {
         pipelined_list<D>(
-            row0 + lane_id(), cnt, len, [&](uint32_t j) __attribute__((always_inline)) { return recs[j]; },
-            body);
+            L.nbr + L.off[w] + lane_id(), cnt, len,
+            [&](uint32_t j) __attribute__((always_inline)) { return recs[j]; }, body);
     } else {
-        staged_list<D, kOff32>(row0, cnt, len, recs, lds, body);
+        staged_list<D, kOff32>(L, w, cnt, len, recs, lds, body);
     }
 }
 
@@ -473,7 +490,7 @@ __device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, con
     for (int e = 0; e < kN; ++e) { p[e] = R(0); sm[e] = R(0); cm[e] = R(0); }
     nnb = 0;
     list_loop<RecQV<R>, kOff32>(
-        L.nbr + L.off[w], cnt, len, qv, lds,
+        L, w, cnt, len, qv, lds,
         [&](const RecQV<R>& d, int k) __attribute__((always_inline)) {
             const R Vj = d.V;
             const R x[3] = {sep<R>(qi.x, d.q[0]), sep<R>(qi.y, d.q[1]), sep<R>(qi.z, d.q[2])};
@@ -624,6 +641,9 @@ struct crk_leaves {
     int32_t* ell_len_gather = nullptr;  // per tile: longest gather part
     int32_t* build_err = nullptr;       // lanes whose count and fill passes disagreed
     uint32_t* nbr = nullptr;
+    uint32_t* srec = nullptr;  // per slot: its distinct particles (Lists)
+    uint8_t* sidx = nullptr;   // per entry: its particle's position in the slot's set
+    int32_t* scnt = nullptr;   // per slot: size of the set
     double* partials = nullptr;
     unsigned long long* counts = nullptr;
     void* scratch = nullptr;
