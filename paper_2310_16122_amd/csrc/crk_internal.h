@@ -277,7 +277,8 @@ __device__ __forceinline__ void staged_list(const Lists& L, int w, int cnt, int 
     const int last = len - 1;
     const int64_t off = L.off[w];
     const uint32_t* row0 = uniform_ptr((kShared ? L.srec : L.nbr) + off);
-    const int32_t* cnt0 = uniform_ptr(L.scnt + (off >> 6));
+    const __amdgpu_buffer_rsrc_t sets = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<int32_t*>(uniform_ptr(L.scnt + (off >> 6))), 0, len * 4, 0x00020000);
     // the tile's positions as a buffer: slot k's byte row at a scalar offset
     const __amdgpu_buffer_rsrc_t pos = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint8_t*>(uniform_ptr(L.sidx + off)), 0, len * kWave, 0x00020000);
@@ -296,25 +297,27 @@ __device__ __forceinline__ void staged_list(const Lists& L, int w, int cnt, int 
         __builtin_amdgcn_global_load_lds(row + lane, rowbuf, 4, 0, 0);
     };
     auto load_count = [&](int k) __attribute__((always_inline)) {
-        return kShared ? cnt0[k < last ? k : last] : kWave;
+        return kShared ? __builtin_amdgcn_raw_buffer_load_b32(sets, 0, (k < last ? k : last) * 4, 0) : kWave;
     };
     auto load_pos = [&](int k) __attribute__((always_inline)) {
         return kShared ? uint32_t(__builtin_amdgcn_raw_buffer_load_b8(pos, lane, (k < last ? k : last) * kWave, 0))
                        : uint32_t(lane);
     };
-    auto read_idx = [&](int m) __attribute__((always_inline)) {
+    auto read_idx = [&](int) __attribute__((always_inline)) {
 #pragma unroll
-        for (int t = 0; t < NCH; ++t)
-            if (t * kWave < m * NCH) idx[t] = rowbuf[roff[t]];
+        for (int t = 0; t < NCH; ++t) idx[t] = rowbuf[roff[t]];
     };
+    // only the loads that hold chunks of the set are issued (a wave-uniform
+    // test); the lanes of the last one past the set fetch the set's first
+    // record again (the rows are padded with it): lines already in flight
     auto stage = [&](int m) __attribute__((always_inline)) {
         const char* base = reinterpret_cast<const char*>(recs);
 #pragma unroll
         for (int t = 0; t < NCH; ++t) {
-            if (t * kWave < m * NCH) {  // wave-uniform: loads that hold chunks of the set
+            if (t * kWave < m * NCH) {
                 const char* src = kOff32 ? base + (record_offset<D>(idx[t]) + coff[t])
                                          : base + size_t(idx[t]) * sizeof(D) + coff[t];
-                if (t * kWave + lane < m * NCH) __builtin_amdgcn_global_load_lds(src, lds + t * kWave, 16, 0, 0);
+                __builtin_amdgcn_global_load_lds(src, lds + t * kWave, 16, 0, 0);
             }
         }
     };
