@@ -116,7 +116,10 @@ typedef struct {
  *
  *  h != NULL (hydro mode): radius max(2h_i, 2h_j); a per-particle neighbour
  *    list (j != i, |x_ij| < max(2h_i, 2h_j)) is built on the GPU for the CRK
- *    passes.  Requires 2 max(h) < 1/2.
+ *    passes, then ordered per tile so that lanes sharing a neighbour take it
+ *    at the same list position (each particle's neighbours with |x_ij| < 2h_i
+ *    first; deterministic).  The order changes only the summation order of the
+ *    passes, never which pairs they sum.  Requires 2 max(h) < 1/2.
  *  h == NULL (fixed-radius mode): radius r_fixed (< 1/2), for sr_gravity.
  *
  * prec gives the precision of h.  leaf_max in [1, 1<<20].  On success *out
