@@ -220,6 +220,7 @@ __global__ __launch_bounds__(64) void k_cull(Queue qu, int n, const uint4* __res
 // whose neighbour set overflows the table keeps its order with the identity
 // sets (64 per slot).  One wave per tile.
 constexpr int kSchedHash = 2048;
+static_assert(kSchedHash / kWave <= 32, "one 32-bit mask of live slots per lane");
 
 __global__ __launch_bounds__(64) void k_schedule(int n, const int32_t* __restrict__ cnt,
                                                  const int32_t* __restrict__ cntg,
@@ -270,6 +271,10 @@ __global__ __launch_bounds__(64) void k_schedule(int n, const int32_t* __restric
         }
         return;
     }
+    // this lane's scan covers slots lane + 64 i; live[i] while some lane still needs the entry
+    uint32_t live = 0;
+    for (int i = 0; i < kSchedHash / kWave; ++i)
+        if (key[lane + kWave * i] != 0xFFFFFFFFu) live |= 1u << i;
     int remg = cg, remb = c - cg;
     const unsigned long long bit = 1ull << lane;
     for (int k = 0; k < len; ++k) {
@@ -281,9 +286,9 @@ __global__ __launch_bounds__(64) void k_schedule(int n, const int32_t* __restric
         while (open != 0 && m < kWave) {
             int bc = 0, bs = -1;
             uint32_t bk = 0xFFFFFFFFu;
-            for (int t = lane; t < kSchedHash; t += kWave) {
+            for (uint32_t lv = live; lv != 0; lv &= lv - 1) {
+                const int t = lane + kWave * __builtin_ctz(lv);
                 const uint32_t kk = key[t];
-                if (kk == 0xFFFFFFFFu) continue;
                 const int cv = __popcll(((gm[t] & gph) | (bm[t] & ~gph)) & open);
                 if (cv > bc || (cv == bc && cv > 0 && kk < bk)) {
                     bc = cv;
@@ -319,6 +324,7 @@ __global__ __launch_bounds__(64) void k_schedule(int n, const int32_t* __restric
                 srec[off + int64_t(k) * kWave + m] = bk;
             }
             __syncthreads();
+            if ((bs & (kWave - 1)) == lane && gm[bs] == 0 && bm[bs] == 0) live &= ~(1u << (bs / kWave));
             if (m == 0) first = bk;
             open &= ~take;
             ++m;
