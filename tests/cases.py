@@ -33,3 +33,17 @@ def planar_case():
     return dict(n=n, x=x, y=y, z=z, h=synth.f32(np.full(n, 1.3 / k)), m=synth.f32(np.full(n, 1.0 / n)),
                 vx=synth.f32(rng.normal(0, 0.1, n)), vy=synth.f32(rng.normal(0, 0.1, n)),
                 vz=np.zeros(n), u=np.ones(n), gamma=5.0 / 3.0)
+
+
+def dense_case():
+    """6000 random particles with h for about 600 neighbours: the neighbours of
+    a tile's 64 particles number more than the list schedule's table holds, so
+    its tiles keep their fill order with one-per-lane staging sets."""
+    rng = np.random.default_rng(17)
+    n = 6000
+    x, y, z = (synth.grid_round(rng.random(n)) for _ in range(3))
+    H = synth.knn_support(x, y, z, np.full(n, 600))
+    return dict(n=n, x=x, y=y, z=z, h=synth.f32(0.5 * H), m=synth.f32(np.full(n, 1.0 / n)),
+                vx=synth.f32(rng.normal(0, 0.1, n)), vy=synth.f32(rng.normal(0, 0.1, n)),
+                vz=synth.f32(rng.normal(0, 0.1, n)), u=synth.f32(np.exp(0.5 * rng.normal(size=n))),
+                gamma=5.0 / 3.0)

@@ -14,7 +14,7 @@ import torch
 
 import oracle
 import synth
-from tests.cases import fallback_case
+from tests.cases import dense_case, fallback_case
 
 pytestmark = pytest.mark.gpu
 
@@ -184,6 +184,21 @@ def test_gradients_through_the_fallback(crk):
     g = pick(gpu_gradients(crk, cfg, "f64", leaf_max=32), parts, kinds)
     assert rel_err(g, gd).max() <= 1e-9
     assert rel_err(g, gf).max() <= 1e-6
+
+
+def test_gradients_dense_neighbourhoods(crk):
+    """Gradients where most tiles keep one-per-lane staging sets (about 600
+    neighbours per particle), at 16 coordinates against the oracle."""
+    cfg = dense_case()
+    n = cfg["n"]
+    rng = np.random.default_rng(2)
+    cfg["w"], cfg["c"] = rng.random(n), rng.random(n)
+    parts = rng.choice(n, size=16, replace=False).astype(np.int64)
+    kinds = rng.integers(0, 7, 16).astype(np.int32)
+    gd, gf, _ = oracle.grad(cfg, parts, kinds)
+    for prec, tol in (("f64", 1e-9), ("f32", 1e-4)):
+        g = pick(gpu_gradients(crk, cfg, prec, leaf_max=64), parts, kinds)
+        assert rel_err(g, gd).max() <= tol, prec
 
 
 def test_velocity_gradient_vanishes_without_energy_weight(crk):

@@ -14,7 +14,7 @@ import torch
 
 import oracle
 import synth
-from tests.cases import fallback_case, planar_case
+from tests.cases import dense_case, fallback_case, planar_case
 
 pytestmark = pytest.mark.gpu
 
@@ -172,6 +172,19 @@ def test_wide_record_addressing_is_bitwise_identical(crk, prec):
     assert L.get_tuning()["addr64"] == 1
     for k in KEYS:
         assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_dense_neighbourhoods(crk, prec):
+    """About 600 neighbours per particle: most tiles' neighbour sets overflow
+    the list schedule's table and keep one-per-lane staging, the others fill it
+    almost to the brim; every output against the oracle."""
+    cfg = dense_case()
+    print(f"case dense n={cfg['n']} prec={prec}", flush=True)
+    ref = oracle.hydro(cfg)
+    got, _ = run_gpu(crk, cfg, prec, leaf_max=64)
+    for k in KEYS:
+        assert normwise(got[k], ref[k]) <= TOL[prec], k
 
 
 def test_kahan_chunk_within_tolerance(crk):
