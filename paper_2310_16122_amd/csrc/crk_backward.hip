@@ -44,20 +44,6 @@ template <class R> struct alignas(128) RecBwd {
 static_assert(sizeof(RecBwd<float>) == 128, "f32 backward record is one line");
 static_assert(sizeof(RecBwd<double>) == 256, "f64 backward record is two lines");
 
-template <class R, int N> struct Sums {
-    R s[N], c[N];
-    __device__ void zero() {
-#pragma unroll
-        for (int e = 0; e < N; ++e) { s[e] = R(0); c[e] = R(0); }
-    }
-    __device__ void add(int e, R t) {
-        if (sizeof(R) == 4) kadd(s[e], c[e], t);
-        else s[e] += t;
-    }
-    __device__ R get(int e) const { return s[e] - c[e]; }
-    __device__ double getd(int e) const { return double(s[e]) - double(c[e]); }
-};
-
 // Wendland C4 shapes and the Hessian factor: W = cW w, grad W = cF f x,
 // grad (cF f) = cF2 f2 x.
 template <class R> __device__ __forceinline__ void shapes(R q, R& w, R& f, R& f2) {
@@ -563,7 +549,7 @@ __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, c
                                                      const RecMom<R>* __restrict__ mrec,
                                                      const R* __restrict__ vpbar, const R* __restrict__ m,
                                                      const R* __restrict__ u, const R* __restrict__ rho, R gm1,
-                                                     R* __restrict__ xbar, RecVA<R>* __restrict__ varec,
+                                                     int chunk, R* __restrict__ xbar, RecVA<R>* __restrict__ varec,
                                                      R* __restrict__ gu) {
     constexpr int kStage = stage_stride<RecMom<R>>();
     extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
@@ -580,11 +566,11 @@ __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, c
         const R cF2i = R(17325.0 / (2.0 * kPi)) * i2 * i2 * i2 * invHi;
         const int cnt = valid ? L.cnt[s] : 0;
         const int len = L.len[w];
-        Sums<R, 4> acc;  // Vbar, xbar[3]; per-pair compensation keeps the register count at 3 waves/SIMD
+        ChunkSums<R, 4> acc;  // Vbar, xbar[3]
         acc.zero();
         staged_list<RecMom<R>, kOff32, false>(  // measured faster with fixed LDS addresses
             L, w, cnt, len, mrec, stage_buf + wave_in_block() * kStage,
-            [&](const RecMom<R>& rj, int) __attribute__((always_inline)) {
+            [&](const RecMom<R>& rj, int k) __attribute__((always_inline)) {
                 const R x[3] = {sep<R>(ri.q[0], rj.q[0]), sep<R>(ri.q[1], rj.q[1]), sep<R>(ri.q[2], rj.q[2])};
                 const R y[3] = {-x[0], -x[1], -x[2]};
                 const R r = dsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
@@ -604,7 +590,9 @@ __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, c
                 acc.add(0, Phi);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) acc.add(1 + c, xb[c] - Vi * g[c]);
+                acc.next(k, chunk);
             });
+        acc.fold();
         if (valid) {
             const int i = perm[s];
             // j = i term of the own moments: V_i phi(0) = V_i W(0) P0
@@ -738,7 +726,7 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
         auto kern = off32<RecMom<R>>(L) ? k_moments_adj<R, true> : k_moments_adj<R, false>;
         hipLaunchKernelGGL(kern, grid, block, stage_bytes<RecMom<R>>(bw), st, q, n, lists(L),
                            L->perm, mrec, vpbar, static_cast<const R*>(g->m), static_cast<const R*>(g->u),
-                           rho, gm1, xbar, varec, gu);
+                           rho, gm1, L->tune.kahan_chunk, xbar, varec, gu);
     }
     LAUNCH_CHECK("moments adjoint");
     reset_queue(L, st);
