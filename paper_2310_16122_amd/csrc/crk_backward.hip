@@ -452,9 +452,14 @@ template <class R> __device__ __forceinline__ void cubic_grad(const R* k, const 
            R(3) * k[9] * Y2[5];
 }
 
-// Phi(y) and grad Phi(y) from the 29 coefficients
+// Phi(y) and grad Phi(y) from the 29 coefficients of a particle, stored
+// pre-multiplied by its kernel normalisations (c[0..9] by cW, c[10..28] by
+// cF), so that with the bare shapes w, f, f2 at q = |y|/H and s2 = 1/H^2:
+//   Phi = w P + f Q,  grad = w dP + f dQ + s2 (a f P + b f2 Q) y,
+// a = (cF / cW) H^2 = -56/3 and b = (cF2 / cF) H^2 = -30 for the Wendland C4.
 template <class R>
-__device__ __forceinline__ void moment_phi(const R* c, R W, R F, R F2, const R y[3], R& Phi, R grad[3]) {
+__device__ __forceinline__ void moment_phi(const R* c, R W, R F, R F2, R s2, const R y[3], R& Phi,
+                                           R grad[3]) {
     R Y2[6];
     Y2[0] = y[0] * y[0]; Y2[1] = y[0] * y[1]; Y2[2] = y[0] * y[2];
     Y2[3] = y[1] * y[1]; Y2[4] = y[1] * y[2]; Y2[5] = y[2] * y[2];
@@ -468,7 +473,7 @@ __device__ __forceinline__ void moment_phi(const R* c, R W, R F, R F2, const R y
     const R P = c[0] + c[1] * y[0] + c[2] * y[1] + c[3] * y[2] + R(0.5) * yP2;
     const R Q = c[10] * y[0] + c[11] * y[1] + c[12] * y[2] + R(0.5) * yQ2 + yQ3 * R(1.0 / 3.0);
     Phi = W * P + F * Q;
-    const R radial = P * F + Q * F2;
+    const R radial = s2 * (R(-56.0 / 3.0) * F * P + R(-30.0) * F2 * Q);
 #pragma unroll
     for (int e = 0; e < 3; ++e)
         grad[e] = W * (c[1 + e] + gP2[e]) + F * (c[10 + e] + gQ2[e] + gQ3[e]) + radial * y[e];
@@ -497,7 +502,11 @@ __device__ inline void moments_adjoint_record(int s, const double M[40], int nnb
     r.q[0] = q.x; r.q[1] = q.y; r.q[2] = q.z;
     r.invH = aux[2 * s];
     r.V = aux[2 * s + 1];
-    for (int e = 0; e < 29; ++e) r.c[e] = R(c[e]);
+    // pre-multiplied by the kernel normalisations of h_s (see moment_phi)
+    const double ih = double(r.invH);
+    const double cW = 495.0 / (32.0 * kPi) * ih * ih * ih;
+    const double cF = -1155.0 / (4.0 * kPi) * ih * ih * ih * ih * ih;
+    for (int e = 0; e < 29; ++e) r.c[e] = R(c[e] * (e < 10 ? cW : cF));
     mrec[s] = r;
 }
 
@@ -561,9 +570,7 @@ __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, c
         const RecMom<R> ri = mrec[valid ? s : 0];
         const R invHi = ri.invH, Vi = ri.V;
         const R i2 = invHi * invHi;
-        const R cWi = R(495.0 / (32.0 * kPi)) * i2 * invHi;
-        const R cFi = R(-1155.0 / (4.0 * kPi)) * i2 * i2 * invHi;
-        const R cF2i = R(17325.0 / (2.0 * kPi)) * i2 * i2 * i2 * invHi;
+
         const int cnt = valid ? L.cnt[s] : 0;
         const int len = L.len[w];
         ChunkSums<R, 4> acc;  // Vbar, xbar[3]
@@ -578,15 +585,13 @@ __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, c
                 // own moments: M_i contains V_j phi(x_ij, h_i)
                 shapes(r * invHi, w_, f_, f2_);
                 R Phi, g[3];
-                moment_phi(ri.c, cWi * w_, cFi * f_, cF2i * f2_, x, Phi, g);
+                moment_phi(ri.c, w_, f_, f2_, i2, x, Phi, g);
                 const R xb[3] = {rj.V * g[0], rj.V * g[1], rj.V * g[2]};
                 // the neighbour's moments contain V_i phi(x_ji, h_j)
                 const R invHj = rj.invH;
                 const R j2 = invHj * invHj;
                 shapes(r * invHj, w_, f_, f2_);
-                moment_phi(rj.c, R(495.0 / (32.0 * kPi)) * j2 * invHj * w_,
-                           R(-1155.0 / (4.0 * kPi)) * j2 * j2 * invHj * f_,
-                           R(17325.0 / (2.0 * kPi)) * j2 * j2 * j2 * invHj * f2_, y, Phi, g);
+                moment_phi(rj.c, w_, f_, f2_, j2, y, Phi, g);
                 acc.add(0, Phi);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) acc.add(1 + c, xb[c] - Vi * g[c]);
@@ -596,7 +601,7 @@ __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, c
         if (valid) {
             const int i = perm[s];
             // j = i term of the own moments: V_i phi(0) = V_i W(0) P0
-            const double Vbar = double(acc.get(0)) + double(cWi) * double(ri.c[0]) + double(vpbar[2 * s]);
+            const double Vbar = double(acc.get(0)) + double(ri.c[0]) + double(vpbar[2 * s]);
             const double Pbar = double(vpbar[2 * s + 1]);
             const double rhobar = double(gm1) * double(u[i]) * Pbar;
             const double Sbar = -Vbar * double(Vi) * double(Vi) + double(m[i]) * rhobar;
