@@ -189,15 +189,14 @@ struct Lists {
 
 
 // Neighbour-list loop of one lane with software-pipelined loads: the data of
-// entry k+1 and the list indices of entries k+2, k+3 are requested before
-// entry k is processed, so the two dependent memory round trips per neighbour
-// overlap the arithmetic.  The loop is unrolled by two with ping-pong buffers
-// and every load is unconditional: slots past a lane's count hold a valid
-// index (the list build pads them with the lane's own particle) and slot
-// numbers are clamped to the tile's last slot, so no record is copied between
-// iterations.  lst points at the lane's slot 0 (slot k at lst[64 k]); len is
-// the tile's longest list; load(j) fetches neighbour j's data; body(d, k) runs
-// for k < cnt.
+// entries k+2 and k+3 and the list indices of entries k+4 and k+5 are
+// requested before entries k and k+1 are processed, so the two dependent
+// memory round trips per neighbour overlap two entries' arithmetic.  The loop
+// is unrolled by two and every load is unconditional: slots past a lane's
+// count hold a valid index (the list build pads them with the lane's own
+// particle) and slot numbers are clamped to the tile's last slot.  lst points
+// at the lane's slot 0 (slot k at lst[64 k]); len is the tile's longest list;
+// load(j) fetches neighbour j's data; body(d, k) runs for k < cnt.
 template <class D, class Load, class Body>
 __device__ __forceinline__ void pipelined_list(const uint32_t* __restrict__ lst, int cnt, int len,
                                                Load load, Body body) {
@@ -207,15 +206,18 @@ __device__ __forceinline__ void pipelined_list(const uint32_t* __restrict__ lst,
     auto slot = [&](int k) __attribute__((always_inline)) {
         return lst[int64_t(k < last ? k : last) * kWave];
     };
-    D dA = load(slot(0));
-    uint32_t jB = slot(1);
+    D dA = load(slot(0)), dB = load(slot(1));
+    uint32_t jC = slot(2), jD = slot(3);
     for (int k = 0; k < len; k += 2) {
-        const uint32_t jC = slot(k + 2);
-        const D dB = load(jB);
+        const uint32_t jE = slot(k + 4), jF = slot(k + 5);
+        const D dC = load(jC);
         if (k < cnt) body(dA, k);
-        jB = slot(k + 3);
-        dA = load(jC);
+        const D dD = load(jD);
         if (k + 1 < cnt) body(dB, k + 1);
+        dA = dC;
+        dB = dD;
+        jC = jE;
+        jD = jF;
     }
 }
 
