@@ -96,7 +96,8 @@ typedef struct crk_leaves crk_leaves;
 typedef struct {
     int persistent;      /* 1: persistent grid draining an atomic work queue; 0: one tile per wave */
     int waves_per_cu;    /* persistent grid size = CUs * waves_per_cu waves */
-    int kahan_chunk;     /* FP32 pair sums (all passes): plain sums over this many pairs, compensated across chunks (1 = every pair) */
+    int kahan_chunk;     /* FP32 pair sums (all passes): plain sums over this many pairs, compensated across chunks
+                            (1 = every pair); a power of two in [1, 64] */
     int block_waves;     /* waves per workgroup for the list-driven pair passes (1, 2, 4) */
     int xcd_groups;      /* tile order is cut into this many contiguous chunks, one per XCD (1..16) */
     int tile_order;      /* 0: tree order (locality); 1: longest tiles first */
