@@ -459,6 +459,10 @@ def test_invalid_arguments(crk):
     assert e.value.code == -4
     with pytest.raises(crk.CrkError):
         L.set_tuning(block_waves=3)
+    with pytest.raises(crk.CrkError):
+        L.set_tuning(kahan_chunk=3)  # not a power of two
+    with pytest.raises(crk.CrkError):
+        L.set_tuning(addr64=2)
     m = torch.ones(100, dtype=torch.float32, device="cuda")
     with pytest.raises(crk.CrkError):
         crk.sr_gravity(L, x, x, x, m, 1.0, 0.0, r_cut=0.2, prec="f32")  # r_cut > r_fixed
