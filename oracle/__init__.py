@@ -67,6 +67,11 @@ def _load():
         lib.oracle_count_pairs.restype = I64
         lib.oracle_kernel.argtypes = [I64, P, D, P, P]
         lib.oracle_grad.argtypes = [I64] + [P] * 9 + [D, P, P, I64, P, P, D, P, P, P]
+        lib.oracle_flops.argtypes = [P]
+        lib.oracle_flops_selftest.argtypes = [P]
+        lib.oracle_passes_listed.argtypes = [I64] + [P] * 9 + [D] + [P] * 6 + [I64, P, P, P,
+                                                                               ctypes.c_int] + [P] * 4
+        lib.oracle_passes_listed.restype = I64
         _lib = lib
     return _lib
 
@@ -245,3 +250,46 @@ def grad_coordinates(n, n_pos=32, n_vel=16, n_u=16, seed=19):
     kinds = np.concatenate([rng.integers(0, 3, n_pos), rng.integers(3, 6, n_vel),
                             np.full(n_u, 6)]).astype(np.int32)
     return parts, kinds
+
+
+FLOP_KINDS = ("volume", "moments", "accel", "gravity", "gravity_poly", "volume_adj", "moments_adj",
+              "accel_adj")
+
+
+def flops():
+    """FLOP per ordered pair inside each pass's radius, counted on the oracle's
+    own per-pair code with its operation-recording scalar (per-particle work
+    hoisted, common subexpressions once, FMA = 2, sqrt and division 1; the
+    adjoints as the reverse-mode derivative of the pair term with respect to
+    the lane particle's inputs).  Returns {kind: count}."""
+    out = np.zeros(len(FLOP_KINDS))
+    _load().oracle_flops(_p(out))
+    return {k: int(v) for k, v in zip(FLOP_KINDS, out)}
+
+
+def flops_selftest():
+    """Counts of eight small expressions that pin the counting rules
+    (see oracle_flops_selftest in crk_oracle.cpp)."""
+    out = np.zeros(8)
+    _load().oracle_flops_selftest(_p(out))
+    return [int(v) for v in out]
+
+
+def passes_listed(g, targets, off, idx, V, rho, corr, threads=0):
+    """Volume, corrections and accel/energy of the targets over precomputed
+    candidate lists (CSR off/idx, one row per target).  V, rho and corr are the
+    values of all particles the passes read.  Returns (2 x gather pairs,
+    V of the targets, A of the targets, a_x of the targets, du/dt of the targets)."""
+    keys = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "m")
+    arr = [_c(g[k]) for k in keys]
+    V, rho = _c(V), _c(rho)
+    A, B, dA, dB = (_c(c) for c in corr[:4])
+    t = _c(targets, np.int64)
+    off, idx = _c(off, np.int64), _c(idx, np.int64)
+    nt = t.size
+    Vo, Ao, ax, du = (np.empty(nt) for _ in range(4))
+    pairs = _load().oracle_passes_listed(arr[0].size, *[_p(v) for v in arr], float(g["gamma"]),
+                                         _p(V), _p(rho), _p(A), _p(B), _p(dA), _p(dB), nt, _p(t),
+                                         _p(off), _p(idx), int(threads), _p(Vo), _p(Ao), _p(ax),
+                                         _p(du))
+    return int(pairs), Vo, Ao, ax, du

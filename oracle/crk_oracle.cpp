@@ -51,6 +51,8 @@
 #include <cstring>
 #include <vector>
 #include <algorithm>
+#include <map>
+#include <tuple>
 
 #ifdef _OPENMP
 #include <omp.h>
@@ -79,6 +81,200 @@ inline Dual sqrt(Dual a) { double s = std::sqrt(a.v); return {s, s > 0 ? a.d / (
 inline double val(double a) { return a; }
 inline double val(Dual a) { return a.v; }
 using std::sqrt;
+
+// ---------------------------------------------------------------- operation counting
+// Ops records every arithmetic operation into an expression graph (one per
+// thread), so that the oracle's own per-pair code can be counted.  Each value
+// carries the set of particles it depends on (bit 0: the particle whose sums
+// are formed, bits 1 and 2: two of its neighbours).  A value that depends on
+// one particle alone is per-particle work, computed once outside the pair loop;
+// only operations on values that combine two particles are pair work.
+// Identical operations are recorded once (common subexpressions), constants
+// are folded, and the algebraic identities a+0, a*1, a*0, -(-a), and a sign
+// moved out of products, quotients and differences are applied, so that
+// evaluating a quantity from x_ji = -x_ij costs nothing beyond evaluating it
+// from x_ij.  Counting: add, sub, mul, div, sqrt = 1 FLOP each (so a
+// multiply-add is 2); negation is free (a sign on an operand).
+struct OpNode {
+    char op;    // 'L' leaf/constant, '+', '-', '*', '/', 'n' (negate), 's' (sqrt)
+    int a, b;   // operand node ids
+    unsigned mask;
+    double v;
+};
+
+struct OpGraph {
+    std::vector<OpNode> nodes;
+    std::map<std::tuple<char, int, int>, int> memo;
+    std::map<double, int> consts;
+};
+inline OpGraph& op_graph() {
+    static thread_local OpGraph g;
+    return g;
+}
+
+struct Ops {
+    int id;
+    Ops() : Ops(0.0) {}
+    Ops(double c) {
+        OpGraph& g = op_graph();
+        auto it = g.consts.find(c);
+        if (it != g.consts.end()) { id = it->second; return; }
+        id = int(g.nodes.size());
+        g.nodes.push_back({'L', -1, -1, 0u, c});
+        g.consts[c] = id;
+    }
+    static Ops from_id(int i) { Ops o(0.0); o.id = i; return o; }
+    // a new independent input value that depends on the particles in `mask`
+    static Ops leaf(double v, unsigned mask) {
+        OpGraph& g = op_graph();
+        Ops o(0.0);
+        o.id = int(g.nodes.size());
+        g.nodes.push_back({'L', -1, -1, mask, v});
+        return o;
+    }
+    const OpNode& node() const { return op_graph().nodes[id]; }
+    bool is_const(double c) const { return node().op == 'L' && node().mask == 0u && node().v == c; }
+    bool is_const() const { return node().op == 'L' && node().mask == 0u; }
+};
+inline double val(Ops a) { return a.node().v; }
+
+inline Ops op_make(char op, Ops a, Ops b, double v) {
+    OpGraph& g = op_graph();
+    if (a.is_const() && (op == 'n' || op == 's' || b.is_const())) return Ops(v);  // constant folding
+    auto key = std::make_tuple(op, a.id, b.id);
+    auto it = g.memo.find(key);
+    if (it != g.memo.end()) return Ops::from_id(it->second);
+    const unsigned mask = a.node().mask | (b.id >= 0 ? b.node().mask : 0u);
+    const int id = int(g.nodes.size());
+    g.nodes.push_back({op, a.id, b.id, mask, v});
+    g.memo[key] = id;
+    return Ops::from_id(id);
+}
+inline Ops operator-(Ops a) {
+    if (a.node().op == 'n') return Ops::from_id(a.node().a);
+    OpGraph& g = op_graph();
+    if (a.is_const()) return Ops(-val(a));
+    auto key = std::make_tuple('n', a.id, -1);
+    auto it = g.memo.find(key);
+    if (it != g.memo.end()) return Ops::from_id(it->second);
+    const int id = int(g.nodes.size());
+    g.nodes.push_back({'n', a.id, -1, a.node().mask, -val(a)});
+    g.memo[key] = id;
+    return Ops::from_id(id);
+}
+inline bool is_neg(Ops a) { return a.node().op == 'n'; }
+inline Ops un_neg(Ops a) { return Ops::from_id(a.node().a); }
+inline Ops operator*(Ops a, Ops b) {
+    if (a.is_const(0.0) || b.is_const(0.0)) return Ops(0.0);
+    if (a.is_const(1.0)) return b;
+    if (b.is_const(1.0)) return a;
+    if (a.is_const(-1.0)) return -b;
+    if (b.is_const(-1.0)) return -a;
+    if (is_neg(a)) return -(un_neg(a) * b);
+    if (is_neg(b)) return -(a * un_neg(b));
+    if (a.id > b.id) std::swap(a, b);
+    return op_make('*', a, b, val(a) * val(b));
+}
+inline Ops operator/(Ops a, Ops b) {
+    if (a.is_const(0.0)) return Ops(0.0);
+    if (b.is_const(1.0)) return a;
+    if (is_neg(a)) return -(un_neg(a) / b);
+    if (is_neg(b)) return -(a / un_neg(b));
+    return op_make('/', a, b, val(a) / val(b));
+}
+Ops operator-(Ops a, Ops b);
+inline Ops operator+(Ops a, Ops b) {
+    if (a.is_const(0.0)) return b;
+    if (b.is_const(0.0)) return a;
+    if (is_neg(a) && is_neg(b)) return -(un_neg(a) + un_neg(b));
+    if (is_neg(b)) return a - un_neg(b);
+    if (is_neg(a)) return b - un_neg(a);
+    if (a.id > b.id) std::swap(a, b);
+    return op_make('+', a, b, val(a) + val(b));
+}
+inline Ops operator-(Ops a, Ops b) {
+    if (b.is_const(0.0)) return a;
+    if (a.is_const(0.0)) return -b;
+    if (is_neg(b)) return a + un_neg(b);
+    if (is_neg(a)) return -(un_neg(a) + b);
+    if (a.id > b.id) return -(b - a);
+    return op_make('-', a, b, val(a) - val(b));
+}
+inline Ops& operator+=(Ops& a, Ops b) { a = a + b; return a; }
+inline Ops& operator-=(Ops& a, Ops b) { a = a - b; return a; }
+inline bool operator<(Ops a, Ops b) { return val(a) < val(b); }
+inline bool operator>=(Ops a, Ops b) { return val(a) >= val(b); }
+inline Ops sqrt(Ops a) { return op_make('s', a, Ops::from_id(-1), std::sqrt(val(a))); }
+
+inline void op_reset() {
+    OpGraph& g = op_graph();
+    g.nodes.clear();
+    g.memo.clear();
+    g.consts.clear();
+}
+
+// Pair work among the values needed for `roots`: operations whose operands
+// combine the lane particle (bit 0) with a neighbour, or two neighbours.
+inline int64_t pair_flops(const std::vector<Ops>& roots) {
+    const OpGraph& g = op_graph();
+    std::vector<char> seen(g.nodes.size(), 0);
+    std::vector<int> stack;
+    for (const Ops& r : roots) stack.push_back(r.id);
+    int64_t count = 0;
+    while (!stack.empty()) {
+        const int id = stack.back();
+        stack.pop_back();
+        if (id < 0 || seen[id]) continue;
+        seen[id] = 1;
+        const OpNode& nd = g.nodes[id];
+        if (nd.op == 'L') continue;
+        if (nd.op != 'n' && __builtin_popcount(nd.mask) >= 2) ++count;
+        stack.push_back(nd.a);
+        stack.push_back(nd.b);
+    }
+    return count;
+}
+
+// Reverse-mode derivative of `out` with respect to `wanted`, recorded in the
+// same graph: every node's adjoint is formed from its consumers' adjoints in
+// reverse order of creation (the standard adjoint sweep, restricted to nodes
+// that depend on a wanted input).  Returns the adjoint of each wanted input.
+inline std::vector<Ops> reverse_sweep(Ops out, const std::vector<Ops>& wanted) {
+    OpGraph& g = op_graph();
+    const int top = out.id;
+    std::vector<char> active(top + 1, 0);
+    for (const Ops& w : wanted)
+        if (w.id <= top) active[w.id] = 1;
+    for (int id = 0; id <= top; ++id) {
+        const OpNode nd = g.nodes[id];
+        if (nd.op == 'L') continue;
+        active[id] = (nd.a >= 0 && active[nd.a]) || (nd.b >= 0 && active[nd.b]);
+    }
+    std::vector<int> adj(top + 1, -1);  // adjoint node id, -1 = none yet
+    adj[top] = Ops(1.0).id;
+    auto add_to = [&](int target, Ops contrib) {
+        if (target < 0 || !active[target]) return;
+        adj[target] = adj[target] < 0 ? contrib.id : (Ops::from_id(adj[target]) + contrib).id;
+    };
+    for (int id = top; id >= 0; --id) {
+        if (adj[id] < 0 || !active[id]) continue;
+        const OpNode nd = g.nodes[id];
+        const Ops z = Ops::from_id(id), zb = Ops::from_id(adj[id]);
+        const Ops a = Ops::from_id(nd.a), b = Ops::from_id(nd.b);
+        switch (nd.op) {
+            case '+': add_to(nd.a, zb); add_to(nd.b, zb); break;
+            case '-': add_to(nd.a, zb); add_to(nd.b, -zb); break;
+            case 'n': add_to(nd.a, -zb); break;
+            case '*': add_to(nd.a, zb * b); add_to(nd.b, zb * a); break;
+            case '/': add_to(nd.a, zb / b); add_to(nd.b, -(zb * z / b)); break;
+            case 's': add_to(nd.a, zb * (Ops(0.5) / z)); break;
+            default: break;
+        }
+    }
+    std::vector<Ops> res;
+    for (const Ops& w : wanted) res.push_back(w.id <= top && adj[w.id] >= 0 ? Ops::from_id(adj[w.id]) : Ops(0.0));
+    return res;
+}
 
 template <class T> T wrap(T d) {
     if (val(d) >= 0.5) d = d - T(1.0);
@@ -270,6 +466,24 @@ template <class T> void corrected_gradient(const Corr<T>& C, const T x[3], T W, 
     }
 }
 
+// One ordered pair of the force pass: F_ij and F_ij . (v_i - v_j).
+template <class T> void accel_pair(const Gas<T>& g, const T* V, const T* rho, const Corr<T>* C,
+                                   double gamma, int64_t i, int64_t j, const Sep<T>& s, const T& Pi,
+                                   T F[3], T& Fdotv) {
+    const T Pj = T(gamma - 1.0) * rho[j] * g.u[j];
+    T xji[3] = {-s.d[0], -s.d[1], -s.d[2]};
+    T Gij[3], Gji[3];
+    corrected_gradient(C[i], s.d, kernel_W(s.r, g.h[i]), kernel_F(s.r, g.h[i]), Gij);
+    corrected_gradient(C[j], xji, kernel_W(s.r, g.h[j]), kernel_F(s.r, g.h[j]), Gji);
+    const T coef = T(-0.5) * V[i] * V[j] * (Pi + Pj);
+    T vij[3] = {g.vx[i] - g.vx[j], g.vy[i] - g.vy[j], g.vz[i] - g.vz[j]};
+    Fdotv = T(0.0);
+    for (int cc = 0; cc < 3; ++cc) {
+        F[cc] = coef * (Gij[cc] - Gji[cc]);
+        Fdotv += F[cc] * vij[cc];
+    }
+}
+
 template <class T> void accel_one(const Gas<T>& g, const T* V, const T* rho, const Corr<T>* C,
                                   double gamma, int64_t i, Cand c, T a[3], T& dudt) {
     const T Pi = T(gamma - 1.0) * rho[i] * g.u[i];
@@ -281,24 +495,34 @@ template <class T> void accel_one(const Gas<T>& g, const T* V, const T* rho, con
         Sep<T> s = separation(g, i, j);
         const double Hi = 2.0 * g.h[i], Hj = 2.0 * g.h[j];
         if (!(val(s.r) < std::max(Hi, Hj))) continue;
-        const T Pj = T(gamma - 1.0) * rho[j] * g.u[j];
-        T xji[3] = {-s.d[0], -s.d[1], -s.d[2]};
-        T Gij[3], Gji[3];
-        corrected_gradient(C[i], s.d, kernel_W(s.r, g.h[i]), kernel_F(s.r, g.h[i]), Gij);
-        corrected_gradient(C[j], xji, kernel_W(s.r, g.h[j]), kernel_F(s.r, g.h[j]), Gji);
-        const T coef = T(-0.5) * V[i] * V[j] * (Pi + Pj);
-        T vij[3] = {g.vx[i] - g.vx[j], g.vy[i] - g.vy[j], g.vz[i] - g.vz[j]};
-        T Fdotv = T(0.0);
-        for (int cc = 0; cc < 3; ++cc) {
-            T Fc = coef * (Gij[cc] - Gji[cc]);
-            a[cc] += Fc;
-            Fdotv += Fc * vij[cc];
-        }
+        T F[3], Fdotv;
+        accel_pair(g, V, rho, C, gamma, i, j, s, Pi, F, Fdotv);
+        for (int cc = 0; cc < 3; ++cc) a[cc] += F[cc];
         dudt += Fdotv;
     }
     const T mi = T(g.m[i]);
     for (int cc = 0; cc < 3; ++cc) a[cc] = a[cc] / mi;
     dudt = T(-0.5) * dudt / mi;
+}
+
+// ---------------------------------------------------------------- gravity
+// a_i for j != i with r_ij < r_c over the candidates (all species).
+template <class T> void gravity_one(const Gas<T>& g, const T* m, double G, double eps, double r_cut,
+                                    const double* poly, int64_t i, Cand c, T a[3]) {
+    a[0] = a[1] = a[2] = T(0.0);
+    for (int64_t k = 0; k < c.n; ++k) {
+        const int64_t j = c.at(k);
+        if (j == i) continue;
+        Sep<T> s = separation(g, i, j);
+        if (!(val(s.r) < r_cut)) continue;
+        const T r2 = s.r * s.r;
+        T f = T(1.0) / ((r2 + T(eps * eps)) * sqrt(r2 + T(eps * eps)));
+        if (poly) {
+            T rk = T(1.0);
+            for (int p = 0; p < 6; ++p) { f -= T(poly[p]) * rk; rk = rk * r2; }
+        }
+        for (int cc = 0; cc < 3; ++cc) a[cc] -= T(G) * m[j] * s.d[cc] * f;
+    }
 }
 
 // ---------------------------------------------------------------- closure
@@ -414,6 +638,174 @@ T cone_loss(const Gas<T>& g, const NbrLists& nb, const Cone& c, double gamma, co
     }
     return L;
 }
+
+
+// ---------------------------------------------------------------- operation counts per pair
+// The algorithmic work of each pass per ordered pair inside its radius, counted
+// on the oracle's own code with the Ops scalar: the pass is evaluated for one
+// lane particle with one neighbour and with two neighbours, and the pair work
+// of the second minus that of the first is the cost of one more pair (the
+// accumulation into the lane's sums included, per-particle work excluded).
+//
+// The adjoint passes are counted as the reverse-mode derivative of the pair's
+// contribution to a loss, with respect to the lane particle's own inputs (the
+// gather form: every lane accumulates its own adjoints only):
+//   volume adjoint   l = sum_j [Sb_i W(r_ij, h_i) + Sb_j W(r_ij, h_j)],  d/dx_i
+//   moments adjoint  l = Mb_i . M_i + sum_j Mb_j . (V_i phi(x_ji, h_j)),  d/dx_i, d/dV_i
+//   force adjoint    l = sum_j [F_ij . (ab_i/m_i - ab_j/m_j)
+//                               - (db_i/2m_i + db_j/2m_j) F_ij . (v_i - v_j)]
+//                    with respect to x_i, v_i, V_i, rho_i, u_i and A_i, B_i, dA_i, dB_i
+// where Sb, Mb, ab, db are the upstream adjoints (per-particle inputs), phi the
+// 40 moment integrands of the moments pass, and the force adjoint's l is the
+// pair's whole share of L = sum_k ab_k . a_k + db_k du_k/dt (F_ji = -F_ij).
+namespace flops {
+
+constexpr int kMaxP = 3;  // the lane particle and up to two neighbours
+
+struct Setup {
+    int np;
+    std::vector<Ops> x, y, z, vx, vy, vz, u, V, rho, m;
+    std::vector<double> h, md;
+    std::vector<Corr<Ops>> C;
+    Gas<Ops> g;
+};
+
+Setup make(int nbrs) {
+    op_reset();
+    const double px[kMaxP] = {0.5, 0.521, 0.482}, py[kMaxP] = {0.5, 0.493, 0.514},
+                 pz[kMaxP] = {0.5, 0.507, 0.491};
+    Setup s;
+    s.np = nbrs + 1;
+    for (int p = 0; p < s.np; ++p) {
+        const unsigned mk = 1u << p;
+        auto L = [&](double v) { return Ops::leaf(v, mk); };
+        s.x.push_back(L(px[p])); s.y.push_back(L(py[p])); s.z.push_back(L(pz[p]));
+        s.vx.push_back(L(0.01 * (p + 1))); s.vy.push_back(L(-0.02 * p)); s.vz.push_back(L(0.015));
+        s.u.push_back(L(1.0 + 0.1 * p));
+        s.V.push_back(L(1.0e-3 * (1.0 + 0.05 * p)));
+        s.rho.push_back(L(1.0 + 0.02 * p));
+        s.m.push_back(L(1.0e-3));
+        s.h.push_back(0.05 + 0.002 * p);
+        s.md.push_back(1.0e-3);
+        Corr<Ops> c;
+        c.A = L(1.0 + 0.01 * p);
+        for (int a = 0; a < 3; ++a) {
+            c.B[a] = L(0.1 * (a + 1));
+            c.dA[a] = L(0.2 * (a - 1));
+            for (int b = 0; b < 3; ++b) c.dB[a][b] = L(0.05 * (a + 2 * b + 1));
+        }
+        s.C.push_back(c);
+    }
+    s.g.n = s.np;
+    s.g.x = s.x.data(); s.g.y = s.y.data(); s.g.z = s.z.data();
+    s.g.vx = s.vx.data(); s.g.vy = s.vy.data(); s.g.vz = s.vz.data(); s.g.u = s.u.data();
+    s.g.h = s.h.data(); s.g.m = s.md.data();
+    return s;
+}
+
+int64_t volume(int nbrs) {
+    Setup s = make(nbrs);
+    return pair_flops({volume_sum(s.g, 0, Cand{nullptr, s.np})});
+}
+
+int64_t moments(int nbrs) {
+    Setup s = make(nbrs);
+    Moments<Ops> M;
+    moments_one(s.g, s.V.data(), 0, Cand{nullptr, s.np}, M);
+    std::vector<Ops> roots{M.m0};
+    for (int a = 0; a < 3; ++a) { roots.push_back(M.m1[a]); roots.push_back(M.g0[a]); }
+    for (int p = 0; p < 6; ++p) {
+        roots.push_back(M.m2[p]);
+        for (int c = 0; c < 3; ++c) roots.push_back(M.g2[p][c]);
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) roots.push_back(M.g1[a][c]);
+    return pair_flops(roots);
+}
+
+int64_t accel(int nbrs) {
+    Setup s = make(nbrs);
+    Ops a[3], du;
+    accel_one(s.g, s.V.data(), s.rho.data(), s.C.data(), 5.0 / 3.0, 0, Cand{nullptr, s.np}, a, du);
+    return pair_flops({a[0], a[1], a[2], du});
+}
+
+int64_t gravity(int nbrs, bool poly) {
+    Setup s = make(nbrs);
+    const double p6[6] = {1.0, -2.0, 3.0, 0.5, -0.25, 0.125};
+    Ops a[3];
+    gravity_one(s.g, s.m.data(), 1.0, 1e-3, 0.2, poly ? p6 : nullptr, 0, Cand{nullptr, s.np}, a);
+    return pair_flops({a[0], a[1], a[2]});
+}
+
+int64_t volume_adj(int nbrs) {
+    Setup s = make(nbrs);
+    std::vector<Ops> Sb;
+    for (int p = 0; p < s.np; ++p) Sb.push_back(Ops::leaf(0.3 + 0.1 * p, 1u << p));
+    Ops l(0.0);
+    for (int j = 1; j < s.np; ++j) {
+        Sep<Ops> sp = separation(s.g, 0, j);
+        l += Sb[0] * kernel_W(sp.r, s.h[0]) + Sb[j] * kernel_W(sp.r, s.h[j]);
+    }
+    return pair_flops(reverse_sweep(l, {s.x[0], s.y[0], s.z[0]}));
+}
+
+std::vector<Ops> moment_list(const Moments<Ops>& M) {
+    std::vector<Ops> r{M.m0};
+    for (int a = 0; a < 3; ++a) r.push_back(M.m1[a]);
+    for (int p = 0; p < 6; ++p) r.push_back(M.m2[p]);
+    for (int a = 0; a < 3; ++a) r.push_back(M.g0[a]);
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) r.push_back(M.g1[a][c]);
+    for (int p = 0; p < 6; ++p)
+        for (int c = 0; c < 3; ++c) r.push_back(M.g2[p][c]);
+    return r;
+}
+
+int64_t moments_adj(int nbrs) {
+    Setup s = make(nbrs);
+    Ops l(0.0);
+    for (int p = 0; p < s.np; ++p) {
+        std::vector<Ops> Mb;
+        for (int k = 0; k < 40; ++k) Mb.push_back(Ops::leaf(0.01 * (k + 1) + 0.1 * p, 1u << p));
+        Moments<Ops> M;
+        const int64_t lane = 0;
+        if (p == 0) moments_one(s.g, s.V.data(), 0, Cand{nullptr, s.np}, M);
+        else moments_one(s.g, s.V.data(), p, Cand{&lane, 1}, M);
+        const std::vector<Ops> ml = moment_list(M);
+        for (int k = 0; k < 40; ++k) l += Mb[k] * ml[k];
+    }
+    return pair_flops(reverse_sweep(l, {s.x[0], s.y[0], s.z[0], s.V[0]}));
+}
+
+int64_t accel_adj(int nbrs) {
+    Setup s = make(nbrs);
+    std::vector<std::vector<Ops>> w(s.np);
+    std::vector<Ops> kap;
+    for (int p = 0; p < s.np; ++p) {
+        for (int c = 0; c < 3; ++c) w[p].push_back(Ops::leaf(0.2 * (c + 1) - 0.1 * p, 1u << p));
+        kap.push_back(Ops::leaf(0.05 + 0.01 * p, 1u << p));
+    }
+    const Ops Pi = Ops(5.0 / 3.0 - 1.0) * s.rho[0] * s.u[0];
+    Ops l(0.0);
+    for (int j = 1; j < s.np; ++j) {
+        Sep<Ops> sp = separation(s.g, 0, j);
+        Ops F[3], Fv;
+        accel_pair(s.g, s.V.data(), s.rho.data(), s.C.data(), 5.0 / 3.0, 0, j, sp, Pi, F, Fv);
+        for (int c = 0; c < 3; ++c) l += F[c] * (w[0][c] - w[j][c]);
+        l -= (kap[0] + kap[j]) * Fv;
+    }
+    std::vector<Ops> wanted{s.x[0], s.y[0], s.z[0], s.vx[0], s.vy[0], s.vz[0], s.V[0], s.rho[0], s.u[0],
+                            s.C[0].A};
+    for (int a = 0; a < 3; ++a) {
+        wanted.push_back(s.C[0].B[a]);
+        wanted.push_back(s.C[0].dA[a]);
+        for (int c = 0; c < 3; ++c) wanted.push_back(s.C[0].dB[a][c]);
+    }
+    return pair_flops(reverse_sweep(l, wanted));
+}
+
+}  // namespace flops
 
 }  // namespace
 
@@ -633,19 +1025,8 @@ int oracle_gravity(int64_t n, const double* x, const double* y, const double* z,
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t k = 0; k < cnt; ++k) {
         const int64_t i = targets ? targets[k] : k;
-        double a[3] = {0.0, 0.0, 0.0};
-        for (int64_t j = 0; j < n; ++j) {
-            if (j == i) continue;
-            Sep<double> s = separation(g, i, j);
-            if (!(s.r < r_cut)) continue;
-            const double r2 = s.r * s.r;
-            double f = 1.0 / ((r2 + eps * eps) * std::sqrt(r2 + eps * eps));
-            if (poly) {
-                double rk = 1.0;
-                for (int p = 0; p < 6; ++p) { f -= poly[p] * rk; rk *= r2; }
-            }
-            for (int c = 0; c < 3; ++c) a[c] -= G * m[j] * s.d[c] * f;
-        }
+        double a[3];
+        gravity_one(g, m, G, eps, r_cut, poly, i, Cand{nullptr, n}, a);
         ax[k] = a[0]; ay[k] = a[1]; az[k] = a[2];
     }
     return 0;
@@ -674,6 +1055,98 @@ int64_t oracle_count_pairs(int64_t n, const double* x, const double* y, const do
         total += c;
     }
     return total;
+}
+
+
+// FLOP per ordered pair inside the pass radius, counted on the oracle's code
+// (see the flops namespace): [volume, moments, accel, gravity, gravity with the
+// polynomial term, volume adjoint, moments adjoint, force adjoint].
+void oracle_flops(double* out) {
+    using namespace flops;
+    out[0] = double(volume(2) - volume(1));
+    out[1] = double(moments(2) - moments(1));
+    out[2] = double(accel(2) - accel(1));
+    out[3] = double(gravity(2, false) - gravity(1, false));
+    out[4] = double(gravity(2, true) - gravity(1, true));
+    out[5] = double(volume_adj(2) - volume_adj(1));
+    out[6] = double(moments_adj(2) - moments_adj(1));
+    out[7] = double(accel_adj(2) - accel_adj(1));
+    op_reset();
+}
+
+// Counts of small expressions, which pin the counting rules (a, c depend on the
+// lane particle, b and e on a neighbour):
+//   [0] a*b + c   [1] (a*c)*b   [2] (a-b)*(a-b) + (a-b)*(a-b)   [3] {(a-b)^2, (b-a)^2}
+//   [4] d/da of (a*b)*(a*b)   [5] sqrt(a*b)/c   [6] d/da of sqrt(a - b)   [7] e*b
+void oracle_flops_selftest(double* out) {
+    auto run = [](int k) -> int64_t {
+        op_reset();
+        const Ops a = Ops::leaf(1.5, 1u), c = Ops::leaf(0.7, 1u), b = Ops::leaf(0.25, 2u),
+                  e = Ops::leaf(2.0, 2u);
+        switch (k) {
+            case 0: return pair_flops({a * b + c});
+            case 1: return pair_flops({(a * c) * b});
+            case 2: { const Ops d = a - b; return pair_flops({d * d + d * d}); }
+            case 3: { const Ops d = a - b, f = b - a; return pair_flops({d * d, f * f}); }
+            case 4: { const Ops t = a * b; return pair_flops(reverse_sweep(t * t, {a})); }
+            case 5: return pair_flops({sqrt(a * b) / c});
+            case 6: return pair_flops(reverse_sweep(sqrt(a - b), {a}));
+            case 7: return pair_flops({e * b});
+        }
+        return -1;
+    };
+    for (int k = 0; k < 8; ++k) out[k] = double(run(k));
+    op_reset();
+}
+
+
+// The three hydro passes for target particles over precomputed candidate
+// lists (CSR: the candidates of targets[k] are idx[off[k] .. off[k+1])), for
+// timing the oracle's arithmetic without its brute-force search.  Each pass
+// still tests its own radius on every candidate.  V, rho and the corrections
+// of all n particles are inputs (the volume and corrections outputs of the
+// targets are written to V_o, A_o, ax, dudt).  Returns the number of in-radius
+// ordered pairs of the volume and moments passes (2 x those with r < 2h_i);
+// the force pass evaluates the pairs with r < 2 max(h_i, h_j) among the
+// candidates (all of them when the lists hold exactly those).
+int64_t oracle_passes_listed(int64_t n, const double* x, const double* y, const double* z,
+                             const double* vx, const double* vy, const double* vz, const double* u,
+                             const double* h, const double* m, double gamma, const double* V,
+                             const double* rho, const double* A, const double* B, const double* dA,
+                             const double* dB, int64_t nt, const int64_t* targets, const int64_t* off,
+                             const int64_t* idx, int threads, double* V_o, double* A_o, double* ax,
+                             double* dudt) {
+    Gas<double> g = make_gas(n, x, y, z, vx, vy, vz, u, h, m);
+    std::vector<Corr<double>> C(n);
+    for (int64_t i = 0; i < n; ++i) {
+        C[i].A = A[i];
+        for (int a = 0; a < 3; ++a) {
+            C[i].B[a] = B[3 * i + a];
+            C[i].dA[a] = dA[3 * i + a];
+            for (int c = 0; c < 3; ++c) C[i].dB[a][c] = dB[9 * i + 3 * a + c];
+        }
+    }
+    int64_t pairs = 0;
+#ifdef _OPENMP
+    const int nth = threads > 0 ? threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : pairs) num_threads(nth)
+#endif
+    for (int64_t k = 0; k < nt; ++k) {
+        const int64_t i = targets[k];
+        const Cand c{idx + off[k], off[k + 1] - off[k]};
+        V_o[k] = 1.0 / volume_sum(g, i, c);
+        Moments<double> M;
+        moments_one(g, V, i, c, M);
+        Corr<double> Ci;
+        solve_corrections(M, Ci);
+        A_o[k] = Ci.A;
+        double a[3], du;
+        accel_one(g, V, rho, C.data(), gamma, i, c, a, du);
+        ax[k] = a[0];
+        dudt[k] = du;
+        pairs += 2 * int64_t(M.nnb);
+    }
+    return pairs;
 }
 
 // Kernel values for pinning: W(r, h) and F(r, h) at n radii.

@@ -335,3 +335,109 @@ def test_gradient_dual_matches_cone_finite_differences(oracle_lib):
     # cones of positions are nested: D1 inside D2 inside D3
     pos = kinds < 3
     assert np.all(cs[pos, 0] <= cs[pos, 1]) and np.all(cs[pos, 1] <= cs[pos, 2])
+
+
+# ---------------------------------------------------------------- pair counts
+def test_count_pairs_against_dense_masks(tiny, oracle_lib):
+    """Ordered pairs j != i inside each pass's radius, against dense masks:
+    mode 0 r < 2h_i, mode 1 r < 2 max(h_i, h_j), mode 2 r < r_fixed; totals
+    and per-particle counts, for all particles and for a sample."""
+    g, _, _ = tiny
+    _, r = dense_crk.separations(g)
+    H = 2.0 * g["h"]
+    off = ~np.eye(g["n"], dtype=bool)
+    masks = {0: (r < H[:, None]) & off,
+             1: (r < np.maximum(H[:, None], H[None, :])) & off,
+             2: (r < 0.1) & off}
+    # mode 1 differs from mode 0 on this set (variable h), so a swapped radius shows
+    assert masks[1].sum() > masks[0].sum()
+    t = synth.sample_targets(g["n"], 37, seed=4)
+    for mode, mk in masks.items():
+        tot, per = oracle_lib.count_pairs(g, mode, r_fixed=0.1)
+        assert tot == mk.sum(), mode
+        assert np.array_equal(per, mk.sum(1)), mode
+        tot_t, per_t = oracle_lib.count_pairs(g, mode, targets=t, r_fixed=0.1)
+        assert np.array_equal(per_t, mk[t].sum(1)) and tot_t == mk[t].sum(), mode
+
+
+def test_count_pairs_on_the_support_boundary(oracle_lib):
+    """A pair exactly at distance 2h (or r_fixed) is outside: the radius test is strict."""
+    x = synth.grid_round(np.array([0.25, 0.25 + 0.0625]))
+    g = dict(x=x, y=np.full(2, 0.5), z=np.full(2, 0.5), h=np.array([0.03125, 0.015625]))
+    assert oracle_lib.count_pairs(g, 0)[0] == 0   # r = 2 h_0 exactly
+    assert oracle_lib.count_pairs(g, 1)[0] == 0   # r = 2 max(h) exactly
+    g["h"] = np.array([0.03125 + 2.0 ** -20, 0.015625])
+    assert list(oracle_lib.count_pairs(g, 0)[1]) == [1, 0]  # inside 2h_0 only
+    assert oracle_lib.count_pairs(g, 1)[0] == 2             # both see the pair in 2 max(h)
+    assert oracle_lib.count_pairs(g, 2, r_fixed=0.0625)[0] == 0
+    assert oracle_lib.count_pairs(g, 2, r_fixed=0.0625 + 2.0 ** -20)[0] == 2
+
+
+# ---------------------------------------------------------------- operation counts
+def test_operation_counter_rules(oracle_lib):
+    """The counting scalar on small expressions whose counts follow from its
+    stated rules (a, c: lane particle; b, e: a neighbour):
+    a*b + c -> 2; (a*c)*b -> 1 (a*c is per-particle); (a-b)^2 + (a-b)^2 -> 3
+    (sub, mul once, add); {(a-b)^2, (b-a)^2} -> 2 (the sign is free); d/da of
+    (a*b)^2 -> 3 (t = a*b, t + t, (t + t)*b); sqrt(a*b)/c -> 3; d/da of
+    sqrt(a-b) -> 3 (sub, sqrt, 0.5/z); e*b -> 0 (one neighbour alone)."""
+    assert oracle_lib.flops_selftest() == [2, 1, 3, 2, 3, 3, 3, 0]
+
+
+def test_operation_counts_of_volume_and_gravity_by_hand(oracle_lib):
+    """The counted per-pair work of the two simplest passes equals a count by
+    hand of the formulas in crk_oracle.cpp.
+    Volume: separation 3, r^2 5, sqrt 1, q = r/H 1, t = 1 - q 1, t^2 1, t^6 2,
+    1 + 6q + 35q^2/3 5, norm * t^6 * poly 2, accumulation 1 = 22.
+    Gravity: separation 3, r^2 5, sqrt 1, r*r 1, + eps^2 1, sqrt 1, product 1,
+    reciprocal 1, per component (G m_j) x f and accumulation 3 x 3 = 23; the
+    polynomial in r^2 adds p_0 1 and, for k = 1..5, p_k r^2k 1, subtraction 1
+    and the next power 1 (none after k = 5): 1 + 4 x 3 + 2 = 15."""
+    f = oracle_lib.flops()
+    assert f["volume"] == 22
+    assert f["gravity"] == 23
+    assert f["gravity_poly"] == 23 + 15
+
+
+def test_operation_counts_ordering(oracle_lib):
+    """Every pass adds work per pair, the force pass needs the gradients of
+    two corrected kernels (more than the moments' shape functions), and each
+    adjoint costs more than its forward pass."""
+    f = oracle_lib.flops()
+    assert all(v > 0 for v in f.values())
+    assert f["volume_adj"] > f["volume"] and f["moments_adj"] > f["moments"]
+    assert f["accel_adj"] > f["accel"] > 2 * f["volume"]
+
+
+def test_flop_table_is_current(oracle_lib):
+    """oracle/flop_per_pair.json (read by the benchmark) is what the oracle counts now."""
+    import json
+    import os
+
+    from oracle import flop_table
+
+    with open(flop_table.TABLE) as fh:
+        stored = json.load(fh)
+    assert stored["flop_per_pair"] == oracle_lib.flops()
+
+
+# ---------------------------------------------------------------- listed passes (CPU baseline)
+def test_passes_over_lists_match_brute_force(tiny, oracle_lib):
+    """The listed form of the three passes (exact candidate lists r < 2 max(h))
+    gives the brute-force values of the targets and counts their gather pairs."""
+    g, o, _ = tiny
+    _, r = dense_crk.separations(g)
+    H = 2.0 * g["h"]
+    mask = (r < np.maximum(H[:, None], H[None, :])) & ~np.eye(g["n"], dtype=bool)
+    t = synth.sample_targets(g["n"], 50, seed=6)
+    rows = [np.nonzero(mask[i])[0] for i in t]
+    off = np.concatenate([[0], np.cumsum([len(x) for x in rows])])
+    idx = np.concatenate(rows)
+    corr = (o["A"], o["B"], o["dA"], o["dB"])
+    for threads in (0, 1):
+        pairs, V, A, ax, du = oracle_lib.passes_listed(g, t, off, idx, o["V"], o["rho"], corr, threads)
+        assert pairs == 2 * oracle_lib.count_pairs(g, 0, targets=t)[0]
+        assert np.abs(V - o["V"][t]).max() <= 1e-14 * np.abs(o["V"]).max()
+        assert np.abs(A - o["A"][t]).max() <= 1e-12 * np.abs(o["A"]).max()
+        assert np.abs(ax - o["a"][t, 0]).max() <= 1e-12 * np.abs(o["a"]).max()
+        assert np.abs(du - o["dudt"][t]).max() <= 1e-12 * np.abs(o["dudt"]).max()
