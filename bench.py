@@ -3,21 +3,25 @@
 
 One step = one pass of the hot path over one synthetic particle set already
 resident in HBM: for the CRK workloads the position packing, the volume pass,
-the corrections pass (40 moments + FP64 solve), the fused acceleration /
-energy pass with FP64 totals, and the backward (force, moments and volume
-adjoints, with the moments recomputed); for the gravity workload one
-short-range gravity evaluation.  The tree and the neighbour lists are built
-once before the timed region (reported separately as build time); particles
-are held in tree order.  The launch/tiling choices are autotuned first.
+the corrections pass (40 moments + FP64 solve; the moment sums are kept for
+the backward), the fused acceleration / energy pass with FP64 totals, and the
+backward (force adjoint, the solve adjoint from the stored sums, moments and
+volume adjoints); for the gravity workload one short-range gravity
+evaluation.  The tree and the neighbour lists are built once before the timed
+region (reported separately as build time); particles are held in tree order.
+The launch/tiling choices are autotuned first.
 
-The default run measures the CRK step on C2 (the headline line) and then the
-gravity step on its own workload (C3, gas + dark matter), reported in the same
-JSON line under ``sr_gravity``; ``--config`` runs one workload alone.
+The default run measures the CRK step on the 128^3 clustered gas (the
+headline line), then the same step on the 256^3 gas with 32-256 neighbours
+(``c5``: FP32 against the FP64 form, forward and backward) and the gravity
+step on 128^3 gas + 128^3 dark matter (``sr_gravity``), in one JSON line;
+``--config`` runs one workload alone.
 
-Prints ONE JSON line.  ``value`` is pair interactions per second: ordered
-pairs j != i inside each pass's radius (2h_i for volume and moments,
-max(2h_i, 2h_j) for forces, r_c for gravity), counted exactly in FP64 on the
-device, summed over the passes of a step, divided by the step time.
+``value`` is pair interactions per second: the ordered pairs j != i inside the
+radius of every pair pass the step launches (2h_i for volume and moments,
+max(2h_i, 2h_j) for the force pass and the three adjoint pair passes, r_c for
+gravity), counted exactly in FP64 on the device, summed over the launches of a
+step and divided by the step time.
 """
 
 import argparse
@@ -31,19 +35,17 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "CRK-SPH pair interactions/s & % FP32 VALU peak; fwd+bwd ms vs FP64 GPU form"
-
-# Algorithmic FP32 work per ordered pair inside the pass radius (FMA = 2 FLOP,
-# square root / reciprocal square root = 1), per-particle constants hoisted;
-# compensation arithmetic excluded.
-FLOP_PER_PAIR = {"volume": 21, "moments": 112, "accel": 141, "gravity": 19,
-                 "accel_adj": 520, "moments_adj": 365, "volume_adj": 40}
 HYDRO_KERNELS = ("volume", "moments", "accel", "accel_adj", "moments_adj", "volume_adj")
 PEAK_FP32_VALU_TFLOPS = 157.3  # 256 CUs x 2.4 GHz x 256 FLOP/clk/CU
+
+# FLOP per ordered pair of every pass, counted by the oracle on its own per-pair
+# code (oracle/flop_table.py writes the file; a CPU test keeps it current).
+FLOP_TABLE = os.path.join(ROOT, "oracle", "flop_per_pair.json")
 
 WORKLOADS = {
     "C2": "128^3 clustered gas (lognormal, P(k)~k^-2, sigma_ln=1), h for 64+-8 neighbours, "
           "leaf 128; FP32 pairs + compensated sums, FP64 solve/totals",
-    "C5": "256^3 clustered gas, 32..256 neighbours over a 16x density contrast; FP32 mixed",
+    "C5": "256^3 clustered gas, 32..256 neighbours over a 16x density contrast, leaf 128; FP32 mixed",
     "C3": "128^3 gas + 128^3 dark matter, Plummer-softened short-range gravity, r_c = 3 spacing, "
           "uneven RCB leaves 16..512; FP32 + compensated sums",
 }
@@ -51,6 +53,11 @@ WORKLOADS = {
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def flop_table():
+    with open(FLOP_TABLE) as f:
+        return json.load(f)["flop_per_pair"]
 
 
 def timed_steps(step, steps, warmup, torch):
@@ -64,73 +71,146 @@ def timed_steps(step, steps, warmup, torch):
     return (time.perf_counter() - t0) / steps * 1e3
 
 
-def sampled(run, k0, n, budget_s):
-    """Time run(k) on a sample of k targets sized to take about budget_s seconds
-    (one small warm-up call first: library load and thread start-up)."""
-    run(min(8, k0))
-    k = k0
-    dt, inter = run(k)
-    for _ in range(3):
-        if dt >= budget_s / 2 or k >= n:
-            break
-        k = int(min(k * budget_s / max(dt, 1e-3), n))
-        dt, inter = run(k)
-    return k, dt, inter
+# ---------------------------------------------------------------- CPU baseline (the oracle)
+def _csr(rows):
+    import numpy as np
+
+    off = np.zeros(len(rows) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(r) for r in rows])
+    idx = np.concatenate(rows).astype(np.int64) if rows else np.zeros(0, np.int64)
+    return off, idx
 
 
-def cpu_baseline_hydro(cfg, budget_s):
-    """The oracle (brute-force FP64 passes) on a sample of target particles of the workload."""
+def force_lists(cfg, targets):
+    """Exact candidate lists of the targets: every j != i with |x_ij| <
+    max(2h_i, 2h_j) (periodic), from k-d trees over particles binned by h, so
+    that a dense target never scans the support of the sparsest particle.
+    Input preparation for the CPU baseline (scipy), not timed."""
+    import numpy as np
+    from scipy.spatial import cKDTree
+
+    P = np.stack([cfg["x"], cfg["y"], cfg["z"]], 1)
+    H = 2.0 * np.asarray(cfg["h"], dtype=np.float64)
+    edges = np.exp2(np.arange(np.floor(np.log2(H.min())), np.ceil(np.log2(H.max())) + 0.26, 0.25))
+    b = np.clip(np.searchsorted(edges, H, side="right") - 1, 0, len(edges) - 2)
+    Pt, Ht = P[targets], H[targets]
+    rows = [[] for _ in targets]
+    for k in range(len(edges) - 1):
+        sel = np.nonzero(b == k)[0]
+        if sel.size == 0:
+            continue
+        tree = cKDTree(P[sel], boxsize=1.0)
+        R = np.maximum(Ht, edges[k + 1])
+        for t, c in enumerate(tree.query_ball_point(Pt, R, workers=-1)):
+            if c:
+                rows[t].append(sel[np.asarray(c)])
+    out = []
+    for t, i in enumerate(targets):
+        c = np.concatenate(rows[t]) if rows[t] else np.zeros(0, np.int64)
+        d = P[c] - P[i]
+        d -= np.floor(d + 0.5)
+        r = np.sqrt((d * d).sum(1))
+        keep = (r < np.maximum(H[i], H[c])) & (c != i)
+        out.append(np.sort(c[keep]))
+    return out
+
+
+def repeat_timed(fn, min_s):
+    """Run fn until min_s seconds have passed (at least twice); seconds per call."""
+    fn()
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        fn()
+        k += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_s and k >= 2:
+            return dt / k
+
+
+def cpu_baseline_hydro(cfg, budget_s, n_targets=16384):
+    """The oracle's FP64 passes on the host cores: physics only (the three hydro
+    passes of sampled targets over precomputed exact neighbour lists), on all
+    threads and on one; and the brute-force form (every particle scanned per
+    target) per pass, extrapolated to the whole workload."""
     import numpy as np
 
     import oracle
     import synth
 
     n = cfg["n"]
-    # Brute force costs the same whatever the field values; the pass inputs the
-    # sample needs for all particles (V, rho, corrections) are placeholders.
+    t = synth.sample_targets(n, min(n_targets, n), seed=123)
+    t0 = time.perf_counter()
+    rows = force_lists(cfg, t)
+    off, idx = _csr(rows)
+    prep_s = time.perf_counter() - t0
+    # V, rho and corrections of the neighbours are placeholders: the work per
+    # pair does not depend on their values
     V = np.full(n, 1.0 / n)
     rho = cfg["m"] / V
     corr = (np.ones(n), np.zeros((n, 3)), np.zeros((n, 3)), np.zeros((n, 3, 3)))
+    F = int(off[-1])
+    res = {}
+    for label, threads, share in (("all", 0, 0.6), ("one", 1, 0.25)):
+        nt = len(t) if threads == 0 else max(256, len(t) // 16)
+        o2, i2 = off[:nt + 1], idx[:off[nt]]
+        pairs = {}
 
-    def run(k):
-        t = synth.sample_targets(n, k, seed=123)
-        t0 = time.perf_counter()
-        oracle.volume(cfg, t)
-        oracle.corrections(cfg, V, t)
-        oracle.accel(cfg, V, rho, corr, t)
-        dt = time.perf_counter() - t0
-        inter = 2 * oracle.count_pairs(cfg, 0, t)[0] + oracle.count_pairs(cfg, 1, t)[0]
-        return dt, inter
+        def run():
+            pairs["g2"] = oracle.passes_listed(cfg, t[:nt], o2, i2, V, rho, corr, threads)[0]
 
-    k, dt, inter = sampled(run, 64, n, budget_s)
-    return {"value": inter / dt, "unit": "interactions/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"{k} sampled particles of the {n}-particle workload through the oracle's "
-                      f"brute-force volume, corrections and accel/energy passes (each scans all "
-                      f"{n} particles per target); {dt:.1f} s"}
+        dt = repeat_timed(run, budget_s * share)
+        res[label] = ((pairs["g2"] + int(o2[-1])) / dt, nt, dt)
+    # brute force per pass on a few targets, extrapolated to all n particles
+    tb = t[:32]
+    bf = {}
+    for name, fn in (("volume", lambda: oracle.volume(cfg, tb)),
+                     ("corrections", lambda: oracle.corrections(cfg, V, tb)),
+                     ("accel", lambda: oracle.accel(cfg, V, rho, corr, tb))):
+        dt = repeat_timed(fn, budget_s * 0.05)
+        bf[name] = round(dt / len(tb) * n, 1)
+    rate, nt, dt = res["all"]
+    return {"value": rate, "unit": "interactions/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{nt} sampled particles of the {n}-particle workload through the oracle's FP64 "
+                      f"volume, corrections and accel/energy passes over exact precomputed neighbour "
+                      f"lists ({F} force-list entries; the lists built by scipy k-d trees in "
+                      f"{prep_s:.1f} s, not timed), repeated for {dt:.2f} s per pass set",
+            "single_thread": {"value": res["one"][0], "targets": res["one"][1]},
+            "brute_force_s_per_pass_extrapolated": bf,
+            "brute_force_note": "brute-force oracle (every particle scanned per target) timed on 32 "
+                                "targets per pass and scaled to all particles"}
 
 
-def cpu_baseline_gravity(cfg, budget_s):
+def cpu_baseline_gravity(cfg, budget_s, n_targets=16384):
+    import numpy as np
+    from scipy.spatial import cKDTree
+
     import oracle
     import synth
 
     n = cfg["n"]
+    t = synth.sample_targets(n, min(n_targets, n), seed=123)
+    P = np.stack([cfg["x"], cfg["y"], cfg["z"]], 1)
+    rows = [np.asarray(sorted(c), dtype=np.int64)
+            for c in cKDTree(P, boxsize=1.0).query_ball_point(P[t], cfg["r_cut"], workers=-1)]
+    off, idx = _csr(rows)
+    inter = int(off[-1]) - len(t)  # every list holds the target itself
+    res = {}
+    for label, threads, share in (("all", 0, 0.6), ("one", 1, 0.3)):
+        nt = len(t) if threads == 0 else max(256, len(t) // 16)
+        o2, i2 = off[:nt + 1], idx[:off[nt]]
+        dt = repeat_timed(lambda: oracle.gravity_listed(cfg, t[:nt], o2, i2, threads), budget_s * share)
+        res[label] = ((int(o2[-1]) - nt) / dt, nt, dt)
+    rate, nt, dt = res["all"]
+    return {"value": rate, "unit": "interactions/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{nt} sampled particles of the {n}-particle workload through the oracle's FP64 "
+                      f"gravity over precomputed candidate lists (r < r_c, {inter} pairs), repeated "
+                      f"for {dt:.2f} s",
+            "single_thread": {"value": res["one"][0], "targets": res["one"][1]}}
 
-    def run(k):
-        t = synth.sample_targets(n, k, seed=123)
-        t0 = time.perf_counter()
-        oracle.gravity(cfg, t)
-        dt = time.perf_counter() - t0
-        return dt, oracle.count_pairs(cfg, 2, t, r_fixed=cfg["r_cut"])[0]
 
-    k, dt, inter = sampled(run, 256, n, budget_s)
-    return {"value": inter / dt, "unit": "interactions/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"{k} sampled particles of the {n}-particle workload through the oracle's "
-                      f"brute-force gravity (all {n} particles scanned per target); {dt:.1f} s"}
-
-
-# HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, calibrated
+# ---------------------------------------------------------------- counters and roofline
+# HBM traffic and executed FLOP per launch from rocprofv3 --pmc runs, calibrated
 # against a device copy of known size (profiles/*_hbm_traffic.json, written by
 # paper_2310_16122_amd.profiling); used only while the kernel sources are the
 # ones the counters were taken on.
@@ -158,83 +238,161 @@ def measured_counters(config, kind):
     return max(hits, key=lambda v: v.get("dispatches", 0)) if hits else None
 
 
-def roofline(kind, ms_total, launches, units, config):
+def flop_per_unit(kind, units, config, table):
+    """(FLOP per pair used for the algorithmic rate, oracle count, executed
+    count per pair or None).  The algorithmic count is the oracle's, unless the
+    kernel executes fewer FLOP per pair (counter, padding and compensation
+    included): then the executed figure, so that the rate never claims work
+    the kernel did not do."""
+    ref = table["gravity" if kind == "gravity" else kind]
+    k = measured_counters(config, kind)
+    ex = None
+    if k is not None and "SQ_INSTS_VALU_FLOPS_FP32" in k and units:
+        ex = 64.0 * k["SQ_INSTS_VALU_FLOPS_FP32"] / units
+    return (min(ref, ex) if ex is not None else ref), ref, ex
+
+
+def roofline(kind, ms_total, launches, units, config, table):
     avg_ms = ms_total / max(launches, 1)
-    achieved = FLOP_PER_PAIR[kind] * units / (avg_ms * 1e-3) / 1e12
+    flop, ref, ex = flop_per_unit(kind, units, config, table)
+    achieved = flop * units / (avg_ms * 1e-3) / 1e12
     k = measured_counters(config, kind)
     out = {"bound": "alu", "kernel": kind, "achieved": round(achieved, 3),
            "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
            "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4),
            "traffic": None if k is None else round(k["hbm_bytes"]),
-           "avg_launch_ms": round(avg_ms, 4), "flop_per_unit": FLOP_PER_PAIR[kind],
+           "avg_launch_ms": round(avg_ms, 4), "flop_per_unit": round(flop, 2),
+           "flop_per_unit_oracle": ref,
+           "flop_per_unit_executed": None if ex is None else round(ex, 2),
            "units_per_launch": units}
     if k is not None and "SQ_INSTS_VALU_FLOPS_FP32" in k:
         # executed FP32 FLOP (counter: per wave instruction, FMA = 2; x 64 lanes),
         # padding, compensation and masked lanes included
-        ex = 64.0 * k["SQ_INSTS_VALU_FLOPS_FP32"] / (avg_ms * 1e-3) / 1e12
-        out["executed_counter"] = round(ex, 3)
-        out["executed_frac"] = round(ex / PEAK_FP32_VALU_TFLOPS, 4)
+        exr = 64.0 * k["SQ_INSTS_VALU_FLOPS_FP32"] / (avg_ms * 1e-3) / 1e12
+        out["executed_counter"] = round(exr, 3)
+        out["executed_frac"] = round(exr / PEAK_FP32_VALU_TFLOPS, 4)
     return out
 
 
-def bench_hydro(args, torch, crk):
+# ---------------------------------------------------------------- CRK step
+def tree_ordered(crk, cfg, leaf_max, torch):
+    """Particles in tree order, as a simulation keeps them: build once on the
+    generated (random) order, reorder the arrays along the tree and rebuild,
+    which gives the identity permutation (coalesced particle I/O).  Returns
+    (cfg in tree order, handle, the generated order's handle, perm, build ms,
+    list-build GPU ms, identity)."""
     import numpy as np
 
-    import synth
-
-    t0 = time.perf_counter()
-    cfg = synth.make_config(args.config)
-    log(f"[bench] generated {args.config}: n={cfg['n']} in {time.perf_counter() - t0:.1f}s")
-    # Particles are kept in tree order, as a simulation keeps them: build once
-    # on the generated (random) order, reorder the arrays along the tree and
-    # rebuild, which gives the identity permutation (coalesced particle I/O).
     g_rand = crk.gas_to_device(cfg, "f32")
     torch.cuda.synchronize()
     tb = time.perf_counter()
     L_rand = crk.crk_build_leaf_pairs(g_rand["x"], g_rand["y"], g_rand["z"], g_rand["h"],
-                                      leaf_max=args.leaf_max, prec="f32")
+                                      leaf_max=leaf_max, prec="f32")
     build_ms = (time.perf_counter() - tb) * 1e3
     cull = L_rand.kernel_times()["cull"]
     perm = L_rand.perm().cpu().numpy()
     cfg_t = {k: (v[perm] if isinstance(v, np.ndarray) and v.shape == (cfg["n"],) else v)
              for k, v in cfg.items()}
     g32 = crk.gas_to_device(cfg_t, "f32")
-    L = crk.crk_build_leaf_pairs(g32["x"], g32["y"], g32["z"], g32["h"], leaf_max=args.leaf_max,
-                                 prec="f32")
+    L = crk.crk_build_leaf_pairs(g32["x"], g32["y"], g32["z"], g32["h"], leaf_max=leaf_max, prec="f32")
     identity = bool((L.perm().cpu().numpy() == np.arange(cfg["n"])).all())
-    if args.tuning:
-        L.set_tuning(**json.loads(args.tuning))
-        L_rand.set_tuning(**json.loads(args.tuning))
+    return cfg_t, g32, L, L_rand, g_rand, perm, build_ms, cull, identity
+
+
+def crk_step(crk, Lh, g, cfg, prec, ga, gdu, backward=True):
+    """One step: forward with the moment sums kept, then the backward from them."""
+    def step():
+        o = crk.forward(Lh, g, cfg["gamma"], prec, store_sums=backward)
+        if backward:
+            crk.crk_accel_energy_backward(Lh, g, o["V"], o["rho"], (o["A"], o["B"], o["dA"], o["dB"], o["M"]),
+                                          ga, gdu, cfg["gamma"], prec)
+    return step
+
+
+def upstream(crk, L, g, cfg_t, prec, torch):
+    """dL/da = 2 w a and dL/d(du/dt) = c for L = sum w |a|^2 + sum c du/dt."""
+    dt = torch.float32 if prec == "f32" else torch.float64
+    dev = g["x"].device
+    w = torch.as_tensor(cfg_t["w"]).to(dt).to(dev)
+    c = torch.as_tensor(cfg_t["c"]).to(dt).to(dev)
+    o = crk.forward(L, g, cfg_t["gamma"], prec)
+    return (2.0 * w[:, None] * o["a"]).contiguous(), c
+
+
+def interactions(kt, steps, G, F):
+    """Ordered pairs per step summed over the pair kernels the step launched."""
+    units = {"volume": G, "moments": G, "accel": F, "accel_adj": F, "moments_adj": F, "volume_adj": F}
+    return sum(units[k] * kt[k][1] for k in HYDRO_KERNELS) // steps, units
+
+
+def per_kernel_table(kt, steps, units, config, table):
+    ran = [k for k in HYDRO_KERNELS if kt[k][1] > 0]
+    out = {}
+    for k in ran:
+        avg = kt[k][0] / kt[k][1]
+        flop, ref, ex = flop_per_unit(k, units[k], config, table)
+        out[k] = {"avg_ms": round(avg, 4), "launches_per_step": kt[k][1] / steps,
+                  "tflops": round(flop * units[k] / avg * 1e-9, 3),
+                  "flop_per_pair": round(flop, 2), "flop_per_pair_oracle": ref,
+                  "flop_per_pair_executed": None if ex is None else round(ex, 2)}
+    out["pack_ms_per_step"] = round(kt["pack"][0] / steps, 4)
+    out["solve_adj_ms_per_step"] = round(kt["solve_adj"][0] / steps, 4)
+    return ran, out
+
+
+def fp32_vs_fp64(crk, L, g32, g64, cfg_t, torch):
+    """Normwise errors of the FP32 mixed path against the FP64 GPU form over
+    every particle: forward outputs, and the backward's gradients for the
+    benchmark loss."""
+    acc = {}
+    o32 = crk.forward(L, g32, cfg_t["gamma"], "f32", store_sums=True)
+    o64 = crk.forward(L, g64, cfg_t["gamma"], "f64", store_sums=True)
+    for k in ("V", "rho", "A", "B", "dA", "dB", "a", "dudt"):
+        d = (o32[k].double() - o64[k]).abs().max().item()
+        acc[k] = float(f"{d / o64[k].abs().max().item():.3e}")
+    dev = g32["x"].device
+    w = torch.as_tensor(cfg_t["w"]).to(dev)
+    c = torch.as_tensor(cfg_t["c"]).to(dev)
+    # the same upstream adjoints (from the FP64 forward) for both backward forms
+    ga64 = (2.0 * w[:, None] * o64["a"]).contiguous()
+    b64 = crk.crk_accel_energy_backward(L, g64, o64["V"], o64["rho"],
+                                        (o64["A"], o64["B"], o64["dA"], o64["dB"], o64["M"]),
+                                        ga64, c, cfg_t["gamma"], "f64")
+    b32 = crk.crk_accel_energy_backward(L, g32, o32["V"], o32["rho"],
+                                        (o32["A"], o32["B"], o32["dA"], o32["dB"], o32["M"]),
+                                        ga64.float(), c.float(), cfg_t["gamma"], "f32")
+    for k, u, v in zip(("gx", "gv", "gu"), b32, b64):
+        d = (u.double() - v).abs().max().item()
+        acc[k] = float(f"{d / v.abs().max().item():.3e}")
+    del o32, o64, b32, b64
+    return acc
+
+
+def bench_hydro(args, torch, crk, config=None, tuning=None, autotune=True, random_order=True,
+                f64=True, cpu=True):
+    import numpy as np
+
+    import synth
+
+    config = config or args.config
+    table = flop_table()
+    t0 = time.perf_counter()
+    cfg = synth.make_config(config)
+    gen_s = time.perf_counter() - t0
+    log(f"[bench] generated {config}: n={cfg['n']} in {gen_s:.1f}s")
+    cfg_t, g32, L, L_rand, g_rand, perm, build_ms, cull, identity = tree_ordered(crk, cfg, args.leaf_max, torch)
+    if tuning:
+        L.set_tuning(**tuning)
+        L_rand.set_tuning(**tuning)
     st = L.stats()
     G, F = st["pairs_gather"], st["pairs_force"]
     log(f"[bench] build {build_ms:.0f} ms (list build on GPU {cull[0]:.2f} ms); identity order "
         f"after rebuild: {identity}; stats {st}")
-    inter_fwd = 2 * G + F
-    inter = inter_fwd + (G + 3 * F if not args.no_backward else 0)
-    dev = g32["x"].device
-
-    def adjoints(g, prec):
-        dt = torch.float32 if prec == "f32" else torch.float64
-        w = torch.as_tensor(cfg_t["w"]).to(dt).to(dev)
-        c = torch.as_tensor(cfg_t["c"]).to(dt).to(dev)
-        o = crk.forward(L, g, cfg["gamma"], prec)
-        return (2.0 * w[:, None] * o["a"]).contiguous(), c
-
-    def make_step(Lh, g, prec, ga, gdu):
-        # the forward keeps its per-particle moment sums for the backward
-        # (30 doubles per particle); pair terms are recomputed, never stored
-        def step():
-            o = crk.forward(Lh, g, cfg["gamma"], prec, store_sums=not args.no_backward)
-            if not args.no_backward:
-                crk.crk_accel_energy_backward(Lh, g, o["V"], o["rho"],
-                                              (o["A"], o["B"], o["dA"], o["dB"], o["M"]),
-                                              ga, gdu, cfg["gamma"], prec)
-        return step
-
-    ga32, gdu32 = adjoints(g32, "f32")
-    step32 = make_step(L, g32, "f32", ga32, gdu32)
+    backward = not args.no_backward
+    ga32, gdu32 = upstream(crk, L, g32, cfg_t, "f32", torch)
+    step32 = crk_step(crk, L, g32, cfg_t, "f32", ga32, gdu32, backward)
     tuned = None
-    if not args.no_autotune and not args.tuning:
+    if autotune and not tuning:
         from paper_2310_16122_amd import tune
 
         best, best_ms, tried = tune.autotune(L, step32, repeats=2)
@@ -244,59 +402,60 @@ def bench_hydro(args, torch, crk):
     L.timing(False)
     timed_steps(step32, 2, args.warmup, torch)
     L.timing(True)
-    ms32 = timed_steps(step32, args.steps, 0, torch)
+    steps = args.steps
+    ms32 = timed_steps(step32, steps, 0, torch)
     kt = L.kernel_times()
     L.timing(False)
-    log(f"[bench] f32 step {ms32:.3f} ms; kernels {kt}")
-    units = {"volume": G, "moments": G, "accel": F, "accel_adj": F, "moments_adj": F, "volume_adj": F}
-    ran = [k for k in HYDRO_KERNELS if kt[k][1] > 0]
+    log(f"[bench] {config} f32 step {ms32:.3f} ms; kernels {kt}")
+    inter, units = interactions(kt, steps, G, F)
+    ran, per_kernel = per_kernel_table(kt, steps, units, config, table)
     dom = max(ran, key=lambda k: kt[k][0])
-    rl = roofline(dom, kt[dom][0], kt[dom][1], units[dom], args.config)
-    per_kernel = {k: {"avg_ms": round(kt[k][0] / kt[k][1], 4), "launches_per_step": kt[k][1] / args.steps,
-                      "tflops": round(FLOP_PER_PAIR[k] * units[k] / (kt[k][0] / kt[k][1]) * 1e-9, 3)}
-                  for k in ran}
-    per_kernel["pack_ms_per_step"] = round(kt["pack"][0] / args.steps, 4)
-    per_kernel["solve_adj_ms_per_step"] = round(kt["solve_adj"][0] / args.steps, 4)
-    flop_step = sum(FLOP_PER_PAIR[k] * units[k] * kt[k][1] / args.steps for k in ran)
+    rl = roofline(dom, kt[dom][0], kt[dom][1], units[dom], config, table)
+    rl_accel = roofline("accel", kt["accel"][0], kt["accel"][1], units["accel"], config, table)
+    flop_step = sum(per_kernel[k]["flop_per_pair"] * units[k] * kt[k][1] / steps for k in ran)
 
     # the same step with particle arrays in the generated (random) order
     ms_rand = None
-    if not args.no_random_order:
-        inv = torch.as_tensor(np.argsort(perm)).to(dev)  # tree position of each generated particle
-        ms_rand = timed_steps(make_step(L_rand, g_rand, "f32", ga32[inv].contiguous(),
-                                        gdu32[inv].contiguous()), max(2, args.steps // 4), 1, torch)
-        log(f"[bench] f32 step, random particle order: {ms_rand:.3f} ms")
+    if random_order:
+        inv = torch.as_tensor(np.argsort(perm)).to(g32["x"].device)  # tree position of each generated particle
+        ms_rand = timed_steps(crk_step(crk, L_rand, g_rand, cfg_t, "f32", ga32[inv].contiguous(),
+                                       gdu32[inv].contiguous(), backward), max(2, steps // 4), 1, torch)
+        log(f"[bench] {config} f32 step, random particle order: {ms_rand:.3f} ms")
+    L_rand.free()
+    del g_rand, L_rand
+    torch.cuda.empty_cache()
 
-    ms64 = None
-    acc = None
-    if not args.no_f64:
+    ms64 = acc = None
+    if f64:
         g64 = crk.gas_to_device(cfg_t, "f64")
-        ga64, gdu64 = adjoints(g64, "f64")
-        ms64 = timed_steps(make_step(L, g64, "f64", ga64, gdu64), max(2, args.steps // 4), 1, torch)
-        log(f"[bench] f64 step {ms64:.3f} ms")
-        # the FP32 mixed path against the FP64 GPU form, every particle, per output
-        o32 = crk.forward(L, g32, cfg["gamma"], "f32")
-        o64 = crk.forward(L, g64, cfg["gamma"], "f64")
-        acc = {}
-        for k in ("V", "rho", "A", "B", "dA", "dB", "a", "dudt"):
-            d = (o32[k].double() - o64[k]).abs().max().item()
-            acc[k] = float(f"{d / o64[k].abs().max().item():.3e}")
-        log(f"[bench] FP32 vs FP64 normwise errors {acc}")
-        del g64, o32, o64
+        ga64, gdu64 = upstream(crk, L, g64, cfg_t, "f64", torch)
+        ms64 = timed_steps(crk_step(crk, L, g64, cfg_t, "f64", ga64, gdu64, backward), max(2, steps // 4), 1,
+                           torch)
+        log(f"[bench] {config} f64 step {ms64:.3f} ms")
+        del ga64, gdu64
+        acc = fp32_vs_fp64(crk, L, g32, g64, cfg_t, torch)
+        log(f"[bench] {config} FP32 vs FP64 normwise errors {acc}")
+        del g64
+    torch.cuda.empty_cache()
 
     out = {
         "metric": METRIC, "value": inter / (ms32 * 1e-3), "unit": "interactions/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms32, 4),
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": round(ms32, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "n": cfg["n"],
+        "config": {"workload": f"{config}: {WORKLOADS[config]}", "n": cfg["n"],
                    "leaf_max": args.leaf_max,
                    "passes": "volume+corrections+accel_energy" +
-                             ("" if args.no_backward else "+backward(accel,moments,volume adjoints)"),
+                             ("+backward(accel adjoint, solve adjoint from stored sums, moments and "
+                              "volume adjoints)" if backward else ""),
                    "particle_order": "tree order (identity permutation)" if identity else "tree-built",
                    "interactions_per_step": inter, "pairs_gather": G, "pairs_force": F,
+                   "interactions_rule": "sum over the step's pair-kernel launches of their in-radius "
+                                        "ordered pairs: volume, moments G each; accel and its three "
+                                        "adjoint pair passes F each",
                    "list_entries": st["list_entries"], "tuning": L.get_tuning(), "autotune": tuned},
         "roofline": rl,
+        "roofline_forward_accel": rl_accel,
         "kernels": per_kernel,
         "fp32_frac_step": round(flop_step / (ms32 * 1e-3) / 1e12 / PEAK_FP32_VALU_TFLOPS, 4),
         "fp64_gpu_ms_per_step": None if ms64 is None else round(ms64, 4),
@@ -304,23 +463,28 @@ def bench_hydro(args, torch, crk):
         "fp32_vs_fp64_normwise": acc,
         "random_order_ms_per_step": None if ms_rand is None else round(ms_rand, 4),
         "build_ms": round(build_ms, 1), "list_build_gpu_ms": round(cull[0], 3),
+        "list_build_note": "neighbour-list count, fill and schedule kernels of one build",
+        "generate_s": round(gen_s, 1),
     }
-    if not args.no_cpu:
+    if cpu and not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_hydro(cfg, args.cpu_budget)
+    L.free()
+    del L, g32, ga32, gdu32
+    torch.cuda.empty_cache()
     return out
 
 
-def bench_gravity(args, torch, crk):
+# ---------------------------------------------------------------- gravity step
+def bench_gravity(args, torch, crk, tuning=None, leaf_max=None):
     import synth
 
-    import numpy as np
-
+    table = flop_table()
     cfg = synth.make_config("C3")
     log(f"[bench] generated C3: n={cfg['n']}")
     x, y, z = (torch.as_tensor(cfg[k]).cuda() for k in ("x", "y", "z"))
 
-    def build(leaf_max, xx, yy, zz):
-        return crk.crk_build_leaf_pairs(xx, yy, zz, None, r_fixed=cfg["r_cut"], leaf_max=leaf_max,
+    def build(lm, xx, yy, zz):
+        return crk.crk_build_leaf_pairs(xx, yy, zz, None, r_fixed=cfg["r_cut"], leaf_max=lm,
                                         leaf_min=16, split_extent=cfg["r_cut"], prec="f32")
 
     # particles in tree order (as a simulation holds them): build, reorder, rebuild
@@ -338,10 +502,10 @@ def bench_gravity(args, torch, crk):
         return step
 
     tuned = None
-    if args.tuning or args.no_autotune:
-        L = build(args.leaf_max if args.leaf_max != 128 else 512, x, y, z)
-        if args.tuning:
-            L.set_tuning(**json.loads(args.tuning))
+    if tuning or args.no_autotune:
+        L = build(leaf_max or 512, x, y, z)
+        if tuning:
+            L.set_tuning(**tuning)
     else:
         from paper_2310_16122_amd import tune
 
@@ -365,13 +529,26 @@ def bench_gravity(args, torch, crk):
         "data": "synthetic",
         "config": {"workload": f"C3: {WORKLOADS['C3']}", "n": cfg["n"],
                    "interactions_per_step": inter, "candidate_pairs": st["candidate_pairs"],
-                   "leaves": st["leaves"], "particle_order": "tree order",
-                   "tuning": L.get_tuning(), "autotune": tuned},
-        "roofline": roofline("gravity", kt["gravity"][0], kt["gravity"][1], inter, "C3"),
+                   "leaves": st["leaves"], "leaf_max": (tuned or {}).get("leaf_max", leaf_max or 512),
+                   "particle_order": "tree order", "tuning": L.get_tuning(), "autotune": tuned},
+        "roofline": roofline("gravity", kt["gravity"][0], kt["gravity"][1], inter, "C3", table),
         "build_ms": round(build_ms, 1),
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_gravity(cfg, args.cpu_budget)
+    L.free()
+    return out
+
+
+def c5_summary(r):
+    """The C5 leg of the default run, condensed into the headline line."""
+    keys = ("ms_per_step", "value", "fp64_gpu_ms_per_step", "fp64_over_fp32_time", "fp32_vs_fp64_normwise",
+            "roofline", "roofline_forward_accel", "kernels", "build_ms", "list_build_gpu_ms", "generate_s")
+    out = {k: r[k] for k in keys if k in r}
+    out["workload"] = r["config"]["workload"]
+    out["interactions_per_step"] = r["config"]["interactions_per_step"]
+    out["tuning"] = r["config"]["tuning"]
+    out["steps"] = r["steps"]
     return out
 
 
@@ -385,6 +562,8 @@ def main():
     ap.add_argument("--tuning", default=None, help="JSON dict of crk_tuning fields")
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default tuning")
     ap.add_argument("--no-gravity", action="store_true", help="C2 only: skip the gravity workload")
+    ap.add_argument("--no-c5", action="store_true", help="C2 only: skip the 256^3 workload")
+    ap.add_argument("--c5-steps", type=int, default=6)
     ap.add_argument("--no-random-order", action="store_true",
                     help="skip the comparison step on randomly ordered particle arrays")
     ap.add_argument("--gravity-tuning", default=None, help="JSON crk_tuning for the gravity workload")
@@ -393,7 +572,7 @@ def main():
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-backward", action="store_true", help="forward passes only")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work per workload")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy a buffer of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -410,19 +589,33 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    tuning = json.loads(args.tuning) if args.tuning else None
     if args.config == "C3":
-        out = bench_gravity(args, torch, crk)
+        out = bench_gravity(args, torch, crk, json.loads(args.gravity_tuning) if args.gravity_tuning else tuning,
+                            args.gravity_leaf_max if args.gravity_tuning else args.leaf_max)
     else:
-        out = bench_hydro(args, torch, crk)
-        if args.config == "C2" and not args.no_gravity:
-            # the gravity pass on its own workload, in the same JSON line
+        out = bench_hydro(args, torch, crk, tuning=tuning, autotune=not args.no_autotune,
+                          random_order=not args.no_random_order, f64=not args.no_f64)
+        if args.config == "C2":
             import gc
 
-            gc.collect()
-            torch.cuda.empty_cache()
-            gargs = argparse.Namespace(**vars(args))
-            gargs.config, gargs.tuning, gargs.leaf_max = "C3", args.gravity_tuning, args.gravity_leaf_max
-            out["sr_gravity"] = bench_gravity(gargs, torch, crk)
+            if not args.no_c5:
+                # the paper's per-GPU gas share, with the C2 workload's tuning
+                cargs = argparse.Namespace(**vars(args))
+                cargs.steps = args.c5_steps
+                cargs.warmup = 1
+                r5 = bench_hydro(cargs, torch, crk, config="C5", tuning=out["config"]["tuning"],
+                                 autotune=False, random_order=False, f64=not args.no_f64, cpu=False)
+                out["c5"] = c5_summary(r5)
+                gc.collect()
+                torch.cuda.empty_cache()
+            if not args.no_gravity:
+                # the gravity pass on its own workload, in the same JSON line
+                gc.collect()
+                torch.cuda.empty_cache()
+                out["sr_gravity"] = bench_gravity(
+                    args, torch, crk, json.loads(args.gravity_tuning) if args.gravity_tuning else None,
+                    args.gravity_leaf_max)
     if args.calibrate_copy:
         # a plain device copy of known size: its FETCH_SIZE / WRITE_SIZE counter
         # readings calibrate the counters of the pair kernels

@@ -25,16 +25,18 @@
  *    are row-major per particle: a[3*i + c], B[3*i + a], dB[9*i + 3*a + c].
  *  - Inputs and outputs are in the caller's particle order; the library
  *    reorders internally along the tree.
- *  - All device buffers passed in are owned by the caller and must not alias
- *    each other.  The library owns the memory behind a crk_leaves handle
- *    (tree order, interaction lists and per-pass scratch) until
- *    crk_leaves_free.  The scratch is allocated (hipMalloc) by the first pass
- *    that needs it and grown, after a device synchronisation, when a later
- *    pass needs more; steady-state calls allocate nothing.
+ *  - The library allocates no device memory.  All device buffers passed in
+ *    are owned by the caller and must not alias each other.  A crk_leaves
+ *    handle is host metadata pointing into a caller-owned device workspace
+ *    (`ws` of crk_build_leaf_pairs): tree order, fixed-point positions,
+ *    interaction lists and the per-pass scratch (sized at the build for
+ *    passes in either precision) all live there.  The workspace must stay
+ *    allocated, and must not be written by the caller, until the handle is
+ *    freed and the work queued on it is done.
  *  - Work is enqueued on `stream` (a hipStream_t).  crk_build_leaf_pairs,
- *    crk_leaves_stats, crk_timing, crk_kernel_times and crk_leaves_free
- *    synchronise with the host.  Calls that use the same handle share its
- *    scratch and must not run concurrently.
+ *    crk_leaves_stats, crk_timing and crk_kernel_times synchronise with the
+ *    host; no pass call synchronises.  Calls that use the same handle share
+ *    its scratch and must not run concurrently.
  *  - Return value: CRK_OK (0) or a negative code; crk_last_error() then
  *    returns a message (thread-local).  Asynchronous device errors surface at
  *    a later call.
@@ -59,9 +61,9 @@ extern "C" {
 enum {
     CRK_OK = 0,
     CRK_EINVAL = -1, /* invalid argument (null pointer, size, radius >= half the box, ...) */
-    CRK_ENOMEM = -2, /* device or host allocation failed */
     CRK_EHIP = -3,   /* a HIP runtime or launch error */
-    CRK_ESTATE = -4  /* handle built in the wrong mode for this call */
+    CRK_ESTATE = -4, /* handle built in the wrong mode for this call */
+    CRK_ENOSPC = -5  /* the caller's workspace is too small (crk_build_leaf_pairs sets *ws_needed) */
 };
 
 typedef enum { CRK_F32 = 0, CRK_F64 = 1 } crk_prec;
@@ -123,13 +125,26 @@ typedef struct {
  *    passes, never which pairs they sum.  Requires 2 max(h) < 1/2.
  *  h == NULL (fixed-radius mode): radius r_fixed (< 1/2), for sr_gravity.
  *
- * prec gives the precision of h.  leaf_max in [1, 1<<20].  On success *out
- * owns device memory until crk_leaves_free.  Synchronises `stream`.
+ * Workspace: ws is caller-owned device memory of ws_bytes bytes, 256-byte
+ * aligned (NULL with ws_bytes = 0 asks for the size).  *ws_needed (host,
+ * required) receives the bytes the handle needs.  If ws_bytes is smaller the
+ * call returns CRK_ENOSPC with *out = NULL (what it wrote into ws is then of
+ * no use); the caller allocates *ws_needed bytes and calls again with the
+ * same arguments.
+ * The size of the neighbour lists is known only after they are counted on
+ * the GPU, which needs the rest of the workspace: a first CRK_ENOSPC may
+ * therefore report that rest alone (the lists come on top), and the retry
+ * with that much then reports the exact total; a repeated call resumes from
+ * the host tree and list counts of the one that stopped.  On success the
+ * handle uses the first *ws_needed bytes of ws.
+ *
+ * prec gives the precision of h.  leaf_max in [1, 1<<20].  Synchronises
+ * `stream`.
  */
 int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const double* z,
                          const void* h, double r_fixed, int leaf_max, int leaf_min,
-                         double split_extent, crk_prec prec, crk_leaves** out,
-                         hipStream_t stream);
+                         double split_extent, crk_prec prec, void* ws, size_t ws_bytes,
+                         size_t* ws_needed, crk_leaves** out, hipStream_t stream);
 
 /*
  * Geometry pass (Sec. 5, "Geometry": particle volumes).
@@ -239,7 +254,7 @@ int crk_set_tuning(crk_leaves* leaves, const crk_tuning* in);
  * enabled (ms and launches: host arrays of CRK_K_COUNT).
  */
 enum {
-    CRK_K_CULL = 0,    /* neighbour-list build (count and fill passes) */
+    CRK_K_CULL = 0,    /* neighbour-list build (count, fill and schedule passes) */
     CRK_K_VOLUME = 1,  /* volume pair kernel */
     CRK_K_MOMENTS = 2, /* correction moments + FP64 solve (and their recomputation in the backward) */
     CRK_K_ACCEL = 3,   /* acceleration/energy pair kernel */
@@ -254,7 +269,8 @@ enum {
 int crk_timing(crk_leaves* leaves, int enable);
 int crk_kernel_times(crk_leaves* leaves, double* ms, int64_t* launches);
 
-/* Release a handle (NULL is ignored).  Synchronises the device. */
+/* Release a handle's host metadata (NULL is ignored).  Its workspace stays the
+ * caller's: free it once the work queued on the handle is done. */
 void crk_leaves_free(crk_leaves* leaves);
 
 /* Message for the last non-zero return on this thread ("" if none). */

@@ -72,6 +72,10 @@ def _load():
         lib.oracle_passes_listed.argtypes = [I64] + [P] * 9 + [D] + [P] * 6 + [I64, P, P, P,
                                                                                ctypes.c_int] + [P] * 4
         lib.oracle_passes_listed.restype = I64
+        lib.oracle_hydro_listed.argtypes = [I64] + [P] * 9 + [D] + [P] * 12
+        lib.oracle_hydro_listed.restype = I64
+        lib.oracle_gravity_listed.argtypes = [I64, P, P, P, P, D, D, D, P, I64, P, P, P, ctypes.c_int,
+                                              P, P, P]
         _lib = lib
     return _lib
 
@@ -293,3 +297,72 @@ def passes_listed(g, targets, off, idx, V, rho, corr, threads=0):
                                          _p(off), _p(idx), int(threads), _p(Vo), _p(Ao), _p(ax),
                                          _p(du))
     return int(pairs), Vo, Ao, ax, du
+
+
+def gravity_listed(g, targets, off, idx, threads=0, poly=None):
+    """Short-range gravity of the targets over precomputed candidate lists (CSR off/idx)."""
+    x, y, z, m = (_c(g[k]) for k in ("x", "y", "z", "m"))
+    t = _c(targets, np.int64)
+    off, idx = _c(off, np.int64), _c(idx, np.int64)
+    pc = None if poly is None else _c(poly)
+    a = np.empty((3, t.size))
+    _load().oracle_gravity_listed(x.size, _p(x), _p(y), _p(z), _p(m), float(g["G"]), float(g["eps"]),
+                                  float(g["r_cut"]), _p(pc), t.size, _p(t), _p(off), _p(idx),
+                                  int(threads), _p(a[0]), _p(a[1]), _p(a[2]))
+    return a.T.copy()
+
+
+def hydro_listed(g, off, idx):
+    """Full forward chain of all particles with candidates from precomputed
+    lists (CSR off/idx over all particles).  With exact lists in increasing
+    index order (``neighbour_lists``) it equals ``hydro`` bit for bit."""
+    keys = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "m")
+    arr = [_c(g[k]) for k in keys]
+    n = arr[0].size
+    off, idx = _c(off, np.int64), _c(idx, np.int64)
+    V, rho, A, du = (np.empty(n) for _ in range(4))
+    B, dA = np.empty((n, 3)), np.empty((n, 3))
+    dB = np.empty((n, 3, 3))
+    a = np.empty((3, n))
+    nf = _load().oracle_hydro_listed(n, *[_p(v) for v in arr], float(g["gamma"]), _p(off), _p(idx),
+                                     _p(V), _p(rho), _p(A), _p(B), _p(dA), _p(dB), _p(a[0]), _p(a[1]),
+                                     _p(a[2]), _p(du))
+    a = a.T.copy()
+    return dict(V=V, rho=rho, A=A, B=B, dA=dA, dB=dB, a=a, dudt=du, n_fallback=int(nf),
+                totals=totals(g, a, du))
+
+
+def neighbour_lists(g, margin=1e-9):
+    """Candidate lists for the listed oracle entries: CSR (off, idx) holding,
+    for every particle i, every j != i with |x_ij| < max(2h_i, 2h_j) (and a
+    few more within a relative margin, which the passes reject themselves) in
+    increasing index order.  Built from the nearest neighbours of a periodic
+    k-d tree (scipy; input preparation, no method arithmetic): the gather
+    pairs r < 2h_i of every particle, united with their transposes."""
+    from scipy.spatial import cKDTree
+
+    P = np.stack([np.asarray(g[k], dtype=np.float64) for k in ("x", "y", "z")], 1)
+    H = 2.0 * np.asarray(g["h"], dtype=np.float64) * (1.0 + margin)
+    n = len(H)
+    tree = cKDTree(P, boxsize=1.0)
+    gi, gj = [], []
+    todo = np.arange(n, dtype=np.int64)
+    k = 64
+    while todo.size:
+        k = min(k, n)
+        d, j = tree.query(P[todo], k=k, workers=-1)
+        d = d.reshape(len(todo), k)
+        j = j.reshape(len(todo), k)
+        done = np.ones(len(todo), bool) if k == n else d[:, -1] >= H[todo]
+        ii = np.repeat(todo[done], k)
+        jj = j[done].ravel().astype(np.int64)
+        keep = (d[done].ravel() < np.repeat(H[todo[done]], k)) & (jj != ii)
+        gi.append(ii[keep])
+        gj.append(jj[keep])
+        todo = todo[~done]
+        k *= 2
+    gi, gj = np.concatenate(gi), np.concatenate(gj)
+    key = np.unique(np.concatenate([gi * n + gj, gj * n + gi]))
+    i, j = key // n, key % n
+    off = np.searchsorted(i, np.arange(n + 1, dtype=np.int64))
+    return off.astype(np.int64), j.astype(np.int64)

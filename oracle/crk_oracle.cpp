@@ -1149,6 +1149,71 @@ int64_t oracle_passes_listed(int64_t n, const double* x, const double* y, const 
     return pairs;
 }
 
+
+// Short-range gravity of target particles over precomputed candidate lists
+// (CSR as in oracle_passes_listed), for timing the oracle's arithmetic
+// without its brute-force search; the cutoff is still tested per candidate.
+int oracle_gravity_listed(int64_t n, const double* x, const double* y, const double* z, const double* m,
+                          double G, double eps, double r_cut, const double* poly, int64_t nt,
+                          const int64_t* targets, const int64_t* off, const int64_t* idx, int threads,
+                          double* ax, double* ay, double* az) {
+    Gas<double> g = make_gas(n, x, y, z, nullptr, nullptr, nullptr, nullptr, nullptr, m);
+#ifdef _OPENMP
+    const int nth = threads > 0 ? threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nth)
+#endif
+    for (int64_t k = 0; k < nt; ++k) {
+        double a[3];
+        gravity_one(g, m, G, eps, r_cut, poly, targets[k], Cand{idx + off[k], off[k + 1] - off[k]}, a);
+        ax[k] = a[0]; ay[k] = a[1]; az[k] = a[2];
+    }
+    return 0;
+}
+
+
+// The full forward chain (volumes, corrections, forces, totals) of all n
+// particles with the candidates of particle i taken from a precomputed list
+// (CSR: idx[off[i] .. off[i+1])) instead of a scan of every particle.  Each
+// pass still tests its own radius on every candidate, so with lists that hold
+// every j within max(2h_i, 2h_j) in increasing index order the result is the
+// brute-force chain's bit for bit (the same terms summed in the same order).
+// Outputs as oracle_hydro_targets for all particles; returns the fallbacks.
+int64_t oracle_hydro_listed(int64_t n, const double* x, const double* y, const double* z, const double* vx,
+                            const double* vy, const double* vz, const double* u, const double* h,
+                            const double* m, double gamma, const int64_t* off, const int64_t* idx,
+                            double* V_o, double* rho_o, double* A_o, double* B_o, double* dA_o,
+                            double* dB_o, double* ax, double* ay, double* az, double* dudt) {
+    Gas<double> g = make_gas(n, x, y, z, vx, vy, vz, u, h, m);
+    auto cand = [&](int64_t i) { return Cand{idx + off[i], off[i + 1] - off[i]}; };
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        const double S = volume_sum(g, i, cand(i));
+        V_o[i] = 1.0 / S;
+        rho_o[i] = m[i] * S;
+    }
+    std::vector<Corr<double>> C(n);
+    int64_t fallbacks = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : fallbacks)
+    for (int64_t i = 0; i < n; ++i) {
+        Moments<double> M;
+        moments_one(g, V_o, i, cand(i), M);
+        fallbacks += solve_corrections(M, C[i]);
+        A_o[i] = C[i].A;
+        for (int a = 0; a < 3; ++a) {
+            B_o[3 * i + a] = C[i].B[a];
+            dA_o[3 * i + a] = C[i].dA[a];
+            for (int c = 0; c < 3; ++c) dB_o[9 * i + 3 * a + c] = C[i].dB[a][c];
+        }
+    }
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        double a[3], du;
+        accel_one(g, V_o, rho_o, C.data(), gamma, i, cand(i), a, du);
+        ax[i] = a[0]; ay[i] = a[1]; az[i] = a[2]; dudt[i] = du;
+    }
+    return fallbacks;
+}
+
 // Kernel values for pinning: W(r, h) and F(r, h) at n radii.
 void oracle_kernel(int64_t n, const double* r, double h, double* W, double* F) {
     for (int64_t k = 0; k < n; ++k) {

@@ -24,7 +24,8 @@ LIB_PATH = os.path.join(_HERE, "libcrk.so")
 CRK_F32, CRK_F64 = 0, 1
 _PREC = {"f32": CRK_F32, "f64": CRK_F64}
 _DTYPE = {"f32": torch.float32, "f64": torch.float64}
-_STATUS = {0: "CRK_OK", -1: "CRK_EINVAL", -2: "CRK_ENOMEM", -3: "CRK_EHIP", -4: "CRK_ESTATE"}
+CRK_ENOSPC = -5
+_STATUS = {0: "CRK_OK", -1: "CRK_EINVAL", -3: "CRK_EHIP", -4: "CRK_ESTATE", -5: "CRK_ENOSPC"}
 
 # the C symbols declared in include/crk.h
 EXPORTS = ("crk_build_leaf_pairs", "crk_volume", "crk_corrections", "crk_accel_energy",
@@ -81,7 +82,8 @@ def load_library(path=None):
         raise RuntimeError(f"HIP library not built: {path} is missing (run __graft_entry__.build())")
     lib = ctypes.CDLL(path)
     P, I64, D, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
-    lib.crk_build_leaf_pairs.argtypes = [I64, P, P, P, P, D, I, I, D, I, ctypes.POINTER(P), P]
+    lib.crk_build_leaf_pairs.argtypes = [I64, P, P, P, P, D, I, I, D, I, P, ctypes.c_size_t,
+                                         ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(P), P]
     lib.crk_volume.argtypes = [P, ctypes.POINTER(_Gas), I, P, P, P]
     lib.crk_corrections.argtypes = [P, ctypes.POINTER(_Gas), P, I, ctypes.POINTER(_Corr), P, P]
     lib.crk_accel_energy.argtypes = [P, ctypes.POINTER(_Gas), P, P, ctypes.POINTER(_Corr), D, I,
@@ -140,13 +142,15 @@ def _gas(gas, prec, keys):
 
 
 class Leaves:
-    """Owner of a ``crk_leaves`` handle (tree, interaction lists, scratch)."""
+    """Owner of a ``crk_leaves`` handle and of the device workspace it points
+    into (tree order, interaction lists, scratch: a uint8 torch tensor)."""
 
-    def __init__(self, handle, n, hydro, prec):
+    def __init__(self, handle, n, hydro, prec, ws):
         self._h = handle
         self.n = n
         self.hydro = hydro
         self.prec = prec
+        self.ws = ws
 
     @property
     def handle(self):
@@ -191,6 +195,7 @@ class Leaves:
         if self._h is not None:
             load_library().crk_leaves_free(self._h)
             self._h = None
+        self.ws = None  # back to torch's allocator, ordered on the stream the passes ran on
 
     def __del__(self):
         try:
@@ -199,20 +204,44 @@ class Leaves:
             pass
 
 
+def _ws_guess(n, hydro):
+    """First workspace size tried: per particle the tree order, positions,
+    counts and the scratch of an FP64 backward pass, plus (hydro) about 128
+    neighbour-list slots of 9 bytes.  The library reports the exact need when
+    it is larger."""
+    return (1 << 20) + n * ((830 + 9 * 128) if hydro else 96)
+
+
 def crk_build_leaf_pairs(x, y, z, h=None, r_fixed=0.0, leaf_max=128, leaf_min=1,
-                         split_extent=0.0, prec="f32"):
-    """Tree + interaction lists (hydro mode when h is given, else radius r_fixed)."""
+                         split_extent=0.0, prec="f32", ws=None):
+    """Tree + interaction lists (hydro mode when h is given, else radius r_fixed).
+
+    The handle lives in a device workspace: ``ws`` (a uint8 CUDA tensor) when
+    given and large enough, else one allocated here; on CRK_ENOSPC the
+    workspace is reallocated at the size the library reports and the call
+    repeated (the library resumes from the host tree it built)."""
     lib = load_library()
     for t in (x, y, z):
         _dev(t, torch.float64)
     if h is not None:
         _dev(h, _DTYPE[prec])
-    out = ctypes.c_void_p()
-    _check("crk_build_leaf_pairs",
-           lib.crk_build_leaf_pairs(int(x.numel()), _ptr(x), _ptr(y), _ptr(z), _ptr(h),
-                                    float(r_fixed), int(leaf_max), int(leaf_min),
-                                    float(split_extent), _PREC[prec], ctypes.byref(out), _stream()))
-    return Leaves(out, int(x.numel()), h is not None, prec)
+    n = int(x.numel())
+    need = ctypes.c_size_t(0)
+    size = _ws_guess(n, h is not None) if ws is None else int(ws.numel())
+    for _ in range(4):
+        if ws is None or int(ws.numel()) < size:
+            ws = torch.empty(size, dtype=torch.uint8, device=x.device)
+        out = ctypes.c_void_p()
+        code = lib.crk_build_leaf_pairs(n, _ptr(x), _ptr(y), _ptr(z), _ptr(h), float(r_fixed),
+                                        int(leaf_max), int(leaf_min), float(split_extent), _PREC[prec],
+                                        _ptr(ws), int(ws.numel()), ctypes.byref(need), ctypes.byref(out),
+                                        _stream())
+        if code != CRK_ENOSPC:
+            _check("crk_build_leaf_pairs", code)
+            return Leaves(out, n, h is not None, prec, ws)
+        size = int(need.value)
+        ws = None
+    _check("crk_build_leaf_pairs", code)
 
 
 def crk_volume(leaves, gas, prec="f32"):

@@ -772,26 +772,11 @@ __global__ __launch_bounds__(64) void k_gravity(Queue qu, int n, const int32_t* 
 namespace crk {
 
 
-void release(crk_leaves* L) {
-    void* ptrs[] = {L->perm, L->quant, L->Hd, L->rng_off, L->rng, L->order_cull, L->order_pair, L->order_tree,
-                    L->counter, L->cnt, L->cnt_gather, L->ell_off, L->ell_len, L->ell_len_gather, L->nbr,
-                    L->build_err, L->partials, L->counts, L->srec, L->sidx, L->scnt,
-                    L->scratch};
-    for (void* p : ptrs)
-        if (p) (void)hipFree(p);
-}
-
-int ensure_scratch(crk_leaves* L, size_t bytes) {
-    if (bytes <= L->scratch_bytes) return CRK_OK;
-    if (L->scratch) {
-        HIP_TRY(hipDeviceSynchronize());
-        HIP_TRY(hipFree(L->scratch));
-        L->scratch = nullptr;
-        L->scratch_bytes = 0;
-    }
-    hipError_t e = hipMalloc(&L->scratch, bytes);
-    if (e != hipSuccess) return fail(CRK_ENOMEM, "scratch hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
-    L->scratch_bytes = bytes;
+int pass_scratch(crk_leaves* L, size_t bytes, void** out) {
+    if (bytes > L->scratch_bytes)
+        return fail(CRK_ENOSPC, "pass needs %zu bytes of scratch, the handle's workspace holds %zu", bytes,
+                    L->scratch_bytes);
+    *out = L->scratch;
     return CRK_OK;
 }
 
@@ -876,8 +861,9 @@ int corrections_impl(crk_leaves* L, const crk_gas* g, const R* V, const crk_corr
     const int n = int(L->n);
     int rc = pack_positions<R>(L, g->x, g->y, g->z, static_cast<const R*>(g->h), st);
     if (rc) return rc;
-    if ((rc = ensure_scratch(L, sizeof(RecQV<R>) * size_t(n)))) return rc;
-    RecQV<R>* qv = static_cast<RecQV<R>*>(L->scratch);
+    void* sp = nullptr;
+    if ((rc = pass_scratch(L, sizeof(RecQV<R>) * size_t(n), &sp))) return rc;
+    RecQV<R>* qv = static_cast<RecQV<R>*>(sp);
     {
         TimeScope tp(L, st, CRK_K_PACK);
         hipLaunchKernelGGL(k_pack_qv<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, L->quant, V, qv);
@@ -902,8 +888,9 @@ int accel_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const 
     const int n = int(L->n);
     int rc = pack_positions<R>(L, g->x, g->y, g->z, static_cast<const R*>(g->h), st);
     if (rc) return rc;
-    if ((rc = ensure_scratch(L, sizeof(RecAcc<R>) * size_t(n)))) return rc;
-    RecAcc<R>* rec = static_cast<RecAcc<R>*>(L->scratch);
+    void* sp = nullptr;
+    if ((rc = pass_scratch(L, sizeof(RecAcc<R>) * size_t(n), &sp))) return rc;
+    RecAcc<R>* rec = static_cast<RecAcc<R>*>(sp);
     {
     TimeScope tp(L, st, CRK_K_PACK);
     hipLaunchKernelGGL(k_pack_acc<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, L->quant,
@@ -943,8 +930,9 @@ int gravity_impl(crk_leaves* L, const double* x, const double* y, const double* 
     const int n = int(L->n);
     int rc = pack_positions<R>(L, x, y, z, nullptr, st);
     if (rc) return rc;
-    if ((rc = ensure_scratch(L, sizeof(R) * size_t(n)))) return rc;
-    R* ms = static_cast<R*>(L->scratch);
+    void* sp = nullptr;
+    if ((rc = pass_scratch(L, sizeof(R) * size_t(n), &sp))) return rc;
+    R* ms = static_cast<R*>(sp);
     {
         TimeScope tp(L, st, CRK_K_PACK);
         hipLaunchKernelGGL(k_gather<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, m, ms);
@@ -996,9 +984,7 @@ int crk_kernel_times(crk_leaves* L, double* ms, int64_t* launches) {
 
 void crk_leaves_free(crk_leaves* L) {
     if (!L) return;
-    (void)hipDeviceSynchronize();
     drop_timed(L);
-    release(L);
     delete L;
 }
 
@@ -1030,11 +1016,72 @@ int crk_set_tuning(crk_leaves* L, const crk_tuning* in) {
     return CRK_OK;
 }
 
-int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const double* z,
+}  // extern "C"
+
+namespace {
+
+// Host state of the last build that stopped for want of workspace: a call that
+// repeats it (same sizes and options, same positions and h) resumes from the
+// tree and list counts instead of building them again.
+struct BuildMemo {
+    bool valid = false;
+    bool counted = false;
+    int64_t n = 0;
+    int leaf_max = 0, leaf_min = 0, hydro = 0;
+    double r_fixed = 0.0, split_extent = 0.0;
+    std::vector<double> hx, hy, hz, H;
+    crk::TreeOutput tree;
+    std::vector<int32_t> counts;  // list lengths in the tree's order (when counted)
+};
+thread_local BuildMemo g_memo;
+
+// Workspace layout of a handle.  Part A (everything but the neighbour lists)
+// depends on n, the tile count and the number of candidate ranges; part B
+// holds the lists and their per-slot sets (hydro mode, `entries` slots).
+void carve_part_a(crk_leaves* L, Carver& c, int64_t n, int64_t nt, size_t nr) {
+    L->counter = c.take<int32_t>(kMaxGroups);
+    L->counts = c.take<unsigned long long>(4);
+    L->build_err = c.take<int32_t>(kMaxGroups);  // cleared by k_reset
+    L->perm = c.take<int32_t>(n);
+    L->quant = c.take<uint4>(n);
+    L->rng_off = c.take<int32_t>(nt + 1);
+    L->rng = c.take<int2>(nr);
+    L->order_cull = c.take<int32_t>(nt);
+    L->order_pair = c.take<int32_t>(nt);
+    L->order_tree = c.take<int32_t>(nt);
+    L->partials = c.take<double>(8 * nt + 8 * kTotalsBlocks);
+    if (L->hydro) {
+        L->Hd = c.take<double>(n);
+        L->cnt = c.take<int32_t>(n);
+        L->cnt_gather = c.take<int32_t>(n);
+        L->ell_off = c.take<int64_t>(nt);
+        L->ell_len = c.take<int32_t>(nt);
+        L->ell_len_gather = c.take<int32_t>(nt);
+    }
+    // per-pass scratch, for both precisions: the backward's records (hydro),
+    // the masses in tree order (gravity)
+    L->scratch_bytes = L->hydro ? std::max(crk::backward_scratch_bytes(n, true),
+                                           size_t(n) * sizeof(RecAcc<double>))
+                                : size_t(n) * sizeof(double);
+    L->scratch = c.take<char>(L->scratch_bytes);
+}
+
+void carve_part_b(crk_leaves* L, Carver& c, int64_t slots) {
+    L->nbr = c.take<uint32_t>(size_t(slots));
+    L->srec = c.take<uint32_t>(size_t(slots));
+    L->sidx = c.take<uint8_t>(size_t(slots));
+    L->scnt = c.take<int32_t>(size_t(slots / kWave));
+}
+
+}  // namespace
+
+extern "C" int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const double* z,
                          const void* h, double r_fixed, int leaf_max, int leaf_min,
-                         double split_extent, crk_prec prec, crk_leaves** out, hipStream_t stream) {
-    if (!out) return fail(CRK_EINVAL, "out is NULL");
+                         double split_extent, crk_prec prec, void* ws, size_t ws_bytes,
+                         size_t* ws_needed, crk_leaves** out, hipStream_t stream) {
+    if (!out || !ws_needed) return fail(CRK_EINVAL, "out and ws_needed must not be NULL");
     *out = nullptr;
+    *ws_needed = 0;
     if (n < 0 || n >= (int64_t(1) << 31)) return fail(CRK_EINVAL, "n = %lld out of range [0, 2^31)", (long long)n);
     if (prec != CRK_F32 && prec != CRK_F64) return fail(CRK_EINVAL, "unknown precision");
     if (leaf_max < 1 || leaf_max > (1 << 20)) return fail(CRK_EINVAL, "leaf_max out of range [1, 2^20]");
@@ -1042,6 +1089,8 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
     if (n > 0 && !h && !(r_fixed > 0.0 && r_fixed < 0.5))
         return fail(CRK_EINVAL, "fixed radius must be in (0, 1/2) of the box");
     if (n > 0 && (!x || !y || !z)) return fail(CRK_EINVAL, "positions are NULL");
+    if (ws_bytes > 0 && !ws) return fail(CRK_EINVAL, "ws is NULL but ws_bytes = %zu", ws_bytes);
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(CRK_EINVAL, "ws must be 256-byte aligned");
     const auto t0 = std::chrono::steady_clock::now();
 
     crk_leaves* L = new crk_leaves();
@@ -1049,19 +1098,26 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
     L->hydro = h != nullptr;
     L->prec = prec;
     L->r_fixed = r_fixed;
+    L->ws = static_cast<char*>(ws);
+    L->ws_bytes = ws_bytes;
     int dev = 0;
-    int rc = CRK_OK;
     auto bail = [&](int code) {
         drop_timed(L);
-        release(L);
         delete L;
         return code;
     };
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&L->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return bail(fail(CRK_EHIP, "cannot query the device"));
-    if ((rc = dalloc(&L->counter, kMaxGroups)) || (rc = dalloc(&L->counts, 4))) return bail(rc);
+    const int64_t nt = (n + kWave - 1) / kWave;
+    L->n_tiles = nt;
     if (n == 0) {
+        Carver c(nullptr);
+        carve_part_a(L, c, 0, 0, 0);
+        *ws_needed = c.used();
+        if (ws_bytes < *ws_needed) return bail(fail(CRK_ENOSPC, "workspace of %zu bytes, need %zu", ws_bytes, *ws_needed));
+        Carver cw(L->ws);
+        carve_part_a(L, cw, 0, 0, 0);
         *out = L;
         return CRK_OK;
     }
@@ -1116,21 +1172,58 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
     tin.leaf_max = leaf_max;
     tin.leaf_min = leaf_min;
     tin.split_extent = split_extent;
+    // the same call as the one that last ran out of workspace: resume from its host state
+    BuildMemo& memo = g_memo;
+    const bool resume = memo.valid && memo.n == n && memo.leaf_max == leaf_max && memo.leaf_min == leaf_min &&
+                        memo.hydro == L->hydro && memo.r_fixed == r_fixed && memo.split_extent == split_extent &&
+                        memo.hx == hx && memo.hy == hy && memo.hz == hz && memo.H == H;
     crk::TreeOutput tout;
+    std::vector<int32_t> hc;  // list lengths in tree order
+    bool counted = false;
     const char* terr = nullptr;
-    if (!crk::build_tree(tin, tout, &terr)) return bail(fail(CRK_EINVAL, "tree: %s", terr));
+    if (resume) {
+        tout = std::move(memo.tree);
+        hc = std::move(memo.counts);
+        counted = memo.counted;
+    } else if (!crk::build_tree(tin, tout, &terr)) {
+        return bail(fail(CRK_EINVAL, "tree: %s", terr));
+    }
+    memo.valid = false;
+    auto keep_for_retry = [&](bool with_counts) {
+        memo.valid = true;
+        memo.counted = with_counts;
+        memo.n = n;
+        memo.leaf_max = leaf_max;
+        memo.leaf_min = leaf_min;
+        memo.hydro = L->hydro;
+        memo.r_fixed = r_fixed;
+        memo.split_extent = split_extent;
+        memo.hx = std::move(hx);
+        memo.hy = std::move(hy);
+        memo.hz = std::move(hz);
+        memo.H = std::move(H);
+        memo.tree = std::move(tout);
+        memo.counts = std::move(hc);
+    };
     L->n_leaves = int64_t(tout.leaf_begin.size());
-    L->n_tiles = (n + kWave - 1) / kWave;
-    const int64_t nt = L->n_tiles;
+    const size_t nr = tout.rng.size() / 2;
 
-    if ((rc = dalloc(&L->perm, n)) || (rc = dalloc(&L->quant, n)) || (rc = dalloc(&L->rng_off, nt + 1)) ||
-        (rc = dalloc(&L->order_cull, nt)) || (rc = dalloc(&L->order_pair, nt)) ||
-        (rc = dalloc(&L->order_tree, nt)) || (rc = dalloc(&L->partials, 8 * nt + 8 * kTotalsBlocks)))
-        return bail(rc);
-    if (L->hydro && ((rc = dalloc(&L->Hd, n)) || (rc = dalloc(&L->cnt, n)) || (rc = dalloc(&L->ell_off, nt)) ||
-                     (rc = dalloc(&L->ell_len, nt)) || (rc = dalloc(&L->cnt_gather, n)) ||
-                     (rc = dalloc(&L->ell_len_gather, nt)) || (rc = dalloc(&L->build_err, 1))))
-        return bail(rc);
+    // part A of the workspace
+    {
+        Carver c(nullptr);
+        carve_part_a(L, c, n, nt, nr);
+        if (c.used() > ws_bytes) {
+            *ws_needed = c.used();  // the lists come on top: not counted yet
+            keep_for_retry(false);
+            return bail(fail(CRK_ENOSPC, "workspace of %zu bytes, need at least %zu (before the lists)",
+                             ws_bytes, *ws_needed));
+        }
+        Carver cw(L->ws);
+        carve_part_a(L, cw, n, nt, nr);
+        *ws_needed = cw.used();
+    }
+    const size_t part_a = *ws_needed;
+
     // tree-order fixed-point positions and support radii, candidate ranges and
     // the tile orders of one tree order, uploaded (host buffers must outlive
     // the asynchronous copies: they are synchronised before reuse)
@@ -1138,8 +1231,8 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
     std::vector<double> hH(L->hydro ? n : 0);
     std::vector<int32_t> order(nt), tree_order(nt);
     std::iota(tree_order.begin(), tree_order.end(), 0);
-    size_t rng_alloc = 0;
     auto upload = [&](const crk::TreeOutput& t) -> int {
+        if (t.rng.size() / 2 != nr) return fail(CRK_EHIP, "tree rebuild changed the candidate ranges");
         for (int64_t s = 0; s < n; ++s) {
             const int32_t i = t.perm[s];
             uint32_t hw = 0;
@@ -1154,14 +1247,6 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
         std::iota(order.begin(), order.end(), 0);
         std::stable_sort(order.begin(), order.end(),
                          [&](int32_t a, int32_t b) { return t.tile_cand[a] > t.tile_cand[b]; });
-        const size_t nr = t.rng.size() / 2;
-        if (nr > rng_alloc) {
-            if (L->rng && hipFree(L->rng) != hipSuccess) return fail(CRK_EHIP, "freeing candidate ranges failed");
-            L->rng = nullptr;
-            int e = dalloc(&L->rng, nr);
-            if (e) return e;
-            rng_alloc = nr;
-        }
         if (hipMemcpyAsync(L->perm, t.perm.data(), n * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
             hipMemcpyAsync(L->quant, hq.data(), n * 16, hipMemcpyHostToDevice, stream) != hipSuccess ||
             hipMemcpyAsync(L->rng_off, t.rng_off.data(), (nt + 1) * 4, hipMemcpyHostToDevice, stream) !=
@@ -1177,31 +1262,32 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
         L->stats[2] = t.cand_pairs;
         return CRK_OK;
     };
+    int rc = CRK_OK;
     if ((rc = upload(tout))) return bail(rc);
     L->stats[0] = L->n_leaves;
     L->stats[1] = nt;
+    L->timing = true;  // the list build is always timed (read by crk_kernel_times)
 
     if (L->hydro) {
-        // count pass
-        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, L->counter);
-        L->timing = true;  // the list build is always timed (read by crk_kernel_times)
-        {
-            TimeScope ts(L, stream, CRK_K_CULL);
-            hipLaunchKernelGGL(k_cull<false>, dim3(grid_1wave(L)), dim3(kWave), 0, stream,
-                               make_queue(L, L->order_cull), int(n), L->quant, L->rng_off, L->rng,
-                               L->cnt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
-        }
-        if (hipGetLastError() != hipSuccess) return bail(fail(CRK_EHIP, "launch cull count failed"));
-        std::vector<int32_t> hc(n);
-        if (hipMemcpyAsync(hc.data(), L->cnt, n * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-            hipStreamSynchronize(stream) != hipSuccess)
-            return bail(fail(CRK_EHIP, "cull count failed"));
-        // Tiles of similar list lengths: order every leaf by decreasing count
-        // (the leaves, their boxes and every particle's count stay the same;
-        // only the tiles and their candidate ranges change), so that a tile's
-        // longest list -- the slots all its lanes step through -- is closer
-        // to its average one.
-        {
+        if (!counted) {
+            // count pass
+            hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, L->counter);
+            {
+                TimeScope ts(L, stream, CRK_K_CULL);
+                hipLaunchKernelGGL(k_cull<false>, dim3(grid_1wave(L)), dim3(kWave), 0, stream,
+                                   make_queue(L, L->order_cull), int(n), L->quant, L->rng_off, L->rng,
+                                   L->cnt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+            }
+            if (hipGetLastError() != hipSuccess) return bail(fail(CRK_EHIP, "launch cull count failed"));
+            hc.resize(n);
+            if (hipMemcpyAsync(hc.data(), L->cnt, n * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+                hipStreamSynchronize(stream) != hipSuccess)
+                return bail(fail(CRK_EHIP, "cull count failed"));
+            // Tiles of similar list lengths: order every leaf by decreasing count
+            // (the leaves, their boxes and every particle's count stay the same;
+            // only the tiles and their candidate ranges change), so that a tile's
+            // longest list -- the slots all its lanes step through -- is closer
+            // to its average one.
             std::vector<int32_t> work(n);
             for (int64_t s = 0; s < n; ++s) work[tout.perm[s]] = hc[s];
             tin.weight = work.data();
@@ -1212,10 +1298,10 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
             tout = std::move(tb);
             if ((rc = upload(tout))) return bail(rc);
             for (int64_t s = 0; s < n; ++s) hc[s] = work[tout.perm[s]];
-            if (hipMemcpyAsync(L->cnt, hc.data(), n * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
-                hipStreamSynchronize(stream) != hipSuccess)
-                return bail(fail(CRK_EHIP, "uploading list counts failed"));
         }
+        if (hipMemcpyAsync(L->cnt, hc.data(), n * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+            return bail(fail(CRK_EHIP, "uploading list counts failed"));
         std::vector<int32_t> len(nt, 0);
         std::vector<int64_t> off(nt, 0);
         int64_t total = 0, entries = 0;
@@ -1229,13 +1315,26 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
             off[t] = total;
             total += int64_t(mx) * kWave;
         }
-        if ((rc = dalloc(&L->nbr, size_t(total)))) return bail(rc);
+        // part B: the lists
+        {
+            Carver c(nullptr);
+            c.off = part_a;
+            carve_part_b(L, c, total);
+            if (c.used() > ws_bytes) {
+                *ws_needed = c.used();
+                keep_for_retry(true);
+                return bail(fail(CRK_ENOSPC, "workspace of %zu bytes, need %zu", ws_bytes, *ws_needed));
+            }
+            Carver cw(L->ws);
+            cw.off = part_a;
+            carve_part_b(L, cw, total);
+            *ws_needed = cw.used();
+        }
         if (hipMemcpyAsync(L->ell_off, off.data(), nt * 8, hipMemcpyHostToDevice, stream) != hipSuccess ||
             hipMemcpyAsync(L->ell_len, len.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
             return bail(fail(CRK_EHIP, "uploading list offsets failed"));
         hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, L->counter);
-        if (hipMemsetAsync(L->build_err, 0, sizeof(int32_t), stream) != hipSuccess)
-            return bail(fail(CRK_EHIP, "clearing the list check failed"));
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, L->build_err);
         {
             TimeScope ts(L, stream, CRK_K_CULL);
             hipLaunchKernelGGL(k_cull<true>, dim3(grid_1wave(L)), dim3(kWave), 0, stream,
@@ -1243,7 +1342,6 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
                                L->cnt, L->ell_off, L->ell_len, L->nbr, L->cnt_gather, L->ell_len_gather,
                                L->build_err);
         }
-        L->timing = false;
         if (hipGetLastError() != hipSuccess) return bail(fail(CRK_EHIP, "launch cull fill failed"));
         // pair passes: tiles with the longest lists first
         std::vector<int32_t> po(nt);
@@ -1259,22 +1357,25 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
             return bail(fail(CRK_EHIP, "neighbour lists: count and fill passes disagree on %d particles",
                              mismatched));
         // shared-record slots: reorder the lists, name each slot's particles
-        if ((rc = dalloc(&L->srec, size_t(total))) || (rc = dalloc(&L->sidx, size_t(total))) ||
-            (rc = dalloc(&L->scnt, size_t(total / kWave))))
-            return bail(rc);
-        hipLaunchKernelGGL(k_schedule, dim3(unsigned(nt)), dim3(kWave), 0, stream, int(n), L->cnt, L->cnt_gather,
-                           L->ell_off, L->ell_len, L->nbr, L->srec, L->sidx, L->scnt);
+        {
+            TimeScope ts(L, stream, CRK_K_CULL);
+            hipLaunchKernelGGL(k_schedule, dim3(unsigned(nt)), dim3(kWave), 0, stream, int(n), L->cnt,
+                               L->cnt_gather, L->ell_off, L->ell_len, L->nbr, L->srec, L->sidx, L->scnt);
+        }
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(stream) != hipSuccess)
             return bail(fail(CRK_EHIP, "list schedule failed"));
         L->stats[3] = entries;
         L->stats[6] = total - entries;
     }
+    L->timing = false;
     if (hipStreamSynchronize(stream) != hipSuccess) return bail(fail(CRK_EHIP, "build sync failed"));
     L->stats[7] = std::chrono::duration_cast<std::chrono::microseconds>(
                       std::chrono::steady_clock::now() - t0).count();
     *out = L;
     return CRK_OK;
 }
+
+extern "C" {
 
 int crk_leaves_stats(crk_leaves* L, int64_t* host_out) {
     if (!L || !host_out) return fail(CRK_EINVAL, "null argument");

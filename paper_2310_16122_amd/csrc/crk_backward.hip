@@ -670,16 +670,22 @@ template <class T> T* carve(char*& p, size_t count) {
     return r;
 }
 
+// scratch of one backward call: records and per-particle partial adjoints
+template <class R> size_t scratch_bytes(int64_t n) {
+    const size_t per = sizeof(RecBwd<R>) + sizeof(RecMom<R>) + sizeof(RecQV<R>) + sizeof(RecVA<R>) +
+                       sizeof(R) * (16 + 2 + 4 + 2);
+    return per * size_t(n) + 8 * 256;  // eight arrays, each on a 256-byte boundary
+}
+
 template <class R>
 int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const crk_corr* C,
                   double gamma, const R* ga, const R* gdu, R* gx, R* gv, R* gu, hipStream_t st) {
     const int n = int(L->n);
     int rc = pack_positions<R>(L, g->x, g->y, g->z, static_cast<const R*>(g->h), st);
     if (rc) return rc;
-    const size_t per = sizeof(RecBwd<R>) + sizeof(RecMom<R>) + sizeof(RecQV<R>) + sizeof(RecVA<R>) +
-                       sizeof(R) * (16 + 2 + 4 + 2);
-    if ((rc = ensure_scratch(L, per * size_t(n) + 8 * 256))) return rc;
-    char* p = static_cast<char*>(L->scratch);
+    void* sp = nullptr;
+    if ((rc = pass_scratch(L, scratch_bytes<R>(n), &sp))) return rc;
+    char* p = static_cast<char*>(sp);
     RecBwd<R>* rec = carve<RecBwd<R>>(p, n);
     R* aux = carve<R>(p, 2 * size_t(n));
     RecQV<R>* qv = carve<RecQV<R>>(p, n);
@@ -746,6 +752,10 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
 }
 
 }  // namespace
+
+size_t crk::backward_scratch_bytes(int64_t n, bool f64) {
+    return f64 ? scratch_bytes<double>(n) : scratch_bytes<float>(n);
+}
 
 extern "C" int crk_accel_energy_backward(crk_leaves* L, const crk_gas* g, const void* V,
                                          const void* rho, const crk_corr* C, double gamma,

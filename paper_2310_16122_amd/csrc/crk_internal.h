@@ -651,6 +651,10 @@ struct crk_leaves {
     int32_t* scnt = nullptr;   // per slot: size of the set
     double* partials = nullptr;
     unsigned long long* counts = nullptr;
+    // the caller's workspace: every device array above points into it, and
+    // the per-pass scratch (records, adjoint partials) is its last part
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
     int64_t stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -667,16 +671,26 @@ struct crk_leaves {
 
 namespace crk {
 
-template <class T> int dalloc(T** p, size_t count) {
-    *p = nullptr;
-    if (count == 0) count = 1;
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
-    if (e != hipSuccess) return fail(CRK_ENOMEM, "hipMalloc(%zu bytes): %s", count * sizeof(T), hipGetErrorString(e));
-    return CRK_OK;
-}
+// Lays arrays out in the caller's workspace, each on a 256-byte boundary.
+// With a null base it only measures (the pointers it returns are null).
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(char* b) : base(b) {}
+    template <class T> T* take(size_t count) {
+        off = (off + 255) / 256 * 256;
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += (count == 0 ? 1 : count) * sizeof(T);
+        return p;
+    }
+    size_t used() const { return (off + 255) / 256 * 256; }
+};
 
-void release(crk_leaves* L);
-int ensure_scratch(crk_leaves* L, size_t bytes);
+// Per-pass scratch of a handle (carved from its workspace at build time and
+// sized for both precisions): CRK_ENOSPC if a pass would need more.
+int pass_scratch(crk_leaves* L, size_t bytes, void** out);
+// Scratch the backward pass needs for n particles in precision prec.
+size_t backward_scratch_bytes(int64_t n, bool f64);
 void drop_timed(crk_leaves* L);
 Queue make_queue(const crk_leaves* L, const int32_t* order);
 int grid_1wave(const crk_leaves* L);

@@ -38,3 +38,20 @@ def test_last_error_returns_a_string():
 
     lib = crk.load_library()
     assert isinstance(lib.crk_last_error(), bytes)
+
+
+def test_library_imports_no_device_allocator():
+    """The library allocates no device memory: it does not even link hipMalloc,
+    hipFree or their relatives (the handle lives in the caller's workspace)."""
+    import subprocess
+
+    import paper_2310_16122_amd as crk
+
+    if not os.path.exists(crk.LIB_PATH):
+        pytest.fail("libcrk.so is not built (run __graft_entry__.build())")
+    out = subprocess.run(["nm", "-D", "--undefined-only", crk.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    imported = {line.split()[-1].split("@")[0] for line in out.splitlines() if line.strip()}
+    for name in ("hipMalloc", "hipFree", "hipMallocAsync", "hipFreeAsync", "hipMallocManaged",
+                 "hipExtMallocWithFlags", "hipHostMalloc", "hipMallocPitch", "hipMalloc3D"):
+        assert name not in imported, name

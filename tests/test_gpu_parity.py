@@ -19,6 +19,9 @@ from tests.cases import dense_case, fallback_case, planar_case
 pytestmark = pytest.mark.gpu
 
 TOL = {"f64": 1e-12, "f32": 1e-5}
+# C5 backward, FP32 mixed path against the FP64 form, normwise over all 2^24
+# particles (measured values in the test's output)
+C5_BACKWARD_TOL = {"gx": 1e-4, "gv": 1e-4, "gu": 1e-4}
 KEYS = ("V", "rho", "A", "B", "dA", "dB", "a", "dudt")
 
 
@@ -223,10 +226,49 @@ def test_full_size_sampled_closure(crk, prec):
     assert np.abs(T[:3]).max() <= lim * T[4]
 
 
+_listed = {}
+
+
+def oracle_listed(name):
+    """The oracle's full chain over exact neighbour lists (equal to its
+    brute-force chain bit for bit, pinned on the CPU), cached per workload."""
+    if name not in _listed:
+        cfg = synth.make_config(name)
+        off, idx = oracle.neighbour_lists(cfg)
+        _listed[name] = (cfg, oracle.hydro_listed(cfg, off, idx))
+    return _listed[name]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("name", ["C4", "C2"])
+def test_full_size_every_particle(crk, name, prec):
+    """C4 (64^3) and C2 (128^3) at full size, leaf 128: every output of every
+    particle against the oracle's FP64 chain, element by element."""
+    cfg, ref = oracle_listed(name)
+    print(f"case {name} full every particle n={cfg['n']} prec={prec}", flush=True)
+    got, L = run_gpu(crk, cfg, prec, leaf_max=128)
+    errs = {k: normwise(got[k], ref[k]) for k in KEYS}
+    print(errs, flush=True)
+    for k in KEYS:
+        assert errs[k] <= TOL[prec], (k, errs[k])
+    assert int(got["n_fallback"][0]) == 0 == ref["n_fallback"]
+    T = got["totals"]
+    lim = 1e-13 if prec == "f64" else 2e-6
+    assert np.abs(T[:3]).max() <= lim * T[4]
+    assert abs(T[3]) <= lim * T[5]
+    st = L.stats()
+    if name == "C4":
+        assert st["pairs_gather"] == oracle.count_pairs(cfg, 0)[0]
+        assert st["pairs_force"] == oracle.count_pairs(cfg, 1)[0]
+    L.free()
+
+
 def test_c5_full_size_sampled(crk):
     """C5 at 256^3 (32-256 neighbours over a 16x density contrast), leaf 128, the
-    benchmarked tuning: 32 sampled particles of the FP32 and FP64 forward chains
-    against the oracle's per-target closure, and the momentum totals."""
+    benchmarked tuning: 128 sampled particles of the FP32 and FP64 forward chains
+    against the oracle's per-target closure, and the momentum totals; then the
+    FP32 mixed path against the FP64 GPU form over every particle, forward and
+    backward (gradients of L = sum w |a|^2 + sum c du/dt)."""
     cfg = synth.make_config("C5")
     print(f"case C5 full n={cfg['n']}", flush=True)
     t = synth.sample_targets(cfg["n"], 128, seed=17)
@@ -244,12 +286,27 @@ def test_c5_full_size_sampled(crk):
         T = got["totals"]
         assert np.abs(T[:3]).max() <= (1e-13 if prec == "f64" else 2e-6) * T[4]
         res[prec] = {k: got[k] for k in KEYS}
+        # the backward with the same upstream adjoints (from the FP64 forward's a)
+        if prec == "f64":
+            a64 = torch.as_tensor(got["a"]).cuda()
+        g = crk.gas_to_device(cfg, prec)
+        o = crk.forward(L, g, cfg["gamma"], prec, store_sums=True)
+        dt = o["a"].dtype
+        ga = (2.0 * torch.as_tensor(cfg["w"]).cuda()[:, None] * a64).to(dt).contiguous()
+        gdu = torch.as_tensor(cfg["c"]).to(dt).cuda()
+        grads = crk.crk_accel_energy_backward(L, g, o["V"], o["rho"], (o["A"], o["B"], o["dA"], o["dB"], o["M"]),
+                                              ga, gdu, cfg["gamma"], prec)
+        res[prec].update({k: v.double().cpu().numpy() for k, v in zip(("gx", "gv", "gu"), grads)})
         L.free()
-        del got
+        del got, g, o, grads
         torch.cuda.empty_cache()
     # the FP32 mixed path against the FP64 GPU path over every particle
+    errs = {k: normwise(res["f32"][k], res["f64"][k]) for k in KEYS + ("gx", "gv", "gu")}
+    print("C5 FP32 vs FP64", errs, flush=True)
     for k in KEYS:
-        assert normwise(res["f32"][k], res["f64"][k]) <= TOL["f32"], k
+        assert errs[k] <= TOL["f32"], k
+    for k in ("gx", "gv", "gu"):
+        assert errs[k] <= C5_BACKWARD_TOL[k], (k, errs[k])
 
 
 # ---------------------------------------------------------------- gravity
@@ -369,19 +426,28 @@ def test_gravity_spread_tiles(crk, prec):
         assert np.all(err <= TOL[prec] * np.abs(ref).max() + borderline_bound(cfg)), (leaf_max, err.max())
 
 
-@pytest.mark.parametrize("tuning", [None, {"xcd_groups": 1, "tile_order": 1},
-                                    {"persistent": 1, "waves_per_cu": 8}])
-def test_gravity_full_size_sampled(crk, tuning):
-    """C3 at 2 x 128^3, leaf 512 (the benchmarked launch), FP32: 256 sampled
-    particles against the brute-force oracle."""
-    cfg = synth.make_config("C3")
-    print(f"case C3 full n={cfg['n']} tuning={tuning}", flush=True)
-    a, L = gravity_gpu(crk, cfg, "f32", leaf_max=512, tuning=tuning)
-    t = synth.sample_targets(cfg["n"], 256, seed=13)
-    ref = oracle.gravity(cfg, t)
-    bound = borderline_bound_targets(cfg, t)
+_c3 = {}
+
+
+def c3_reference():
+    if not _c3:
+        cfg = synth.make_config("C3")
+        t = synth.sample_targets(cfg["n"], 256, seed=13)
+        _c3.update(cfg=cfg, t=t, ref=oracle.gravity(cfg, t), bound=borderline_bound_targets(cfg, t))
+    return _c3["cfg"], _c3["t"], _c3["ref"], _c3["bound"]
+
+
+@pytest.mark.parametrize("prec,tuning", [("f32", None), ("f32", {"xcd_groups": 1, "tile_order": 1}),
+                                         ("f32", {"persistent": 1, "waves_per_cu": 8}), ("f64", None)])
+def test_gravity_full_size_sampled(crk, prec, tuning):
+    """C3 at 2 x 128^3, leaf 512 (the benchmarked launch): 256 sampled particles
+    against the brute-force oracle, FP32 (three launch forms) and FP64."""
+    cfg, t, ref, bound = c3_reference()
+    print(f"case C3 full n={cfg['n']} prec={prec} tuning={tuning}", flush=True)
+    a, L = gravity_gpu(crk, cfg, prec, leaf_max=512, tuning=tuning)
     err = np.abs(a[t] - ref).max(1)
-    assert np.all(err <= TOL["f32"] * np.abs(a).max() + bound), err.max()
+    assert np.all(err <= TOL[prec] * np.abs(a).max() + bound), err.max()
+    L.free()
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -466,3 +532,55 @@ def test_invalid_arguments(crk):
     m = torch.ones(100, dtype=torch.float32, device="cuda")
     with pytest.raises(crk.CrkError):
         crk.sr_gravity(L, x, x, x, m, 1.0, 0.0, r_cut=0.2, prec="f32")  # r_cut > r_fixed
+
+
+# ---------------------------------------------------------------- caller-owned workspace
+def test_workspace_protocol(crk):
+    """crk_build_leaf_pairs through the C ABI with too small a workspace: it
+    returns CRK_ENOSPC and sets ws_needed (first the part without the lists,
+    then the exact total once the lists are counted), and the call with that
+    much succeeds and gives the same results as a build through the wrapper."""
+    import ctypes
+
+    cfg, _ = oracle_full("C2", 21)
+    g = crk.gas_to_device(cfg, "f32")
+    lib = crk.load_library()
+    n = cfg["n"]
+    need = ctypes.c_size_t(0)
+    out = ctypes.c_void_p()
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def call(ws, nbytes, h=g["h"], r_fixed=0.0, needp=ctypes.byref(need)):
+        return lib.crk_build_leaf_pairs(n, g["x"].data_ptr(), g["y"].data_ptr(), g["z"].data_ptr(),
+                                        None if h is None else h.data_ptr(), r_fixed, 64, 1, 0.0, 0,
+                                        None if ws is None else ws.data_ptr(), nbytes, needp,
+                                        ctypes.byref(out), stream)
+
+    assert call(None, 0, needp=None) == -1  # ws_needed is required
+    assert call(None, 0) == crk.CRK_ENOSPC and not out.value
+    part_a = need.value
+    assert part_a > 0
+    ws = torch.empty(part_a, dtype=torch.uint8, device="cuda")
+    assert call(ws, part_a) == crk.CRK_ENOSPC and not out.value  # the lists come on top
+    total = need.value
+    assert total > part_a
+    ws = torch.empty(total + 4096, dtype=torch.uint8, device="cuda")
+    view = ws[256:]  # an aligned view works; an unaligned one is refused
+    assert call(ws[1:], total) == -1
+    assert call(view, total) == 0 and out.value
+    assert need.value == total
+    L = crk.Leaves(out, n, True, "f32", ws)
+    got = crk.forward(L, g, cfg["gamma"], "f32")
+    ref, _ = run_gpu(crk, cfg, "f32", leaf_max=64)
+    torch.cuda.synchronize()
+    for k in KEYS:
+        assert np.array_equal(got[k].double().cpu().numpy(), ref[k]), k
+    # one byte short: refused again with the same figure
+    short = torch.empty(total - 1, dtype=torch.uint8, device="cuda")
+    assert call(short, total - 1) == crk.CRK_ENOSPC and need.value == total
+    # fixed-radius mode needs no lists: the first figure is exact
+    assert call(None, 0, h=None, r_fixed=0.05) == crk.CRK_ENOSPC
+    ws_g = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+    assert call(ws_g, need.value, h=None, r_fixed=0.05) == 0
+    lib.crk_leaves_free(out)
+    L.free()

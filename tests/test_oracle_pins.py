@@ -441,3 +441,41 @@ def test_passes_over_lists_match_brute_force(tiny, oracle_lib):
         assert np.abs(A - o["A"][t]).max() <= 1e-12 * np.abs(o["A"]).max()
         assert np.abs(ax - o["a"][t, 0]).max() <= 1e-12 * np.abs(o["a"]).max()
         assert np.abs(du - o["dudt"][t]).max() <= 1e-12 * np.abs(o["dudt"]).max()
+
+
+def test_gravity_over_lists_matches_brute_force(oracle_lib):
+    """The listed form of the gravity pass (candidates within r_c) gives the brute-force values."""
+    from scipy.spatial import cKDTree
+
+    g = synth.make_gravity(n_side=8)
+    P = np.stack([g["x"], g["y"], g["z"]], 1)
+    t = synth.sample_targets(g["n"], 40, seed=3)
+    rows = [np.asarray(sorted(c), dtype=np.int64)
+            for c in cKDTree(P, boxsize=1.0).query_ball_point(P[t], g["r_cut"])]
+    off = np.concatenate([[0], np.cumsum([len(r) for r in rows])])
+    ref = oracle_lib.gravity(g, t)
+    for threads in (0, 1):
+        a = oracle_lib.gravity_listed(g, t, off, np.concatenate(rows), threads)
+        assert np.abs(a - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------- listed chain (full-size references)
+@pytest.mark.parametrize("name,n_side", [("C1", None), ("C2", 16), ("C5", 16)])
+def test_listed_chain_is_the_brute_force_chain(oracle_lib, name, n_side):
+    """With the exact neighbour lists (every j within max(2h_i, 2h_j), each
+    checked against dense masks) the listed chain sums the same terms in the
+    same order as the brute-force chain: equal bit for bit."""
+    g = synth.make_config(name, n_side)
+    off, idx = oracle_lib.neighbour_lists(g)
+    _, r = dense_crk.separations(g)
+    H = 2.0 * g["h"]
+    mask = (r < np.maximum(H[:, None], H[None, :])) & ~np.eye(g["n"], dtype=bool)
+    for i in range(0, g["n"], 97):
+        row = idx[off[i]:off[i + 1]]
+        assert np.all(np.diff(row) > 0)
+        assert set(np.nonzero(mask[i])[0]) <= set(row)
+    assert off[-1] - mask.sum() <= 1e-6 * mask.sum()  # extras only inside the margin
+    a, b = oracle_lib.hydro(g), oracle_lib.hydro_listed(g, off, idx)
+    for k in ("V", "rho", "A", "B", "dA", "dB", "a", "dudt", "totals"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["n_fallback"] == b["n_fallback"]
