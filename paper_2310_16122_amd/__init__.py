@@ -146,7 +146,8 @@ class Leaves:
     into (tree order, interaction lists, scratch: a uint8 torch tensor)."""
 
     def __init__(self, handle, n, hydro, prec, ws):
-        self._h = handle
+        # a copy of the pointer: the caller's ctypes object may be reused
+        self._h = ctypes.c_void_p(handle.value if isinstance(handle, ctypes.c_void_p) else handle)
         self.n = n
         self.hydro = hydro
         self.prec = prec

@@ -882,15 +882,15 @@ int corrections_impl(crk_leaves* L, const crk_gas* g, const R* V, const crk_corr
     return CRK_OK;
 }
 
+// The force pass with its scratch given: rec holds n records, partials
+// 8 (n_tiles + kTotalsBlocks) doubles.
 template <class R>
-int accel_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const crk_corr* C,
-               double gamma, R* a, R* dudt, double* totals, hipStream_t st) {
+int accel_run(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const crk_corr* C,
+              double gamma, R* a, R* dudt, double* totals, RecAcc<R>* rec, double* partials,
+              hipStream_t st) {
     const int n = int(L->n);
     int rc = pack_positions<R>(L, g->x, g->y, g->z, static_cast<const R*>(g->h), st);
     if (rc) return rc;
-    void* sp = nullptr;
-    if ((rc = pass_scratch(L, sizeof(RecAcc<R>) * size_t(n), &sp))) return rc;
-    RecAcc<R>* rec = static_cast<RecAcc<R>*>(sp);
     {
     TimeScope tp(L, st, CRK_K_PACK);
     hipLaunchKernelGGL(k_pack_acc<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, L->quant,
@@ -908,21 +908,32 @@ int accel_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const 
         const int bw = L->tune.block_waves;
         hipLaunchKernelGGL(kern, dim3(grid_nwave(L)), dim3(kWave * bw), stage_bytes<RecAcc<R>>(bw), st,
                            make_queue(L, L->order_pair), n, lists(L), L->perm, rec,
-                           static_cast<const R*>(g->m), L->tune.kahan_chunk, a, dudt, L->partials);
+                           static_cast<const R*>(g->m), L->tune.kahan_chunk, a, dudt, partials);
     }
     LAUNCH_CHECK("accel");
     if (totals) {
         TimeScope tt(L, st, CRK_K_PACK);
         const int nt = int(L->n_tiles);
         const int per = (nt + kTotalsBlocks - 1) / kTotalsBlocks;
-        double* blocks = L->partials + 8 * int64_t(nt);  // kTotalsBlocks x 8 after the tile partials
-        hipLaunchKernelGGL(k_totals_blocks, dim3(kTotalsBlocks), dim3(256), 0, st, nt, per, L->partials, blocks);
+        double* blocks = partials + 8 * int64_t(nt);  // kTotalsBlocks x 8 after the tile partials
+        hipLaunchKernelGGL(k_totals_blocks, dim3(kTotalsBlocks), dim3(256), 0, st, nt, per, partials, blocks);
         hipLaunchKernelGGL(k_totals_blocks, dim3(1), dim3(256), 0, st, kTotalsBlocks, kTotalsBlocks, blocks,
                            totals);
         LAUNCH_CHECK("totals");
     }
     return CRK_OK;
 }
+
+// The force pass on the handle's workspace.
+template <class R>
+int accel_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const crk_corr* C,
+               double gamma, R* a, R* dudt, double* totals, hipStream_t st) {
+    void* sp = nullptr;
+    int rc = pass_scratch(L, sizeof(RecAcc<R>) * size_t(L->n), &sp);
+    if (rc) return rc;
+    return accel_run<R>(L, g, V, rho, C, gamma, a, dudt, totals, static_cast<RecAcc<R>*>(sp), L->partials, st);
+}
+
 
 template <class R>
 int gravity_impl(crk_leaves* L, const double* x, const double* y, const double* z, const R* m,
@@ -1035,17 +1046,19 @@ struct BuildMemo {
 };
 thread_local BuildMemo g_memo;
 
-// Workspace layout of a handle.  Part A (everything but the neighbour lists)
-// depends on n, the tile count and the number of candidate ranges; part B
-// holds the lists and their per-slot sets (hydro mode, `entries` slots).
-void carve_part_a(crk_leaves* L, Carver& c, int64_t n, int64_t nt, size_t nr) {
+// Workspace layout of a handle: part A (everything that depends only on n and
+// the tile count), then the candidate ranges of the tiles (their number
+// depends on where the tiles are cut, which the list-length balancing of the
+// hydro build changes), then part B: the neighbour lists and their per-slot
+// sets (hydro mode, `slots` list slots).  Returns the bytes used; with a null
+// base it only measures.
+void carve_part_a(crk_leaves* L, Carver& c, int64_t n, int64_t nt) {
     L->counter = c.take<int32_t>(kMaxGroups);
     L->counts = c.take<unsigned long long>(4);
     L->build_err = c.take<int32_t>(kMaxGroups);  // cleared by k_reset
     L->perm = c.take<int32_t>(n);
     L->quant = c.take<uint4>(n);
     L->rng_off = c.take<int32_t>(nt + 1);
-    L->rng = c.take<int2>(nr);
     L->order_cull = c.take<int32_t>(nt);
     L->order_pair = c.take<int32_t>(nt);
     L->order_tree = c.take<int32_t>(nt);
@@ -1071,6 +1084,15 @@ void carve_part_b(crk_leaves* L, Carver& c, int64_t slots) {
     L->srec = c.take<uint32_t>(size_t(slots));
     L->sidx = c.take<uint8_t>(size_t(slots));
     L->scnt = c.take<int32_t>(size_t(slots / kWave));
+}
+
+// slots < 0: no lists (fixed-radius mode, or hydro before the lists are counted)
+size_t carve(crk_leaves* L, char* base, int64_t n, int64_t nt, size_t nr, int64_t slots) {
+    Carver c(base);
+    carve_part_a(L, c, n, nt);
+    L->rng = c.take<int2>(nr);
+    if (slots >= 0) carve_part_b(L, c, slots);
+    return c.used();
 }
 
 }  // namespace
@@ -1112,12 +1134,9 @@ extern "C" int crk_build_leaf_pairs(int64_t n, const double* x, const double* y,
     const int64_t nt = (n + kWave - 1) / kWave;
     L->n_tiles = nt;
     if (n == 0) {
-        Carver c(nullptr);
-        carve_part_a(L, c, 0, 0, 0);
-        *ws_needed = c.used();
+        *ws_needed = carve(L, nullptr, 0, 0, 0, -1);
         if (ws_bytes < *ws_needed) return bail(fail(CRK_ENOSPC, "workspace of %zu bytes, need %zu", ws_bytes, *ws_needed));
-        Carver cw(L->ws);
-        carve_part_a(L, cw, 0, 0, 0);
+        carve(L, L->ws, 0, 0, 0, -1);
         *out = L;
         return CRK_OK;
     }
@@ -1206,23 +1225,7 @@ extern "C" int crk_build_leaf_pairs(int64_t n, const double* x, const double* y,
         memo.counts = std::move(hc);
     };
     L->n_leaves = int64_t(tout.leaf_begin.size());
-    const size_t nr = tout.rng.size() / 2;
-
-    // part A of the workspace
-    {
-        Carver c(nullptr);
-        carve_part_a(L, c, n, nt, nr);
-        if (c.used() > ws_bytes) {
-            *ws_needed = c.used();  // the lists come on top: not counted yet
-            keep_for_retry(false);
-            return bail(fail(CRK_ENOSPC, "workspace of %zu bytes, need at least %zu (before the lists)",
-                             ws_bytes, *ws_needed));
-        }
-        Carver cw(L->ws);
-        carve_part_a(L, cw, n, nt, nr);
-        *ws_needed = cw.used();
-    }
-    const size_t part_a = *ws_needed;
+    auto ranges = [](const crk::TreeOutput& t) { return t.rng.size() / 2; };
 
     // tree-order fixed-point positions and support radii, candidate ranges and
     // the tile orders of one tree order, uploaded (host buffers must outlive
@@ -1232,7 +1235,7 @@ extern "C" int crk_build_leaf_pairs(int64_t n, const double* x, const double* y,
     std::vector<int32_t> order(nt), tree_order(nt);
     std::iota(tree_order.begin(), tree_order.end(), 0);
     auto upload = [&](const crk::TreeOutput& t) -> int {
-        if (t.rng.size() / 2 != nr) return fail(CRK_EHIP, "tree rebuild changed the candidate ranges");
+        const size_t nr = ranges(t);
         for (int64_t s = 0; s < n; ++s) {
             const int32_t i = t.perm[s];
             uint32_t hw = 0;
@@ -1263,14 +1266,29 @@ extern "C" int crk_build_leaf_pairs(int64_t n, const double* x, const double* y,
         return CRK_OK;
     };
     int rc = CRK_OK;
-    if ((rc = upload(tout))) return bail(rc);
     L->stats[0] = L->n_leaves;
     L->stats[1] = nt;
-    L->timing = true;  // the list build is always timed (read by crk_kernel_times)
 
-    if (L->hydro) {
+    if (!L->hydro) {
+        *ws_needed = carve(L, nullptr, n, nt, ranges(tout), -1);
+        if (*ws_needed > ws_bytes) {
+            keep_for_retry(false);
+            return bail(fail(CRK_ENOSPC, "workspace of %zu bytes, need %zu", ws_bytes, *ws_needed));
+        }
+        carve(L, L->ws, n, nt, ranges(tout), -1);
+        if ((rc = upload(tout))) return bail(rc);
+    } else {
+        L->timing = true;  // the list build is always timed (read by crk_kernel_times)
         if (!counted) {
-            // count pass
+            // count pass on the first tree, in a workspace without the lists
+            *ws_needed = carve(L, nullptr, n, nt, ranges(tout), -1);
+            if (*ws_needed > ws_bytes) {
+                keep_for_retry(false);  // the lists come on top: not counted yet
+                return bail(fail(CRK_ENOSPC, "workspace of %zu bytes, need at least %zu (before the lists)",
+                                 ws_bytes, *ws_needed));
+            }
+            carve(L, L->ws, n, nt, ranges(tout), -1);
+            if ((rc = upload(tout))) return bail(rc);
             hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, L->counter);
             {
                 TimeScope ts(L, stream, CRK_K_CULL);
@@ -1296,12 +1314,10 @@ extern "C" int crk_build_leaf_pairs(int64_t n, const double* x, const double* y,
             if (int64_t(tb.leaf_begin.size()) != L->n_leaves)
                 return bail(fail(CRK_EHIP, "tree rebuild changed the leaves"));
             tout = std::move(tb);
-            if ((rc = upload(tout))) return bail(rc);
             for (int64_t s = 0; s < n; ++s) hc[s] = work[tout.perm[s]];
+            counted = true;
         }
-        if (hipMemcpyAsync(L->cnt, hc.data(), n * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
-            hipStreamSynchronize(stream) != hipSuccess)
-            return bail(fail(CRK_EHIP, "uploading list counts failed"));
+        // the final tree and its list lengths (tree order): list offsets per tile
         std::vector<int32_t> len(nt, 0);
         std::vector<int64_t> off(nt, 0);
         int64_t total = 0, entries = 0;
@@ -1315,24 +1331,18 @@ extern "C" int crk_build_leaf_pairs(int64_t n, const double* x, const double* y,
             off[t] = total;
             total += int64_t(mx) * kWave;
         }
-        // part B: the lists
-        {
-            Carver c(nullptr);
-            c.off = part_a;
-            carve_part_b(L, c, total);
-            if (c.used() > ws_bytes) {
-                *ws_needed = c.used();
-                keep_for_retry(true);
-                return bail(fail(CRK_ENOSPC, "workspace of %zu bytes, need %zu", ws_bytes, *ws_needed));
-            }
-            Carver cw(L->ws);
-            cw.off = part_a;
-            carve_part_b(L, cw, total);
-            *ws_needed = cw.used();
+        *ws_needed = carve(L, nullptr, n, nt, ranges(tout), total);
+        if (*ws_needed > ws_bytes) {
+            keep_for_retry(true);
+            return bail(fail(CRK_ENOSPC, "workspace of %zu bytes, need %zu", ws_bytes, *ws_needed));
         }
-        if (hipMemcpyAsync(L->ell_off, off.data(), nt * 8, hipMemcpyHostToDevice, stream) != hipSuccess ||
-            hipMemcpyAsync(L->ell_len, len.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
-            return bail(fail(CRK_EHIP, "uploading list offsets failed"));
+        carve(L, L->ws, n, nt, ranges(tout), total);
+        if ((rc = upload(tout))) return bail(rc);
+        if (hipMemcpyAsync(L->cnt, hc.data(), n * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+            hipMemcpyAsync(L->ell_off, off.data(), nt * 8, hipMemcpyHostToDevice, stream) != hipSuccess ||
+            hipMemcpyAsync(L->ell_len, len.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+            return bail(fail(CRK_EHIP, "uploading list counts and offsets failed"));
         hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, L->counter);
         hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, L->build_err);
         {
@@ -1428,7 +1438,10 @@ int crk_accel_energy(crk_leaves* L, const crk_gas* g, const void* V, const void*
     int rc = check_gas(L, g, true);
     if (rc) return rc;
     if (L->n == 0) {
-        if (totals) HIP_TRY(hipMemsetAsync(totals, 0, 8 * sizeof(double), st));
+        if (totals) {  // a fill kernel, not a memset: callers may capture this call in a graph
+            hipLaunchKernelGGL(k_zero8, dim3(1), dim3(64), 0, st, totals);
+            LAUNCH_CHECK("zero totals");
+        }
         return CRK_OK;
     }
     if (!V || !rho || !C || !C->A || !C->B || !C->dA || !C->dB || !a || !dudt)

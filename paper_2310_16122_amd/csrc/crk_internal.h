@@ -141,6 +141,10 @@ static __global__ void k_reset(int32_t* c) {
     if (threadIdx.x < kMaxGroups) c[threadIdx.x] = 0;
 }
 
+static __global__ void k_zero8(double* t) {
+    if (threadIdx.x < 8) t[threadIdx.x] = 0.0;
+}
+
 // ------------------------------------------------------------------ packing (tree order)
 
 __device__ __forceinline__ uint32_t quantize(double x) {
