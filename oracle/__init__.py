@@ -76,6 +76,8 @@ def _load():
         lib.oracle_hydro_listed.restype = I64
         lib.oracle_gravity_listed.argtypes = [I64, P, P, P, P, D, D, D, P, I64, P, P, P, ctypes.c_int,
                                               P, P, P]
+        lib.oracle_long_range_force.argtypes = [I64, P, D, P]
+        lib.oracle_gravity_grad.argtypes = [I64, P, P, P, P, D, D, D, P, P, I64, P, P, D, P, P]
         _lib = lib
     return _lib
 
@@ -209,6 +211,54 @@ def gravity(g, targets=None, poly=None):
     _load().oracle_gravity(x.size, _p(x), _p(y), _p(z), _p(m), float(g["G"]), float(g["eps"]),
                            float(g["r_cut"]), _p(pc), nt, _p(t), _p(a[0]), _p(a[1]), _p(a[2]))
     return a.T.copy()
+
+
+def long_range_force(r, r_s):
+    """Long-range (particle-mesh) force per unit mass at separations r > 0 for
+    a mesh potential filtered by exp(-k^2 r_s^2): [erf(x) - 2x exp(-x^2)/sqrt(pi)] / r^2,
+    x = r / (2 r_s) (crk_oracle.cpp)."""
+    r = _c(np.atleast_1d(r))
+    f = np.empty_like(r)
+    _load().oracle_long_range_force(r.size, _p(r), float(r_s), _p(f))
+    return f
+
+
+FIT_SAMPLES = 256
+
+
+def fit_poly(r_s, r_cut, samples=FIT_SAMPLES, target=None):
+    """The six coefficients p_0..p_5 of P(s) = sum_k p_k s^k, s = r^2, that the
+    short-range gravity subtracts (its pair kernel is
+    x [(r^2 + eps^2)^(-3/2) - P(r^2)]): the weighted least-squares fit of the
+    long-range force over r, g(s) = f_L(r)/r, at s_k = r_cut^2 (k + 1/2) / samples,
+    minimising sum_k [r_k^3 (g(s_k) - P(s_k))]^2 -- the error of the pair force
+    relative to the Newtonian force at each separation.  Solved in the scaled
+    variable t = s / r_cut^2 with numpy's least squares.  target(r), when
+    given, replaces f_L(r)/r (to check the fit on known functions)."""
+    t = (np.arange(samples) + 0.5) / samples
+    r = r_cut * np.sqrt(t)
+    y = long_range_force(r, r_s) / r if target is None else target(r)
+    w = r ** 3
+    A = np.vander(t, 6, increasing=True)
+    c = np.linalg.lstsq(A * w[:, None], y * w, rcond=None)[0]
+    return c / (r_cut * r_cut) ** np.arange(6)
+
+
+def gravity_grad(g, abar, parts, kinds, poly=None, fd_step=1e-7):
+    """dL/dx of L = sum_i abar_i . a_i (short-range gravity, masses fixed) at
+    coordinates (parts[k], kinds[k] in 0..2).  Returns (forward-mode dual-number
+    gradient, central differences)."""
+    x, y, z, m = (_c(g[k]) for k in ("x", "y", "z", "m"))
+    ab = _c(abar).reshape(-1)
+    pt = _c(parts, np.int64)
+    kd = _c(kinds, np.int32)
+    pc = None if poly is None else _c(poly)
+    gd = np.empty(pt.size)
+    gf = np.empty(pt.size)
+    _load().oracle_gravity_grad(x.size, _p(x), _p(y), _p(z), _p(m), float(g["G"]), float(g["eps"]),
+                                float(g["r_cut"]), _p(pc), _p(ab), pt.size, _p(pt), _p(kd),
+                                float(fd_step), _p(gd), _p(gf))
+    return gd, gf
 
 
 def count_pairs(g, mode, targets=None, r_fixed=0.0):

@@ -41,6 +41,15 @@
 //                  du_i/dt = -(1/(2 m_i)) sum_j F_ij . (v_i - v_j)
 //   gravity      j != i with r_ij < r_c (all species):
 //                  a_i = -G sum_j m_j x_ij [ (r^2 + eps^2)^(-3/2) - sum_k p_k r^(2k) ]
+//   PM split     the polynomial stands for the long-range (particle-mesh)
+//                part of the force, here that of a mesh potential filtered by
+//                exp(-k^2 r_s^2): per unit mass f_L(r) = M(<r)/r^2 for a
+//                Gaussian cloud of variance 2 r_s^2 per axis,
+//                  f_L(r) = [erf(x) - (2x/sqrt(pi)) exp(-x^2)] / r^2,  x = r/(2 r_s),
+//                and sum_k p_k s^k is the least-squares fit of f_L(sqrt s)/sqrt s
+//                over s in [0, r_c^2] (oracle/__init__.py, fit_poly)
+//   gravity adjoint  L = sum_i abar_i . a_i:  dL/dx by forward-mode dual numbers
+//                and by central differences (masses held fixed)
 //
 // Moment storage order (40 values): m0, m1[3], m2[6] (xx xy xz yy yz zz),
 // g0[3], g1[9] (g1[a][c], a-major), g2[18] (g2[ab][c], ab in the m2 order).
@@ -1313,4 +1322,89 @@ int oracle_grad(int64_t n, const double* x, const double* y, const double* z, co
     return 0;
 }
 
+// ---------------------------------------------------------------- PM-filtered split
+// F(x) = erf(x) - (2x/sqrt(pi)) exp(-x^2) = (4/sqrt(pi)) int_0^x t^2 exp(-t^2) dt:
+// the series of the integral for small x (where the closed form cancels), the
+// closed form beyond.
+static double split_F(double x) {
+    if (x < 0.5) {
+        double term = x * x * x, sum = 0.0, fact = 1.0;
+        for (int k = 0; k < 30; ++k) {
+            if (k > 0) fact *= double(k);
+            const double t = (k % 2 ? -1.0 : 1.0) * term / (fact * double(2 * k + 3));
+            sum += t;
+            term *= x * x;
+            if (std::fabs(t) < 1e-18 * std::fabs(sum)) break;
+        }
+        return 4.0 / std::sqrt(kPi) * sum;
+    }
+    return std::erf(x) - 2.0 * x / std::sqrt(kPi) * std::exp(-x * x);
+}
+
+// Long-range force per unit mass at separations r (r > 0), filter scale r_s.
+void oracle_long_range_force(int64_t n, const double* r, double r_s, double* f) {
+    for (int64_t k = 0; k < n; ++k) f[k] = split_F(r[k] / (2.0 * r_s)) / (r[k] * r[k]);
+}
+
+// dL/dx for L = sum_i abar_i . a_i, a the short-range gravity of every
+// particle (masses fixed), at ncoord coordinates kind 0-2 (x, y, z) of
+// particle part[k].  A coordinate of p changes a_p and the a_j of every j
+// within r_c of p; only those enter.  g_dual: forward-mode dual numbers;
+// g_fd: central differences with absolute step fd_step.
+int oracle_gravity_grad(int64_t n, const double* x, const double* y, const double* z, const double* m,
+                        double G, double eps, double r_cut, const double* poly, const double* abar,
+                        int64_t ncoord, const int64_t* part, const int32_t* kind, double fd_step,
+                        double* g_dual, double* g_fd) {
+    Gas<double> g0 = make_gas(n, x, y, z, nullptr, nullptr, nullptr, nullptr, nullptr, m);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < ncoord; ++k) {
+        const int64_t p = part[k];
+        const int kd = kind[k];
+        std::vector<int64_t> affected{p};
+        for (int64_t j = 0; j < n; ++j)
+            if (j != p && separation(g0, p, j).r < r_cut) affected.push_back(j);
+        {
+            std::vector<Dual> f[3], md(n);
+            const double* src[3] = {x, y, z};
+            for (int a = 0; a < 3; ++a) {
+                f[a].resize(n);
+                for (int64_t i = 0; i < n; ++i) f[a][i] = Dual(src[a][i], 0.0);
+            }
+            for (int64_t i = 0; i < n; ++i) md[i] = Dual(m[i], 0.0);
+            f[kd][p].d = 1.0;
+            Gas<Dual> gd;
+            gd.n = n; gd.x = f[0].data(); gd.y = f[1].data(); gd.z = f[2].data();
+            gd.vx = gd.vy = gd.vz = gd.u = nullptr; gd.h = nullptr; gd.m = m;
+            Dual L(0.0);
+            for (int64_t i : affected) {
+                Dual a[3];
+                gravity_one(gd, md.data(), G, eps, r_cut, poly, i, Cand{nullptr, n}, a);
+                for (int c = 0; c < 3; ++c) L += Dual(abar[3 * i + c]) * a[c];
+            }
+            g_dual[k] = L.d;
+        }
+        {
+            std::vector<double> f[3];
+            const double* src[3] = {x, y, z};
+            for (int a = 0; a < 3; ++a) f[a].assign(src[a], src[a] + n);
+            double Lpm[2];
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                f[kd][p] = src[kd][p] + (sgn == 0 ? fd_step : -fd_step);
+                Gas<double> gp = make_gas(n, f[0].data(), f[1].data(), f[2].data(), nullptr, nullptr, nullptr,
+                                          nullptr, nullptr, m);
+                double L = 0.0;
+                for (int64_t i : affected) {
+                    double a[3];
+                    gravity_one(gp, m, G, eps, r_cut, poly, i, Cand{nullptr, n}, a);
+                    for (int c = 0; c < 3; ++c) L += abar[3 * i + c] * a[c];
+                }
+                Lpm[sgn] = L;
+            }
+            g_fd[k] = (Lpm[0] - Lpm[1]) / (2.0 * fd_step);
+        }
+    }
+    return 0;
+}
+
 }  // extern "C"
+

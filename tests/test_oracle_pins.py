@@ -479,3 +479,100 @@ def test_listed_chain_is_the_brute_force_chain(oracle_lib, name, n_side):
     for k in ("V", "rho", "A", "B", "dA", "dB", "a", "dudt", "totals"):
         assert np.array_equal(a[k], b[k]), k
     assert a["n_fallback"] == b["n_fallback"]
+
+
+# ---------------------------------------------------------------- particle-mesh split
+def test_long_range_force_is_the_pull_of_a_gaussian_cloud(oracle_lib):
+    """f_L(r) = M(<r)/r^2 for the Gaussian cloud whose potential the filtered
+    mesh force is: the enclosed mass by Gauss-Legendre quadrature of the density
+    (4 pi r_s^2)^(-3/2) exp(-s^2/(4 r_s^2)), no error function involved."""
+    r_s = 0.37
+    r = np.array([1e-4, 3e-3, 0.05, 0.2, 0.36, 0.5, 1.0, 2.0, 4.0])
+    xg, wg = np.polynomial.legendre.leggauss(60)
+    M = np.empty_like(r)
+    for k, rk in enumerate(r):
+        s = 0.5 * rk * (xg + 1.0)
+        rho = (4.0 * np.pi * r_s ** 2) ** -1.5 * np.exp(-s ** 2 / (4.0 * r_s ** 2))
+        M[k] = 0.5 * rk * np.sum(wg * 4.0 * np.pi * s ** 2 * rho)
+    f = oracle_lib.long_range_force(r, r_s)
+    assert np.allclose(f, M / r ** 2, rtol=1e-13, atol=0.0)
+
+
+def test_long_range_force_limits(oracle_lib):
+    r_s = 0.01
+    # small r: f_L / r -> 1 / (6 sqrt(pi) r_s^3); large r: Newtonian 1/r^2
+    g0 = oracle_lib.long_range_force(np.array([1e-9]), r_s)[0] / 1e-9
+    assert g0 == pytest.approx(1.0 / (6.0 * math.sqrt(math.pi) * r_s ** 3), rel=1e-12)
+    r = np.array([0.2, 0.3])
+    assert np.allclose(oracle_lib.long_range_force(r, r_s) * r ** 2, 1.0, rtol=1e-15)
+    # the two forms (series below x = 1/2, closed form above) meet
+    x = np.array([0.5 - 1e-12, 0.5 + 1e-12]) * 2.0 * r_s
+    f = oracle_lib.long_range_force(x, r_s)
+    assert abs(f[0] - f[1]) <= 1e-10 * f[0]
+
+
+def test_fit_recovers_a_polynomial(oracle_lib):
+    """Weighted least squares on samples of an exact quintic in s returns it."""
+    rc = 3.0 / 128
+    p = np.array([2.0, -3.0, 1.5, 0.25, -0.75, 0.5]) / (rc * rc) ** np.arange(6) * 1e5
+    got = oracle_lib.fit_poly(rc / 5, rc, target=lambda r: np.polyval(p[::-1], r * r))
+    assert np.allclose(got, p, rtol=1e-9, atol=0.0)
+
+
+def test_fit_of_the_mesh_force_is_a_least_squares_optimum(oracle_lib):
+    """The fitted residual is orthogonal to every weighted basis function (the
+    normal equations hold), and the fit follows the mesh force to 0.2 % of the
+    Newtonian pair force for r_s = r_c / 5."""
+    rc = 3.0 / 128
+    r_s = rc / 5
+    p = oracle_lib.fit_poly(r_s, rc)
+    K = oracle_lib.FIT_SAMPLES
+    t = (np.arange(K) + 0.5) / K
+    r = rc * np.sqrt(t)
+    y = oracle_lib.long_range_force(r, r_s) / r
+    w = r ** 3
+    res = w * (y - np.polyval(p[::-1], r * r))
+    basis = w[:, None] * (r[:, None] ** 2) ** np.arange(6)
+    assert np.abs(basis.T @ res).max() <= 1e-9 * np.abs(basis.T @ (w * y)).max()
+    rr = np.linspace(1e-3, 1.0, 2001) * rc
+    err = np.abs(np.polyval(p[::-1], rr * rr) - oracle_lib.long_range_force(rr, r_s) / rr) * rr ** 3
+    assert err.max() < 2e-3
+
+
+# ---------------------------------------------------------------- gravity adjoint
+def test_gravity_gradient_two_body_closed_form(oracle_lib):
+    """L = abar_1 . a_1 + abar_2 . a_2 for two bodies: dL/dx_1 = -G [phi d + 2 phi' (x.d) x]
+    with d = m_2 abar_1 - m_1 abar_2, phi = (s + eps^2)^(-3/2) - P(s), s = r^2."""
+    x = synth.grid_round(np.array([0.25, 0.257]))
+    y = synth.grid_round(np.array([0.5, 0.503]))
+    z = synth.grid_round(np.array([0.5, 0.4985]))
+    m = np.array([2.0, 3.0])
+    eps = 0.002
+    for poly in (None, np.array([3.0, -2.0, 0.5, 0.25, -0.125, 1.0]) * 1e3):
+        g = dict(x=x, y=y, z=z, m=m, G=1.5, eps=eps, r_cut=0.05)
+        ab = np.array([[0.3, -1.2, 0.7], [-0.4, 0.9, 1.1]])
+        gd, gf = oracle_lib.gravity_grad(g, ab, np.array([0, 0, 0]), np.array([0, 1, 2]), poly=poly)
+        xv = np.array([x[0] - x[1], y[0] - y[1], z[0] - z[1]])
+        s = xv @ xv
+        P = 0.0 if poly is None else sum(poly[k] * s ** k for k in range(6))
+        dP = 0.0 if poly is None else sum(k * poly[k] * s ** (k - 1) for k in range(1, 6))
+        phi = (s + eps * eps) ** -1.5 - P
+        dphi = -1.5 * (s + eps * eps) ** -2.5 - dP
+        d = m[1] * ab[0] - m[0] * ab[1]
+        ref = -1.5 * (phi * d + 2.0 * dphi * (xv @ d) * xv)
+        assert np.allclose(gd, ref, rtol=1e-12, atol=0.0)
+        assert np.allclose(gf, ref, rtol=1e-5, atol=0.0)
+
+
+def test_gravity_gradient_dual_matches_finite_differences(oracle_lib):
+    g = synth.make_gravity(n_side=8)
+    rng = np.random.default_rng(3)
+    ab = rng.standard_normal((g["n"], 3))
+    parts = rng.choice(g["n"], 12, replace=False)
+    kinds = rng.integers(0, 3, 12)
+    poly = oracle_lib.fit_poly(g["r_cut"] / 5, g["r_cut"])
+    for p in (None, poly):
+        gd, gf = oracle_lib.gravity_grad(g, ab, parts, kinds, poly=p, fd_step=1e-8)
+        scale = np.abs(gd).max()
+        assert scale > 0
+        assert np.abs(gd - gf).max() <= 1e-5 * scale
