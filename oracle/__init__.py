@@ -77,6 +77,8 @@ def _load():
         lib.oracle_gravity_listed.argtypes = [I64, P, P, P, P, D, D, D, P, I64, P, P, P, ctypes.c_int,
                                               P, P, P]
         lib.oracle_long_range_force.argtypes = [I64, P, D, P]
+        lib.oracle_extras.argtypes = [I64] + [P] * 14 + [I64, P, P, P, P]
+        lib.oracle_accel_visc.argtypes = [I64] + [P] * 16 + [D, D, D, D, I64, P, P, P, P, P]
         lib.oracle_gravity_grad.argtypes = [I64, P, P, P, P, D, D, D, P, P, I64, P, P, D, P, P]
         _lib = lib
     return _lib
@@ -158,6 +160,49 @@ def accel(g, V, rho, corr, targets=None):
                          _p(dA), _p(dB), float(g["gamma"]), nt, _p(t), _p(a[0]), _p(a[1]),
                          _p(a[2]), _p(du))
     return a.T.copy(), du
+
+
+VISC_DEFAULT = dict(Cl=1.0, Cq=2.0, eps_q=0.01)
+
+
+def extras(g, V, corr, targets=None):
+    """CRK density rhoR[n], velocity gradients dv[n,3,3] (dv[i,a,c] = d_c v^a) and
+    energy gradients du[n,3] over the gather support (crk_oracle.cpp)."""
+    keys = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "m")
+    arr = [_c(g[k]) for k in keys]
+    A, B, dA, dB = (_c(c) for c in corr[:4])
+    t, nt = _targets(targets, arr[0].size)
+    rhoR = np.empty(nt)
+    dv = np.empty((nt, 3, 3))
+    du = np.empty((nt, 3))
+    _load().oracle_extras(arr[0].size, *[_p(v) for v in arr], _p(_c(V)), _p(A), _p(B), _p(dA), _p(dB),
+                          nt, _p(t), _p(rhoR), _p(dv), _p(du))
+    return dict(rhoR=rhoR, dv=dv, du=du)
+
+
+def accel_visc(g, V, rho, corr, dv, targets=None, Cl=1.0, Cq=2.0, eps_q=0.01):
+    """Accelerations and du/dt with the artificial viscosity fed by the
+    velocity gradients dv [n,3,3] (all particles)."""
+    keys = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "m")
+    arr = [_c(g[k]) for k in keys]
+    A, B, dA, dB = (_c(c) for c in corr[:4])
+    t, nt = _targets(targets, arr[0].size)
+    a = np.empty((3, nt))
+    du = np.empty(nt)
+    _load().oracle_accel_visc(arr[0].size, *[_p(v) for v in arr], _p(_c(V)), _p(_c(rho)), _p(A), _p(B),
+                              _p(dA), _p(dB), _p(_c(dv)), float(Cl), float(Cq), float(eps_q),
+                              float(g["gamma"]), nt, _p(t), _p(a[0]), _p(a[1]), _p(a[2]), _p(du))
+    return a.T.copy(), du
+
+
+def hydro_visc(g, **visc):
+    """Full brute-force chain with the extras pass and the viscous forces."""
+    V, rho = volume(g)
+    A, B, dA, dB, nf = corrections(g, V)
+    ex = extras(g, V, (A, B, dA, dB))
+    a, du = accel_visc(g, V, rho, (A, B, dA, dB), ex["dv"], **{**VISC_DEFAULT, **visc})
+    return dict(V=V, rho=rho, A=A, B=B, dA=dA, dB=dB, a=a, dudt=du, n_fallback=nf,
+                totals=totals(g, a, du), **ex)
 
 
 def totals(g, a, dudt):

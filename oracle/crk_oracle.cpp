@@ -39,6 +39,19 @@
 //                  F_ij   = -1/2 V_i V_j (P_i + P_j) (G_ij - G_ji)
 //                  a_i    = (1/m_i) sum_j F_ij
 //                  du_i/dt = -(1/(2 m_i)) sum_j F_ij . (v_i - v_j)
+//   extras       over the gather support (j with r_ij < H_i), W^R_ij = A_i (1 + B_i.x_ij) W_ij,
+//                G_ij its x_i-gradient (as in the forces):
+//                  rhoR_i = sum_j m_j W^R_ij  (j = i included: m_i A_i W(0, h_i))
+//                  dv_i[a][c] = sum_{j != i} V_j (v_j^a - v_i^a) G_ij^c,
+//                  du_i[c]    = sum_{j != i} V_j (u_j - u_i) G_ij^c
+//                (exact for linear fields, by the reproducing conditions)
+//   viscosity    (optional in the forces) per force pair, s_k = x_ij . (dv_k x_ij),
+//                  Phi = max(0, 4 s_i s_j / (s_i + s_j)^2)   (van Leer on s_i / s_j)
+//                  w = v_i - v_j - Phi/2 (dv_i + dv_j) x_ij   (velocities reconstructed
+//                                                          to the pair's midpoint)
+//                  mu_k = min(0, h_k (w.x_ij) / (r^2 + eps_q h_k^2)),  c_k = sqrt(gamma (gamma-1) u_k)
+//                  Q_k = rho_k (-C_l c_k mu_k + C_q mu_k^2)              (k = i, j)
+//                and P_i + P_j in F_ij becomes P_i + P_j + Q_i + Q_j (still F_ij = -F_ji)
 //   gravity      j != i with r_ij < r_c (all species):
 //                  a_i = -G sum_j m_j x_ij [ (r^2 + eps^2)^(-3/2) - sum_k p_k r^(2k) ]
 //   PM split     the polynomial stands for the long-range (particle-mesh)
@@ -493,8 +506,80 @@ template <class T> void accel_pair(const Gas<T>& g, const T* V, const T* rho, co
     }
 }
 
+// ---------------------------------------------------------------- extras
+// CRK density and reproducing-kernel gradients of v and u of particle i.
+template <class T> void extras_one(const Gas<T>& g, const T* V, const Corr<T>* C, int64_t i, Cand c,
+                                   T& rhoR, T dv[3][3], T du[3]) {
+    const double H = 2.0 * g.h[i];
+    const Corr<T>& Ci = C[i];
+    rhoR = T(g.m[i]) * Ci.A * kernel_W(T(0.0), g.h[i]);  // j = i: x_ii = 0
+    for (int a = 0; a < 3; ++a) {
+        du[a] = T(0.0);
+        for (int cc = 0; cc < 3; ++cc) dv[a][cc] = T(0.0);
+    }
+    const T vi[3] = {g.vx[i], g.vy[i], g.vz[i]};
+    for (int64_t k = 0; k < c.n; ++k) {
+        const int64_t j = c.at(k);
+        if (j == i) continue;
+        Sep<T> s = separation(g, i, j);
+        if (!(val(s.r) < H)) continue;
+        const T W = kernel_W(s.r, g.h[i]);
+        const T lin = T(1.0) + Ci.B[0] * s.d[0] + Ci.B[1] * s.d[1] + Ci.B[2] * s.d[2];
+        rhoR += T(g.m[j]) * Ci.A * lin * W;
+        T G[3];
+        corrected_gradient(Ci, s.d, W, kernel_F(s.r, g.h[i]), G);
+        const T vj[3] = {g.vx[j], g.vy[j], g.vz[j]};
+        const T fu = g.u[j] - g.u[i];
+        for (int cc = 0; cc < 3; ++cc) {
+            for (int a = 0; a < 3; ++a) dv[a][cc] += V[j] * (vj[a] - vi[a]) * G[cc];
+            du[cc] += V[j] * fu * G[cc];
+        }
+    }
+}
+
+// Artificial viscosity parameters and the velocity gradients it reads
+// (dv[9 i + 3 a + c] = d_c v^a of particle i).
+struct Visc {
+    const double* dv = nullptr;
+    double Cl = 1.0, Cq = 2.0, eps_q = 0.01;
+};
+
+// Q_i + Q_j of one force pair (see the header).
+template <class T> T visc_pair(const Gas<T>& g, const T* rho, double gamma, const Visc& q, int64_t i,
+                               int64_t j, const Sep<T>& s) {
+    T Di[3], Dj[3];
+    for (int a = 0; a < 3; ++a) {
+        Di[a] = T(0.0);
+        Dj[a] = T(0.0);
+        for (int cc = 0; cc < 3; ++cc) {
+            Di[a] += T(q.dv[9 * i + 3 * a + cc]) * s.d[cc];
+            Dj[a] += T(q.dv[9 * j + 3 * a + cc]) * s.d[cc];
+        }
+    }
+    const T si = s.d[0] * Di[0] + s.d[1] * Di[1] + s.d[2] * Di[2];
+    const T sj = s.d[0] * Dj[0] + s.d[1] * Dj[1] + s.d[2] * Dj[2];
+    T phi = T(0.0);
+    if (val(si) * val(sj) > 0.0) phi = T(4.0) * si * sj / ((si + sj) * (si + sj));
+    const T vi[3] = {g.vx[i], g.vy[i], g.vz[i]}, vj[3] = {g.vx[j], g.vy[j], g.vz[j]};
+    T wx = T(0.0);
+    for (int a = 0; a < 3; ++a) wx += (vi[a] - vj[a] - T(0.5) * phi * (Di[a] + Dj[a])) * s.d[a];
+    const T r2 = s.r * s.r;
+    T Q = T(0.0);
+    const int64_t side[2] = {i, j};
+    for (int k = 0; k < 2; ++k) {
+        const int64_t p = side[k];
+        const double hp = g.h[p];
+        T mu = T(hp) * wx / (r2 + T(q.eps_q * hp * hp));
+        if (!(val(mu) < 0.0)) mu = T(0.0);
+        const T cs = sqrt(T(gamma * (gamma - 1.0)) * g.u[p]);
+        Q += rho[p] * (T(-q.Cl) * cs * mu + T(q.Cq) * mu * mu);
+    }
+    return Q;
+}
+
 template <class T> void accel_one(const Gas<T>& g, const T* V, const T* rho, const Corr<T>* C,
-                                  double gamma, int64_t i, Cand c, T a[3], T& dudt) {
+                                  double gamma, int64_t i, Cand c, T a[3], T& dudt,
+                                  const Visc* visc = nullptr) {
     const T Pi = T(gamma - 1.0) * rho[i] * g.u[i];
     a[0] = a[1] = a[2] = T(0.0);
     dudt = T(0.0);
@@ -505,7 +590,8 @@ template <class T> void accel_one(const Gas<T>& g, const T* V, const T* rho, con
         const double Hi = 2.0 * g.h[i], Hj = 2.0 * g.h[j];
         if (!(val(s.r) < std::max(Hi, Hj))) continue;
         T F[3], Fdotv;
-        accel_pair(g, V, rho, C, gamma, i, j, s, Pi, F, Fdotv);
+        accel_pair(g, V, rho, C, gamma, i, j, s, visc ? Pi + visc_pair(g, rho, gamma, *visc, i, j, s) : Pi,
+                   F, Fdotv);
         for (int cc = 0; cc < 3; ++cc) a[cc] += F[cc];
         dudt += Fdotv;
     }
@@ -920,6 +1006,70 @@ int oracle_accel(int64_t n, const double* x, const double* y, const double* z, c
         const int64_t i = targets ? targets[k] : k;
         double a[3], du;
         accel_one(g, V, rho, C.data(), gamma, i, Cand{nullptr, n}, a, du);
+        ax[k] = a[0]; ay[k] = a[1]; az[k] = a[2]; dudt[k] = du;
+    }
+    return 0;
+}
+
+// CRK density and velocity / energy gradients for targets (all when NULL).
+int oracle_extras(int64_t n, const double* x, const double* y, const double* z, const double* vx,
+                  const double* vy, const double* vz, const double* u, const double* h,
+                  const double* m, const double* V, const double* A, const double* B,
+                  const double* dA, const double* dB, int64_t nt, const int64_t* targets,
+                  double* rhoR, double* dv, double* du) {
+    Gas<double> g = make_gas(n, x, y, z, vx, vy, vz, u, h, m);
+    std::vector<Corr<double>> C(n);
+    for (int64_t i = 0; i < n; ++i) {
+        C[i].A = A[i];
+        for (int a = 0; a < 3; ++a) {
+            C[i].B[a] = B[3 * i + a];
+            C[i].dA[a] = dA[3 * i + a];
+            for (int c = 0; c < 3; ++c) C[i].dB[a][c] = dB[9 * i + 3 * a + c];
+        }
+    }
+    const int64_t cnt = targets ? nt : n;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < cnt; ++k) {
+        const int64_t i = targets ? targets[k] : k;
+        double r, v[3][3], e[3];
+        extras_one(g, V, C.data(), i, Cand{nullptr, n}, r, v, e);
+        rhoR[k] = r;
+        for (int a = 0; a < 3; ++a) {
+            du[3 * k + a] = e[a];
+            for (int c = 0; c < 3; ++c) dv[9 * k + 3 * a + c] = v[a][c];
+        }
+    }
+    return 0;
+}
+
+// Forces with the artificial viscosity (dv: the velocity gradients, 9 per particle).
+int oracle_accel_visc(int64_t n, const double* x, const double* y, const double* z, const double* vx,
+                      const double* vy, const double* vz, const double* u, const double* h,
+                      const double* m, const double* V, const double* rho, const double* A,
+                      const double* B, const double* dA, const double* dB, const double* dv,
+                      double Cl, double Cq, double eps_q, double gamma, int64_t nt,
+                      const int64_t* targets, double* ax, double* ay, double* az, double* dudt) {
+    Gas<double> g = make_gas(n, x, y, z, vx, vy, vz, u, h, m);
+    std::vector<Corr<double>> C(n);
+    for (int64_t i = 0; i < n; ++i) {
+        C[i].A = A[i];
+        for (int a = 0; a < 3; ++a) {
+            C[i].B[a] = B[3 * i + a];
+            C[i].dA[a] = dA[3 * i + a];
+            for (int c = 0; c < 3; ++c) C[i].dB[a][c] = dB[9 * i + 3 * a + c];
+        }
+    }
+    Visc q;
+    q.dv = dv;
+    q.Cl = Cl;
+    q.Cq = Cq;
+    q.eps_q = eps_q;
+    const int64_t cnt = targets ? nt : n;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < cnt; ++k) {
+        const int64_t i = targets ? targets[k] : k;
+        double a[3], du;
+        accel_one(g, V, rho, C.data(), gamma, i, Cand{nullptr, n}, a, du, &q);
         ax[k] = a[0]; ay[k] = a[1]; az[k] = a[2]; dudt[k] = du;
     }
     return 0;

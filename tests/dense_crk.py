@@ -80,4 +80,51 @@ def chain(g, corr_override=None):
     a = Fij.sum(1) / g["m"][:, None]
     dudt = -0.5 * np.einsum("ijc,ijc->i", Fij, vij) / g["m"]
     return dict(V=V, rho=rho, m0=m0, m1=m1, m2=m2, g0=g0, g1=g1, g2=g2, A=A, B=B, dA=dA, dB=dB,
-                a=a, dudt=dudt, d=d, r=r, Wi=Wi, Fi=Fi, Gij=Gij)
+                a=a, dudt=dudt, d=d, r=r, Wi=Wi, Fi=Fi, Gij=Gij, Gji=Gji)
+
+
+def extras_and_viscosity(g, dn, Cl=1.0, Cq=2.0, eps_q=0.01):
+    """CRK density, gradients of v and u, and the forces with the artificial
+    viscosity, densely from a chain() result (same readings as the oracle:
+    gather support r < 2h_i for the extras; per force pair the van Leer limiter
+    on s_k = x.(dv_k x), midpoint-reconstructed velocities, Q_k =
+    rho_k (-Cl c_k mu_k + Cq mu_k^2) added to the pressures)."""
+    d, r = dn["d"], dn["r"]
+    n = r.shape[0]
+    h = np.asarray(g["h"])
+    off = ~np.eye(n, dtype=bool)
+    gather = (r < (2.0 * h)[:, None]) & off
+    WR = dn["A"][:, None] * (1.0 + np.einsum("ia,ija->ij", dn["B"], d)) * dn["Wi"]
+    rhoR = (WR * g["m"][None, :]).sum(1)  # the diagonal carries the self term
+    v = np.stack([g["vx"], g["vy"], g["vz"]], axis=1)
+    wgt = dn["V"][None, :] * gather
+    dv = np.einsum("ij,ija,ijc->iac", wgt, v[None, :, :] - v[:, None, :], dn["Gij"])
+    du = np.einsum("ij,ij,ijc->ic", wgt, g["u"][None, :] - g["u"][:, None], dn["Gij"])
+    # viscosity per ordered pair (i, j)
+    Di = np.einsum("iac,ijc->ija", dv, d)
+    Dj = np.einsum("jac,ijc->ija", dv, d)
+    si = np.einsum("ija,ija->ij", d, Di)
+    sj = np.einsum("ija,ija->ij", d, Dj)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        phi = np.where(si * sj > 0, 4.0 * si * sj / (si + sj) ** 2, 0.0)
+    w = (v[:, None, :] - v[None, :, :]) - 0.5 * phi[:, :, None] * (Di + Dj)
+    wx = np.einsum("ija,ija->ij", w, d)
+    cs = np.sqrt(g["gamma"] * (g["gamma"] - 1.0) * g["u"])
+    r2 = r * r
+
+    def q(side_h, side_rho, side_c):
+        mu = np.minimum(0.0, side_h * wx / (r2 + eps_q * side_h ** 2))
+        return side_rho * (-Cl * side_c * mu + Cq * mu * mu)
+
+    Q = q(h[:, None], dn["rho"][:, None], cs[:, None]) + q(h[None, :], dn["rho"][None, :], cs[None, :])
+    # forces: rebuild the pair sums with P_i + P_j + Q_ij
+    Hmax = np.maximum(2.0 * h[:, None], 2.0 * h[None, :])
+    mask = (r < Hmax) & off
+    P = (g["gamma"] - 1.0) * dn["rho"] * g["u"]
+    V = dn["V"]
+    coef = -0.5 * V[:, None] * V[None, :] * (P[:, None] + P[None, :] + Q) * mask
+    Fij = coef[:, :, None] * (dn["Gij"] - dn["Gji"])
+    vij = v[:, None, :] - v[None, :, :]
+    a = Fij.sum(1) / g["m"][:, None]
+    dudt = -0.5 * np.einsum("ijc,ijc->i", Fij, vij) / g["m"]
+    return dict(rhoR=rhoR, dv=dv, du=du, a=a, dudt=dudt)
