@@ -191,6 +191,26 @@ int crk_accel_energy(crk_leaves* leaves, const crk_gas* gas, const void* V, cons
                      double* totals, hipStream_t stream);
 
 /*
+ * crk_accel_energy without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid allocation).  Same arguments, kernels and results (bit for bit) as
+ * crk_accel_energy, but the pass's scratch -- the neighbour records and the
+ * FP64 totals partials -- lives in a fixed device array of 80 MiB compiled
+ * into the library, one per GPU, held from the first call on that GPU until
+ * the process ends, instead of in the handle's workspace.  Scratch needed:
+ * n x 128 bytes (FP32; 256 in FP64) plus 64 bytes per 64 particles plus
+ * 8 KiB, i.e. up to about 640k particles in FP32 and 320k in FP64; larger
+ * inputs are refused with CRK_EINVAL before anything is launched.  Allocates
+ * nothing and enqueues no memset.  Every call on a GPU shares that GPU's array
+ * (it keeps the last call's contents; every byte a call reads it first
+ * writes): calls that overlap on one GPU -- concurrent streams, threads or
+ * handles -- race, and the caller must order them.
+ */
+int crk_accel_energy_noalloc(crk_leaves* leaves, const crk_gas* gas, const void* V, const void* rho,
+                             const crk_corr* corr, double gamma, crk_prec prec, void* a, void* dudt,
+                             double* totals, hipStream_t stream);
+
+/*
  * Short-range particle-particle gravity (Sec. 3.1 force split; all species).
  *   a_i = -G sum_{j != i, r_ij < r_cut} m_j x_ij [ (r^2 + eps^2)^(-3/2) - sum_k p_k r^(2k) ]
  * poly: host array of 6 coefficients p_0..p_5 or NULL (no polynomial term).

@@ -29,7 +29,7 @@ _STATUS = {0: "CRK_OK", -1: "CRK_EINVAL", -3: "CRK_EHIP", -4: "CRK_ESTATE", -5: 
 
 # the C symbols declared in include/crk.h
 EXPORTS = ("crk_build_leaf_pairs", "crk_volume", "crk_corrections", "crk_accel_energy",
-           "sr_gravity", "crk_accel_energy_backward", "crk_leaves_stats", "crk_leaves_perm",
+           "crk_accel_energy_noalloc", "sr_gravity", "crk_accel_energy_backward", "crk_leaves_stats", "crk_leaves_perm",
            "crk_get_tuning", "crk_set_tuning",
            "crk_timing", "crk_kernel_times", "crk_leaves_free", "crk_last_error")
 KERNEL_KINDS = ("cull", "volume", "moments", "accel", "gravity", "pack", "accel_adj",
@@ -88,6 +88,7 @@ def load_library(path=None):
     lib.crk_corrections.argtypes = [P, ctypes.POINTER(_Gas), P, I, ctypes.POINTER(_Corr), P, P]
     lib.crk_accel_energy.argtypes = [P, ctypes.POINTER(_Gas), P, P, ctypes.POINTER(_Corr), D, I,
                                      P, P, P, P]
+    lib.crk_accel_energy_noalloc.argtypes = lib.crk_accel_energy.argtypes
     lib.sr_gravity.argtypes = [P, I64, P, P, P, P, D, D, D, P, I, P, P]
     lib.crk_accel_energy_backward.argtypes = [P, ctypes.POINTER(_Gas), P, P, ctypes.POINTER(_Corr), D,
                                               P, P, I, P, P, P, P]
@@ -274,7 +275,10 @@ def crk_corrections(leaves, gas, V, prec="f32", n_fallback=None, store_sums=Fals
     return (A, B, dA, dB, M) if store_sums else (A, B, dA, dB)
 
 
-def crk_accel_energy(leaves, gas, V, rho, corr, gamma=5.0 / 3.0, prec="f32", totals=True):
+def crk_accel_energy(leaves, gas, V, rho, corr, gamma=5.0 / 3.0, prec="f32", totals=True,
+                     noalloc=False):
+    """(a [n,3], du/dt [n], totals [8] FP64 or None).  noalloc: the variant whose
+    scratch is the library's fixed device array (crk_accel_energy_noalloc)."""
     g = _gas(gas, prec, ("vx", "vy", "vz", "u", "h", "m"))
     dt, dev = _DTYPE[prec], gas["x"].device
     for t in (V, rho, *corr[:4]):
@@ -283,11 +287,15 @@ def crk_accel_energy(leaves, gas, V, rho, corr, gamma=5.0 / 3.0, prec="f32", tot
     a = torch.empty(g.n, 3, dtype=dt, device=dev)
     du = torch.empty(g.n, dtype=dt, device=dev)
     tot = torch.empty(8, dtype=torch.float64, device=dev) if totals else None
-    _check("crk_accel_energy",
-           load_library().crk_accel_energy(leaves.handle, ctypes.byref(g), _ptr(V), _ptr(rho),
-                                           ctypes.byref(c), float(gamma), _PREC[prec], _ptr(a),
-                                           _ptr(du), _ptr(tot), _stream()))
+    name = "crk_accel_energy_noalloc" if noalloc else "crk_accel_energy"
+    _check(name, getattr(load_library(), name)(leaves.handle, ctypes.byref(g), _ptr(V), _ptr(rho),
+                                               ctypes.byref(c), float(gamma), _PREC[prec], _ptr(a),
+                                               _ptr(du), _ptr(tot), _stream()))
     return a, du, tot
+
+
+def crk_accel_energy_noalloc(leaves, gas, V, rho, corr, gamma=5.0 / 3.0, prec="f32", totals=True):
+    return crk_accel_energy(leaves, gas, V, rho, corr, gamma, prec, totals, noalloc=True)
 
 
 def crk_accel_energy_backward(leaves, gas, V, rho, corr, ga, gdudt, gamma=5.0 / 3.0, prec="f32"):

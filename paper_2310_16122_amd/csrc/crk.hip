@@ -29,6 +29,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 
 #include "crk_internal.h"
@@ -882,6 +883,15 @@ int corrections_impl(crk_leaves* L, const crk_gas* g, const R* V, const crk_corr
     return CRK_OK;
 }
 
+// Scratch of one force pass: the neighbour records (n), then the FP64 totals
+// partials (8 per tile, then 8 per reduction block).
+template <class R> size_t accel_scratch_records(int64_t n) {
+    return (sizeof(RecAcc<R>) * size_t(n) + 255) / 256 * 256;
+}
+template <class R> size_t accel_scratch_bytes(int64_t n, int64_t n_tiles) {
+    return accel_scratch_records<R>(n) + sizeof(double) * size_t(8 * n_tiles + 8 * kTotalsBlocks);
+}
+
 // The force pass with its scratch given: rec holds n records, partials
 // 8 (n_tiles + kTotalsBlocks) doubles.
 template <class R>
@@ -934,6 +944,47 @@ int accel_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const 
     return accel_run<R>(L, g, V, rho, C, gamma, a, dudt, totals, static_cast<RecAcc<R>*>(sp), L->partials, st);
 }
 
+// ---------------------------------------------------------------- force pass without a workspace
+// Scratch of crk_accel_energy_noalloc: a fixed array in device memory, one per
+// GPU, held from the library's first use on that GPU until the process ends.
+// Host code never uses the array's name as an address: the device address is
+// looked up once per device (hipGetSymbolAddress, with that device current)
+// and kept in noalloc_ptr.
+constexpr size_t kNoAllocBytes = size_t(80) << 20;
+static __device__ __align__(256) char noalloc_scratch[kNoAllocBytes];
+constexpr int kMaxDevices = 64;
+std::mutex noalloc_mutex;
+void* noalloc_ptr[kMaxDevices] = {};
+
+int noalloc_scratch_of_device(void** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(CRK_EINVAL, "device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(noalloc_mutex);
+    if (!noalloc_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch)));
+        if (!p) return fail(CRK_EHIP, "no device address for the static scratch on device %d", dev);
+        noalloc_ptr[dev] = p;
+    }
+    *out = noalloc_ptr[dev];
+    return CRK_OK;
+}
+
+template <class R>
+int accel_noalloc_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const crk_corr* C,
+                       double gamma, R* a, R* dudt, double* totals, hipStream_t st) {
+    const size_t need = accel_scratch_bytes<R>(L->n, L->n_tiles);
+    if (need > kNoAllocBytes)
+        return fail(CRK_EINVAL, "crk_accel_energy_noalloc: n = %lld needs %zu bytes of scratch; the static "
+                    "array holds %zu (use crk_accel_energy)", (long long)L->n, need, kNoAllocBytes);
+    void* base = nullptr;
+    int rc = noalloc_scratch_of_device(&base);
+    if (rc) return rc;
+    char* p = static_cast<char*>(base);
+    return accel_run<R>(L, g, V, rho, C, gamma, a, dudt, totals, reinterpret_cast<RecAcc<R>*>(p),
+                        reinterpret_cast<double*>(p + accel_scratch_records<R>(L->n)), st);
+}
 
 template <class R>
 int gravity_impl(crk_leaves* L, const double* x, const double* y, const double* z, const R* m,
@@ -1432,9 +1483,9 @@ int crk_corrections(crk_leaves* L, const crk_gas* g, const void* V, crk_prec pre
     return fail(CRK_EINVAL, "unknown precision");
 }
 
-int crk_accel_energy(crk_leaves* L, const crk_gas* g, const void* V, const void* rho,
-                     const crk_corr* C, double gamma, crk_prec prec, void* a, void* dudt,
-                     double* totals, hipStream_t st) {
+static int accel_entry(bool noalloc, crk_leaves* L, const crk_gas* g, const void* V, const void* rho,
+                       const crk_corr* C, double gamma, crk_prec prec, void* a, void* dudt, double* totals,
+                       hipStream_t st) {
     int rc = check_gas(L, g, true);
     if (rc) return rc;
     if (L->n == 0) {
@@ -1447,12 +1498,24 @@ int crk_accel_energy(crk_leaves* L, const crk_gas* g, const void* V, const void*
     if (!V || !rho || !C || !C->A || !C->B || !C->dA || !C->dB || !a || !dudt)
         return fail(CRK_EINVAL, "V, rho, corrections, a and dudt are required");
     if (prec == CRK_F32)
-        return accel_impl<float>(L, g, (const float*)V, (const float*)rho, C, gamma, (float*)a,
-                                 (float*)dudt, totals, st);
+        return (noalloc ? accel_noalloc_impl<float> : accel_impl<float>)(
+            L, g, (const float*)V, (const float*)rho, C, gamma, (float*)a, (float*)dudt, totals, st);
     if (prec == CRK_F64)
-        return accel_impl<double>(L, g, (const double*)V, (const double*)rho, C, gamma, (double*)a,
-                                  (double*)dudt, totals, st);
+        return (noalloc ? accel_noalloc_impl<double> : accel_impl<double>)(
+            L, g, (const double*)V, (const double*)rho, C, gamma, (double*)a, (double*)dudt, totals, st);
     return fail(CRK_EINVAL, "unknown precision");
+}
+
+int crk_accel_energy(crk_leaves* L, const crk_gas* g, const void* V, const void* rho,
+                     const crk_corr* C, double gamma, crk_prec prec, void* a, void* dudt,
+                     double* totals, hipStream_t st) {
+    return accel_entry(false, L, g, V, rho, C, gamma, prec, a, dudt, totals, st);
+}
+
+int crk_accel_energy_noalloc(crk_leaves* L, const crk_gas* g, const void* V, const void* rho,
+                             const crk_corr* C, double gamma, crk_prec prec, void* a, void* dudt,
+                             double* totals, hipStream_t st) {
+    return accel_entry(true, L, g, V, rho, C, gamma, prec, a, dudt, totals, st);
 }
 
 int sr_gravity(crk_leaves* L, int64_t n, const double* x, const double* y, const double* z,
