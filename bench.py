@@ -438,6 +438,8 @@ def bench_hydro(args, torch, crk, config=None, tuning=None, autotune=True, rando
         del g64
     torch.cuda.empty_cache()
 
+    # the Extras pass and the viscous force pass, on the headline workload only
+    ev = extras_viscosity(args, torch, crk, L, g32, cfg_t, G, F, config, table, f64=f64) if config == "C2" else None
     out = {
         "metric": METRIC, "value": inter / (ms32 * 1e-3), "unit": "interactions/s",
         "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": round(ms32, 4),
@@ -465,6 +467,7 @@ def bench_hydro(args, torch, crk, config=None, tuning=None, autotune=True, rando
         "build_ms": round(build_ms, 1), "list_build_gpu_ms": round(cull[0], 3),
         "list_build_note": "neighbour-list count, fill and schedule kernels of one build",
         "generate_s": round(gen_s, 1),
+        "extras_viscosity": ev,
     }
     if cpu and not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_hydro(cfg, args.cpu_budget)
@@ -472,6 +475,55 @@ def bench_hydro(args, torch, crk, config=None, tuning=None, autotune=True, rando
     del L, g32, ga32, gdu32
     torch.cuda.empty_cache()
     return out
+
+
+def extras_viscosity(args, torch, crk, L, g32, cfg_t, G, F, config, table, f64=True):
+    """The Extras pass and the force pass with the artificial viscosity on the
+    same tree (not part of the headline step): per-launch times, interactions/s
+    (G gather pairs for Extras, F force pairs for the viscous force pass), the
+    algorithmic FP32 rate from the oracle's FLOP counts, and the FP32 outputs
+    against the FP64 GPU form over every particle."""
+    def run(g, prec):
+        o = crk.forward(L, g, cfg_t["gamma"], prec)
+        corr = (o["A"], o["B"], o["dA"], o["dB"])
+        return o, corr
+
+    o32, c32 = run(g32, "f32")
+    reps = max(4, args.steps // 2)
+
+    def step():
+        rhoR, dv, du = crk.crk_extras(L, g32, o32["V"], c32, "f32")
+        crk.crk_accel_energy_visc(L, g32, o32["V"], o32["rho"], c32, dv, cfg_t["gamma"], "f32")
+
+    timed_steps(step, 1, 1, torch)
+    L.timing(True)
+    timed_steps(step, reps, 0, torch)
+    kt = L.kernel_times()
+    L.timing(False)
+    res = {}
+    for kind, units in (("extras", G), ("accel_visc", F)):
+        ms = kt[kind][0] / max(kt[kind][1], 1)
+        flop = table[kind]
+        res[kind] = {"avg_ms": round(ms, 4), "interactions_per_s": units / (ms * 1e-3),
+                     "tflops_algorithmic": round(flop * units / (ms * 1e-3) / 1e12, 3),
+                     "frac_fp32_peak": round(flop * units / (ms * 1e-3) / 1e12 / PEAK_FP32_VALU_TFLOPS, 4),
+                     "flop_per_pair_oracle": flop, "units_per_launch": units}
+    log(f"[bench] {config} extras {res['extras']['avg_ms']:.3f} ms, viscous force pass "
+        f"{res['accel_visc']['avg_ms']:.3f} ms")
+    if f64:
+        g64 = crk.gas_to_device(cfg_t, "f64")
+        o64, c64 = run(g64, "f64")
+        e32 = crk.crk_extras(L, g32, o32["V"], c32, "f32")
+        e64 = crk.crk_extras(L, g64, o64["V"], c64, "f64")
+        a32 = crk.crk_accel_energy_visc(L, g32, o32["V"], o32["rho"], c32, e32[1], cfg_t["gamma"], "f32")
+        a64 = crk.crk_accel_energy_visc(L, g64, o64["V"], o64["rho"], c64, e64[1], cfg_t["gamma"], "f64")
+        err = {}
+        for k, u, v in zip(("rhoR", "dv", "du", "a_visc", "dudt_visc"), e32 + a32[:2], e64 + a64[:2]):
+            err[k] = float(f"{((u.double() - v).abs().max() / v.abs().max()).item():.3e}")
+        res["fp32_vs_fp64_normwise"] = err
+        del g64, o64, c64, e64, a64
+    torch.cuda.empty_cache()
+    return res
 
 
 # ---------------------------------------------------------------- gravity step
@@ -510,7 +562,8 @@ def bench_gravity(args, torch, crk, tuning=None, leaf_max=None):
         from paper_2310_16122_amd import tune
 
         leaf, L, tun, best_ms, per_leaf = tune.autotune_leaf_size(
-            lambda lm: build(lm, x, y, z), make_step, leaf_values=(128, 256, 512), log=log, repeats=2)
+            lambda lm: build(lm, x, y, z), make_step, leaf_values=(128, 256, 512), log=log, repeats=2,
+            space=tune.GRAVITY_SPACE)
         tuned = {"leaf_max": leaf, "ms_by_leaf": {str(k): round(v, 3) for k, v in per_leaf.items()},
                  "best_ms": round(best_ms, 3)}
         log(f"[bench] autotuned gravity: leaf {leaf}, {tun} ({best_ms:.3f} ms)")
@@ -521,7 +574,27 @@ def bench_gravity(args, torch, crk, tuning=None, leaf_max=None):
     L.timing(True)
     ms = timed_steps(step, args.steps, 0, torch)
     kt = L.kernel_times()
+    L.timing(False)
     inter = st["pairs_force"]
+    # the adjoint (dL/dx for seeded dL/da), same tree and tuning
+    ga = torch.randn(cfg["n"], 3, generator=torch.Generator().manual_seed(3)).float().cuda()
+
+    def adj_step():
+        crk.sr_gravity_backward(L, x, y, z, m, ga, cfg["G"], cfg["eps"], cfg["r_cut"], prec="f32")
+
+    timed_steps(adj_step, 1, 1, torch)
+    L.timing(True)
+    ms_adj = timed_steps(adj_step, max(2, args.steps // 2), 0, torch)
+    kta = L.kernel_times()
+    L.timing(False)
+    adj_launch = kta["gravity_adj"][0] / max(kta["gravity_adj"][1], 1)
+    adj = {"ms_per_call": round(ms_adj, 4), "avg_launch_ms": round(adj_launch, 4),
+           "interactions_per_s": inter / (adj_launch * 1e-3),
+           "tflops_algorithmic": round(table["gravity_adj"] * inter / (adj_launch * 1e-3) / 1e12, 3),
+           "frac_fp32_peak": round(table["gravity_adj"] * inter / (adj_launch * 1e-3) / 1e12 /
+                                   PEAK_FP32_VALU_TFLOPS, 4),
+           "flop_per_pair_oracle": table["gravity_adj"]}
+    log(f"[bench] C3 gravity adjoint {adj_launch:.3f} ms per launch")
     out = {
         "metric": METRIC, "value": inter / (ms * 1e-3), "unit": "interactions/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
@@ -532,6 +605,7 @@ def bench_gravity(args, torch, crk, tuning=None, leaf_max=None):
                    "leaves": st["leaves"], "leaf_max": (tuned or {}).get("leaf_max", leaf_max or 512),
                    "particle_order": "tree order", "tuning": L.get_tuning(), "autotune": tuned},
         "roofline": roofline("gravity", kt["gravity"][0], kt["gravity"][1], inter, "C3", table),
+        "adjoint": adj,
         "build_ms": round(build_ms, 1),
     }
     if not args.no_cpu:

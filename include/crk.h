@@ -106,6 +106,10 @@ typedef struct {
     int addr64;          /* 0: staged record loads use 32-bit offsets from the array base while the records
                             span at most 4 GiB, 64-bit addresses beyond; 1: 64-bit addresses always
                             (same results bit for bit; kept to exercise the wide form on small inputs) */
+    int exchange;        /* sr_gravity and its adjoint: how a block's kept candidates reach the lanes
+                            (Sec. 5.3's variants): 0 compacted into LDS and read as LDS broadcasts,
+                            1 scalar-register broadcast (v_readlane), 2 cross-lane permute (ds_bpermute);
+                            same results bit for bit */
 } crk_tuning;
 
 /*
@@ -211,6 +215,48 @@ int crk_accel_energy_noalloc(crk_leaves* leaves, const crk_gas* gas, const void*
                              double* totals, hipStream_t stream);
 
 /*
+ * Extras pass (Sec. 5, "Extras": the density and the state gradients), over
+ * each particle's gather support (j with |x_ij| < 2h_i), with the corrected
+ * kernel W^R_ij = A_i (1 + B_i.x_ij) W_ij and its x_i-gradient G_ij (as in
+ * crk_accel_energy):
+ *   rhoR_i     = sum_j m_j W^R_ij                       (j = i included)
+ *   dv_i[a][c] = sum_{j != i} V_j (v_j^a - v_i^a) G_ij^c   (= d_c v^a)
+ *   du_i[c]    = sum_{j != i} V_j (u_j - u_i) G_ij^c
+ * (the reproducing conditions make both gradients exact for linear fields).
+ * Reads gas x, y, z, vx, vy, vz, u, h, m, V[n] and the corrections.  Writes
+ * rhoR[n], dv[9n] (dv[9i + 3a + c]) and du[3n].
+ */
+int crk_extras(crk_leaves* leaves, const crk_gas* gas, const void* V, const crk_corr* corr, crk_prec prec,
+               void* rhoR, void* dv, void* du, hipStream_t stream);
+
+/* Artificial viscosity constants (see crk_accel_energy_visc). */
+typedef struct {
+    double Cl;    /* linear coefficient (>= 0) */
+    double Cq;    /* quadratic coefficient (>= 0) */
+    double eps_q; /* softening of mu, relative to h^2 (> 0) */
+} crk_visc;
+
+/*
+ * crk_accel_energy with an artificial viscosity fed by the Extras pass's
+ * velocity gradients dv (the step between Corrections and Acceleration in the
+ * paper's kernel sequence, Sec. 5).  For each force pair, with D_k = dv_k x_ij
+ * and s_k = x_ij . D_k (k = i, j), the van Leer limiter
+ *   Phi = max(0, 4 s_i s_j / (s_i + s_j)^2)
+ * weights the linear reconstruction of both velocities to the pair's midpoint,
+ *   w = v_i - v_j - Phi/2 (D_i + D_j),
+ *   mu_k = min(0, h_k (w.x_ij) / (r_ij^2 + eps_q h_k^2)),
+ *   Q_k = rho_k (-Cl c_k mu_k + Cq mu_k^2),  c_k = sqrt(gamma (gamma - 1) u_k),
+ * and P_i + P_j in F_ij becomes P_i + P_j + Q_i + Q_j (still F_ij = -F_ji, so
+ * momentum and total energy stay conserved).  A linear velocity field gives
+ * Phi = 1 and w = 0: no viscosity.  dv: [9n] as written by crk_extras.  Other
+ * arguments, outputs and totals as crk_accel_energy.  (No adjoint: the
+ * backward call covers the inviscid pass.)
+ */
+int crk_accel_energy_visc(crk_leaves* leaves, const crk_gas* gas, const void* V, const void* rho,
+                          const crk_corr* corr, const void* dv, const crk_visc* visc, double gamma,
+                          crk_prec prec, void* a, void* dudt, double* totals, hipStream_t stream);
+
+/*
  * Short-range particle-particle gravity (Sec. 3.1 force split; all species).
  *   a_i = -G sum_{j != i, r_ij < r_cut} m_j x_ij [ (r^2 + eps^2)^(-3/2) - sum_k p_k r^(2k) ]
  * poly: host array of 6 coefficients p_0..p_5 or NULL (no polynomial term).
@@ -220,6 +266,32 @@ int crk_accel_energy_noalloc(crk_leaves* leaves, const crk_gas* gas, const void*
 int sr_gravity(crk_leaves* leaves, int64_t n, const double* x, const double* y, const double* z,
                const void* m, double G, double eps, double r_cut, const double* poly,
                crk_prec prec, void* a, hipStream_t stream);
+
+/*
+ * Adjoint of sr_gravity with respect to positions (masses held fixed).  Given
+ * ga = dL/da [3n], writes gx = dL/dx [3n]:
+ *   gx_i = -G sum_{j != i, r_ij < r_cut} [phi d + 2 phi'(s) (x_ij . d) x_ij],
+ *   d = m_j ga_i - m_i ga_j,  s = r_ij^2,  phi(s) = (s + eps^2)^(-3/2) - P(s),
+ * the derivative of every a_k with x_i in it.  Each particle's adjoint is
+ * accumulated by its own lane (no atomics; bitwise reproducible).  Arguments
+ * otherwise as sr_gravity.  (The paper has no adjoint.)
+ */
+int sr_gravity_backward(crk_leaves* leaves, int64_t n, const double* x, const double* y, const double* z,
+                        const void* m, double G, double eps, double r_cut, const double* poly,
+                        const void* ga, crk_prec prec, void* gx, hipStream_t stream);
+
+/*
+ * The polynomial of the particle-mesh force split (Sec. 3.1; the build option
+ * HACC_CUDA_POLY_ORDER=5, appendix), for a mesh potential filtered by
+ * exp(-k^2 r_s^2): the long-range force per unit mass is that of a Gaussian
+ * cloud, f_L(r) = [erf(x) - (2x/sqrt(pi)) exp(-x^2)] / r^2 with x = r/(2 r_s),
+ * and poly[0..5] (host) receives the p_k of P(s) = sum_k p_k s^k that
+ * minimise sum_k [r_k^3 (f_L(r_k)/r_k - P(r_k^2))]^2 -- the error of the pair
+ * force relative to the Newtonian one -- at s_k = r_cut^2 (k + 1/2) / samples,
+ * k < samples (Householder least squares in s / r_cut^2).  sr_gravity with
+ * these p_k then evaluates the short-range remainder of the split.  Host only.
+ */
+int sr_gravity_fit_poly(double r_s, double r_cut, int samples, double* poly);
 
 /*
  * Adjoint of crk_accel_energy together with the corrections and volume passes
@@ -241,6 +313,29 @@ int crk_accel_energy_backward(crk_leaves* leaves, const crk_gas* gas, const void
                               const void* rho, const crk_corr* corr, double gamma, const void* ga,
                               const void* gdudt, crk_prec prec, void* gx, void* gv, void* gu,
                               hipStream_t stream);
+
+/*
+ * Global time step (the paper's port reduces floating-point minima with atomic
+ * fetch_min, Sec. 5.1): dt = min_i min(c_cfl 2h_i / (c_i + |v_i|),
+ * c_acc sqrt(2h_i / |a_i|)), c_i = sqrt(gamma (gamma - 1) u_i), the second limit
+ * only where |a_i| > 0.  h, u, vx, vy, vz [n] and a [3n] are device arrays of
+ * the precision `prec`; dt is one device value of that precision, written on
+ * `stream` (reduced per workgroup, then with atomic minima on the bits of the
+ * positive values: deterministic).  n = 0 gives +inf.  No host synchronisation.
+ */
+int crk_timestep(int64_t n, const void* h, const void* u, const void* vx, const void* vy, const void* vz,
+                 const void* a, double gamma, double c_cfl, double c_acc, crk_prec prec, void* dt,
+                 hipStream_t stream);
+
+/*
+ * Kick-drift update with the device time step dt (one value, as written by
+ * crk_timestep): v += a dt, u += du/dt dt, then x += v dt (the updated v) with
+ * each position wrapped into [0, 1).  x, y, z: FP64 device arrays [n], updated
+ * in place; vx, vy, vz, u [n] updated in place, a [3n] and dudt [n] read, all
+ * in the precision `prec`.
+ */
+int crk_kick_drift(int64_t n, double* x, double* y, double* z, void* vx, void* vy, void* vz, void* u,
+                   const void* a, const void* dudt, const void* dt, crk_prec prec, hipStream_t stream);
 
 /*
  * Statistics of a handle (host int64[8]):
@@ -284,7 +379,10 @@ enum {
     CRK_K_MOMENTS_ADJ = 7, /* moments adjoint pair kernel */
     CRK_K_VOLUME_ADJ = 8,  /* volume adjoint pair kernel */
     CRK_K_SOLVE_ADJ = 9,   /* per-particle solve adjoint from stored moment sums (crk_corr.M) */
-    CRK_K_COUNT = 10
+    CRK_K_GRAVITY_ADJ = 10, /* short-range gravity adjoint */
+    CRK_K_EXTRAS = 11,      /* Extras pass (CRK density, gradients of v and u) */
+    CRK_K_ACCEL_VISC = 12,  /* acceleration/energy pair kernel with the artificial viscosity */
+    CRK_K_COUNT = 13
 };
 int crk_timing(crk_leaves* leaves, int enable);
 int crk_kernel_times(crk_leaves* leaves, double* ms, int64_t* launches);

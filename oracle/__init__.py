@@ -78,6 +78,7 @@ def _load():
                                               P, P, P]
         lib.oracle_long_range_force.argtypes = [I64, P, D, P]
         lib.oracle_extras.argtypes = [I64] + [P] * 14 + [I64, P, P, P, P]
+        lib.oracle_visc_listed.argtypes = [I64] + [P] * 9 + [D, D, D, D] + [P] * 15
         lib.oracle_accel_visc.argtypes = [I64] + [P] * 16 + [D, D, D, D, I64, P, P, P, P, P]
         lib.oracle_gravity_grad.argtypes = [I64, P, P, P, P, D, D, D, P, P, I64, P, P, D, P, P]
         _lib = lib
@@ -203,6 +204,35 @@ def hydro_visc(g, **visc):
     a, du = accel_visc(g, V, rho, (A, B, dA, dB), ex["dv"], **{**VISC_DEFAULT, **visc})
     return dict(V=V, rho=rho, A=A, B=B, dA=dA, dB=dB, a=a, dudt=du, n_fallback=nf,
                 totals=totals(g, a, du), **ex)
+
+
+def timestep(g, a, gamma, c_cfl, c_acc):
+    """Global time step: the minimum over particles of
+    min(c_cfl 2h_i / (c_i + |v_i|), c_acc sqrt(2h_i / |a_i|)), c_i = sqrt(gamma (gamma-1) u_i)
+    (the acceleration limit only where |a_i| > 0); a plain loop in FP64."""
+    best = np.inf
+    for i in range(len(g["h"])):
+        H = 2.0 * float(g["h"][i])
+        cs = np.sqrt(gamma * (gamma - 1.0) * float(g["u"][i]))
+        v = np.sqrt(float(g["vx"][i]) ** 2 + float(g["vy"][i]) ** 2 + float(g["vz"][i]) ** 2)
+        t = c_cfl * H / (cs + v)
+        am = np.sqrt(float(a[i, 0]) ** 2 + float(a[i, 1]) ** 2 + float(a[i, 2]) ** 2)
+        if am > 0.0:
+            t = min(t, c_acc * np.sqrt(H / am))
+        best = min(best, t)
+    return best
+
+
+def kick_drift(g, a, dudt, dt):
+    """v + a dt, u + du/dt dt, then x + v_new dt wrapped into [0, 1): returns a new dict."""
+    out = dict(g)
+    for c, k in enumerate(("vx", "vy", "vz")):
+        out[k] = np.asarray(g[k], dtype=np.float64) + np.asarray(a)[:, c] * dt
+    out["u"] = np.asarray(g["u"], dtype=np.float64) + np.asarray(dudt) * dt
+    for k, kv in zip(("x", "y", "z"), ("vx", "vy", "vz")):
+        q = np.asarray(g[k], dtype=np.float64) + out[kv] * dt
+        out[k] = q - np.floor(q)
+    return out
 
 
 def totals(g, a, dudt):
@@ -352,7 +382,7 @@ def grad_coordinates(n, n_pos=32, n_vel=16, n_u=16, seed=19):
 
 
 FLOP_KINDS = ("volume", "moments", "accel", "gravity", "gravity_poly", "volume_adj", "moments_adj",
-              "accel_adj")
+              "accel_adj", "extras", "accel_visc", "gravity_adj", "gravity_adj_poly")
 
 
 def flops():
@@ -425,6 +455,25 @@ def hydro_listed(g, off, idx):
     a = a.T.copy()
     return dict(V=V, rho=rho, A=A, B=B, dA=dA, dB=dB, a=a, dudt=du, n_fallback=int(nf),
                 totals=totals(g, a, du))
+
+
+def visc_listed(g, off, idx, ref, Cl=1.0, Cq=2.0, eps_q=0.01):
+    """Extras of all particles and their viscous forces over precomputed lists,
+    from the oracle's own V, rho and corrections ``ref`` (a hydro_listed or
+    hydro result).  With exact lists it equals extras + accel_visc bit for bit."""
+    keys = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "m")
+    arr = [_c(g[k]) for k in keys]
+    n = arr[0].size
+    off, idx = _c(off, np.int64), _c(idx, np.int64)
+    rhoR, du = np.empty(n), np.empty(n)
+    dv, de = np.empty((n, 3, 3)), np.empty((n, 3))
+    a = np.empty((3, n))
+    _load().oracle_visc_listed(n, *[_p(v) for v in arr], float(g["gamma"]), float(Cl), float(Cq), float(eps_q),
+                               _p(off), _p(idx), _p(_c(ref["V"])), _p(_c(ref["rho"])), _p(_c(ref["A"])),
+                               _p(_c(ref["B"])), _p(_c(ref["dA"])), _p(_c(ref["dB"])), _p(rhoR), _p(dv),
+                               _p(de), _p(a[0]), _p(a[1]), _p(a[2]), _p(du))
+    a = a.T.copy()
+    return dict(rhoR=rhoR, dv=dv, du=de, a=a, dudt=du, totals=totals(g, a, du))
 
 
 def neighbour_lists(g, margin=1e-9):

@@ -539,21 +539,21 @@ template <class T> void extras_one(const Gas<T>& g, const T* V, const Corr<T>* C
 
 // Artificial viscosity parameters and the velocity gradients it reads
 // (dv[9 i + 3 a + c] = d_c v^a of particle i).
-struct Visc {
-    const double* dv = nullptr;
+template <class T> struct Visc {
+    const T* dv = nullptr;
     double Cl = 1.0, Cq = 2.0, eps_q = 0.01;
 };
 
 // Q_i + Q_j of one force pair (see the header).
-template <class T> T visc_pair(const Gas<T>& g, const T* rho, double gamma, const Visc& q, int64_t i,
+template <class T> T visc_pair(const Gas<T>& g, const T* rho, double gamma, const Visc<T>& q, int64_t i,
                                int64_t j, const Sep<T>& s) {
     T Di[3], Dj[3];
     for (int a = 0; a < 3; ++a) {
         Di[a] = T(0.0);
         Dj[a] = T(0.0);
         for (int cc = 0; cc < 3; ++cc) {
-            Di[a] += T(q.dv[9 * i + 3 * a + cc]) * s.d[cc];
-            Dj[a] += T(q.dv[9 * j + 3 * a + cc]) * s.d[cc];
+            Di[a] += q.dv[9 * i + 3 * a + cc] * s.d[cc];
+            Dj[a] += q.dv[9 * j + 3 * a + cc] * s.d[cc];
         }
     }
     const T si = s.d[0] * Di[0] + s.d[1] * Di[1] + s.d[2] * Di[2];
@@ -579,7 +579,7 @@ template <class T> T visc_pair(const Gas<T>& g, const T* rho, double gamma, cons
 
 template <class T> void accel_one(const Gas<T>& g, const T* V, const T* rho, const Corr<T>* C,
                                   double gamma, int64_t i, Cand c, T a[3], T& dudt,
-                                  const Visc* visc = nullptr) {
+                                  const Visc<T>* visc = nullptr) {
     const T Pi = T(gamma - 1.0) * rho[i] * g.u[i];
     a[0] = a[1] = a[2] = T(0.0);
     dudt = T(0.0);
@@ -900,6 +900,47 @@ int64_t accel_adj(int nbrs) {
     return pair_flops(reverse_sweep(l, wanted));
 }
 
+int64_t gravity_adj(int nbrs, bool poly) {
+    Setup s = make(nbrs);
+    const double p6[6] = {1.0, -2.0, 3.0, 0.5, -0.25, 0.125};
+    std::vector<std::vector<Ops>> w(s.np);
+    for (int p = 0; p < s.np; ++p)
+        for (int c = 0; c < 3; ++c) w[p].push_back(Ops::leaf(0.2 * (c + 1) - 0.1 * p, 1u << p));
+    // L = abar_0 . a_0 + sum_j abar_j . (a_j's term from particle 0)
+    Ops a0[3];
+    gravity_one(s.g, s.m.data(), 1.0, 1e-3, 0.2, poly ? p6 : nullptr, 0, Cand{nullptr, s.np}, a0);
+    Ops l = w[0][0] * a0[0] + w[0][1] * a0[1] + w[0][2] * a0[2];
+    const int64_t zero = 0;
+    for (int j = 1; j < s.np; ++j) {
+        Ops aj[3];
+        gravity_one(s.g, s.m.data(), 1.0, 1e-3, 0.2, poly ? p6 : nullptr, j, Cand{&zero, 1}, aj);
+        l += w[j][0] * aj[0] + w[j][1] * aj[1] + w[j][2] * aj[2];
+    }
+    return pair_flops(reverse_sweep(l, {s.x[0], s.y[0], s.z[0]}));
+}
+
+int64_t extras(int nbrs) {
+    Setup s = make(nbrs);
+    Ops r, dv[3][3], du[3];
+    extras_one(s.g, s.V.data(), s.C.data(), 0, Cand{nullptr, s.np}, r, dv, du);
+    std::vector<Ops> roots{r, du[0], du[1], du[2]};
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) roots.push_back(dv[a][c]);
+    return pair_flops(roots);
+}
+
+int64_t accel_visc(int nbrs) {
+    Setup s = make(nbrs);
+    std::vector<Ops> dv;
+    for (int p = 0; p < s.np; ++p)
+        for (int k = 0; k < 9; ++k) dv.push_back(Ops::leaf(0.03 * (k + 1) - 0.02 * p, 1u << p));
+    Visc<Ops> q;
+    q.dv = dv.data();
+    Ops a[3], du;
+    accel_one(s.g, s.V.data(), s.rho.data(), s.C.data(), 5.0 / 3.0, 0, Cand{nullptr, s.np}, a, du, &q);
+    return pair_flops({a[0], a[1], a[2], du});
+}
+
 }  // namespace flops
 
 }  // namespace
@@ -1059,7 +1100,7 @@ int oracle_accel_visc(int64_t n, const double* x, const double* y, const double*
             for (int c = 0; c < 3; ++c) C[i].dB[a][c] = dB[9 * i + 3 * a + c];
         }
     }
-    Visc q;
+    Visc<double> q;
     q.dv = dv;
     q.Cl = Cl;
     q.Cq = Cq;
@@ -1219,7 +1260,8 @@ int64_t oracle_count_pairs(int64_t n, const double* x, const double* y, const do
 
 // FLOP per ordered pair inside the pass radius, counted on the oracle's code
 // (see the flops namespace): [volume, moments, accel, gravity, gravity with the
-// polynomial term, volume adjoint, moments adjoint, force adjoint].
+// polynomial term, volume adjoint, moments adjoint, force adjoint, extras, force
+// pass with the viscosity, gravity adjoint, gravity adjoint with the polynomial].
 void oracle_flops(double* out) {
     using namespace flops;
     out[0] = double(volume(2) - volume(1));
@@ -1230,6 +1272,10 @@ void oracle_flops(double* out) {
     out[5] = double(volume_adj(2) - volume_adj(1));
     out[6] = double(moments_adj(2) - moments_adj(1));
     out[7] = double(accel_adj(2) - accel_adj(1));
+    out[8] = double(extras(2) - extras(1));
+    out[9] = double(accel_visc(2) - accel_visc(1));
+    out[10] = double(gravity_adj(2, false) - gravity_adj(1, false));
+    out[11] = double(gravity_adj(2, true) - gravity_adj(1, true));
     op_reset();
 }
 
@@ -1371,6 +1417,49 @@ int64_t oracle_hydro_listed(int64_t n, const double* x, const double* y, const d
         ax[i] = a[0]; ay[i] = a[1]; az[i] = a[2]; dudt[i] = du;
     }
     return fallbacks;
+}
+
+// Extras of all particles, then their forces with the artificial viscosity,
+// over precomputed candidate lists (V, rho and the corrections given).
+int oracle_visc_listed(int64_t n, const double* x, const double* y, const double* z, const double* vx,
+                       const double* vy, const double* vz, const double* u, const double* h,
+                       const double* m, double gamma, double Cl, double Cq, double eps_q, const int64_t* off,
+                       const int64_t* idx, const double* V, const double* rho, const double* A,
+                       const double* B, const double* dA, const double* dB, double* rhoR_o, double* dv_o,
+                       double* du_o, double* ax, double* ay, double* az, double* dudt) {
+    Gas<double> g = make_gas(n, x, y, z, vx, vy, vz, u, h, m);
+    auto cand = [&](int64_t i) { return Cand{idx + off[i], off[i + 1] - off[i]}; };
+    std::vector<Corr<double>> C(n);
+    for (int64_t i = 0; i < n; ++i) {
+        C[i].A = A[i];
+        for (int a = 0; a < 3; ++a) {
+            C[i].B[a] = B[3 * i + a];
+            C[i].dA[a] = dA[3 * i + a];
+            for (int c = 0; c < 3; ++c) C[i].dB[a][c] = dB[9 * i + 3 * a + c];
+        }
+    }
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        double r, v[3][3], e[3];
+        extras_one(g, V, C.data(), i, cand(i), r, v, e);
+        rhoR_o[i] = r;
+        for (int a = 0; a < 3; ++a) {
+            du_o[3 * i + a] = e[a];
+            for (int c = 0; c < 3; ++c) dv_o[9 * i + 3 * a + c] = v[a][c];
+        }
+    }
+    Visc<double> q;
+    q.dv = dv_o;
+    q.Cl = Cl;
+    q.Cq = Cq;
+    q.eps_q = eps_q;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        double a[3], du;
+        accel_one(g, V, rho, C.data(), gamma, i, cand(i), a, du, &q);
+        ax[i] = a[0]; ay[i] = a[1]; az[i] = a[2]; dudt[i] = du;
+    }
+    return 0;
 }
 
 // Kernel values for pinning: W(r, h) and F(r, h) at n radii.

@@ -29,11 +29,12 @@ _STATUS = {0: "CRK_OK", -1: "CRK_EINVAL", -3: "CRK_EHIP", -4: "CRK_ESTATE", -5: 
 
 # the C symbols declared in include/crk.h
 EXPORTS = ("crk_build_leaf_pairs", "crk_volume", "crk_corrections", "crk_accel_energy",
-           "crk_accel_energy_noalloc", "sr_gravity", "crk_accel_energy_backward", "crk_leaves_stats", "crk_leaves_perm",
+           "crk_accel_energy_noalloc", "crk_extras", "crk_accel_energy_visc", "sr_gravity",
+           "sr_gravity_backward", "sr_gravity_fit_poly", "crk_timestep", "crk_kick_drift", "crk_accel_energy_backward", "crk_leaves_stats", "crk_leaves_perm",
            "crk_get_tuning", "crk_set_tuning",
            "crk_timing", "crk_kernel_times", "crk_leaves_free", "crk_last_error")
 KERNEL_KINDS = ("cull", "volume", "moments", "accel", "gravity", "pack", "accel_adj",
-                "moments_adj", "volume_adj", "solve_adj")
+                "moments_adj", "volume_adj", "solve_adj", "gravity_adj", "extras", "accel_visc")
 
 
 class CrkError(RuntimeError):
@@ -60,10 +61,18 @@ def _corr(corr):
     return _Corr(*ptrs, None if M is None else M.data_ptr())
 
 
+class Visc(ctypes.Structure):
+    _fields_ = [("Cl", ctypes.c_double), ("Cq", ctypes.c_double), ("eps_q", ctypes.c_double)]
+
+
+VISC_DEFAULT = dict(Cl=1.0, Cq=2.0, eps_q=0.01)
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("persistent", ctypes.c_int), ("waves_per_cu", ctypes.c_int),
                 ("kahan_chunk", ctypes.c_int), ("block_waves", ctypes.c_int),
-                ("xcd_groups", ctypes.c_int), ("tile_order", ctypes.c_int), ("addr64", ctypes.c_int)]
+                ("xcd_groups", ctypes.c_int), ("tile_order", ctypes.c_int), ("addr64", ctypes.c_int),
+                ("exchange", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -90,6 +99,13 @@ def load_library(path=None):
                                      P, P, P, P]
     lib.crk_accel_energy_noalloc.argtypes = lib.crk_accel_energy.argtypes
     lib.sr_gravity.argtypes = [P, I64, P, P, P, P, D, D, D, P, I, P, P]
+    lib.sr_gravity_backward.argtypes = [P, I64, P, P, P, P, D, D, D, P, P, I, P, P]
+    lib.sr_gravity_fit_poly.argtypes = [D, D, I, P]
+    lib.crk_timestep.argtypes = [I64, P, P, P, P, P, P, D, D, D, I, P, P]
+    lib.crk_kick_drift.argtypes = [I64, P, P, P, P, P, P, P, P, P, P, I, P]
+    lib.crk_extras.argtypes = [P, ctypes.POINTER(_Gas), P, ctypes.POINTER(_Corr), I, P, P, P, P]
+    lib.crk_accel_energy_visc.argtypes = [P, ctypes.POINTER(_Gas), P, P, ctypes.POINTER(_Corr), P,
+                                          ctypes.POINTER(Visc), D, I, P, P, P, P]
     lib.crk_accel_energy_backward.argtypes = [P, ctypes.POINTER(_Gas), P, P, ctypes.POINTER(_Corr), D,
                                               P, P, I, P, P, P, P]
     lib.crk_leaves_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
@@ -349,6 +365,93 @@ class CRKAccelEnergy(torch.autograd.Function):
         return gx.double(), gv, gu, None, None, None, None, None
 
 
+def crk_extras(leaves, gas, V, corr, prec="f32"):
+    """(rhoR [n], dv [n,3,3] with dv[i,a,c] = d_c v^a, du [n,3])."""
+    g = _gas(gas, prec, ("vx", "vy", "vz", "u", "h", "m"))
+    dt, dev = _DTYPE[prec], gas["x"].device
+    for t in (V, *corr[:4]):
+        _dev(t, dt)
+    c = _corr(corr)
+    rhoR = torch.empty(g.n, dtype=dt, device=dev)
+    dv = torch.empty(g.n, 3, 3, dtype=dt, device=dev)
+    du = torch.empty(g.n, 3, dtype=dt, device=dev)
+    _check("crk_extras", load_library().crk_extras(leaves.handle, ctypes.byref(g), _ptr(V), ctypes.byref(c),
+                                                   _PREC[prec], _ptr(rhoR), _ptr(dv), _ptr(du), _stream()))
+    return rhoR, dv, du
+
+
+def crk_accel_energy_visc(leaves, gas, V, rho, corr, dv, gamma=5.0 / 3.0, prec="f32", totals=True, **visc):
+    """Force pass with the artificial viscosity (constants Cl, Cq, eps_q; defaults VISC_DEFAULT)."""
+    g = _gas(gas, prec, ("vx", "vy", "vz", "u", "h", "m"))
+    dt, dev = _DTYPE[prec], gas["x"].device
+    for t in (V, rho, *corr[:4], dv):
+        _dev(t, dt)
+    c = _corr(corr)
+    q = Visc(**{**VISC_DEFAULT, **visc})
+    a = torch.empty(g.n, 3, dtype=dt, device=dev)
+    du = torch.empty(g.n, dtype=dt, device=dev)
+    tot = torch.empty(8, dtype=torch.float64, device=dev) if totals else None
+    _check("crk_accel_energy_visc",
+           load_library().crk_accel_energy_visc(leaves.handle, ctypes.byref(g), _ptr(V), _ptr(rho),
+                                                ctypes.byref(c), _ptr(dv), ctypes.byref(q), float(gamma),
+                                                _PREC[prec], _ptr(a), _ptr(du), _ptr(tot), _stream()))
+    return a, du, tot
+
+
+def forward_visc(leaves, gas, gamma=5.0 / 3.0, prec="f32", **visc):
+    """volume -> corrections -> extras -> accel/energy with the viscosity."""
+    V, rho = crk_volume(leaves, gas, prec)
+    nf = torch.zeros(1, dtype=torch.int64, device=gas["x"].device)
+    corr = crk_corrections(leaves, gas, V, prec, n_fallback=nf)
+    rhoR, dv, du_grad = crk_extras(leaves, gas, V, corr, prec)
+    a, du, tot = crk_accel_energy_visc(leaves, gas, V, rho, corr, dv, gamma, prec, **visc)
+    return dict(V=V, rho=rho, A=corr[0], B=corr[1], dA=corr[2], dB=corr[3], rhoR=rhoR, dv=dv,
+                du=du_grad, a=a, dudt=du, totals=tot, n_fallback=nf)
+
+
+def sr_gravity_fit_poly(r_s, r_cut, samples=256):
+    """The six coefficients of the particle-mesh force polynomial (host fit in the library)."""
+    out = (ctypes.c_double * 6)()
+    _check("sr_gravity_fit_poly", load_library().sr_gravity_fit_poly(float(r_s), float(r_cut), int(samples), out))
+    return [out[k] for k in range(6)]
+
+
+def sr_gravity_backward(leaves, x, y, z, m, ga, G=1.0, eps=0.0, r_cut=None, poly=None, prec="f32"):
+    """dL/dx [n,3] of the short-range gravity given ga = dL/da [n,3]."""
+    dt = _DTYPE[prec]
+    for t in (x, y, z):
+        _dev(t, torch.float64)
+    _dev(m, dt)
+    _dev(ga, dt)
+    n = int(x.numel())
+    gx = torch.empty(n, 3, dtype=dt, device=x.device)
+    pc = None if poly is None else (ctypes.c_double * 6)(*[float(p) for p in poly])
+    _check("sr_gravity_backward",
+           load_library().sr_gravity_backward(leaves.handle, n, _ptr(x), _ptr(y), _ptr(z), _ptr(m), float(G),
+                                              float(eps), float(r_cut), pc, _ptr(ga), _PREC[prec], _ptr(gx),
+                                              _stream()))
+    return gx
+
+
+class SRGravity(torch.autograd.Function):
+    """pos [n,3] f64 -> a [n,3]: short-range gravity over the handle's candidate
+    leaves; backward calls sr_gravity_backward (masses are constants)."""
+
+    @staticmethod
+    def forward(ctx, pos, m, leaves, G=1.0, eps=0.0, r_cut=None, poly=None, prec="f32"):
+        x, y, z = (pos[:, k].contiguous() for k in range(3))
+        ctx.args = (leaves, m, G, eps, r_cut, poly, prec)
+        ctx.save_for_backward(x, y, z)
+        return sr_gravity(leaves, x, y, z, m, G, eps, r_cut, poly, prec)
+
+    @staticmethod
+    def backward(ctx, ga):
+        x, y, z = ctx.saved_tensors
+        leaves, m, G, eps, r_cut, poly, prec = ctx.args
+        gx = sr_gravity_backward(leaves, x, y, z, m, ga.to(_DTYPE[prec]).contiguous(), G, eps, r_cut, poly, prec)
+        return gx.double(), None, None, None, None, None, None, None
+
+
 def sr_gravity(leaves, x, y, z, m, G=1.0, eps=0.0, r_cut=None, poly=None, prec="f32"):
     dt = _DTYPE[prec]
     for t in (x, y, z):
@@ -364,6 +467,37 @@ def sr_gravity(leaves, x, y, z, m, G=1.0, eps=0.0, r_cut=None, poly=None, prec="
                                      float(G), float(eps), float(r_cut), pc, _PREC[prec], _ptr(a),
                                      _stream()))
     return a
+
+
+def crk_timestep(gas, a, gamma=5.0 / 3.0, c_cfl=0.25, c_acc=0.25, prec="f32"):
+    """The global time step as a one-element device tensor (no host synchronisation)."""
+    dt_ = _DTYPE[prec]
+    n = int(gas["h"].numel())
+    for k in ("h", "u", "vx", "vy", "vz"):
+        _dev(gas[k], dt_)
+    _dev(a, dt_)
+    dt = torch.empty(1, dtype=dt_, device=gas["h"].device)
+    _check("crk_timestep",
+           load_library().crk_timestep(n, _ptr(gas["h"]), _ptr(gas["u"]), _ptr(gas["vx"]), _ptr(gas["vy"]),
+                                       _ptr(gas["vz"]), _ptr(a), float(gamma), float(c_cfl), float(c_acc),
+                                       _PREC[prec], _ptr(dt), _stream()))
+    return dt
+
+
+def crk_kick_drift(gas, a, dudt, dt, prec="f32"):
+    """Updates gas x, y, z, vx, vy, vz and u in place with the device time step dt."""
+    dt_ = _DTYPE[prec]
+    for k in ("x", "y", "z"):
+        _dev(gas[k], torch.float64)
+    for k in ("vx", "vy", "vz", "u"):
+        _dev(gas[k], dt_)
+    for t in (a, dudt, dt):
+        _dev(t, dt_)
+    n = int(gas["x"].numel())
+    _check("crk_kick_drift",
+           load_library().crk_kick_drift(n, _ptr(gas["x"]), _ptr(gas["y"]), _ptr(gas["z"]), _ptr(gas["vx"]),
+                                         _ptr(gas["vy"]), _ptr(gas["vz"]), _ptr(gas["u"]), _ptr(a), _ptr(dudt),
+                                         _ptr(dt), _PREC[prec], _stream()))
 
 
 def forward(leaves, gas, gamma=5.0 / 3.0, prec="f32", store_sums=False):

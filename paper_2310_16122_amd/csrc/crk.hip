@@ -76,17 +76,26 @@ template <class R> struct alignas(16) RecAcc {
 static_assert(sizeof(RecAcc<float>) == 128, "f32 record is one 128-byte line");
 static_assert(sizeof(RecAcc<double>) == 256, "f64 record is two 128-byte lines");
 
-template <class R>
-__global__ void k_pack_acc(int n, const int32_t* perm, const uint4* quant, const R* h, const R* u,
-                           const R* vx, const R* vy, const R* vz, const R* V, const R* rho,
-                           const R* A, const R* B, const R* dA, const R* dB, R gm1,
-                           RecAcc<R>* rec) {
-    __shared__ uint4 buf[256 * (sizeof(RecAcc<R>) / 16)];
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = s < n;
-    const int i = valid ? perm[s] : 0;
-    RecAcc<R> r{};
-    const uint4 q = quant[valid ? s : 0];
+// The force record with what the artificial viscosity needs of a particle:
+// its velocity gradient in grid units dvs = s dv (dvs[3a + c] = s d_c v^a),
+// hs = h / s, rcl = rho C_l c_s and rcq = rho C_q (c_s the sound speed).
+template <class R> struct alignas(16) RecAccV {
+    uint32_t q[3];
+    R invHs;
+    R V, P, P4s;
+    R PBs[3], T0[3], v[3];
+    R Qs[9];
+    R dvs[9];
+    R hs, rcl, rcq;
+    R pad[sizeof(R) == 4 ? 3 : 4];
+};
+static_assert(sizeof(RecAccV<float>) == 160 && sizeof(RecAccV<double>) == 320, "whole 16-byte chunks");
+
+// The inviscid part of a force record (shared by both record types).
+template <class R, class Rec>
+__device__ __forceinline__ void fill_acc(Rec& r, int i, const uint4& q, const R* h, const R* u, const R* vx,
+                                         const R* vy, const R* vz, const R* V, const R* rho, const R* A,
+                                         const R* B, const R* dA, const R* dB, R gm1) {
     r.q[0] = q.x; r.q[1] = q.y; r.q[2] = q.z;
     // the folded coefficients in FP64, rounded once
     const double sc = kInvGrid;
@@ -110,6 +119,44 @@ __global__ void k_pack_acc(int n, const int32_t* perm, const uint4* quant, const
             r.Qs[3 * a + c] = R(sc * cW * (Ai * double(dB[9 * i + 3 * a + c]) + dAd[c] * Bd[a]));
     }
     r.v[0] = vx[i]; r.v[1] = vy[i]; r.v[2] = vz[i];
+}
+
+template <class R>
+__global__ void k_pack_acc(int n, const int32_t* perm, const uint4* quant, const R* h, const R* u,
+                           const R* vx, const R* vy, const R* vz, const R* V, const R* rho,
+                           const R* A, const R* B, const R* dA, const R* dB, R gm1,
+                           RecAcc<R>* rec) {
+    __shared__ uint4 buf[256 * (sizeof(RecAcc<R>) / 16)];
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = s < n;
+    const int i = valid ? perm[s] : 0;
+    RecAcc<R> r{};
+    fill_acc<R>(r, i, quant[valid ? s : 0], h, u, vx, vy, vz, V, rho, A, B, dA, dB, gm1);
+    const int first = blockIdx.x * blockDim.x;
+    store_records(rec, r, valid, first, min(int(blockDim.x), n - first), buf);
+}
+
+// viscosity constants of a launch
+struct ViscParams {
+    double Cl, Cq, eps_q, gamma;
+};
+
+template <class R>
+__global__ void k_pack_acc_visc(int n, const int32_t* perm, const uint4* quant, const R* h, const R* u,
+                                const R* vx, const R* vy, const R* vz, const R* V, const R* rho,
+                                const R* A, const R* B, const R* dA, const R* dB, const R* dv, R gm1,
+                                ViscParams vp, RecAccV<R>* rec) {
+    __shared__ uint4 buf[256 * (sizeof(RecAccV<R>) / 16)];
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = s < n;
+    const int i = valid ? perm[s] : 0;
+    RecAccV<R> r{};
+    fill_acc<R>(r, i, quant[valid ? s : 0], h, u, vx, vy, vz, V, rho, A, B, dA, dB, gm1);
+    for (int k = 0; k < 9; ++k) r.dvs[k] = R(kInvGrid * double(dv[9 * i + k]));
+    r.hs = R(double(h[i]) / kInvGrid);
+    const double cs = sqrt(vp.gamma * (vp.gamma - 1.0) * double(u[i]));
+    r.rcl = R(double(rho[i]) * vp.Cl * cs);
+    r.rcq = R(double(rho[i]) * vp.Cq);
     const int first = blockIdx.x * blockDim.x;
     store_records(rec, r, valid, first, min(int(blockDim.x), n - first), buf);
 }
@@ -487,8 +534,8 @@ __global__ __launch_bounds__(256) void k_moments(Queue qu, int n, Lists L, const
 // gradient of a particle's corrected kernel at separation y (grid units, from
 // that particle); the lane's own particle and its neighbour go through the same
 // expression, on exactly negated separations, so that F_ij = -F_ji bit for bit
-template <class R>
-__device__ __forceinline__ void corrected_grad(const RecAcc<R>& r, R wq, R fq, const R y[3], R G[3]) {
+template <class R, class Rec>
+__device__ __forceinline__ void corrected_grad(const Rec& r, R wq, R fq, const R y[3], R G[3]) {
     const R fl = fq * (r.P4s + r.PBs[0] * y[0] + r.PBs[1] * y[1] + r.PBs[2] * y[2]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -525,10 +572,68 @@ __device__ __forceinline__ void accel_pair(const RecAcc<R>& ri, const RecAcc<R>&
     acc.next(k, chunk);
 }
 
+// The same pair with the artificial viscosity: Q_i + Q_j joins P_i + P_j.
+// Per pair, with D_k = dv_k x (velocity units) and s_k = x . D_k, the van
+// Leer limiter Phi = max(0, 4 s_i s_j / (s_i + s_j)^2) weights the linear
+// reconstruction of both velocities to the pair's midpoint, w = v_i - v_j -
+// Phi/2 (D_i + D_j), and mu_k = min(0, h_k (w.x) / (r^2 + eps_q h_k^2)),
+// Q_k = rho_k (-C_l c_k mu_k + C_q mu_k^2).  In grid units (x = s y):
+// D_k = dvs_k y, s_k carries a common factor 1/s, and
+// mu_k = hs_k (w.y) / (|y|^2 + eps_q hs_k^2).  Every quantity is evaluated by
+// the same expressions from both sides of the pair (the two Q terms are
+// separate statements, added commutatively), so F_ij = -F_ji bit for bit.
+template <class R>
+__device__ __forceinline__ void accel_pair_visc(const RecAccV<R>& ri, const RecAccV<R>& rj, R eps_q, int k,
+                                                int chunk, ChunkSums<R, 4>& acc) {
+    const R y[3] = {grid_sep<R>(ri.q[0], rj.q[0]), grid_sep<R>(ri.q[1], rj.q[1]),
+                    grid_sep<R>(ri.q[2], rj.q[2])};
+    const R yo[3] = {-y[0], -y[1], -y[2]};
+    const R r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+    const R r = dsqrt(r2);
+    R wi, fi, wj, fj;
+    wendland(r * ri.invHs, wi, fi);
+    wendland(r * rj.invHs, wj, fj);
+    R Gi[3], Gj[3];
+    corrected_grad(ri, wi, fi, y, Gi);
+    corrected_grad(rj, wj, fj, yo, Gj);
+    R Di[3], Dj[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        Di[a] = ri.dvs[3 * a] * y[0] + ri.dvs[3 * a + 1] * y[1] + ri.dvs[3 * a + 2] * y[2];
+        Dj[a] = rj.dvs[3 * a] * y[0] + rj.dvs[3 * a + 1] * y[1] + rj.dvs[3 * a + 2] * y[2];
+    }
+    const R si = y[0] * Di[0] + y[1] * Di[1] + y[2] * Di[2];
+    const R sj = y[0] * Dj[0] + y[1] * Dj[1] + y[2] * Dj[2];
+    const R sp = si * sj;
+    const R ss = si + sj;
+    const R half_phi = sp > R(0) ? R(2) * sp / (ss * ss) : R(0);
+    R wy = R(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const R wa = (ri.v[a] - rj.v[a]) - half_phi * (Di[a] + Dj[a]);
+        wy += wa * y[a];
+    }
+    const R mi = fmin(R(0), ri.hs * wy / (r2 + eps_q * ri.hs * ri.hs));
+    const R mj = fmin(R(0), rj.hs * wy / (r2 + eps_q * rj.hs * rj.hs));
+    const R qi = mi * (ri.rcq * mi - ri.rcl);
+    const R qj = mj * (rj.rcq * mj - rj.rcl);
+    const R Q = qi + qj;
+    const R coef = (ri.V * rj.V) * ((ri.P + rj.P) + Q);
+    R Fv = R(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const R F = coef * (Gi[c] - Gj[c]);
+        Fv += F * (ri.v[c] - rj.v[c]);
+        acc.add(c, F);
+    }
+    acc.add(3, Fv);
+    acc.next(k, chunk);
+}
+
 // a_i = -1/2 sum / m_i and du_i/dt = 1/4 (dot-product sum) / m_i; the tile's
 // FP64 partial totals go to partials[8 w ...]
-template <class R>
-__device__ __forceinline__ void accel_finish(int w, int s, bool valid, const RecAcc<R>& ri,
+template <class R, class Rec>
+__device__ __forceinline__ void accel_finish(int w, int s, bool valid, const Rec& ri,
                                              ChunkSums<R, 4>& acc, const int32_t* __restrict__ perm,
                                              const R* __restrict__ m, R* __restrict__ a_out,
                                              R* __restrict__ du_out, double* __restrict__ partials) {
@@ -587,6 +692,32 @@ __global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const i
     }
 }
 
+template <class R, bool kOff32>
+__global__ __launch_bounds__(256) void k_accel_visc(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
+                                                    const RecAccV<R>* __restrict__ rec, const R* __restrict__ m,
+                                                    R eps_q, int chunk, R* __restrict__ a_out,
+                                                    R* __restrict__ du_out, double* __restrict__ partials) {
+    constexpr int kStage = stage_stride<RecAccV<R>>();
+    extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
+    const int lane = lane_id();
+    QState qs;
+    for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
+        const int s = w * kWave + lane;
+        const bool valid = s < n;
+        const RecAccV<R> ri = rec[valid ? s : 0];
+        const int cnt = valid ? L.cnt[s] : 0;
+        const int len = L.len[w];
+        ChunkSums<R, 4> acc;
+        acc.zero();
+        staged_list<RecAccV<R>, kOff32>(
+            L, w, cnt, len, rec, stage_buf + wave_in_block() * kStage,
+            [&](const RecAccV<R>& rj, int k) __attribute__((always_inline)) {
+                accel_pair_visc(ri, rj, eps_q, k, chunk, acc);
+            });
+        accel_finish(w, s, valid, ri, acc, perm, m, a_out, du_out, partials);
+    }
+}
+
 // Fixed-order FP64 reduction of the per-tile totals in two stages: block b
 // sums tiles [b per, (b + 1) per) (thread t takes every 256th from the start),
 // then one block sums the block results.  The order depends only on the tile
@@ -612,160 +743,6 @@ __global__ __launch_bounds__(256) void k_totals_blocks(int n_items, int per, con
         for (int k = 0; k < 8; ++k) t[k] += in[8 * w + k];
     block_sum8(t, red);
     if (threadIdx.x < 8) out[8 * blockIdx.x + threadIdx.x] = red[0][threadIdx.x];
-}
-
-// ------------------------------------------------------------------ gravity
-
-struct GravParams {
-    double G, eps2, rc2;
-    double poly[6];
-    int use_poly;
-};
-
-// A staged candidate: position relative to the tile origin, and mass.
-template <class R> struct alignas(4 * sizeof(R)) GravRec {
-    R x, y, z, m;
-};
-
-// One wave per tile.  Candidates are streamed in blocks of 64 (the next
-// block's loads are issued before the current one is evaluated).  Positions
-// are taken relative to the tile's first particle as reals, so a pair's
-// separation is three subtractions: for a compact tile (every lane within
-// 1/4 of that origin, r_c < 1/4) the relative coordinates of every pair within
-// r_c are exact minimum images and every pair beyond r_c stays beyond it;
-// other tiles use the exact fixed-point separation.  In a compact tile a
-// candidate farther than r_c from the tile's bounding box cannot interact
-// with any lane and is dropped before it reaches LDS; the survivors are
-// compacted, padded with massless entries to whole chunks, and evaluated in
-// straight-line chunks of kChunk with the compensated fold between chunks.
-template <class R, bool kPoly, bool kSoft>
-__global__ __launch_bounds__(64) void k_gravity(Queue qu, int n, const int32_t* __restrict__ perm,
-                                                const uint4* __restrict__ quant, const R* __restrict__ ms,
-                                                const int32_t* __restrict__ rng_off,
-                                                const int2* __restrict__ rng, GravParams gp,
-                                                R* __restrict__ a_out) {
-    constexpr bool kComp = sizeof(R) == 4;
-    constexpr int kChunk = 8;
-    __shared__ GravRec<R> srec[kWave];
-    __shared__ uint4 sq[kWave];
-    const int lane = lane_id();
-    const R rc2 = R(gp.rc2), eps2 = R(gp.eps2);
-    // the box test keeps a margin over the pair test so rounding never drops
-    // a candidate that some lane would count
-    const R keep2 = rc2 * R(1.001);
-    R pc[6];
-    for (int k = 0; k < 6; ++k) pc[k] = R(gp.poly[k]);
-    QState qs;
-    for (int wq = queue_start(qu, qs); wq >= 0; wq = queue_next(qu, qs)) {
-        // tile, ranges and block bounds are wave-uniform: keep them scalar
-        const int w = __builtin_amdgcn_readfirstlane(wq);
-        const int s = w * kWave + lane;
-        const bool valid = s < n;
-        const uint4 qo = quant[w * kWave];  // tile origin (wave-uniform)
-        const uint4 qi = valid ? quant[s] : qo;
-        const R xi = sep<R>(qi.x, qo.x), yi = sep<R>(qi.y, qo.y), zi = sep<R>(qi.z, qo.z);
-        const bool far = fmax(fabs(xi), fmax(fabs(yi), fabs(zi))) >= R(0.25);
-        const bool compact = __ballot(far) == 0 && gp.rc2 < 0.0625;
-        R lo[3] = {xi, yi, zi}, hi[3] = {xi, yi, zi};
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                lo[c] = fmin(lo[c], R(__shfl_xor(lo[c], o)));
-                hi[c] = fmax(hi[c], R(__shfl_xor(hi[c], o)));
-            }
-        R acc[3] = {R(0), R(0), R(0)}, cmp[3] = {R(0), R(0), R(0)}, part[3] = {R(0), R(0), R(0)};
-        auto pair = [&](R dx, R dy, R dz, R mj) __attribute__((always_inline)) {
-            const R r2 = dx * dx + dy * dy + dz * dz;
-            // with softening a coincident pair (the self pair included) has a
-            // finite f and a zero separation, so it adds exactly zero
-            const bool in = kSoft ? r2 < rc2 : (r2 < rc2 && r2 > R(0));
-            const R ir = drsqrt(r2 + eps2);
-            R f = ir * ir * ir;
-            if (kPoly) {
-                R pv = pc[5];
-                for (int k = 4; k >= 0; --k) pv = pv * r2 + pc[k];
-                f -= pv;
-            }
-            f = in ? mj * f : R(0);
-            part[0] += f * dx;
-            part[1] += f * dy;
-            part[2] += f * dz;
-        };
-        auto fold = [&]() __attribute__((always_inline)) {
-            if (kComp)
-                for (int c = 0; c < 3; ++c) { kadd(acc[c], cmp[c], part[c]); part[c] = R(0); }
-        };
-        // candidate blocks: range r, block [b, min(b + 64, e))
-        auto uni = [](int v) __attribute__((always_inline)) { return __builtin_amdgcn_readfirstlane(v); };
-        const int r1 = uni(rng_off[w + 1]);
-        int r = uni(rng_off[w]), b = 0, e = 0;
-        if (r < r1) { const int2 g = rng[r]; b = uni(g.x); e = uni(g.y); }
-        uint4 nq = qo;
-        R nm = R(0);
-        if (r < r1 && lane < e - b) { nq = quant[b + lane]; nm = ms[b + lane]; }
-        while (r < r1) {
-            const int mcnt = min(kWave, e - b);
-            const uint4 qj = nq;
-            const R mj = nm;
-            // advance and prefetch the next block
-            int nb = b + kWave, ne = e, nr = r;
-            if (nb >= ne) {
-                ++nr;
-                if (nr < r1) { const int2 g = rng[nr]; nb = uni(g.x); ne = uni(g.y); }
-            }
-            if (nr < r1 && lane < ne - nb) { nq = quant[nb + lane]; nm = ms[nb + lane]; }
-            r = nr; b = nb; e = ne;
-
-            const GravRec<R> g{sep<R>(qj.x, qo.x), sep<R>(qj.y, qo.y), sep<R>(qj.z, qo.z), mj};
-            bool keep = lane < mcnt;
-            if (compact && keep) {
-                const R d0 = fmax(fmax(lo[0] - g.x, g.x - hi[0]), R(0));
-                const R d1 = fmax(fmax(lo[1] - g.y, g.y - hi[1]), R(0));
-                const R d2 = fmax(fmax(lo[2] - g.z, g.z - hi[2]), R(0));
-                keep = d0 * d0 + d1 * d1 + d2 * d2 < keep2;
-            }
-            const uint64_t mask = __ballot(keep);
-            if (mask == 0) continue;
-            const int cnt = __popcll(mask);
-            const int padded = (cnt + kChunk - 1) / kChunk * kChunk;
-            const int pos = __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32),
-                                                      __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
-            __syncthreads();  // the previous block's entries have been read
-            if (keep) { srec[pos] = g; sq[pos] = qj; }
-            if (lane >= cnt && lane < padded) {
-                srec[lane] = GravRec<R>{R(2), R(2), R(2), R(0)};
-                sq[lane] = qo;
-            }
-            __syncthreads();
-            if (compact) {
-                for (int j0 = 0; j0 < padded; j0 += kChunk) {
-#pragma unroll
-                    for (int u = 0; u < kChunk; ++u) {
-                        const GravRec<R> c = srec[j0 + u];
-                        pair(xi - c.x, yi - c.y, zi - c.z, c.m);
-                    }
-                    fold();
-                }
-            } else {
-                for (int j0 = 0; j0 < padded; j0 += kChunk) {
-#pragma unroll
-                    for (int u = 0; u < kChunk; ++u) {
-                        const uint4 c = sq[j0 + u];
-                        pair(sep<R>(qi.x, c.x), sep<R>(qi.y, c.y), sep<R>(qi.z, c.z), srec[j0 + u].m);
-                    }
-                    fold();
-                }
-            }
-        }
-        if (valid) {
-            const int i = perm[s];
-            for (int c = 0; c < 3; ++c) {
-                const R tot = kComp ? (acc[c] - cmp[c]) : part[c];
-                a_out[3 * i + c] = R(-gp.G) * tot;
-            }
-        }
-    }
 }
 
 }  // namespace
@@ -944,6 +921,51 @@ int accel_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const 
     return accel_run<R>(L, g, V, rho, C, gamma, a, dudt, totals, static_cast<RecAcc<R>*>(sp), L->partials, st);
 }
 
+// The force pass with the artificial viscosity (dv: velocity gradients, 9 per
+// particle in caller order, from the Extras pass).
+template <class R>
+int accel_visc_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const crk_corr* C, const R* dv,
+                    const crk_visc* q, double gamma, R* a, R* dudt, double* totals, hipStream_t st) {
+    const int n = int(L->n);
+    int rc = pack_positions<R>(L, g->x, g->y, g->z, static_cast<const R*>(g->h), st);
+    if (rc) return rc;
+    void* sp = nullptr;
+    if ((rc = pass_scratch(L, sizeof(RecAccV<R>) * size_t(n), &sp))) return rc;
+    RecAccV<R>* rec = static_cast<RecAccV<R>*>(sp);
+    const ViscParams vp{q->Cl, q->Cq, q->eps_q, gamma};
+    {
+        TimeScope tp(L, st, CRK_K_PACK);
+        hipLaunchKernelGGL(k_pack_acc_visc<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, L->quant,
+                           static_cast<const R*>(g->h), static_cast<const R*>(g->u),
+                           static_cast<const R*>(g->vx), static_cast<const R*>(g->vy),
+                           static_cast<const R*>(g->vz), V, rho, static_cast<const R*>(C->A),
+                           static_cast<const R*>(C->B), static_cast<const R*>(C->dA),
+                           static_cast<const R*>(C->dB), dv, R(gamma - 1.0), vp, rec);
+    }
+    LAUNCH_CHECK("pack_acc_visc");
+    reset_queue(L, st);
+    {
+        TimeScope ts(L, st, CRK_K_ACCEL_VISC);
+        auto kern = off32<RecAccV<R>>(L) ? k_accel_visc<R, true> : k_accel_visc<R, false>;
+        const int bw = L->tune.block_waves;
+        hipLaunchKernelGGL(kern, dim3(grid_nwave(L)), dim3(kWave * bw), stage_bytes<RecAccV<R>>(bw), st,
+                           make_queue(L, L->order_pair), n, lists(L), L->perm, rec,
+                           static_cast<const R*>(g->m), R(q->eps_q), L->tune.kahan_chunk, a, dudt, L->partials);
+    }
+    LAUNCH_CHECK("accel_visc");
+    if (totals) {
+        TimeScope tt(L, st, CRK_K_PACK);
+        const int nt = int(L->n_tiles);
+        const int per = (nt + kTotalsBlocks - 1) / kTotalsBlocks;
+        double* blocks = L->partials + 8 * int64_t(nt);
+        hipLaunchKernelGGL(k_totals_blocks, dim3(kTotalsBlocks), dim3(256), 0, st, nt, per, L->partials, blocks);
+        hipLaunchKernelGGL(k_totals_blocks, dim3(1), dim3(256), 0, st, kTotalsBlocks, kTotalsBlocks, blocks,
+                           totals);
+        LAUNCH_CHECK("totals");
+    }
+    return CRK_OK;
+}
+
 // ---------------------------------------------------------------- force pass without a workspace
 // Scratch of crk_accel_energy_noalloc: a fixed array in device memory, one per
 // GPU, held from the library's first use on that GPU until the process ends.
@@ -986,33 +1008,6 @@ int accel_noalloc_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho
                         reinterpret_cast<double*>(p + accel_scratch_records<R>(L->n)), st);
 }
 
-template <class R>
-int gravity_impl(crk_leaves* L, const double* x, const double* y, const double* z, const R* m,
-                 const GravParams& gp, R* a, hipStream_t st) {
-    const int n = int(L->n);
-    int rc = pack_positions<R>(L, x, y, z, nullptr, st);
-    if (rc) return rc;
-    void* sp = nullptr;
-    if ((rc = pass_scratch(L, sizeof(R) * size_t(n), &sp))) return rc;
-    R* ms = static_cast<R*>(sp);
-    {
-        TimeScope tp(L, st, CRK_K_PACK);
-        hipLaunchKernelGGL(k_gather<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, m, ms);
-    }
-    LAUNCH_CHECK("gather m");
-    reset_queue(L, st);
-    TimeScope ts(L, st, CRK_K_GRAVITY);
-    // softening large enough that a coincident pair's f = m eps^-3 is no larger
-    // than a real close pair's (eps^-3 <= 2^120 in FP32)
-    const bool soft = R(gp.eps2) >= R(0x1p-80);
-    auto kern = gp.use_poly ? (soft ? k_gravity<R, true, true> : k_gravity<R, true, false>)
-                            : (soft ? k_gravity<R, false, true> : k_gravity<R, false, false>);
-    hipLaunchKernelGGL(kern, dim3(grid_1wave(L)), dim3(kWave), 0, st,
-                       make_queue(L, L->order_cull), n, L->perm, L->quant, ms, L->rng_off, L->rng,
-                       gp, a);
-    LAUNCH_CHECK("gravity");
-    return CRK_OK;
-}
 
 }  // namespace
 
@@ -1074,6 +1069,7 @@ int crk_set_tuning(crk_leaves* L, const crk_tuning* in) {
     if (in->xcd_groups < 1 || in->xcd_groups > kMaxGroups) return fail(CRK_EINVAL, "xcd_groups in [1, 16]");
     if (in->tile_order != 0 && in->tile_order != 1) return fail(CRK_EINVAL, "tile_order must be 0 or 1");
     if (in->addr64 != 0 && in->addr64 != 1) return fail(CRK_EINVAL, "addr64 must be 0 or 1");
+    if (in->exchange < 0 || in->exchange > 2) return fail(CRK_EINVAL, "exchange must be 0, 1 or 2");
     L->tune = *in;
     return CRK_OK;
 }
@@ -1123,10 +1119,10 @@ void carve_part_a(crk_leaves* L, Carver& c, int64_t n, int64_t nt) {
         L->ell_len_gather = c.take<int32_t>(nt);
     }
     // per-pass scratch, for both precisions: the backward's records (hydro),
-    // the masses in tree order (gravity)
+    // the masses and upstream adjoints in tree order (gravity)
     L->scratch_bytes = L->hydro ? std::max(crk::backward_scratch_bytes(n, true),
                                            size_t(n) * sizeof(RecAcc<double>))
-                                : size_t(n) * sizeof(double);
+                                : size_t(n) * 4 * sizeof(double);  // masses and adjoints (gravity)
     L->scratch = c.take<char>(L->scratch_bytes);
 }
 
@@ -1512,33 +1508,37 @@ int crk_accel_energy(crk_leaves* L, const crk_gas* g, const void* V, const void*
     return accel_entry(false, L, g, V, rho, C, gamma, prec, a, dudt, totals, st);
 }
 
+int crk_accel_energy_visc(crk_leaves* L, const crk_gas* g, const void* V, const void* rho, const crk_corr* C,
+                          const void* dv, const crk_visc* q, double gamma, crk_prec prec, void* a, void* dudt,
+                          double* totals, hipStream_t st) {
+    int rc = check_gas(L, g, true);
+    if (rc) return rc;
+    if (!q) return fail(CRK_EINVAL, "viscosity parameters are required");
+    if (!(q->Cl >= 0.0) || !(q->Cq >= 0.0) || !(q->eps_q > 0.0))
+        return fail(CRK_EINVAL, "viscosity needs Cl >= 0, Cq >= 0 and eps_q > 0");
+    if (!(gamma > 1.0)) return fail(CRK_EINVAL, "gamma must exceed 1 (the sound speed)");
+    if (L->n == 0) {
+        if (totals) {
+            hipLaunchKernelGGL(k_zero8, dim3(1), dim3(64), 0, st, totals);
+            LAUNCH_CHECK("zero totals");
+        }
+        return CRK_OK;
+    }
+    if (!V || !rho || !C || !C->A || !C->B || !C->dA || !C->dB || !dv || !a || !dudt)
+        return fail(CRK_EINVAL, "V, rho, corrections, dv, a and dudt are required");
+    if (prec == CRK_F32)
+        return accel_visc_impl<float>(L, g, (const float*)V, (const float*)rho, C, (const float*)dv, q, gamma,
+                                      (float*)a, (float*)dudt, totals, st);
+    if (prec == CRK_F64)
+        return accel_visc_impl<double>(L, g, (const double*)V, (const double*)rho, C, (const double*)dv, q, gamma,
+                                       (double*)a, (double*)dudt, totals, st);
+    return fail(CRK_EINVAL, "unknown precision");
+}
+
 int crk_accel_energy_noalloc(crk_leaves* L, const crk_gas* g, const void* V, const void* rho,
                              const crk_corr* C, double gamma, crk_prec prec, void* a, void* dudt,
                              double* totals, hipStream_t st) {
     return accel_entry(true, L, g, V, rho, C, gamma, prec, a, dudt, totals, st);
-}
-
-int sr_gravity(crk_leaves* L, int64_t n, const double* x, const double* y, const double* z,
-               const void* m, double G, double eps, double r_cut, const double* poly, crk_prec prec,
-               void* a, hipStream_t st) {
-    if (!L) return fail(CRK_EINVAL, "null handle");
-    if (n != L->n) return fail(CRK_EINVAL, "n does not match the handle");
-    if (n == 0) return CRK_OK;
-    if (L->hydro) return fail(CRK_ESTATE, "sr_gravity needs a handle built in fixed-radius mode");
-    if (!(r_cut > 0.0) || r_cut > L->r_fixed)
-        return fail(CRK_EINVAL, "r_cut must be in (0, r_fixed of the handle]");
-    if (!(eps >= 0.0)) return fail(CRK_EINVAL, "eps must be >= 0");
-    if (n == 0) return CRK_OK;
-    if (!x || !y || !z || !m || !a) return fail(CRK_EINVAL, "x, y, z, m and a are required");
-    GravParams gp;
-    gp.G = G;
-    gp.eps2 = eps * eps;
-    gp.rc2 = r_cut * r_cut;
-    gp.use_poly = poly != nullptr;
-    for (int k = 0; k < 6; ++k) gp.poly[k] = poly ? poly[k] : 0.0;
-    if (prec == CRK_F32) return gravity_impl<float>(L, x, y, z, (const float*)m, gp, (float*)a, st);
-    if (prec == CRK_F64) return gravity_impl<double>(L, x, y, z, (const double*)m, gp, (double*)a, st);
-    return fail(CRK_EINVAL, "unknown precision");
 }
 
 }  // extern "C"

@@ -633,7 +633,7 @@ struct crk_leaves {
     double r_fixed = 0.0;
     int64_t n_tiles = 0, n_leaves = 0;
     int n_cu = 1;
-    crk_tuning tune{0, 16, 4, 4, 8, 0, 0};  // measured best on the C2 workload
+    crk_tuning tune{0, 16, 4, 4, 8, 0, 0, 0};  // measured best on the C2 workload
     int32_t* perm = nullptr;
     uint4* quant = nullptr;
     double* Hd = nullptr;

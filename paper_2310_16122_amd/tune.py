@@ -26,6 +26,9 @@ SPACE = {
     "block_waves": (1, 2, 4),
     "kahan_chunk": (1, 4, 8),
 }
+# short-range gravity also chooses how candidates are exchanged between lanes
+# (LDS broadcast, scalar-register broadcast, cross-lane permute)
+GRAVITY_SPACE = dict(SPACE, exchange=(0, 1, 2))
 
 
 def _sync():

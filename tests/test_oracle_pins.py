@@ -660,3 +660,42 @@ def test_viscous_forces_conserve_and_are_galilean(tiny, oracle_lib):
     os_ = oracle_lib.hydro_visc(gs)
     assert np.abs(os_["a"] - ov["a"]).max() < 1e-12 * np.abs(ov["a"]).max()
     assert np.abs(os_["dudt"] - ov["dudt"]).max() < 1e-12 * np.abs(ov["dudt"]).max()
+
+
+def test_listed_viscous_chain_is_the_brute_force_chain(oracle_lib):
+    """Extras and viscous forces over exact lists equal the brute-force ones bit for bit."""
+    g = synth.make_config("C2", n_side=10)
+    o = oracle_lib.hydro(g)
+    ov = oracle_lib.hydro_visc(g)
+    off, idx = oracle_lib.neighbour_lists(g)
+    ol = oracle_lib.visc_listed(g, off, idx, o)
+    for k in ("rhoR", "dv", "du", "a", "dudt"):
+        assert np.array_equal(ol[k], ov[k]), k
+
+
+# ---------------------------------------------------------------- time step
+def test_timestep_closed_form(oracle_lib):
+    """Three particles whose limits are known: the slowest-signal one sets the
+    Courant limit unless an acceleration limit is smaller."""
+    gamma = 5.0 / 3.0
+    g = dict(h=np.array([0.01, 0.02, 0.005]), u=np.array([1.0, 0.5, 4.0]),
+             vx=np.array([0.0, 0.3, 0.0]), vy=np.array([0.0, 0.4, 0.0]), vz=np.zeros(3))
+    a = np.zeros((3, 3))
+    cs = np.sqrt(gamma * (gamma - 1.0) * g["u"])
+    cfl = 0.25 * 2.0 * g["h"] / (cs + np.array([0.0, 0.5, 0.0]))
+    assert oracle_lib.timestep(g, a, gamma, 0.25, 0.5) == pytest.approx(cfl.min(), rel=1e-15)
+    a[1] = [3.0, 0.0, 4.0]  # |a| = 5 on particle 1: limit 0.5 sqrt(0.04 / 5)
+    acc = 0.5 * math.sqrt(0.04 / 5.0)
+    assert oracle_lib.timestep(g, a, gamma, 0.25, 0.5) == pytest.approx(min(cfl.min(), acc), rel=1e-15)
+
+
+def test_kick_drift_moves_and_wraps(oracle_lib):
+    g = dict(x=np.array([0.99, 0.2]), y=np.array([0.5, 0.01]), z=np.array([0.0, 0.7]),
+             vx=np.array([0.5, 0.0]), vy=np.array([0.0, -1.0]), vz=np.array([0.1, 0.0]), u=np.array([1.0, 2.0]))
+    a = np.array([[1.0, 0.0, 0.0], [0.0, 0.0, 2.0]])
+    out = oracle_lib.kick_drift(g, a, np.array([-1.0, 0.5]), 0.1)
+    assert out["vx"][0] == pytest.approx(0.6) and out["vz"][1] == pytest.approx(0.2)
+    assert out["u"][0] == pytest.approx(0.9) and out["u"][1] == pytest.approx(2.05)
+    assert out["x"][0] == pytest.approx(0.99 + 0.06 - 1.0)  # wrapped
+    assert out["y"][1] == pytest.approx(0.01 - 0.1 + 1.0)   # wrapped from below
+    assert out["z"][1] == pytest.approx(0.7 + 0.02)
