@@ -110,6 +110,9 @@ typedef struct {
                             (Sec. 5.3's variants): 0 compacted into LDS and read as LDS broadcasts,
                             1 scalar-register broadcast (v_readlane), 2 cross-lane permute (ds_bpermute);
                             same results bit for bit */
+    int stage16;         /* volume and moments passes (16-byte FP32 neighbour records): 0 gathered lane by
+                            lane, 1 each slot's distinct particles staged through LDS like the larger
+                            records (same results bit for bit) */
 } crk_tuning;
 
 /*

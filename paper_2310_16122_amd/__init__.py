@@ -72,7 +72,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("persistent", ctypes.c_int), ("waves_per_cu", ctypes.c_int),
                 ("kahan_chunk", ctypes.c_int), ("block_waves", ctypes.c_int),
                 ("xcd_groups", ctypes.c_int), ("tile_order", ctypes.c_int), ("addr64", ctypes.c_int),
-                ("exchange", ctypes.c_int)]
+                ("exchange", ctypes.c_int), ("stage16", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

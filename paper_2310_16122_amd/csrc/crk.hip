@@ -446,11 +446,13 @@ __global__ __launch_bounds__(64) void k_count_fixed(int n_tiles, int n, const ui
 
 // ------------------------------------------------------------------ volume
 
-template <class R>
+template <class R, bool kStage16, bool kOff32>
 __global__ __launch_bounds__(256) void k_volume(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
                                                 const uint4* __restrict__ quant, const R* __restrict__ h,
                                                 const R* __restrict__ m, int chunk, R* __restrict__ V_out,
                                                 R* __restrict__ rho_out) {
+    constexpr int kStage = stage_stride<uint4, kStage16>();
+    extern __shared__ uint4 stage_buf[];  // kStage per wave when staged (stage_bytes)
     const int lane = lane_id();
     QState qs;
     for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
@@ -462,12 +464,11 @@ __global__ __launch_bounds__(256) void k_volume(Queue qu, int n, Lists L, const 
         const R invH = R(1) / H;
         const int cnt = valid ? L.cnt[s] : 0;
         const int len = L.len[w];
-        const uint32_t* lst = L.nbr + L.off[w] + lane;
         ChunkSums<R, 1> S;
         S.zero();
         S.add(0, R(1));  // self term: w(0) = 1
-        pipelined_list<uint4>(
-            lst, cnt, len, [&](uint32_t j) __attribute__((always_inline)) { return quant[j]; },
+        list_loop<uint4, kOff32, kStage16>(
+            L, w, cnt, len, quant, stage_buf + wave_in_block() * kStage,
             [&](const uint4& qj, int k) __attribute__((always_inline)) {
                 const R dx = sep<R>(qi.x, qj.x), dy = sep<R>(qi.y, qj.y), dz = sep<R>(qi.z, qj.z);
                 const R r = dsqrt(dx * dx + dy * dy + dz * dz);
@@ -489,7 +490,7 @@ __global__ __launch_bounds__(256) void k_volume(Queue qu, int n, Lists L, const 
 
 // Moments over the neighbour list and the FP64 solve; corrections written in
 // caller order.
-template <class R, bool kOff32>
+template <class R, bool kOff32, bool kStage16>
 __global__ __launch_bounds__(256) void k_moments(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
                                                  const RecQV<R>* __restrict__ qv,
                                                  const R* __restrict__ h, int chunk, R* __restrict__ A_out,
@@ -497,7 +498,7 @@ __global__ __launch_bounds__(256) void k_moments(Queue qu, int n, Lists L, const
                                                  R* __restrict__ dB_out,
                                                  unsigned long long* __restrict__ n_fallback,
                                                  double* __restrict__ sums_out) {
-    constexpr int kStage = stage_stride<RecQV<R>>();
+    constexpr int kStage = stage_stride<RecQV<R>, kStage16>();
     extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
     const int lane = lane_id();
     QState qs;
@@ -508,7 +509,7 @@ __global__ __launch_bounds__(256) void k_moments(Queue qu, int n, Lists L, const
         const R H = valid ? R(2) * h[i] : R(1);
         double S[29], M[40];
         int nnb = 0;
-        moment_sums<R, kOff32>(w, s, valid, L, qv, stage_buf + wave_in_block() * kStage, H, chunk, S, nnb);
+        moment_sums<R, kOff32, kStage16>(w, s, valid, L, qv, stage_buf + wave_in_block() * kStage, H, chunk, S, nnb);
         if (valid && sums_out) {
             // kept for the backward (caller order, one row of n per sum)
             for (int e = 0; e < 29; ++e) sums_out[int64_t(e) * n + i] = S[e];
@@ -825,7 +826,11 @@ template <class R> int volume_impl(crk_leaves* L, const crk_gas* g, R* V, R* rho
     if (rc) return rc;
     reset_queue(L, st);
     TimeScope ts(L, st, CRK_K_VOLUME);
-    hipLaunchKernelGGL(k_volume<R>, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves), 0, st,
+    const bool st16 = L->tune.stage16 != 0, o32 = off32<uint4>(L);
+    auto kern = st16 ? (o32 ? k_volume<R, true, true> : k_volume<R, true, false>) : k_volume<R, false, true>;
+    const int bw = L->tune.block_waves;
+    const size_t lds = st16 ? stage_bytes<uint4, true>(bw) : size_t(0);
+    hipLaunchKernelGGL(kern, dim3(grid_nwave(L)), dim3(kWave * bw), lds, st,
                        make_queue(L, L->order_pair), int(L->n), lists_gather(L), L->perm, L->quant,
                        static_cast<const R*>(g->h), static_cast<const R*>(g->m), L->tune.kahan_chunk, V,
                        rho);
@@ -849,9 +854,12 @@ int corrections_impl(crk_leaves* L, const crk_gas* g, const R* V, const crk_corr
     LAUNCH_CHECK("pack position/volume");
     reset_queue(L, st);
     TimeScope ts(L, st, CRK_K_MOMENTS);
-    auto kern = off32<RecQV<R>>(L) ? k_moments<R, true> : k_moments<R, false>;
-    hipLaunchKernelGGL(kern, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves),
-                       stage_bytes<RecQV<R>>(L->tune.block_waves), st,
+    const bool st16 = L->tune.stage16 != 0;
+    auto kern = off32<RecQV<R>>(L) ? (st16 ? k_moments<R, true, true> : k_moments<R, true, false>)
+                                   : (st16 ? k_moments<R, false, true> : k_moments<R, false, false>);
+    const size_t lds = st16 ? stage_bytes<RecQV<R>, true>(L->tune.block_waves)
+                            : stage_bytes<RecQV<R>>(L->tune.block_waves);
+    hipLaunchKernelGGL(kern, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves), lds, st,
                        make_queue(L, L->order_pair), n, lists_gather(L), L->perm, qv,
                        static_cast<const R*>(g->h), L->tune.kahan_chunk, static_cast<R*>(out->A),
                        static_cast<R*>(out->B), static_cast<R*>(out->dA), static_cast<R*>(out->dB),
@@ -1070,6 +1078,7 @@ int crk_set_tuning(crk_leaves* L, const crk_tuning* in) {
     if (in->tile_order != 0 && in->tile_order != 1) return fail(CRK_EINVAL, "tile_order must be 0 or 1");
     if (in->addr64 != 0 && in->addr64 != 1) return fail(CRK_EINVAL, "addr64 must be 0 or 1");
     if (in->exchange < 0 || in->exchange > 2) return fail(CRK_EINVAL, "exchange must be 0, 1 or 2");
+    if (in->stage16 != 0 && in->stage16 != 1) return fail(CRK_EINVAL, "stage16 must be 0 or 1");
     L->tune = *in;
     return CRK_OK;
 }

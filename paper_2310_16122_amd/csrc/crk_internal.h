@@ -418,24 +418,33 @@ template <class R> __global__ void k_pack_qv(int n, const int32_t* perm, const u
     out[s] = r;
 }
 
+// Whether a list-driven pass stages its neighbour records through LDS: always
+// for records larger than 16 bytes; for 16-byte records when kStage16 (else
+// they are gathered lane by lane).
+template <class D, bool kStage16 = false> __host__ __device__ constexpr bool staged() {
+    return sizeof(D) > 16 || kStage16;
+}
+
 // LDS of one wave in a list-driven pass, in 16-byte units: the staged records
-// of a slot and the slot's row of indices (one-chunk records need none).
-template <class D> __host__ __device__ constexpr int stage_stride() {
-    return sizeof(D) > 16 ? int(sizeof(D) / 16) * kWave + kWave / 4 : 1;
+// of a slot and the slot's row of indices (gathered records need none).
+template <class D, bool kStage16 = false> __host__ __device__ constexpr int stage_stride() {
+    return staged<D, kStage16>() ? int(sizeof(D) / 16) * kWave + kWave / 4 : 1;
 }
 
 // Dynamic LDS of a list-driven launch: one wave's buffers per wave of the
 // workgroup.
-template <class D> inline size_t stage_bytes(int block_waves) {
-    return size_t(stage_stride<D>()) * 16 * size_t(sizeof(D) > 16 ? block_waves : 1);
+template <class D, bool kStage16 = false> inline size_t stage_bytes(int block_waves) {
+    return size_t(stage_stride<D, kStage16>()) * 16 * size_t(staged<D, kStage16>() ? block_waves : 1);
 }
 
-// One-chunk records are gathered lane by lane (a cooperative load saves
-// nothing there); larger ones are staged through LDS.
-template <class D, bool kOff32, class Body>
+// 16-byte records are gathered lane by lane, with the loads software-pipelined
+// (kStage16 = false), or staged through LDS like the larger ones: each slot's
+// distinct particles fetched once (about 14 of 64 on the clustered gas), so a
+// slot touches that many cache lines instead of one per lane.
+template <class D, bool kOff32, bool kStage16 = false, class Body>
 __device__ __forceinline__ void list_loop(const Lists& L, int w, int cnt, int len,
                                           const D* __restrict__ recs, uint4* __restrict__ lds, Body body) {
-    if constexpr (sizeof(D) == 16) {
+    if constexpr (!staged<D, kStage16>()) {
         pipelined_list<D>(
             L.nbr + L.off[w] + lane_id(), cnt, len,
             [&](uint32_t j) __attribute__((always_inline)) { return recs[j]; }, body);
@@ -482,7 +491,7 @@ template <class R, int N> struct ChunkSums {
 // g2^abc = delta^ac m1^b + delta^bc m1^a + t3^abc.  FP32: plain sums over
 // `chunk` pairs folded into compensated sums.  Every lane of the wave must call
 // this (the loop runs over the tile's longest list).
-template <class R, bool kOff32>
+template <class R, bool kOff32, bool kStage16 = false>
 __device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, const RecQV<R>* __restrict__ qv,
                                    uint4* __restrict__ lds, R H, int chunk, double S[29], int& nnb) {
     constexpr bool kComp = sizeof(R) == 4;
@@ -498,7 +507,7 @@ __device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, con
 #pragma unroll
     for (int e = 0; e < kN; ++e) { p[e] = R(0); sm[e] = R(0); cm[e] = R(0); }
     nnb = 0;
-    list_loop<RecQV<R>, kOff32>(
+    list_loop<RecQV<R>, kOff32, kStage16>(
         L, w, cnt, len, qv, lds,
         [&](const RecQV<R>& d, int k) __attribute__((always_inline)) {
             const R Vj = d.V;
@@ -633,7 +642,7 @@ struct crk_leaves {
     double r_fixed = 0.0;
     int64_t n_tiles = 0, n_leaves = 0;
     int n_cu = 1;
-    crk_tuning tune{0, 16, 4, 4, 8, 0, 0, 0};  // measured best on the C2 workload
+    crk_tuning tune{0, 16, 4, 4, 8, 0, 0, 0, 0};  // measured best on the C2 workload
     int32_t* perm = nullptr;
     uint4* quant = nullptr;
     double* Hd = nullptr;

@@ -25,6 +25,7 @@ SPACE = {
     "waves_per_cu": (8, 16, 32),
     "block_waves": (1, 2, 4),
     "kahan_chunk": (1, 4, 8),
+    "stage16": (0, 1),
 }
 # short-range gravity also chooses how candidates are exchanged between lanes
 # (LDS broadcast, scalar-register broadcast, cross-lane permute)

@@ -177,6 +177,21 @@ def test_wide_record_addressing_is_bitwise_identical(crk, prec):
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_staged_16_byte_records_are_bitwise_identical(crk, prec):
+    """Staging the volume and moments passes' neighbour records through LDS
+    (one fetch per distinct particle of a slot) instead of gathering them lane
+    by lane changes no bit, with and without the 64-bit record addressing."""
+    cfg, _ = oracle_full("C2", 21)
+    a, _ = run_gpu(crk, cfg, prec)
+    for extra in ({}, {"addr64": 1}):
+        b, L = run_gpu(crk, cfg, prec, tuning={"stage16": 1, **extra})
+        assert L.get_tuning()["stage16"] == 1
+        for k in KEYS:
+            assert np.array_equal(a[k], b[k]), (k, extra)
+        L.free()
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_dense_neighbourhoods(crk, prec):
     """About 600 neighbours per particle: most tiles' neighbour sets overflow

@@ -62,26 +62,33 @@ def test_timestep_is_deterministic_and_handles_empty(crk):
     assert float(crk.crk_timestep(empty, a[:0].contiguous(), prec="f32").item()) == float("inf")
 
 
-def test_simulation_steps_conserve_momentum(crk):
-    """A few kick-drift steps of the FP64 chain (rebuilding the lists each step):
-    total momentum stays at roundoff, total energy drifts only at the order of
-    the time-integration error."""
+def test_simulation_steps_conserve_momentum_and_energy(crk):
+    """A few kick-drift steps of the FP64 chain (lists rebuilt every step): total
+    momentum is unchanged to roundoff, and each kick changes the total energy
+    sum m (|v|^2/2 + u) by exactly dt sum m (v.a + du/dt) + dt^2/2 sum m |a|^2,
+    whose first term the antisymmetric forces make vanish."""
     cfg = synth.make_config("C2", n_side=14)
     g = crk.gas_to_device(cfg, "f64")
     m = g["m"]
-    e0 = p0 = None
+    p0 = None
     for step in range(3):
         L = crk.crk_build_leaf_pairs(g["x"], g["y"], g["z"], g["h"], leaf_max=64, prec="f64")
         out = crk.forward(L, g, cfg["gamma"], "f64")
         T = out["totals"].cpu().numpy()
         assert np.abs(T[:3]).max() <= 1e-13 * T[4]
+        assert abs(T[3]) <= 1e-13 * T[5]
         v = torch.stack([g["vx"], g["vy"], g["vz"]], 1)
-        e = float((m * (0.5 * (v * v).sum(1) + g["u"])).sum())
         p = (m[:, None] * v).sum(0)
-        if e0 is None:
-            e0, p0 = e, p
+        if p0 is None:
+            p0 = p
         assert (p - p0).abs().max().item() <= 1e-12 * float((m[:, None] * v.abs()).sum())
+        e_before = float((m * (0.5 * (v * v).sum(1) + g["u"])).sum())
         dt = crk.crk_timestep(g, out["a"], cfg["gamma"], 0.1, 0.1, "f64")
         crk.crk_kick_drift(g, out["a"], out["dudt"], dt, "f64")
+        v = torch.stack([g["vx"], g["vy"], g["vz"]], 1)
+        e_after = float((m * (0.5 * (v * v).sum(1) + g["u"])).sum())
+        d = float(dt.item())
+        second = 0.5 * d * d * float((m * (out["a"] * out["a"]).sum(1)).sum())
+        assert second > 0
+        assert abs((e_after - e_before) - second) <= 1e-12 * e_before + 1e-6 * second
         L.free()
-    assert abs(e - e0) <= 1e-3 * e0

@@ -14,11 +14,11 @@ class MockLeaves:
     """Step time = sum of per-field penalties; the optimum is known."""
 
     BEST = {"persistent": 0, "waves_per_cu": 16, "kahan_chunk": 4, "block_waves": 4,
-            "xcd_groups": 8, "tile_order": 0}
+            "xcd_groups": 8, "tile_order": 0, "stage16": 1}
 
     def __init__(self):
         self.t = {"persistent": 1, "waves_per_cu": 32, "kahan_chunk": 1, "block_waves": 1,
-                  "xcd_groups": 1, "tile_order": 1}
+                  "xcd_groups": 1, "tile_order": 1, "stage16": 0}
         self.timing_on = False
         self.sets = 0
 
