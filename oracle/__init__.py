@@ -80,6 +80,7 @@ def _load():
         lib.oracle_extras.argtypes = [I64] + [P] * 14 + [I64, P, P, P, P]
         lib.oracle_visc_listed.argtypes = [I64] + [P] * 9 + [D, D, D, D] + [P] * 15
         lib.oracle_accel_visc.argtypes = [I64] + [P] * 16 + [D, D, D, D, I64, P, P, P, P, P]
+        lib.oracle_accel_compat.argtypes = [I64] + [P] * 16 + [D, D, D, D, D, I64, P, P, P, P, P]
         lib.oracle_gravity_grad.argtypes = [I64, P, P, P, P, D, D, D, P, P, I64, P, P, D, P, P]
         _lib = lib
     return _lib
@@ -193,6 +194,23 @@ def accel_visc(g, V, rho, corr, dv, targets=None, Cl=1.0, Cq=2.0, eps_q=0.01):
     _load().oracle_accel_visc(arr[0].size, *[_p(v) for v in arr], _p(_c(V)), _p(_c(rho)), _p(A), _p(B),
                               _p(dA), _p(dB), _p(_c(dv)), float(Cl), float(Cq), float(eps_q),
                               float(g["gamma"]), nt, _p(t), _p(a[0]), _p(a[1]), _p(a[2]), _p(du))
+    return a.T.copy(), du
+
+
+def accel_compat(g, V, rho, corr, eps_u=0.1, dv=None, targets=None, Cl=1.0, Cq=2.0, eps_q=0.01):
+    """Accelerations and du/dt with the compatible energy partition (weights
+    f_ij of the pair work, see crk_oracle.cpp), with the artificial viscosity
+    when the velocity gradients dv [n,3,3] are given."""
+    keys = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "m")
+    arr = [_c(g[k]) for k in keys]
+    A, B, dA, dB = (_c(c) for c in corr[:4])
+    t, nt = _targets(targets, arr[0].size)
+    a = np.empty((3, nt))
+    du = np.empty(nt)
+    _load().oracle_accel_compat(arr[0].size, *[_p(v) for v in arr], _p(_c(V)), _p(_c(rho)), _p(A), _p(B),
+                                _p(dA), _p(dB), None if dv is None else _p(_c(dv)), float(Cl), float(Cq),
+                                float(eps_q), float(eps_u), float(g["gamma"]), nt, _p(t), _p(a[0]), _p(a[1]),
+                                _p(a[2]), _p(du))
     return a.T.copy(), du
 
 
@@ -382,7 +400,7 @@ def grad_coordinates(n, n_pos=32, n_vel=16, n_u=16, seed=19):
 
 
 FLOP_KINDS = ("volume", "moments", "accel", "gravity", "gravity_poly", "volume_adj", "moments_adj",
-              "accel_adj", "extras", "accel_visc", "gravity_adj", "gravity_adj_poly")
+              "accel_adj", "extras", "accel_visc", "gravity_adj", "gravity_adj_poly", "accel_compat")
 
 
 def flops():

@@ -52,6 +52,12 @@
 //                  mu_k = min(0, h_k (w.x_ij) / (r^2 + eps_q h_k^2)),  c_k = sqrt(gamma (gamma-1) u_k)
 //                  Q_k = rho_k (-C_l c_k mu_k + C_q mu_k^2)              (k = i, j)
 //                and P_i + P_j in F_ij becomes P_i + P_j + Q_i + Q_j (still F_ij = -F_ji)
+//   compatible   (optional energy partition) each pair's work W_ij = (v_j - v_i) . F_ij
+//   energy         (= W_ji) is split f_ij W_ij to i and f_ji W_ij to j, f_ij + f_ji = 1:
+//                  du_i/dt = (1/m_i) sum_j f_ij W_ij,
+//                  f_ij = 1/2 [1 + sgn(W_ij) (u_j - u_i) / (|u_j - u_i| + eps_u (u_i + u_j))]
+//                (heating goes mostly to the colder particle, cooling comes mostly
+//                 from the hotter; f_ij = 1/2 gives the symmetric form above)
 //   gravity      j != i with r_ij < r_c (all species):
 //                  a_i = -G sum_j m_j x_ij [ (r^2 + eps^2)^(-3/2) - sum_k p_k r^(2k) ]
 //   PM split     the polynomial stands for the long-range (particle-mesh)
@@ -577,9 +583,20 @@ template <class T> T visc_pair(const Gas<T>& g, const T* rho, double gamma, cons
     return Q;
 }
 
+// Share of a pair's work W_ij = (v_j - v_i) . F_ij that goes to particle i
+// under the compatible energy partition (see the header); f_ij + f_ji = 1.
+template <class T> T compat_share(const T& ui, const T& uj, const T& W, double eps_u) {
+    const T d = uj - ui;
+    const T ad = val(d) < 0.0 ? -d : d;
+    const T den = ad + T(eps_u) * (ui + uj);
+    if (!(val(den) > 0.0)) return T(0.5);
+    const double sw = val(W) > 0.0 ? 1.0 : (val(W) < 0.0 ? -1.0 : 0.0);
+    return T(0.5) * (T(1.0) + T(sw) * d / den);
+}
+
 template <class T> void accel_one(const Gas<T>& g, const T* V, const T* rho, const Corr<T>* C,
                                   double gamma, int64_t i, Cand c, T a[3], T& dudt,
-                                  const Visc<T>* visc = nullptr) {
+                                  const Visc<T>* visc = nullptr, const double* compat_eps = nullptr) {
     const T Pi = T(gamma - 1.0) * rho[i] * g.u[i];
     a[0] = a[1] = a[2] = T(0.0);
     dudt = T(0.0);
@@ -593,11 +610,16 @@ template <class T> void accel_one(const Gas<T>& g, const T* V, const T* rho, con
         accel_pair(g, V, rho, C, gamma, i, j, s, visc ? Pi + visc_pair(g, rho, gamma, *visc, i, j, s) : Pi,
                    F, Fdotv);
         for (int cc = 0; cc < 3; ++cc) a[cc] += F[cc];
-        dudt += Fdotv;
+        if (compat_eps) {
+            const T W = -Fdotv;  // (v_j - v_i) . F_ij
+            dudt += compat_share(g.u[i], g.u[j], W, *compat_eps) * W;
+        } else {
+            dudt += Fdotv;
+        }
     }
     const T mi = T(g.m[i]);
     for (int cc = 0; cc < 3; ++cc) a[cc] = a[cc] / mi;
-    dudt = T(-0.5) * dudt / mi;
+    dudt = compat_eps ? dudt / mi : T(-0.5) * dudt / mi;
 }
 
 // ---------------------------------------------------------------- gravity
@@ -941,6 +963,15 @@ int64_t accel_visc(int nbrs) {
     return pair_flops({a[0], a[1], a[2], du});
 }
 
+int64_t accel_compat(int nbrs) {
+    Setup s = make(nbrs);
+    Ops a[3], du;
+    const double eps_u = 0.1;
+    accel_one(s.g, s.V.data(), s.rho.data(), s.C.data(), 5.0 / 3.0, 0, Cand{nullptr, s.np}, a, du,
+              static_cast<const Visc<Ops>*>(nullptr), &eps_u);
+    return pair_flops({a[0], a[1], a[2], du});
+}
+
 }  // namespace flops
 
 }  // namespace
@@ -1116,6 +1147,40 @@ int oracle_accel_visc(int64_t n, const double* x, const double* y, const double*
     return 0;
 }
 
+// Forces with the compatible energy partition (dv NULL: no viscosity).
+int oracle_accel_compat(int64_t n, const double* x, const double* y, const double* z, const double* vx,
+                        const double* vy, const double* vz, const double* u, const double* h,
+                        const double* m, const double* V, const double* rho, const double* A,
+                        const double* B, const double* dA, const double* dB, const double* dv,
+                        double Cl, double Cq, double eps_q, double eps_u, double gamma, int64_t nt,
+                        const int64_t* targets, double* ax, double* ay, double* az, double* dudt) {
+    Gas<double> g = make_gas(n, x, y, z, vx, vy, vz, u, h, m);
+    std::vector<Corr<double>> C(n);
+    for (int64_t i = 0; i < n; ++i) {
+        C[i].A = A[i];
+        for (int a = 0; a < 3; ++a) {
+            C[i].B[a] = B[3 * i + a];
+            C[i].dA[a] = dA[3 * i + a];
+            for (int c = 0; c < 3; ++c) C[i].dB[a][c] = dB[9 * i + 3 * a + c];
+        }
+    }
+    Visc<double> q;
+    q.dv = dv;
+    q.Cl = Cl;
+    q.Cq = Cq;
+    q.eps_q = eps_q;
+    const int64_t cnt = targets ? nt : n;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < cnt; ++k) {
+        const int64_t i = targets ? targets[k] : k;
+        double a[3], du;
+        accel_one(g, V, rho, C.data(), gamma, i, Cand{nullptr, n}, a, du, dv ? &q : static_cast<Visc<double>*>(nullptr),
+                  &eps_u);
+        ax[k] = a[0]; ay[k] = a[1]; az[k] = a[2]; dudt[k] = du;
+    }
+    return 0;
+}
+
 // Momentum and energy totals over all particles:
 // [sum m a_x, sum m a_y, sum m a_z, sum m (v.a + du/dt), sum m |a|,
 //  sum m (|v.a| + |du/dt|), sum m du/dt, sum m v.a]
@@ -1261,7 +1326,8 @@ int64_t oracle_count_pairs(int64_t n, const double* x, const double* y, const do
 // FLOP per ordered pair inside the pass radius, counted on the oracle's code
 // (see the flops namespace): [volume, moments, accel, gravity, gravity with the
 // polynomial term, volume adjoint, moments adjoint, force adjoint, extras, force
-// pass with the viscosity, gravity adjoint, gravity adjoint with the polynomial].
+// pass with the viscosity, gravity adjoint, gravity adjoint with the polynomial,
+// force pass with the compatible energy partition].
 void oracle_flops(double* out) {
     using namespace flops;
     out[0] = double(volume(2) - volume(1));
@@ -1276,6 +1342,7 @@ void oracle_flops(double* out) {
     out[9] = double(accel_visc(2) - accel_visc(1));
     out[10] = double(gravity_adj(2, false) - gravity_adj(1, false));
     out[11] = double(gravity_adj(2, true) - gravity_adj(1, true));
+    out[12] = double(accel_compat(2) - accel_compat(1));
     op_reset();
 }
 

@@ -80,7 +80,7 @@ def chain(g, corr_override=None):
     a = Fij.sum(1) / g["m"][:, None]
     dudt = -0.5 * np.einsum("ijc,ijc->i", Fij, vij) / g["m"]
     return dict(V=V, rho=rho, m0=m0, m1=m1, m2=m2, g0=g0, g1=g1, g2=g2, A=A, B=B, dA=dA, dB=dB,
-                a=a, dudt=dudt, d=d, r=r, Wi=Wi, Fi=Fi, Gij=Gij, Gji=Gji)
+                a=a, dudt=dudt, d=d, r=r, Wi=Wi, Fi=Fi, Gij=Gij, Gji=Gji, Fij=Fij, vij=vij)
 
 
 def extras_and_viscosity(g, dn, Cl=1.0, Cq=2.0, eps_q=0.01):

@@ -673,6 +673,58 @@ def test_listed_viscous_chain_is_the_brute_force_chain(oracle_lib):
         assert np.array_equal(ol[k], ov[k]), k
 
 
+# ---------------------------------------------------------------- compatible energy partition
+def test_compatible_partition_keeps_forces_and_conserves_energy(tiny, oracle_lib):
+    """Only du/dt changes, and the pair work is still split exactly between
+    the two particles (total energy conserved), also with the viscosity."""
+    g, o, _ = tiny
+    corr = (o["A"], o["B"], o["dA"], o["dB"])
+    a, du = oracle_lib.accel_compat(g, o["V"], o["rho"], corr, eps_u=0.1)
+    assert np.array_equal(a, o["a"])
+    T = oracle_lib.totals(g, a, du)
+    assert abs(T[3]) < 1e-13 * T[5]
+    assert np.abs(du - o["dudt"]).max() > 1e-2 * np.abs(o["dudt"]).max()  # a different split
+    ov = oracle_lib.hydro_visc(g)
+    av, duv = oracle_lib.accel_compat(g, o["V"], o["rho"], corr, eps_u=0.1, dv=ov["dv"])
+    assert np.array_equal(av, ov["a"])
+    Tv = oracle_lib.totals(g, av, duv)
+    assert abs(Tv[3]) < 1e-13 * Tv[5]
+
+
+def test_compatible_partition_with_equal_energies_is_the_symmetric_split(tiny, oracle_lib):
+    g, _, _ = tiny
+    g1 = dict(g, u=np.full(g["n"], 1.3))
+    o1 = oracle_lib.hydro(g1)
+    _, du = oracle_lib.accel_compat(g1, o1["V"], o1["rho"], (o1["A"], o1["B"], o1["dA"], o1["dB"]), eps_u=0.1)
+    assert np.array_equal(du, o1["dudt"])
+    # and the split tends to the symmetric one as eps_u grows
+    g, o, _ = tiny
+    _, du = oracle_lib.accel_compat(g, o["V"], o["rho"], (o["A"], o["B"], o["dA"], o["dB"]), eps_u=1e9)
+    assert np.abs(du - o["dudt"]).max() < 1e-8 * np.abs(o["dudt"]).max()
+
+
+def test_compatible_partition_sends_heat_to_the_colder_particle(tiny, oracle_lib):
+    """Summed over ordered pairs, u_i (f_ij - 1/2) W_ij + u_j (f_ji - 1/2) W_ij
+    = -1/2 |W_ij| (u_i - u_j)^2 / (|u_i - u_j| + eps_u (u_i + u_j)): relative to
+    the symmetric split, sum_i m_i u_i (du_i/dt) drops by exactly that amount
+    (the pair forces and work from the dense implementation)."""
+    g, o, dn = tiny
+    eps_u = 0.1
+    _, du = oracle_lib.accel_compat(g, o["V"], o["rho"], (o["A"], o["B"], o["dA"], o["dB"]), eps_u=eps_u)
+    lhs = float(np.sum(g["m"] * g["u"] * (du - o["dudt"])))
+    W = -np.einsum("ijc,ijc->ij", dn["Fij"], dn["vij"])  # (v_j - v_i) . F_ij
+    u = g["u"].astype(np.float64)
+    d = u[None, :] - u[:, None]
+    den = np.abs(d) + eps_u * (u[:, None] + u[None, :])
+    rhs = -0.25 * float(np.sum(np.abs(W) * d * d / den))
+    assert rhs < 0.0
+    assert abs(lhs - rhs) <= 1e-9 * abs(rhs), (lhs, rhs)
+    # the dense split itself
+    f = 0.5 * (1.0 + np.sign(W) * d / den)
+    du_dense = (f * W).sum(1) / g["m"]
+    assert np.abs(du - du_dense).max() <= 1e-12 * np.abs(du_dense).max()
+
+
 # ---------------------------------------------------------------- time step
 def test_timestep_closed_form(oracle_lib):
     """Three particles whose limits are known: the slowest-signal one sets the
