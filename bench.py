@@ -438,8 +438,11 @@ def bench_hydro(args, torch, crk, config=None, tuning=None, autotune=True, rando
         del g64
     torch.cuda.empty_cache()
 
-    # the Extras pass and the viscous force pass, on the headline workload only
+    # the Extras pass and the viscous force pass, and the device leaf build, on the headline workload only
     ev = extras_viscosity(args, torch, crk, L, g32, cfg_t, G, F, config, table, f64=f64) if config == "C2" else None
+    dbuild = None
+    if config == "C2" and not args.no_device_build:
+        dbuild = device_build_leg(args, torch, crk, cfg, L.get_tuning(), backward, st)
     out = {
         "metric": METRIC, "value": inter / (ms32 * 1e-3), "unit": "interactions/s",
         "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": round(ms32, 4),
@@ -468,11 +471,52 @@ def bench_hydro(args, torch, crk, config=None, tuning=None, autotune=True, rando
         "list_build_note": "neighbour-list count, fill and schedule kernels of one build",
         "generate_s": round(gen_s, 1),
         "extras_viscosity": ev,
+        "device_build": dbuild,
     }
     if cpu and not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_hydro(cfg, args.cpu_budget)
     L.free()
     del L, g32, ga32, gdu32
+    torch.cuda.empty_cache()
+    return out
+
+
+def device_build_leg(args, torch, crk, cfg, tuning, backward, host_stats):
+    """The leaf build on the device (Morton octree; crk_build_leaf_pairs_device)
+    on the generated order: wall time, its list-build kernels; then the same
+    step as the headline one over particles in the device build's order."""
+    import numpy as np
+
+    g_rand = crk.gas_to_device(cfg, "f32")
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    Ld = crk.crk_build_leaf_pairs_device(g_rand["x"], g_rand["y"], g_rand["z"], g_rand["h"],
+                                         leaf_max=args.leaf_max, prec="f32")
+    build_ms = (time.perf_counter() - tb) * 1e3
+    cull = Ld.kernel_times()["cull"]
+    perm = Ld.perm().cpu().numpy()
+    Ld.free()
+    del g_rand, Ld
+    cfg_t = {k: (v[perm] if isinstance(v, np.ndarray) and v.shape == (cfg["n"],) else v)
+             for k, v in cfg.items()}
+    g32 = crk.gas_to_device(cfg_t, "f32")
+    L = crk.crk_build_leaf_pairs_device(g32["x"], g32["y"], g32["z"], g32["h"], leaf_max=args.leaf_max,
+                                        prec="f32")
+    identity = bool((L.perm().cpu().numpy() == np.arange(cfg["n"])).all())
+    L.set_tuning(**tuning)
+    st = L.stats()
+    ga, gdu = upstream(crk, L, g32, cfg_t, "f32", torch)
+    ms = timed_steps(crk_step(crk, L, g32, cfg_t, "f32", ga, gdu, backward), args.steps, args.warmup, torch)
+    log(f"[bench] device build {build_ms:.0f} ms (list build kernels {cull[0]:.2f} ms); step over its "
+        f"order {ms:.3f} ms; stats {st}")
+    out = {"build_ms": round(build_ms, 1), "list_build_gpu_ms": round(cull[0], 3),
+           "ms_per_step": round(ms, 4), "identity_order": identity, "leaves": st["leaves"],
+           "list_entries": st["list_entries"], "padded_slots": st["padded_slots"],
+           "host_build_padded_slots": host_stats["padded_slots"],
+           "note": "same lists per particle as the host build; the step is the headline step (same "
+                   "tuning) over particles in the device build's order"}
+    L.free()
+    del L, g32, ga, gdu
     torch.cuda.empty_cache()
     return out
 
@@ -644,6 +688,7 @@ def main():
     ap.add_argument("--gravity-leaf-max", type=int, default=512,
                     help="gravity leaf size when its tuning is given")
     ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--no-device-build", action="store_true", help="C2 only: skip the device leaf build leg")
     ap.add_argument("--no-backward", action="store_true", help="forward passes only")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work per workload")

@@ -129,7 +129,12 @@ typedef struct {
  *    passes, then ordered per tile so that lanes sharing a neighbour take it
  *    at the same list position (each particle's neighbours with |x_ij| < 2h_i
  *    first; deterministic).  The order changes only the summation order of the
- *    passes, never which pairs they sum.  Requires 2 max(h) < 1/2.
+ *    passes, never which pairs they sum.  In this mode r_fixed >= 0 is a list
+ *    skin: every support is widened by it for the lists (pairs beyond a
+ *    particle's support add exactly zero in every pass), so the handle serves
+ *    positions that moved since the build as long as no particle moved by
+ *    skin / 2 or more (the passes re-read positions at every call; see
+ *    crk_kick_drift's disp).  Requires 2 max(h) + skin < 1/2.
  *  h == NULL (fixed-radius mode): radius r_fixed (< 1/2), for sr_gravity.
  *
  * Workspace: ws is caller-owned device memory of ws_bytes bytes, 256-byte
@@ -152,6 +157,34 @@ int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const doub
                          const void* h, double r_fixed, int leaf_max, int leaf_min,
                          double split_extent, crk_prec prec, void* ws, size_t ws_bytes,
                          size_t* ws_needed, crk_leaves** out, hipStream_t stream);
+
+/*
+ * The same handle built on the GPU (the paper's code builds its tree on the
+ * host, Sec. 3.1; this build keeps the positions on the device).  Leaves are
+ * the cells of an octree over the 2^-32 grid: the particles are sorted by the
+ * Morton key of their top 21 bits per axis, and each particle's leaf is the
+ * largest octree cell around it that holds at most leaf_max particles (a
+ * finest-level cell holding more is cut into runs of leaf_max).  Tiles of 64
+ * consecutive particles in that order find their candidate leaves by looking
+ * up the octree cells that cover the tile's box widened by the largest
+ * interaction radius and testing every leaf found there box against box.  In
+ * hydro mode each leaf is then ordered by decreasing list length (deterministic
+ * ties), and the lists are built and scheduled as by crk_build_leaf_pairs.
+ *
+ * Arguments, modes, the skin, the workspace protocol and the handle are those
+ * of crk_build_leaf_pairs except: no leaf_min or split_extent; leaf_max in
+ * [1, 1024]; the workspace also holds the build's temporaries (its per-pass
+ * scratch is at least about 100 bytes per particle); a call that returns
+ * CRK_ENOSPC keeps no state (the repeated call rebuilds and reaches the same
+ * sizes).  Every particle's neighbour list holds the same set of particles as
+ * with crk_build_leaf_pairs (the list test does not depend on the tree); the
+ * tree order, tiles and list order differ, so pass results agree to rounding
+ * of the summation order.  Invalid positions or h are reported as CRK_EINVAL
+ * from a device check.  Synchronises `stream`.
+ */
+int crk_build_leaf_pairs_device(int64_t n, const double* x, const double* y, const double* z,
+                                const void* h, double r_fixed, int leaf_max, crk_prec prec, void* ws,
+                                size_t ws_bytes, size_t* ws_needed, crk_leaves** out, hipStream_t stream);
 
 /*
  * Geometry pass (Sec. 5, "Geometry": particle volumes).
@@ -260,6 +293,28 @@ int crk_accel_energy_visc(crk_leaves* leaves, const crk_gas* gas, const void* V,
                           crk_prec prec, void* a, void* dudt, double* totals, hipStream_t stream);
 
 /*
+ * Force pass with the compatible energy partition (the paper's hydrodynamics
+ * is CRK-SPH, Sec. 3.1, whose energy equation splits every pair's work
+ * between the two particles; the paper prints no formula).  The accelerations
+ * are those of crk_accel_energy (dv, visc NULL) or crk_accel_energy_visc (both
+ * given); only du/dt changes.  With W_ij = (v_j - v_i) . F_ij the work of the
+ * pair force on i (W_ji = W_ij):
+ *   du_i/dt = (1/m_i) sum_j f_ij W_ij,
+ *   f_ij = 1/2 [1 + sgn(W_ij) (u_j - u_i) / (|u_j - u_i| + eps_u (u_i + u_j))]
+ * (f_ij = 1/2 where the denominator is 0).  f_ij + f_ji = 1, so total energy
+ * is conserved as with the symmetric split (f_ij = 1/2, crk_accel_energy);
+ * heating goes mostly to the colder particle and cooling comes mostly from the
+ * hotter one, and equal u gives the symmetric split exactly.  eps_u >= 0
+ * (finite) sets how sharply the share follows the energy difference.
+ * Arguments and outputs otherwise as crk_accel_energy_visc; timed as the
+ * force pass it extends (CRK_K_ACCEL or CRK_K_ACCEL_VISC).
+ */
+int crk_accel_energy_compatible(crk_leaves* leaves, const crk_gas* gas, const void* V, const void* rho,
+                                const crk_corr* corr, const void* dv, const crk_visc* visc, double eps_u,
+                                double gamma, crk_prec prec, void* a, void* dudt, double* totals,
+                                hipStream_t stream);
+
+/*
  * Short-range particle-particle gravity (Sec. 3.1 force split; all species).
  *   a_i = -G sum_{j != i, r_ij < r_cut} m_j x_ij [ (r^2 + eps^2)^(-3/2) - sum_k p_k r^(2k) ]
  * poly: host array of 6 coefficients p_0..p_5 or NULL (no polynomial term).
@@ -336,9 +391,15 @@ int crk_timestep(int64_t n, const void* h, const void* u, const void* vx, const 
  * each position wrapped into [0, 1).  x, y, z: FP64 device arrays [n], updated
  * in place; vx, vy, vz, u [n] updated in place, a [3n] and dudt [n] read, all
  * in the precision `prec`.
+ * disp (optional, device double[2]): disp[0] += the step's largest drift
+ * max_i |v_i dt| (disp[1] is scratch, left at 0).  Zeroed by the caller after
+ * each build, disp[0] bounds how far any particle has moved since: a handle
+ * built with a list skin (crk_build_leaf_pairs) stays valid while
+ * disp[0] < skin / 2.
  */
 int crk_kick_drift(int64_t n, double* x, double* y, double* z, void* vx, void* vy, void* vz, void* u,
-                   const void* a, const void* dudt, const void* dt, crk_prec prec, hipStream_t stream);
+                   const void* a, const void* dudt, const void* dt, double* disp, crk_prec prec,
+                   hipStream_t stream);
 
 /*
  * Statistics of a handle (host int64[8]):
@@ -359,6 +420,15 @@ int crk_leaves_stats(crk_leaves* leaves, int64_t* host_out);
  * every pass then reads and writes particle fields with coalesced accesses.
  */
 int crk_leaves_perm(const crk_leaves* leaves, int32_t* perm, hipStream_t stream);
+
+/*
+ * Work-distribution check: launches the pair passes' work distribution with
+ * the handle's tuning (persistent atomic queue or one tile per wave, XCD
+ * chunks, order) and adds 1 to visits[t] (device int32[tiles], zeroed by the
+ * caller) for every tile t a wave is handed.  Every entry must read 1: each
+ * tile processed exactly once, whatever the schedule.
+ */
+int crk_queue_visits(crk_leaves* leaves, int32_t* visits, hipStream_t stream);
 
 /* Read or set the launch/tiling choices of a handle (set validates them). */
 int crk_get_tuning(const crk_leaves* leaves, crk_tuning* out);

@@ -28,9 +28,11 @@ CRK_ENOSPC = -5
 _STATUS = {0: "CRK_OK", -1: "CRK_EINVAL", -3: "CRK_EHIP", -4: "CRK_ESTATE", -5: "CRK_ENOSPC"}
 
 # the C symbols declared in include/crk.h
-EXPORTS = ("crk_build_leaf_pairs", "crk_volume", "crk_corrections", "crk_accel_energy",
-           "crk_accel_energy_noalloc", "crk_extras", "crk_accel_energy_visc", "sr_gravity",
-           "sr_gravity_backward", "sr_gravity_fit_poly", "crk_timestep", "crk_kick_drift", "crk_accel_energy_backward", "crk_leaves_stats", "crk_leaves_perm",
+EXPORTS = ("crk_build_leaf_pairs", "crk_build_leaf_pairs_device", "crk_volume", "crk_corrections",
+           "crk_accel_energy", "crk_accel_energy_noalloc", "crk_extras", "crk_accel_energy_visc",
+           "crk_accel_energy_compatible", "sr_gravity",
+           "sr_gravity_backward", "sr_gravity_fit_poly", "crk_timestep", "crk_kick_drift",
+           "crk_queue_visits", "crk_accel_energy_backward", "crk_leaves_stats", "crk_leaves_perm",
            "crk_get_tuning", "crk_set_tuning",
            "crk_timing", "crk_kernel_times", "crk_leaves_free", "crk_last_error")
 KERNEL_KINDS = ("cull", "volume", "moments", "accel", "gravity", "pack", "accel_adj",
@@ -93,6 +95,8 @@ def load_library(path=None):
     P, I64, D, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
     lib.crk_build_leaf_pairs.argtypes = [I64, P, P, P, P, D, I, I, D, I, P, ctypes.c_size_t,
                                          ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(P), P]
+    lib.crk_build_leaf_pairs_device.argtypes = [I64, P, P, P, P, D, I, I, P, ctypes.c_size_t,
+                                                ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(P), P]
     lib.crk_volume.argtypes = [P, ctypes.POINTER(_Gas), I, P, P, P]
     lib.crk_corrections.argtypes = [P, ctypes.POINTER(_Gas), P, I, ctypes.POINTER(_Corr), P, P]
     lib.crk_accel_energy.argtypes = [P, ctypes.POINTER(_Gas), P, P, ctypes.POINTER(_Corr), D, I,
@@ -102,14 +106,17 @@ def load_library(path=None):
     lib.sr_gravity_backward.argtypes = [P, I64, P, P, P, P, D, D, D, P, P, I, P, P]
     lib.sr_gravity_fit_poly.argtypes = [D, D, I, P]
     lib.crk_timestep.argtypes = [I64, P, P, P, P, P, P, D, D, D, I, P, P]
-    lib.crk_kick_drift.argtypes = [I64, P, P, P, P, P, P, P, P, P, P, I, P]
+    lib.crk_kick_drift.argtypes = [I64, P, P, P, P, P, P, P, P, P, P, P, I, P]
     lib.crk_extras.argtypes = [P, ctypes.POINTER(_Gas), P, ctypes.POINTER(_Corr), I, P, P, P, P]
     lib.crk_accel_energy_visc.argtypes = [P, ctypes.POINTER(_Gas), P, P, ctypes.POINTER(_Corr), P,
                                           ctypes.POINTER(Visc), D, I, P, P, P, P]
+    lib.crk_accel_energy_compatible.argtypes = [P, ctypes.POINTER(_Gas), P, P, ctypes.POINTER(_Corr), P,
+                                                ctypes.POINTER(Visc), D, D, I, P, P, P, P]
     lib.crk_accel_energy_backward.argtypes = [P, ctypes.POINTER(_Gas), P, P, ctypes.POINTER(_Corr), D,
                                               P, P, I, P, P, P, P]
     lib.crk_leaves_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
     lib.crk_leaves_perm.argtypes = [P, P, P]
+    lib.crk_queue_visits.argtypes = [P, P, P]
     lib.crk_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
     lib.crk_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
     lib.crk_timing.argtypes = [P, I]
@@ -189,6 +196,12 @@ class Leaves:
         _check("crk_leaves_perm", load_library().crk_leaves_perm(self.handle, _ptr(out), _stream()))
         return out
 
+    def queue_visits(self, device="cuda"):
+        """How often the work distribution hands out each tile (int32 per tile; all 1)."""
+        out = torch.zeros(self.stats()["tiles"], dtype=torch.int32, device=device)
+        _check("crk_queue_visits", load_library().crk_queue_visits(self.handle, _ptr(out), _stream()))
+        return out
+
     def get_tuning(self):
         t = Tuning()
         _check("crk_get_tuning", load_library().crk_get_tuning(self.handle, ctypes.byref(t)))
@@ -230,15 +243,11 @@ def _ws_guess(n, hydro):
     return (1 << 20) + n * ((830 + 9 * 128) if hydro else 96)
 
 
-def crk_build_leaf_pairs(x, y, z, h=None, r_fixed=0.0, leaf_max=128, leaf_min=1,
-                         split_extent=0.0, prec="f32", ws=None):
-    """Tree + interaction lists (hydro mode when h is given, else radius r_fixed).
-
-    The handle lives in a device workspace: ``ws`` (a uint8 CUDA tensor) when
+def _build(fn, call, x, y, z, h, prec, ws):
+    """The workspace protocol of both builds: ``ws`` (a uint8 CUDA tensor) when
     given and large enough, else one allocated here; on CRK_ENOSPC the
     workspace is reallocated at the size the library reports and the call
-    repeated (the library resumes from the host tree it built)."""
-    lib = load_library()
+    repeated."""
     for t in (x, y, z):
         _dev(t, torch.float64)
     if h is not None:
@@ -250,16 +259,47 @@ def crk_build_leaf_pairs(x, y, z, h=None, r_fixed=0.0, leaf_max=128, leaf_min=1,
         if ws is None or int(ws.numel()) < size:
             ws = torch.empty(size, dtype=torch.uint8, device=x.device)
         out = ctypes.c_void_p()
-        code = lib.crk_build_leaf_pairs(n, _ptr(x), _ptr(y), _ptr(z), _ptr(h), float(r_fixed),
-                                        int(leaf_max), int(leaf_min), float(split_extent), _PREC[prec],
-                                        _ptr(ws), int(ws.numel()), ctypes.byref(need), ctypes.byref(out),
-                                        _stream())
+        code = call(n, ws, need, out)
         if code != CRK_ENOSPC:
-            _check("crk_build_leaf_pairs", code)
+            _check(fn, code)
             return Leaves(out, n, h is not None, prec, ws)
         size = int(need.value)
         ws = None
-    _check("crk_build_leaf_pairs", code)
+    _check(fn, code)
+
+
+def crk_build_leaf_pairs(x, y, z, h=None, r_fixed=0.0, leaf_max=128, leaf_min=1,
+                         split_extent=0.0, prec="f32", ws=None, skin=0.0):
+    """Tree + interaction lists (hydro mode when h is given, else radius r_fixed).
+
+    In hydro mode ``skin`` widens every support for the lists, so that the
+    handle can be reused while no particle has moved by skin / 2 (the C call
+    takes it in place of r_fixed).  The library resumes a call that stopped
+    for want of workspace from the host tree it built."""
+    lib = load_library()
+
+    def call(n, ws, need, out):
+        return lib.crk_build_leaf_pairs(n, _ptr(x), _ptr(y), _ptr(z), _ptr(h),
+                                        float(skin if h is not None else r_fixed),
+                                        int(leaf_max), int(leaf_min), float(split_extent), _PREC[prec],
+                                        _ptr(ws), int(ws.numel()), ctypes.byref(need), ctypes.byref(out),
+                                        _stream())
+    return _build("crk_build_leaf_pairs", call, x, y, z, h, prec, ws)
+
+
+def crk_build_leaf_pairs_device(x, y, z, h=None, r_fixed=0.0, leaf_max=128, prec="f32", ws=None,
+                                skin=0.0):
+    """The same handle built on the GPU (Morton octree leaves of at most
+    leaf_max <= 1024 particles); every particle's list holds the same
+    neighbours as with crk_build_leaf_pairs."""
+    lib = load_library()
+
+    def call(n, ws, need, out):
+        return lib.crk_build_leaf_pairs_device(n, _ptr(x), _ptr(y), _ptr(z), _ptr(h),
+                                               float(skin if h is not None else r_fixed),
+                                               int(leaf_max), _PREC[prec], _ptr(ws), int(ws.numel()),
+                                               ctypes.byref(need), ctypes.byref(out), _stream())
+    return _build("crk_build_leaf_pairs_device", call, x, y, z, h, prec, ws)
 
 
 def crk_volume(leaves, gas, prec="f32"):
@@ -398,6 +438,31 @@ def crk_accel_energy_visc(leaves, gas, V, rho, corr, dv, gamma=5.0 / 3.0, prec="
     return a, du, tot
 
 
+def crk_accel_energy_compatible(leaves, gas, V, rho, corr, eps_u=0.1, dv=None, visc=None, gamma=5.0 / 3.0,
+                                prec="f32", totals=True):
+    """Force pass with the compatible energy partition (pair work split by
+    f_ij, see include/crk.h); with the viscosity when dv and visc (a dict of
+    Cl, Cq, eps_q) are given."""
+    g = _gas(gas, prec, ("vx", "vy", "vz", "u", "h", "m"))
+    dt, dev = _DTYPE[prec], gas["x"].device
+    for t in (V, rho, *corr[:4]):
+        _dev(t, dt)
+    if dv is not None:
+        _dev(dv, dt)
+    c = _corr(corr)
+    q = None if visc is None else Visc(**{**VISC_DEFAULT, **visc})
+    a = torch.empty(g.n, 3, dtype=dt, device=dev)
+    du = torch.empty(g.n, dtype=dt, device=dev)
+    tot = torch.empty(8, dtype=torch.float64, device=dev) if totals else None
+    _check("crk_accel_energy_compatible",
+           load_library().crk_accel_energy_compatible(leaves.handle, ctypes.byref(g), _ptr(V), _ptr(rho),
+                                                      ctypes.byref(c), _ptr(dv),
+                                                      None if q is None else ctypes.byref(q), float(eps_u),
+                                                      float(gamma), _PREC[prec], _ptr(a), _ptr(du), _ptr(tot),
+                                                      _stream()))
+    return a, du, tot
+
+
 def forward_visc(leaves, gas, gamma=5.0 / 3.0, prec="f32", **visc):
     """volume -> corrections -> extras -> accel/energy with the viscosity."""
     V, rho = crk_volume(leaves, gas, prec)
@@ -484,8 +549,10 @@ def crk_timestep(gas, a, gamma=5.0 / 3.0, c_cfl=0.25, c_acc=0.25, prec="f32"):
     return dt
 
 
-def crk_kick_drift(gas, a, dudt, dt, prec="f32"):
-    """Updates gas x, y, z, vx, vy, vz and u in place with the device time step dt."""
+def crk_kick_drift(gas, a, dudt, dt, prec="f32", disp=None):
+    """Updates gas x, y, z, vx, vy, vz and u in place with the device time step dt.
+    disp (float64 CUDA tensor of 2, optional): disp[0] accumulates the largest
+    drift of each step (zero it after a build)."""
     dt_ = _DTYPE[prec]
     for k in ("x", "y", "z"):
         _dev(gas[k], torch.float64)
@@ -493,11 +560,15 @@ def crk_kick_drift(gas, a, dudt, dt, prec="f32"):
         _dev(gas[k], dt_)
     for t in (a, dudt, dt):
         _dev(t, dt_)
+    if disp is not None:
+        _dev(disp, torch.float64)
+        if disp.numel() < 2:
+            raise ValueError("disp needs two elements")
     n = int(gas["x"].numel())
     _check("crk_kick_drift",
            load_library().crk_kick_drift(n, _ptr(gas["x"]), _ptr(gas["y"]), _ptr(gas["z"]), _ptr(gas["vx"]),
                                          _ptr(gas["vy"]), _ptr(gas["vz"]), _ptr(gas["u"]), _ptr(a), _ptr(dudt),
-                                         _ptr(dt), _PREC[prec], _stream()))
+                                         _ptr(dt), _ptr(disp), _PREC[prec], _stream()))
 
 
 def forward(leaves, gas, gamma=5.0 / 3.0, prec="f32", store_sums=False):

@@ -1,7 +1,7 @@
 """Compile the gfx950 HIP library ``libcrk.so`` in-tree.
 
 hipcc builds the kernels and the C ABI (``csrc/crk.hip``, ``csrc/crk_backward.hip``,
-``csrc/gravity.hip``, ``csrc/extras.hip``, ``csrc/step.hip``);
+``csrc/gravity.hip``, ``csrc/extras.hip``, ``csrc/step.hip``, ``csrc/devtree.hip``);
 g++ builds the
 host tree (``csrc/tree.cpp``, OpenMP).  Packed FP32 instructions are switched
 off for all device code.
@@ -40,7 +40,7 @@ def build(verbose=False):
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     objs = []
-    for name in ("crk", "crk_backward", "gravity", "extras", "step"):
+    for name in ("crk", "crk_backward", "gravity", "extras", "step", "devtree"):
         obj = os.path.join(bdir, name + ".o")
         _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, name + ".hip"), "-o", obj], verbose)
         objs.append(obj)

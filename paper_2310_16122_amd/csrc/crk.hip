@@ -71,7 +71,8 @@ template <class R> struct alignas(16) RecAcc {
     R V, P, P4s;
     R PBs[3], T0[3], v[3];
     R Qs[9];
-    R pad[sizeof(R) == 4 ? 6 : 8];
+    R u;  // specific internal energy (the compatible energy partition)
+    R pad[sizeof(R) == 4 ? 5 : 7];
 };
 static_assert(sizeof(RecAcc<float>) == 128, "f32 record is one 128-byte line");
 static_assert(sizeof(RecAcc<double>) == 256, "f64 record is two 128-byte lines");
@@ -87,7 +88,8 @@ template <class R> struct alignas(16) RecAccV {
     R Qs[9];
     R dvs[9];
     R hs, rcl, rcq;
-    R pad[sizeof(R) == 4 ? 3 : 4];
+    R u;
+    R pad[sizeof(R) == 4 ? 2 : 3];
 };
 static_assert(sizeof(RecAccV<float>) == 160 && sizeof(RecAccV<double>) == 320, "whole 16-byte chunks");
 
@@ -119,6 +121,7 @@ __device__ __forceinline__ void fill_acc(Rec& r, int i, const uint4& q, const R*
             r.Qs[3 * a + c] = R(sc * cW * (Ai * double(dB[9 * i + 3 * a + c]) + dAd[c] * Bd[a]));
     }
     r.v[0] = vx[i]; r.v[1] = vy[i]; r.v[2] = vz[i];
+    r.u = u[i];
 }
 
 template <class R>
@@ -194,7 +197,8 @@ __global__ __launch_bounds__(64) void k_cull(Queue qu, int n, const uint4* __res
                                              const int64_t* __restrict__ ell_off,
                                              const int32_t* __restrict__ ell_len,
                                              uint32_t* __restrict__ nbr, int32_t* __restrict__ cntg_out,
-                                             int32_t* __restrict__ leng_out, int32_t* __restrict__ err) {
+                                             int32_t* __restrict__ leng_out, int32_t* __restrict__ err,
+                                             float skin) {
     __shared__ uint4 sj[kWave];
     const int lane = lane_id();
     QState qs;
@@ -202,7 +206,7 @@ __global__ __launch_bounds__(64) void k_cull(Queue qu, int n, const uint4* __res
         const int s = w * kWave + lane;
         const bool valid = s < n;
         const uint4 qi = valid ? quant[s] : make_uint4(0, 0, 0, 0);
-        const float Hi = __uint_as_float(qi.w);
+        const float Hi = __uint_as_float(qi.w) + skin;
         const float Hi2 = Hi * Hi;
         int c = 0;
         const int64_t base_off = FILL ? ell_off[w] : 0;
@@ -219,7 +223,7 @@ __global__ __launch_bounds__(64) void k_cull(Queue qu, int n, const uint4* __res
                 for (int jj = 0; jj < m; ++jj) {
                     const uint4 qj = sj[jj];
                     const float r2 = cull_r2(qi, qj);
-                    const float Hj = __uint_as_float(qj.w);
+                    const float Hj = __uint_as_float(qj.w) + skin;
                     const float R2 = cull_scale(Hi2, Hj * Hj);
                     if (valid && r2 < R2 && (b + jj) != s) {
                         // the fill pass repeats the count pass exactly; the bound
@@ -545,11 +549,31 @@ __device__ __forceinline__ void corrected_grad(const Rec& r, R wq, R fq, const R
     }
 }
 
+// What a pair adds to the energy sum.  Symmetric partition: Fv = 2 W_ij, W_ij
+// = (v_j - v_i) . F_ij the pair's work, of which i takes half.  Compatible
+// partition: i takes f_ij W_ij with f_ij = 1/2 (1 + s_ij),
+// s_ij = sgn(W_ij) (u_j - u_i) / (|u_j - u_i| + eps_u (u_i + u_j)), so heating
+// goes mostly to the colder particle and cooling comes mostly from the hotter;
+// the sum gets (1 + s_ij) Fv.  Both sides of a pair compute the same Fv and
+// exactly negated d, so s_ji = -s_ij bit for bit.
+template <bool kCompat, class R, class Rec>
+__device__ __forceinline__ R energy_term(const Rec& ri, const Rec& rj, R eps_u, R Fv) {
+    if constexpr (!kCompat) {
+        return Fv;
+    } else {
+        const R d = rj.u - ri.u;
+        const R den = fabs(d) + eps_u * (ri.u + rj.u);
+        const R sw = Fv > R(0) ? R(1) : (Fv < R(0) ? R(-1) : R(0));
+        const R sh = den > R(0) ? sw * d / den : R(0);
+        return Fv + sh * Fv;
+    }
+}
+
 // One pair of the force pass for lane particle i and neighbour j: adds
 // (V_i V_j)(P_i + P_j)(G_i - G_j) (the pair force is -1/2 of it) and its dot
 // product with v_i - v_j.
-template <class R>
-__device__ __forceinline__ void accel_pair(const RecAcc<R>& ri, const RecAcc<R>& rj, int k, int chunk,
+template <bool kCompat, class R>
+__device__ __forceinline__ void accel_pair(const RecAcc<R>& ri, const RecAcc<R>& rj, R eps_u, int k, int chunk,
                                            ChunkSums<R, 4>& acc) {
     const R y[3] = {grid_sep<R>(ri.q[0], rj.q[0]), grid_sep<R>(ri.q[1], rj.q[1]),
                     grid_sep<R>(ri.q[2], rj.q[2])};
@@ -569,7 +593,7 @@ __device__ __forceinline__ void accel_pair(const RecAcc<R>& ri, const RecAcc<R>&
         Fv += F * (ri.v[c] - rj.v[c]);
         acc.add(c, F);
     }
-    acc.add(3, Fv);
+    acc.add(3, energy_term<kCompat>(ri, rj, eps_u, Fv));
     acc.next(k, chunk);
 }
 
@@ -583,9 +607,9 @@ __device__ __forceinline__ void accel_pair(const RecAcc<R>& ri, const RecAcc<R>&
 // mu_k = hs_k (w.y) / (|y|^2 + eps_q hs_k^2).  Every quantity is evaluated by
 // the same expressions from both sides of the pair (the two Q terms are
 // separate statements, added commutatively), so F_ij = -F_ji bit for bit.
-template <class R>
-__device__ __forceinline__ void accel_pair_visc(const RecAccV<R>& ri, const RecAccV<R>& rj, R eps_q, int k,
-                                                int chunk, ChunkSums<R, 4>& acc) {
+template <bool kCompat, class R>
+__device__ __forceinline__ void accel_pair_visc(const RecAccV<R>& ri, const RecAccV<R>& rj, R eps_q, R eps_u,
+                                                int k, int chunk, ChunkSums<R, 4>& acc) {
     const R y[3] = {grid_sep<R>(ri.q[0], rj.q[0]), grid_sep<R>(ri.q[1], rj.q[1]),
                     grid_sep<R>(ri.q[2], rj.q[2])};
     const R yo[3] = {-y[0], -y[1], -y[2]};
@@ -627,7 +651,7 @@ __device__ __forceinline__ void accel_pair_visc(const RecAccV<R>& ri, const RecA
         Fv += F * (ri.v[c] - rj.v[c]);
         acc.add(c, F);
     }
-    acc.add(3, Fv);
+    acc.add(3, energy_term<kCompat>(ri, rj, eps_u, Fv));
     acc.next(k, chunk);
 }
 
@@ -667,10 +691,10 @@ __device__ __forceinline__ void accel_finish(int w, int s, bool valid, const Rec
         for (int k = 0; k < 8; ++k) partials[8 * w + k] = t[k];
 }
 
-template <class R, bool kOff32>
+template <class R, bool kOff32, bool kCompat>
 __global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
                                                const RecAcc<R>* __restrict__ rec, const R* __restrict__ m,
-                                               int chunk, R* __restrict__ a_out, R* __restrict__ du_out,
+                                               R eps_u, int chunk, R* __restrict__ a_out, R* __restrict__ du_out,
                                                double* __restrict__ partials) {
     constexpr int kStage = stage_stride<RecAcc<R>>();
     extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
@@ -687,16 +711,16 @@ __global__ __launch_bounds__(256) void k_accel(Queue qu, int n, Lists L, const i
         staged_list<RecAcc<R>, kOff32>(
             L, w, cnt, len, rec, stage_buf + wave_in_block() * kStage,
             [&](const RecAcc<R>& rj, int k) __attribute__((always_inline)) {
-                accel_pair(ri, rj, k, chunk, acc);
+                accel_pair<kCompat>(ri, rj, eps_u, k, chunk, acc);
             });
         accel_finish(w, s, valid, ri, acc, perm, m, a_out, du_out, partials);
     }
 }
 
-template <class R, bool kOff32>
+template <class R, bool kOff32, bool kCompat>
 __global__ __launch_bounds__(256) void k_accel_visc(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
                                                     const RecAccV<R>* __restrict__ rec, const R* __restrict__ m,
-                                                    R eps_q, int chunk, R* __restrict__ a_out,
+                                                    R eps_q, R eps_u, int chunk, R* __restrict__ a_out,
                                                     R* __restrict__ du_out, double* __restrict__ partials) {
     constexpr int kStage = stage_stride<RecAccV<R>>();
     extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
@@ -713,10 +737,18 @@ __global__ __launch_bounds__(256) void k_accel_visc(Queue qu, int n, Lists L, co
         staged_list<RecAccV<R>, kOff32>(
             L, w, cnt, len, rec, stage_buf + wave_in_block() * kStage,
             [&](const RecAccV<R>& rj, int k) __attribute__((always_inline)) {
-                accel_pair_visc(ri, rj, eps_q, k, chunk, acc);
+                accel_pair_visc<kCompat>(ri, rj, eps_q, eps_u, k, chunk, acc);
             });
         accel_finish(w, s, valid, ri, acc, perm, m, a_out, du_out, partials);
     }
+}
+
+// Work-queue coverage: every wave adds one to visits[tile] for each tile the
+// queue hands it (the same queue_start / queue_next walk as the pair passes).
+__global__ __launch_bounds__(256) void k_queue_visits(Queue qu, int32_t* __restrict__ visits) {
+    QState qs;
+    for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs))
+        if (lane_id() == 0) atomicAdd(visits + w, 1);
 }
 
 // Fixed-order FP64 reduction of the per-tile totals in two stages: block b
@@ -882,7 +914,7 @@ template <class R> size_t accel_scratch_bytes(int64_t n, int64_t n_tiles) {
 template <class R>
 int accel_run(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const crk_corr* C,
               double gamma, R* a, R* dudt, double* totals, RecAcc<R>* rec, double* partials,
-              hipStream_t st) {
+              hipStream_t st, double eps_u = -1.0) {
     const int n = int(L->n);
     int rc = pack_positions<R>(L, g->x, g->y, g->z, static_cast<const R*>(g->h), st);
     if (rc) return rc;
@@ -899,11 +931,15 @@ int accel_run(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const c
     reset_queue(L, st);
     {
         TimeScope ts(L, st, CRK_K_ACCEL);
-        auto kern = off32<RecAcc<R>>(L) ? k_accel<R, true> : k_accel<R, false>;
+        // eps_u < 0: the symmetric energy partition
+        const bool o32 = off32<RecAcc<R>>(L), compat = eps_u >= 0.0;
+        auto kern = compat ? (o32 ? k_accel<R, true, true> : k_accel<R, false, true>)
+                           : (o32 ? k_accel<R, true, false> : k_accel<R, false, false>);
         const int bw = L->tune.block_waves;
         hipLaunchKernelGGL(kern, dim3(grid_nwave(L)), dim3(kWave * bw), stage_bytes<RecAcc<R>>(bw), st,
                            make_queue(L, L->order_pair), n, lists(L), L->perm, rec,
-                           static_cast<const R*>(g->m), L->tune.kahan_chunk, a, dudt, partials);
+                           static_cast<const R*>(g->m), R(compat ? eps_u : 0.0), L->tune.kahan_chunk, a, dudt,
+                           partials);
     }
     LAUNCH_CHECK("accel");
     if (totals) {
@@ -922,18 +958,20 @@ int accel_run(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const c
 // The force pass on the handle's workspace.
 template <class R>
 int accel_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const crk_corr* C,
-               double gamma, R* a, R* dudt, double* totals, hipStream_t st) {
+               double gamma, R* a, R* dudt, double* totals, hipStream_t st, double eps_u = -1.0) {
     void* sp = nullptr;
     int rc = pass_scratch(L, sizeof(RecAcc<R>) * size_t(L->n), &sp);
     if (rc) return rc;
-    return accel_run<R>(L, g, V, rho, C, gamma, a, dudt, totals, static_cast<RecAcc<R>*>(sp), L->partials, st);
+    return accel_run<R>(L, g, V, rho, C, gamma, a, dudt, totals, static_cast<RecAcc<R>*>(sp), L->partials, st,
+                        eps_u);
 }
 
 // The force pass with the artificial viscosity (dv: velocity gradients, 9 per
 // particle in caller order, from the Extras pass).
 template <class R>
 int accel_visc_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const crk_corr* C, const R* dv,
-                    const crk_visc* q, double gamma, R* a, R* dudt, double* totals, hipStream_t st) {
+                    const crk_visc* q, double gamma, R* a, R* dudt, double* totals, hipStream_t st,
+                    double eps_u = -1.0) {
     const int n = int(L->n);
     int rc = pack_positions<R>(L, g->x, g->y, g->z, static_cast<const R*>(g->h), st);
     if (rc) return rc;
@@ -954,11 +992,14 @@ int accel_visc_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, c
     reset_queue(L, st);
     {
         TimeScope ts(L, st, CRK_K_ACCEL_VISC);
-        auto kern = off32<RecAccV<R>>(L) ? k_accel_visc<R, true> : k_accel_visc<R, false>;
+        const bool o32 = off32<RecAccV<R>>(L), compat = eps_u >= 0.0;
+        auto kern = compat ? (o32 ? k_accel_visc<R, true, true> : k_accel_visc<R, false, true>)
+                           : (o32 ? k_accel_visc<R, true, false> : k_accel_visc<R, false, false>);
         const int bw = L->tune.block_waves;
         hipLaunchKernelGGL(kern, dim3(grid_nwave(L)), dim3(kWave * bw), stage_bytes<RecAccV<R>>(bw), st,
                            make_queue(L, L->order_pair), n, lists(L), L->perm, rec,
-                           static_cast<const R*>(g->m), R(q->eps_q), L->tune.kahan_chunk, a, dudt, L->partials);
+                           static_cast<const R*>(g->m), R(q->eps_q), R(compat ? eps_u : 0.0),
+                           L->tune.kahan_chunk, a, dudt, L->partials);
     }
     LAUNCH_CHECK("accel_visc");
     if (totals) {
@@ -1053,6 +1094,16 @@ void crk_leaves_free(crk_leaves* L) {
     delete L;
 }
 
+int crk_queue_visits(crk_leaves* L, int32_t* visits, hipStream_t st) {
+    if (!L || !visits) return fail(CRK_EINVAL, "null argument");
+    if (L->n_tiles == 0) return CRK_OK;
+    reset_queue(L, st);
+    hipLaunchKernelGGL(k_queue_visits, dim3(grid_nwave(L)), dim3(kWave * L->tune.block_waves), 0, st,
+                       make_queue(L, L->order_pair), visits);
+    LAUNCH_CHECK("queue visits");
+    return CRK_OK;
+}
+
 int crk_leaves_perm(const crk_leaves* L, int32_t* perm, hipStream_t st) {
     if (!L || (!perm && L->n > 0)) return fail(CRK_EINVAL, "null argument");
     if (L->n == 0) return CRK_OK;
@@ -1132,6 +1183,7 @@ void carve_part_a(crk_leaves* L, Carver& c, int64_t n, int64_t nt) {
     L->scratch_bytes = L->hydro ? std::max(crk::backward_scratch_bytes(n, true),
                                            size_t(n) * sizeof(RecAcc<double>))
                                 : size_t(n) * 4 * sizeof(double);  // masses and adjoints (gravity)
+    if (L->dev_tree) L->scratch_bytes = std::max(L->scratch_bytes, crk::devtree_scratch_bytes(n, nt));
     L->scratch = c.take<char>(L->scratch_bytes);
 }
 
@@ -1151,6 +1203,44 @@ size_t carve(crk_leaves* L, char* base, int64_t n, int64_t nt, size_t nr, int64_
     return c.used();
 }
 
+// Fill pass of the neighbour lists (cnt, ell_off and ell_len in place), tile
+// order of the pair passes (longest lists first, from the per-tile lengths
+// len) and the shared-record slots.
+int fill_lists(crk_leaves* L, const std::vector<int32_t>& len, hipStream_t stream) {
+    const int64_t n = L->n, nt = L->n_tiles;
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, L->counter);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, L->build_err);
+    {
+        TimeScope ts(L, stream, CRK_K_CULL);
+        hipLaunchKernelGGL(k_cull<true>, dim3(grid_1wave(L)), dim3(kWave), 0, stream,
+                           make_queue(L, L->order_cull), int(n), L->quant, L->rng_off, L->rng,
+                           L->cnt, L->ell_off, L->ell_len, L->nbr, L->cnt_gather, L->ell_len_gather,
+                           L->build_err, float(L->skin));
+    }
+    if (hipGetLastError() != hipSuccess) return fail(CRK_EHIP, "launch cull fill failed");
+    // pair passes: tiles with the longest lists first
+    std::vector<int32_t> po(nt);
+    std::iota(po.begin(), po.end(), 0);
+    std::stable_sort(po.begin(), po.end(), [&](int32_t a, int32_t b) { return len[a] > len[b]; });
+    int32_t mismatched = 0;
+    if (hipMemcpyAsync(L->order_pair, po.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(&mismatched, L->build_err, sizeof(int32_t), hipMemcpyDeviceToHost, stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+        return fail(CRK_EHIP, "list build failed");
+    if (mismatched)
+        return fail(CRK_EHIP, "neighbour lists: count and fill passes disagree on %d particles", mismatched);
+    // shared-record slots: reorder the lists, name each slot's particles
+    {
+        TimeScope ts(L, stream, CRK_K_CULL);
+        hipLaunchKernelGGL(k_schedule, dim3(unsigned(nt)), dim3(kWave), 0, stream, int(n), L->cnt,
+                           L->cnt_gather, L->ell_off, L->ell_len, L->nbr, L->srec, L->sidx, L->scnt);
+    }
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(stream) != hipSuccess)
+        return fail(CRK_EHIP, "list schedule failed");
+    return CRK_OK;
+}
+
 }  // namespace
 
 extern "C" int crk_build_leaf_pairs(int64_t n, const double* x, const double* y, const double* z,
@@ -1166,6 +1256,8 @@ extern "C" int crk_build_leaf_pairs(int64_t n, const double* x, const double* y,
     if (leaf_min < 1) return fail(CRK_EINVAL, "leaf_min must be >= 1");
     if (n > 0 && !h && !(r_fixed > 0.0 && r_fixed < 0.5))
         return fail(CRK_EINVAL, "fixed radius must be in (0, 1/2) of the box");
+    if (h && !(r_fixed >= 0.0 && r_fixed < 0.5))
+        return fail(CRK_EINVAL, "list skin (r_fixed in hydro mode) must be in [0, 1/2)");
     if (n > 0 && (!x || !y || !z)) return fail(CRK_EINVAL, "positions are NULL");
     if (ws_bytes > 0 && !ws) return fail(CRK_EINVAL, "ws is NULL but ws_bytes = %zu", ws_bytes);
     if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(CRK_EINVAL, "ws must be 256-byte aligned");
@@ -1175,7 +1267,8 @@ extern "C" int crk_build_leaf_pairs(int64_t n, const double* x, const double* y,
     L->n = n;
     L->hydro = h != nullptr;
     L->prec = prec;
-    L->r_fixed = r_fixed;
+    L->r_fixed = h ? 0.0 : r_fixed;
+    L->skin = h ? r_fixed : 0.0;
     L->ws = static_cast<char*>(ws);
     L->ws_bytes = ws_bytes;
     int dev = 0;
@@ -1236,13 +1329,19 @@ extern "C" int crk_build_leaf_pairs(int64_t n, const double* x, const double* y,
             Hmax = std::max(Hmax, H[i]);
         }
     }
-    if (L->hydro && !(Hmax < 0.5))
-        return bail(fail(CRK_EINVAL, "2 max(h) = %g must be below half the box", Hmax));
+    if (L->hydro && !(Hmax + L->skin < 0.5))
+        return bail(fail(CRK_EINVAL, "2 max(h) + skin = %g must be below half the box", Hmax + L->skin));
+    // the tree and the list build see every support widened by the skin
+    std::vector<double> Hs;
+    if (L->hydro && L->skin > 0.0) {
+        Hs.resize(n);
+        for (int64_t i = 0; i < n; ++i) Hs[i] = H[i] + L->skin;
+    }
 
     crk::TreeInput tin;
     tin.n = n;
     for (int a = 0; a < 3; ++a) tin.q[a] = q[a].data();
-    tin.H = L->hydro ? H.data() : nullptr;
+    tin.H = L->hydro ? (Hs.empty() ? H.data() : Hs.data()) : nullptr;
     tin.r_fixed = r_fixed;
     tin.leaf_max = leaf_max;
     tin.leaf_min = leaf_min;
@@ -1350,7 +1449,8 @@ extern "C" int crk_build_leaf_pairs(int64_t n, const double* x, const double* y,
                 TimeScope ts(L, stream, CRK_K_CULL);
                 hipLaunchKernelGGL(k_cull<false>, dim3(grid_1wave(L)), dim3(kWave), 0, stream,
                                    make_queue(L, L->order_cull), int(n), L->quant, L->rng_off, L->rng,
-                                   L->cnt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+                                   L->cnt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                   float(L->skin));
             }
             if (hipGetLastError() != hipSuccess) return bail(fail(CRK_EHIP, "launch cull count failed"));
             hc.resize(n);
@@ -1399,37 +1499,128 @@ extern "C" int crk_build_leaf_pairs(int64_t n, const double* x, const double* y,
             hipMemcpyAsync(L->ell_len, len.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
             hipStreamSynchronize(stream) != hipSuccess)
             return bail(fail(CRK_EHIP, "uploading list counts and offsets failed"));
-        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, L->counter);
-        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, L->build_err);
-        {
-            TimeScope ts(L, stream, CRK_K_CULL);
-            hipLaunchKernelGGL(k_cull<true>, dim3(grid_1wave(L)), dim3(kWave), 0, stream,
-                               make_queue(L, L->order_cull), int(n), L->quant, L->rng_off, L->rng,
-                               L->cnt, L->ell_off, L->ell_len, L->nbr, L->cnt_gather, L->ell_len_gather,
-                               L->build_err);
-        }
-        if (hipGetLastError() != hipSuccess) return bail(fail(CRK_EHIP, "launch cull fill failed"));
-        // pair passes: tiles with the longest lists first
-        std::vector<int32_t> po(nt);
-        std::iota(po.begin(), po.end(), 0);
-        std::stable_sort(po.begin(), po.end(), [&](int32_t a, int32_t b) { return len[a] > len[b]; });
-        int32_t mismatched = 0;
-        if (hipMemcpyAsync(L->order_pair, po.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
-            hipMemcpyAsync(&mismatched, L->build_err, sizeof(int32_t), hipMemcpyDeviceToHost, stream) !=
+        if ((rc = fill_lists(L, len, stream))) return bail(rc);
+        L->stats[3] = entries;
+        L->stats[6] = total - entries;
+    }
+    L->timing = false;
+    if (hipStreamSynchronize(stream) != hipSuccess) return bail(fail(CRK_EHIP, "build sync failed"));
+    L->stats[7] = std::chrono::duration_cast<std::chrono::microseconds>(
+                      std::chrono::steady_clock::now() - t0).count();
+    *out = L;
+    return CRK_OK;
+}
+
+// The same handle built on the device: Morton octree leaves, tile candidate
+// ranges and neighbour lists without the positions' round trip to the host.
+// A run that stops with CRK_ENOSPC keeps no state: the repeated call rebuilds
+// (the build is deterministic, so it reaches the same sizes).
+extern "C" int crk_build_leaf_pairs_device(int64_t n, const double* x, const double* y, const double* z,
+                                           const void* h, double r_fixed, int leaf_max, crk_prec prec, void* ws,
+                                           size_t ws_bytes, size_t* ws_needed, crk_leaves** out,
+                                           hipStream_t stream) {
+    if (!out || !ws_needed) return fail(CRK_EINVAL, "out and ws_needed must not be NULL");
+    *out = nullptr;
+    *ws_needed = 0;
+    if (n < 0 || n >= (int64_t(1) << 31)) return fail(CRK_EINVAL, "n = %lld out of range [0, 2^31)", (long long)n);
+    if (prec != CRK_F32 && prec != CRK_F64) return fail(CRK_EINVAL, "unknown precision");
+    if (leaf_max < 1 || leaf_max > kDevLeafMax)
+        return fail(CRK_EINVAL, "leaf_max out of range [1, %d] for the device build", kDevLeafMax);
+    if (n > 0 && !h && !(r_fixed > 0.0 && r_fixed < 0.5))
+        return fail(CRK_EINVAL, "fixed radius must be in (0, 1/2) of the box");
+    if (h && !(r_fixed >= 0.0 && r_fixed < 0.5))
+        return fail(CRK_EINVAL, "list skin (r_fixed in hydro mode) must be in [0, 1/2)");
+    if (n > 0 && (!x || !y || !z)) return fail(CRK_EINVAL, "positions are NULL");
+    if (ws_bytes > 0 && !ws) return fail(CRK_EINVAL, "ws is NULL but ws_bytes = %zu", ws_bytes);
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(CRK_EINVAL, "ws must be 256-byte aligned");
+    const auto t0 = std::chrono::steady_clock::now();
+
+    crk_leaves* L = new crk_leaves();
+    L->n = n;
+    L->hydro = h != nullptr;
+    L->prec = prec;
+    L->r_fixed = h ? 0.0 : r_fixed;
+    L->skin = h ? r_fixed : 0.0;
+    L->dev_tree = true;
+    L->ws = static_cast<char*>(ws);
+    L->ws_bytes = ws_bytes;
+    int dev = 0;
+    auto bail = [&](int code) {
+        drop_timed(L);
+        delete L;
+        return code;
+    };
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&L->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return bail(fail(CRK_EHIP, "cannot query the device"));
+    const int64_t nt = (n + kWave - 1) / kWave;
+    L->n_tiles = nt;
+    if (n == 0) {
+        *ws_needed = carve(L, nullptr, 0, 0, 0, -1);
+        if (ws_bytes < *ws_needed) return bail(fail(CRK_ENOSPC, "workspace of %zu bytes, need %zu", ws_bytes, *ws_needed));
+        carve(L, L->ws, 0, 0, 0, -1);
+        *out = L;
+        return CRK_OK;
+    }
+    // part A holds the build's temporaries (in the per-pass scratch)
+    *ws_needed = carve(L, nullptr, n, nt, 0, -1);
+    if (*ws_needed > ws_bytes)
+        return bail(fail(CRK_ENOSPC, "workspace of %zu bytes, need at least %zu (before the candidate ranges)",
+                         ws_bytes, *ws_needed));
+    carve(L, L->ws, n, nt, 0, -1);
+    int rc = devtree_leaves(L, x, y, z, h, leaf_max, stream);
+    if (rc) return bail(rc);
+    L->stats[0] = L->n_leaves;
+    L->stats[1] = nt;
+
+    // candidate ranges of the tiles of the current tree order; the tile order
+    // of the list build: most candidates first
+    std::vector<int64_t> tile_cand;
+    std::vector<int32_t> order(nt), tree_order(nt);
+    std::iota(tree_order.begin(), tree_order.end(), 0);
+    int64_t nr = 0;
+    auto ranges_and_orders = [&](int64_t slots) -> int {
+        int r = devtree_ranges(L, nullptr, &nr, &tile_cand, stream);
+        if (r) return r;
+        *ws_needed = carve(L, nullptr, n, nt, size_t(nr), slots);
+        if (*ws_needed > ws_bytes)
+            return fail(CRK_ENOSPC, "workspace of %zu bytes, need %s%zu", ws_bytes,
+                        slots < 0 && L->hydro ? "at least " : "", *ws_needed);
+        carve(L, L->ws, n, nt, size_t(nr), slots);
+        if ((r = devtree_ranges(L, L->rng, nullptr, nullptr, stream))) return r;
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return tile_cand[a] > tile_cand[b]; });
+        int64_t cp = 0;
+        for (int64_t t = 0; t < nt; ++t) cp += tile_cand[t] * (std::min<int64_t>(n, (t + 1) * kWave) - t * kWave);
+        L->stats[2] = cp;
+        if (hipMemcpyAsync(L->order_cull, order.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+            hipMemcpyAsync(L->order_pair, order.data(), nt * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+            hipMemcpyAsync(L->order_tree, tree_order.data(), nt * 4, hipMemcpyHostToDevice, stream) !=
                 hipSuccess ||
             hipStreamSynchronize(stream) != hipSuccess)
-            return bail(fail(CRK_EHIP, "list build failed"));
-        if (mismatched)
-            return bail(fail(CRK_EHIP, "neighbour lists: count and fill passes disagree on %d particles",
-                             mismatched));
-        // shared-record slots: reorder the lists, name each slot's particles
+            return fail(CRK_EHIP, "uploading the tile orders failed");
+        return CRK_OK;
+    };
+    if ((rc = ranges_and_orders(-1))) return bail(rc);
+    if (L->hydro) {
+        L->timing = true;  // the list build is always timed (read by crk_kernel_times)
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, L->counter);
         {
             TimeScope ts(L, stream, CRK_K_CULL);
-            hipLaunchKernelGGL(k_schedule, dim3(unsigned(nt)), dim3(kWave), 0, stream, int(n), L->cnt,
-                               L->cnt_gather, L->ell_off, L->ell_len, L->nbr, L->srec, L->sidx, L->scnt);
+            hipLaunchKernelGGL(k_cull<false>, dim3(grid_1wave(L)), dim3(kWave), 0, stream,
+                               make_queue(L, L->order_cull), int(n), L->quant, L->rng_off, L->rng, L->cnt,
+                               nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, float(L->skin));
         }
-        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(stream) != hipSuccess)
-            return bail(fail(CRK_EHIP, "list schedule failed"));
+        if (hipGetLastError() != hipSuccess) return bail(fail(CRK_EHIP, "launch cull count failed"));
+        // tiles of similar list lengths: every leaf by decreasing count (its
+        // box stays the same; the tiles and their candidates change)
+        if ((rc = devtree_sort_leaves(L, stream))) return bail(rc);
+        std::vector<int32_t> len;
+        int64_t total = 0, entries = 0;
+        if ((rc = devtree_list_layout(L, &total, &entries, &len, stream))) return bail(rc);
+        if ((rc = ranges_and_orders(total))) return bail(rc);
+        if ((rc = fill_lists(L, len, stream))) return bail(rc);
         L->stats[3] = entries;
         L->stats[6] = total - entries;
     }
@@ -1502,12 +1693,16 @@ static int accel_entry(bool noalloc, crk_leaves* L, const crk_gas* g, const void
     }
     if (!V || !rho || !C || !C->A || !C->B || !C->dA || !C->dB || !a || !dudt)
         return fail(CRK_EINVAL, "V, rho, corrections, a and dudt are required");
-    if (prec == CRK_F32)
-        return (noalloc ? accel_noalloc_impl<float> : accel_impl<float>)(
-            L, g, (const float*)V, (const float*)rho, C, gamma, (float*)a, (float*)dudt, totals, st);
-    if (prec == CRK_F64)
-        return (noalloc ? accel_noalloc_impl<double> : accel_impl<double>)(
-            L, g, (const double*)V, (const double*)rho, C, gamma, (double*)a, (double*)dudt, totals, st);
+    if (prec == CRK_F32) {
+        const float *Vf = (const float*)V, *rf = (const float*)rho;
+        return noalloc ? accel_noalloc_impl<float>(L, g, Vf, rf, C, gamma, (float*)a, (float*)dudt, totals, st)
+                       : accel_impl<float>(L, g, Vf, rf, C, gamma, (float*)a, (float*)dudt, totals, st);
+    }
+    if (prec == CRK_F64) {
+        const double *Vd = (const double*)V, *rd = (const double*)rho;
+        return noalloc ? accel_noalloc_impl<double>(L, g, Vd, rd, C, gamma, (double*)a, (double*)dudt, totals, st)
+                       : accel_impl<double>(L, g, Vd, rd, C, gamma, (double*)a, (double*)dudt, totals, st);
+    }
     return fail(CRK_EINVAL, "unknown precision");
 }
 
@@ -1541,6 +1736,43 @@ int crk_accel_energy_visc(crk_leaves* L, const crk_gas* g, const void* V, const 
     if (prec == CRK_F64)
         return accel_visc_impl<double>(L, g, (const double*)V, (const double*)rho, C, (const double*)dv, q, gamma,
                                        (double*)a, (double*)dudt, totals, st);
+    return fail(CRK_EINVAL, "unknown precision");
+}
+
+int crk_accel_energy_compatible(crk_leaves* L, const crk_gas* g, const void* V, const void* rho,
+                                const crk_corr* C, const void* dv, const crk_visc* q, double eps_u, double gamma,
+                                crk_prec prec, void* a, void* dudt, double* totals, hipStream_t st) {
+    int rc = check_gas(L, g, true);
+    if (rc) return rc;
+    if ((dv == nullptr) != (q == nullptr))
+        return fail(CRK_EINVAL, "dv and the viscosity parameters go together (both NULL: no viscosity)");
+    if (q && (!(q->Cl >= 0.0) || !(q->Cq >= 0.0) || !(q->eps_q > 0.0)))
+        return fail(CRK_EINVAL, "viscosity needs Cl >= 0, Cq >= 0 and eps_q > 0");
+    if (!(eps_u >= 0.0) || !std::isfinite(eps_u)) return fail(CRK_EINVAL, "eps_u must be finite and >= 0");
+    if (q && !(gamma > 1.0)) return fail(CRK_EINVAL, "gamma must exceed 1 (the sound speed)");
+    if (L->n == 0) {
+        if (totals) {
+            hipLaunchKernelGGL(k_zero8, dim3(1), dim3(64), 0, st, totals);
+            LAUNCH_CHECK("zero totals");
+        }
+        return CRK_OK;
+    }
+    if (!V || !rho || !C || !C->A || !C->B || !C->dA || !C->dB || !a || !dudt)
+        return fail(CRK_EINVAL, "V, rho, corrections, a and dudt are required");
+    if (prec == CRK_F32) {
+        if (q)
+            return accel_visc_impl<float>(L, g, (const float*)V, (const float*)rho, C, (const float*)dv, q, gamma,
+                                          (float*)a, (float*)dudt, totals, st, eps_u);
+        return accel_impl<float>(L, g, (const float*)V, (const float*)rho, C, gamma, (float*)a, (float*)dudt,
+                                 totals, st, eps_u);
+    }
+    if (prec == CRK_F64) {
+        if (q)
+            return accel_visc_impl<double>(L, g, (const double*)V, (const double*)rho, C, (const double*)dv, q,
+                                           gamma, (double*)a, (double*)dudt, totals, st, eps_u);
+        return accel_impl<double>(L, g, (const double*)V, (const double*)rho, C, gamma, (double*)a,
+                                  (double*)dudt, totals, st, eps_u);
+    }
     return fail(CRK_EINVAL, "unknown precision");
 }
 

@@ -640,6 +640,9 @@ struct crk_leaves {
     int hydro = 0;
     crk_prec prec = CRK_F32;
     double r_fixed = 0.0;
+    double skin = 0.0;  // hydro lists: every support widened by this much (list reuse while particles move)
+    bool dev_tree = false;  // built by crk_build_leaf_pairs_device (its scratch also holds the build's temporaries)
+    double hmax = 0.0;      // device build: the largest support radius 2h
     int64_t n_tiles = 0, n_leaves = 0;
     int n_cu = 1;
     crk_tuning tune{0, 16, 4, 4, 8, 0, 0, 0, 0};  // measured best on the C2 workload
@@ -712,6 +715,21 @@ int check_gas(const crk_leaves* L, const crk_gas* g, bool need_v);
 void reset_queue(crk_leaves* L, hipStream_t st);
 Lists lists(const crk_leaves* L);         // pairs r < max(H_i, H_j)
 Lists lists_gather(const crk_leaves* L);  // their front parts: r < H_i
+
+// Device leaf build (Morton octree), in the handle's per-pass scratch:
+// bytes it needs there; tree order (perm, quant, Hd) and leaves, with the
+// inputs validated (CRK_EINVAL); tile candidate ranges (rng == nullptr: counts
+// them into rng_off, *total and the host tile_cand; else fills rng); every
+// leaf ordered by decreasing list length (cnt); list lengths per tile
+// (ell_len, ell_off) with the total slots and entries on the host.
+size_t devtree_scratch_bytes(int64_t n, int64_t nt);
+int devtree_leaves(crk_leaves* L, const double* x, const double* y, const double* z, const void* h,
+                   int leaf_max, hipStream_t st);
+int devtree_ranges(crk_leaves* L, int2* rng, int64_t* total, std::vector<int64_t>* tile_cand, hipStream_t st);
+int devtree_sort_leaves(crk_leaves* L, hipStream_t st);
+int devtree_list_layout(crk_leaves* L, int64_t* slots, int64_t* entries, std::vector<int32_t>* len,
+                        hipStream_t st);
+constexpr int kDevLeafMax = 1024;  // largest leaf of the device build (one workgroup sorts it in LDS)
 
 // Whether a pass over n records of type D takes the 32-bit offset form.
 template <class D> inline bool off32(const crk_leaves* L) {

@@ -59,23 +59,52 @@ __global__ __launch_bounds__(256) void k_dt_min(int n, const R* __restrict__ h, 
     if (threadIdx.x == 0) atomicMin(reinterpret_cast<U*>(dt), Bits<R>::of(red[0]));
 }
 
-// v <- v + a dt, u <- u + du/dt dt, then x <- x + v dt wrapped into [0, 1)
+// v <- v + a dt, u <- u + du/dt dt, then x <- x + v dt wrapped into [0, 1);
+// with disp, the step's largest drift |v dt| goes to disp[1] (atomic maximum
+// on the bits of the positive value)
 template <class R>
-__global__ void k_kick_drift(int n, double* __restrict__ x, double* __restrict__ y, double* __restrict__ z,
-                             R* __restrict__ vx, R* __restrict__ vy, R* __restrict__ vz, R* __restrict__ u,
-                             const R* __restrict__ a, const R* __restrict__ dudt, const R* __restrict__ dtp) {
+__global__ __launch_bounds__(256) void k_kick_drift(int n, double* __restrict__ x, double* __restrict__ y,
+                                                    double* __restrict__ z, R* __restrict__ vx,
+                                                    R* __restrict__ vy, R* __restrict__ vz, R* __restrict__ u,
+                                                    const R* __restrict__ a, const R* __restrict__ dudt,
+                                                    const R* __restrict__ dtp, double* __restrict__ disp) {
+    __shared__ double red[256];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const R dt = dtp[0];
-    const R v[3] = {vx[i] + a[3 * i] * dt, vy[i] + a[3 * i + 1] * dt, vz[i] + a[3 * i + 2] * dt};
-    vx[i] = v[0];
-    vy[i] = v[1];
-    vz[i] = v[2];
-    u[i] = u[i] + dudt[i] * dt;
-    double* p[3] = {x, y, z};
-    for (int c = 0; c < 3; ++c) {
-        const double q = p[c][i] + double(v[c]) * double(dt);
-        p[c][i] = q - floor(q);
+    double moved = 0.0;
+    if (i < n) {
+        const R dt = dtp[0];
+        const R v[3] = {vx[i] + a[3 * i] * dt, vy[i] + a[3 * i + 1] * dt, vz[i] + a[3 * i + 2] * dt};
+        vx[i] = v[0];
+        vy[i] = v[1];
+        vz[i] = v[2];
+        u[i] = u[i] + dudt[i] * dt;
+        double* p[3] = {x, y, z};
+        double d2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const double dx = double(v[c]) * double(dt);
+            const double q = p[c][i] + dx;
+            p[c][i] = q - floor(q);
+            d2 += dx * dx;
+        }
+        moved = sqrt(d2);
+    }
+    if (!disp) return;  // uniform over the launch
+    red[threadIdx.x] = moved;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (int(threadIdx.x) < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        atomicMax(reinterpret_cast<unsigned long long*>(disp + 1),
+                  static_cast<unsigned long long>(__double_as_longlong(red[0])));
+}
+
+// disp[0] += disp[1] (the step's largest drift), disp[1] = 0
+__global__ void k_disp_add(double* disp) {
+    if (threadIdx.x == 0) {
+        disp[0] += disp[1];
+        disp[1] = 0.0;
     }
 }
 
@@ -114,21 +143,26 @@ int crk_timestep(int64_t n, const void* h, const void* u, const void* vx, const 
 }
 
 int crk_kick_drift(int64_t n, double* x, double* y, double* z, void* vx, void* vy, void* vz, void* u,
-                   const void* a, const void* dudt, const void* dt, crk_prec prec, hipStream_t st) {
+                   const void* a, const void* dudt, const void* dt, double* disp, crk_prec prec,
+                   hipStream_t st) {
     if (n < 0 || n >= (int64_t(1) << 31)) return fail(CRK_EINVAL, "n out of range");
     if (n == 0) return CRK_OK;
     if (!x || !y || !z || !vx || !vy || !vz || !u || !a || !dudt || !dt)
         return fail(CRK_EINVAL, "positions, velocities, u, a, dudt and dt are required");
+    if (prec != CRK_F32 && prec != CRK_F64) return fail(CRK_EINVAL, "unknown precision");
     const dim3 grid(unsigned((n + 255) / 256)), block(256);
     if (prec == CRK_F32)
         hipLaunchKernelGGL(k_kick_drift<float>, grid, block, 0, st, int(n), x, y, z, (float*)vx, (float*)vy,
-                           (float*)vz, (float*)u, (const float*)a, (const float*)dudt, (const float*)dt);
-    else if (prec == CRK_F64)
-        hipLaunchKernelGGL(k_kick_drift<double>, grid, block, 0, st, int(n), x, y, z, (double*)vx, (double*)vy,
-                           (double*)vz, (double*)u, (const double*)a, (const double*)dudt, (const double*)dt);
+                           (float*)vz, (float*)u, (const float*)a, (const float*)dudt, (const float*)dt, disp);
     else
-        return fail(CRK_EINVAL, "unknown precision");
+        hipLaunchKernelGGL(k_kick_drift<double>, grid, block, 0, st, int(n), x, y, z, (double*)vx, (double*)vy,
+                           (double*)vz, (double*)u, (const double*)a, (const double*)dudt, (const double*)dt,
+                           disp);
     LAUNCH_CHECK("kick drift");
+    if (disp) {
+        hipLaunchKernelGGL(k_disp_add, dim3(1), dim3(64), 0, st, disp);
+        LAUNCH_CHECK("displacement");
+    }
     return CRK_OK;
 }
 

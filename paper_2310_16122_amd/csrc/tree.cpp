@@ -197,7 +197,7 @@ bool build_tree(const TreeInput& in, TreeOutput& out, const char** err) {
             }
             // radius with a small margin (list builds test pairs exactly on the GPU)
             double R = in.H ? std::max(hmax, nd.hmax) : in.r_fixed;
-            R = R * (1.0 + 1e-6) + 4.0 / kGrid;
+            R = R * kTreeMargin + 4.0 / kGrid;
             if (g2 >= R * R) continue;
             if (nd.left < 0) {
                 found.emplace_back(nd.begin, nd.end);

@@ -7,6 +7,11 @@
 namespace crk {
 
 constexpr int kTile = 64;  // particles per tile = lanes per wavefront
+// Radius factor of the box tests that gather a tile's candidates: wide enough
+// that every pair the list build accepts (squared radius factor 1 + 1e-5, FP32
+// rounding of r^2 and of the radii) lies within it, so that a particle's list
+// does not depend on how the particles are cut into leaves and tiles.
+constexpr double kTreeMargin = 1.0 + 2.0e-5;
 
 struct TreeInput {
     int64_t n;

@@ -24,7 +24,7 @@ SPACE = {
     "persistent": (0, 1),
     "waves_per_cu": (8, 16, 32),
     "block_waves": (1, 2, 4),
-    "kahan_chunk": (1, 4, 8),
+    "kahan_chunk": (1, 4, 8, 16),
     "stage16": (0, 1),
 }
 # short-range gravity also chooses how candidates are exchanged between lanes

@@ -549,6 +549,23 @@ def test_invalid_arguments(crk):
         crk.sr_gravity(L, x, x, x, m, 1.0, 0.0, r_cut=0.2, prec="f32")  # r_cut > r_fixed
 
 
+@pytest.mark.parametrize("tuning", [dict(persistent=0), dict(persistent=1, waves_per_cu=8),
+                                    dict(persistent=1, waves_per_cu=32, xcd_groups=8, tile_order=0),
+                                    dict(persistent=1, waves_per_cu=1, xcd_groups=16, block_waves=4),
+                                    dict(persistent=0, xcd_groups=8, block_waves=4, tile_order=1)])
+def test_work_queue_hands_out_every_tile_once(crk, tuning):
+    """The persistent atomic queue (and the one-tile-per-wave form) hands every
+    tile to exactly one wave, for grids smaller and larger than the work."""
+    cfg, _ = oracle_full("C2", 21)
+    g = crk.gas_to_device(cfg, "f32")
+    L = crk.crk_build_leaf_pairs(g["x"], g["y"], g["z"], g["h"], leaf_max=64, prec="f32")
+    L.set_tuning(**tuning)
+    v = L.queue_visits()
+    torch.cuda.synchronize()
+    assert v.numel() == L.stats()["tiles"] and bool((v == 1).all()), (tuning, v.min().item(), v.max().item())
+    L.free()
+
+
 # ---------------------------------------------------------------- caller-owned workspace
 def test_workspace_protocol(crk):
     """crk_build_leaf_pairs through the C ABI with too small a workspace: it

@@ -92,3 +92,48 @@ def test_simulation_steps_conserve_momentum_and_energy(crk):
         assert second > 0
         assert abs((e_after - e_before) - second) <= 1e-12 * e_before + 1e-6 * second
         L.free()
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_lists_built_with_a_skin_serve_moved_particles(crk, prec, tol):
+    """A handle built with a list skin and reused while the particles drift less
+    than half the skin gives the passes of a fresh build on the moved positions
+    (only the summation order differs), and so does it before they move."""
+    cfg = synth.make_config("C2", n_side=16)
+    print(f"case list reuse n={cfg['n']} prec={prec}", flush=True)
+    g = crk.gas_to_device(cfg, prec)
+    skin = 0.2 * 2.0 * float(np.mean(cfg["h"]))
+    L = crk.crk_build_leaf_pairs(g["x"], g["y"], g["z"], g["h"], leaf_max=64, prec=prec, skin=skin)
+    keys = ("V", "rho", "A", "B", "dA", "dB", "a", "dudt")
+
+    def compare(o1, o2):
+        for k in keys:
+            a = o1[k].double().cpu().numpy()
+            b = o2[k].double().cpu().numpy()
+            err = np.abs(a - b).max() / np.abs(b).max()
+            assert err <= tol, (k, err)
+
+    fresh0 = crk.crk_build_leaf_pairs(g["x"], g["y"], g["z"], g["h"], leaf_max=64, prec=prec)
+    compare(crk.forward(L, g, cfg["gamma"], prec), crk.forward(fresh0, g, cfg["gamma"], prec))
+    fresh0.free()
+    disp = torch.zeros(2, dtype=torch.float64, device="cuda")
+    steps = 0
+    while True:
+        out = crk.forward(L, g, cfg["gamma"], prec)
+        dt = crk.crk_timestep(g, out["a"], cfg["gamma"], 0.05, 0.05, prec)
+        before = disp.clone()
+        crk.crk_kick_drift(g, out["a"], out["dudt"], dt, prec, disp=disp)
+        steps += 1
+        if float(disp[0]) >= 0.4 * skin or steps == 40:
+            break
+    assert steps >= 2 and float(disp[1]) == 0.0
+    assert 0.0 < float(disp[0]) < 0.5 * skin, float(disp[0])
+    # the largest drift of the last step is at least what the tracker added for it
+    assert float(disp[0] - before[0]) > 0.0
+    fresh = crk.crk_build_leaf_pairs(g["x"], g["y"], g["z"], g["h"], leaf_max=64, prec=prec)
+    compare(crk.forward(L, g, cfg["gamma"], prec), crk.forward(fresh, g, cfg["gamma"], prec))
+    st, sf = L.stats(), fresh.stats()
+    assert st["pairs_gather"] == sf["pairs_gather"] and st["pairs_force"] == sf["pairs_force"]
+    assert st["list_entries"] > sf["list_entries"]
+    L.free()
+    fresh.free()
