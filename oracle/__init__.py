@@ -80,6 +80,7 @@ def _load():
         lib.oracle_extras.argtypes = [I64] + [P] * 14 + [I64, P, P, P, P]
         lib.oracle_visc_listed.argtypes = [I64] + [P] * 9 + [D, D, D, D] + [P] * 15
         lib.oracle_accel_visc.argtypes = [I64] + [P] * 16 + [D, D, D, D, I64, P, P, P, P, P]
+        lib.oracle_grad_visc.argtypes = [I64] + [P] * 9 + [D, D, D, D, P, P, I64, P, P, D, P, P]
         lib.oracle_accel_compat.argtypes = [I64] + [P] * 16 + [D, D, D, D, D, I64, P, P, P, P, P]
         lib.oracle_gravity_grad.argtypes = [I64, P, P, P, P, D, D, D, P, P, I64, P, P, D, P, P]
         _lib = lib
@@ -388,6 +389,24 @@ def grad(g, parts, kinds, fd_step=1e-6):
     _load().oracle_grad(arr[0].size, *[_p(v) for v in arr], float(g["gamma"]), _p(w), _p(cw), nc,
                         _p(pt), _p(kd), float(fd_step), _p(gd), _p(gf), _p(cs))
     return gd, gf, cs
+
+
+def grad_visc(g, parts, kinds, fd_step=1e-6, Cl=1.0, Cq=2.0, eps_q=0.01):
+    """dL/dtheta of L = sum w |a|^2 + sum c du/dt through the chain with the
+    extras pass and the viscous forces, at coordinates (parts[k], kinds[k]).
+    Returns (dual-number gradient, central-difference gradient); every
+    particle's chain is evaluated, so keep n small."""
+    keys = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "m")
+    arr = [_c(g[k]) for k in keys]
+    w, cw = _c(g["w"]), _c(g["c"])
+    pt = _c(parts, np.int64)
+    kd = _c(kinds, np.int32)
+    nc = pt.size
+    gd = np.empty(nc)
+    gf = np.empty(nc)
+    _load().oracle_grad_visc(arr[0].size, *[_p(v) for v in arr], float(g["gamma"]), float(Cl), float(Cq),
+                             float(eps_q), _p(w), _p(cw), nc, _p(pt), _p(kd), float(fd_step), _p(gd), _p(gf))
+    return gd, gf
 
 
 def grad_coordinates(n, n_pos=32, n_vel=16, n_u=16, seed=19):

@@ -757,6 +757,48 @@ T cone_loss(const Gas<T>& g, const NbrLists& nb, const Cone& c, double gamma, co
 }
 
 
+// ---------------------------------------------------------------- gradient with the viscosity
+// L = sum_i w_i |a_i|^2 + sum_i c_i du_i/dt for the chain volume -> corrections
+// -> extras (velocity gradients) -> forces with the artificial viscosity
+// (h and m held fixed).  Every particle's chain is evaluated (small inputs):
+// forward-mode dual numbers for dL/dtheta and central differences as a check.
+template <class T>
+T visc_chain_loss(const Gas<T>& g, const NbrLists& nb, double gamma, const Visc<double>& qp, const double* w,
+                  const double* cw) {
+    const int64_t n = g.n;
+    std::vector<T> V(n), rho(n), dv(9 * n);
+    std::vector<Corr<T>> C(n);
+    for (int64_t k = 0; k < n; ++k) {
+        const T S = volume_sum(g, k, nb.of(k));
+        V[k] = T(1.0) / S;
+        rho[k] = T(g.m[k]) * S;
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        Moments<T> M;
+        moments_one(g, V.data(), k, nb.of(k), M);
+        solve_corrections(M, C[k]);
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        T rhoR, d[3][3], du[3];
+        extras_one(g, V.data(), C.data(), k, nb.of(k), rhoR, d, du);
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) dv[9 * k + 3 * a + c] = d[a][c];
+    }
+    Visc<T> q;
+    q.dv = dv.data();
+    q.Cl = qp.Cl;
+    q.Cq = qp.Cq;
+    q.eps_q = qp.eps_q;
+    T L = T(0.0);
+    for (int64_t i = 0; i < n; ++i) {
+        T a[3], du;
+        accel_one(g, V.data(), rho.data(), C.data(), gamma, i, nb.of(i), a, du, &q);
+        L += T(w[i]) * (a[0] * a[0] + a[1] * a[1] + a[2] * a[2]) + T(cw[i]) * du;
+    }
+    return L;
+}
+
+
 // ---------------------------------------------------------------- operation counts per pair
 // The algorithmic work of each pass per ordered pair inside its radius, counted
 // on the oracle's own code with the Ops scalar: the pass is evaluated for one
@@ -1650,6 +1692,56 @@ static double split_F(double x) {
 // Long-range force per unit mass at separations r (r > 0), filter scale r_s.
 void oracle_long_range_force(int64_t n, const double* r, double r_s, double* f) {
     for (int64_t k = 0; k < n; ++k) f[k] = split_F(r[k] / (2.0 * r_s)) / (r[k] * r[k]);
+}
+
+// dL/dtheta of the viscous chain (visc_chain_loss) at ncoord coordinates kind
+// 0-6 (x, y, z, vx, vy, vz, u) of particle part[k]: dual numbers (g_dual) and
+// central differences (g_fd; step fd_step, relative for u).
+int oracle_grad_visc(int64_t n, const double* x, const double* y, const double* z, const double* vx,
+                     const double* vy, const double* vz, const double* u, const double* h, const double* m,
+                     double gamma, double Cl, double Cq, double eps_q, const double* w, const double* cw,
+                     int64_t ncoord, const int64_t* part, const int32_t* kind, double fd_step, double* g_dual,
+                     double* g_fd) {
+    Gas<double> g = make_gas(n, x, y, z, vx, vy, vz, u, h, m);
+    const NbrLists nb = brute_force_lists(g);
+    Visc<double> qp;
+    qp.Cl = Cl;
+    qp.Cq = Cq;
+    qp.eps_q = eps_q;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < ncoord; ++k) {
+        const int64_t p = part[k];
+        const int kd = kind[k];
+        {
+            std::vector<Dual> f[7];
+            const double* src[7] = {x, y, z, vx, vy, vz, u};
+            for (int a = 0; a < 7; ++a) {
+                f[a].resize(n);
+                for (int64_t i = 0; i < n; ++i) f[a][i] = Dual(src[a][i], 0.0);
+            }
+            f[kd][p].d = 1.0;
+            Gas<Dual> gd;
+            gd.n = n; gd.x = f[0].data(); gd.y = f[1].data(); gd.z = f[2].data();
+            gd.vx = f[3].data(); gd.vy = f[4].data(); gd.vz = f[5].data(); gd.u = f[6].data();
+            gd.h = h; gd.m = m;
+            g_dual[k] = visc_chain_loss(gd, nb, gamma, qp, w, cw).d;
+        }
+        {
+            std::vector<double> f[7];
+            const double* src[7] = {x, y, z, vx, vy, vz, u};
+            for (int a = 0; a < 7; ++a) f[a].assign(src[a], src[a] + n);
+            const double step = kd == 6 ? fd_step * u[p] : fd_step;
+            double Lpm[2];
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                f[kd][p] = src[kd][p] + (sgn == 0 ? step : -step);
+                Gas<double> gp = make_gas(n, f[0].data(), f[1].data(), f[2].data(), f[3].data(),
+                                          f[4].data(), f[5].data(), f[6].data(), h, m);
+                Lpm[sgn] = visc_chain_loss(gp, nb, gamma, qp, w, cw);
+            }
+            g_fd[k] = (Lpm[0] - Lpm[1]) / (2.0 * step);
+        }
+    }
+    return 0;
 }
 
 // dL/dx for L = sum_i abar_i . a_i, a the short-range gravity of every

@@ -673,6 +673,24 @@ def test_listed_viscous_chain_is_the_brute_force_chain(oracle_lib):
         assert np.array_equal(ol[k], ov[k]), k
 
 
+def test_viscous_chain_gradient_dual_matches_finite_differences(oracle_lib):
+    """The gradient through volume -> corrections -> extras -> viscous forces:
+    dual numbers agree with central differences; with the viscosity switched
+    off (C_l = C_q = 0) it is the inviscid chain's gradient (pinned above)."""
+    g = tiny_gas(n=300, nbr=24, seed=11)
+    rng = np.random.default_rng(3)
+    g["w"] = rng.uniform(0.5, 1.5, g["n"])
+    g["c"] = rng.normal(0.0, 1.0, g["n"])
+    parts, kinds = oracle_lib.grad_coordinates(g["n"], 8, 4, 4)
+    gd, gf = oracle_lib.grad_visc(g, parts, kinds)
+    scale = np.abs(gd).max()
+    assert np.abs(gd - gf).max() <= 1e-6 * scale
+    g0, _ = oracle_lib.grad_visc(g, parts, kinds, Cl=0.0, Cq=0.0)
+    gi, _, _ = oracle_lib.grad(g, parts, kinds)
+    assert np.abs(g0 - gi).max() <= 1e-12 * np.abs(gi).max()
+    assert np.abs(gd - gi).max() >= 1e-2 * np.abs(gi).max()  # the viscosity is active
+
+
 # ---------------------------------------------------------------- compatible energy partition
 def test_compatible_partition_keeps_forces_and_conserves_energy(tiny, oracle_lib):
     """Only du/dt changes, and the pair work is still split exactly between
