@@ -270,9 +270,23 @@ __global__ __launch_bounds__(64) void k_cull(Queue qu, int n, const uint4* __res
 // keeps serving the gather passes.  The choice depends only on counts and
 // indices, never on the hash layout: the schedule is deterministic.  A tile
 // whose neighbour set overflows the table keeps its order with the identity
-// sets (64 per slot).  One wave per tile.
+// sets (64 per slot).
+//
+// One wave per tile.  The tile's distinct neighbours are collected in an LDS
+// hash table, compacted, and held in registers (lane l keeps entries l,
+// l + 64, ...), so a pick scans registers only.  Once no neighbour is wanted
+// by two free lanes, the greedy would give every free lane its smallest
+// wanted neighbour, in increasing order of index: those picks are made at
+// once (a minimum per lane through LDS, and ranks for the positions).
 constexpr int kSchedHash = 2048;
-static_assert(kSchedHash / kWave <= 32, "one 32-bit mask of live slots per lane");
+constexpr int kSchedRegs = kSchedHash / kWave;  // neighbours per lane at most
+constexpr uint32_t kSchedEmpty = 0xFFFFFFFFu;
+
+__device__ __forceinline__ unsigned long long readlane64(unsigned long long v, int l) {
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v)), l));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v >> 32)), l));
+    return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
 
 __global__ __launch_bounds__(64) void k_schedule(int n, const int32_t* __restrict__ cnt,
                                                  const int32_t* __restrict__ cntg,
@@ -292,7 +306,7 @@ __global__ __launch_bounds__(64) void k_schedule(int n, const int32_t* __restric
     const int64_t off = ell_off[w];
     const uint32_t self = uint32_t(valid ? s : w * kWave);
     for (int t = lane; t < kSchedHash; t += kWave) {
-        key[t] = 0xFFFFFFFFu;
+        key[t] = kSchedEmpty;
         gm[t] = 0;
         bm[t] = 0;
     }
@@ -303,8 +317,8 @@ __global__ __launch_bounds__(64) void k_schedule(int n, const int32_t* __restric
         uint32_t h = (j * 2654435761u) >> 21;
         int probe = 0;
         for (; probe < kSchedHash; ++probe) {
-            const uint32_t prev = atomicCAS(&key[h], 0xFFFFFFFFu, j);
-            if (prev == 0xFFFFFFFFu || prev == j) break;
+            const uint32_t prev = atomicCAS(&key[h], kSchedEmpty, j);
+            if (prev == kSchedEmpty || prev == j) break;
             h = (h + 1) & (kSchedHash - 1);
         }
         if (probe == kSchedHash) {
@@ -323,10 +337,38 @@ __global__ __launch_bounds__(64) void k_schedule(int n, const int32_t* __restric
         }
         return;
     }
-    // this lane's scan covers slots lane + 64 i; live[i] while some lane still needs the entry
-    uint32_t live = 0;
-    for (int i = 0; i < kSchedHash / kWave; ++i)
-        if (key[lane + kWave * i] != 0xFFFFFFFFu) live |= 1u << i;
+    // compact the distinct neighbours to the front of the table (in place: an
+    // entry never moves past a row that is still to be read)
+    int nd = 0;
+    for (int i = 0; i < kSchedRegs; ++i) {
+        const int t = lane + kWave * i;
+        const uint32_t kk = key[t];
+        const unsigned long long g = gm[t], b = bm[t];
+        const bool live = kk != kSchedEmpty;
+        const unsigned long long lb = __ballot(live);
+        const int pos = nd + __popcll(lb & ((1ull << lane) - 1ull));
+        __syncthreads();  // the whole row is read before any of it is overwritten
+        if (live) {
+            key[pos] = kk;
+            gm[pos] = g;
+            bm[pos] = b;
+        }
+        nd += __popcll(lb);
+    }
+    __syncthreads();
+    const int nk = (nd + kWave - 1) / kWave;
+    uint32_t K[kSchedRegs];
+    unsigned long long GM[kSchedRegs], BM[kSchedRegs];
+#pragma unroll
+    for (int i = 0; i < kSchedRegs; ++i) {
+        const int t = lane + kWave * i;
+        const bool ok = i < nk && t < nd;
+        K[i] = ok ? key[t] : kSchedEmpty;
+        GM[i] = ok ? gm[t] : 0ull;
+        BM[i] = ok ? bm[t] : 0ull;
+    }
+    __syncthreads();
+    uint32_t* tmin = key;  // the table is in registers now: its first words hold per-lane minima
     int remg = cg, remb = c - cg;
     const unsigned long long bit = 1ull << lane;
     for (int k = 0; k < len; ++k) {
@@ -336,47 +378,89 @@ __global__ __launch_bounds__(64) void k_schedule(int n, const int32_t* __restric
         int mypos = 0, m = 0;
         uint32_t first = 0;
         while (open != 0 && m < kWave) {
-            int bc = 0, bs = -1;
-            uint32_t bk = 0xFFFFFFFFu;
-            for (uint32_t lv = live; lv != 0; lv &= lv - 1) {
-                const int t = lane + kWave * __builtin_ctz(lv);
-                const uint32_t kk = key[t];
-                const int cv = __popcll(((gm[t] & gph) | (bm[t] & ~gph)) & open);
-                if (cv > bc || (cv == bc && cv > 0 && kk < bk)) {
+            // the neighbour wanted by the most free lanes (ties: smaller index)
+            int bc = 0;
+            uint32_t bk = kSchedEmpty;
+#pragma unroll
+            for (int i = 0; i < kSchedRegs; ++i) {
+                if (i >= nk) continue;
+                const int cv = __popcll(((GM[i] & gph) | (BM[i] & ~gph)) & open);
+                if (cv > bc || (cv == bc && K[i] < bk)) {
                     bc = cv;
-                    bk = kk;
-                    bs = t;
+                    bk = K[i];
                 }
             }
             for (int o = kWave / 2; o > 0; o >>= 1) {
                 const int oc = __shfl_xor(bc, o);
                 const uint32_t ok = uint32_t(__shfl_xor(int(bk), o));
-                const int os = __shfl_xor(bs, o);
                 if (oc > bc || (oc == bc && ok < bk)) {
                     bc = oc;
                     bk = ok;
-                    bs = os;
                 }
             }
             bc = __builtin_amdgcn_readfirstlane(bc);
-            if (bc == 0) break;
-            bs = __builtin_amdgcn_readfirstlane(bs);
             bk = uint32_t(__builtin_amdgcn_readfirstlane(int(bk)));
-            const unsigned long long take = ((gm[bs] & gph) | (bm[bs] & ~gph)) & open;
-            __syncthreads();  // every lane has read the masks before they change
+            if (bc == 0) break;
+            if (bc == 1) {
+                // every free lane takes its smallest wanted neighbour; the
+                // slot positions follow the neighbours' order
+                tmin[lane] = kSchedEmpty;
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < kSchedRegs; ++i) {
+                    if (i >= nk) continue;
+                    const unsigned long long want = ((GM[i] & gph) | (BM[i] & ~gph)) & open;
+                    if (want) atomicMin(&tmin[__builtin_ctzll(want)], K[i]);
+                }
+                __syncthreads();
+                const uint32_t mk = tmin[lane];
+                const bool taker = (open & bit) != 0;
+                int rank = 0;
+                for (int l = 0; l < kWave; ++l) rank += ((open >> l) & 1ull) && tmin[l] < mk;
+#pragma unroll
+                for (int i = 0; i < kSchedRegs; ++i) {
+                    if (i >= nk) continue;
+                    const unsigned long long want = ((GM[i] & gph) | (BM[i] & ~gph)) & open;
+                    if (want && tmin[__builtin_ctzll(want)] == K[i]) {
+                        GM[i] &= ~(want & gph);
+                        BM[i] &= ~(want & ~gph);
+                    }
+                }
+                if (taker) {
+                    mine = mk;
+                    mypos = m + rank;
+                    if (remg > 0) --remg;
+                    else --remb;
+                    srec[off + int64_t(k) * kWave + m + rank] = mk;
+                }
+                const unsigned long long r0 = __ballot(taker && rank == 0);
+                if (m == 0) first = uint32_t(__builtin_amdgcn_readlane(int(mk), __builtin_ctzll(r0)));
+                m += __popcll(open);
+                open = 0;
+                __syncthreads();  // tmin is read before the next slot clears it
+                break;
+            }
+            // its owner lane holds the masks: the lanes it goes to
+            unsigned long long take = 0;
+            bool owner = false;
+#pragma unroll
+            for (int i = 0; i < kSchedRegs; ++i) {
+                if (i >= nk) continue;
+                if (K[i] == bk) {
+                    owner = true;
+                    take = ((GM[i] & gph) | (BM[i] & ~gph)) & open;
+                    GM[i] &= ~(take & gph);
+                    BM[i] &= ~(take & ~gph);
+                }
+            }
+            take = readlane64(take, __builtin_ctzll(__ballot(owner)));
             if (take & bit) {
                 mine = bk;
                 mypos = m;
                 if (remg > 0) --remg;
                 else --remb;
             }
-            if (lane == 0) {
-                gm[bs] &= ~(take & gph);
-                bm[bs] &= ~(take & ~gph);
-                srec[off + int64_t(k) * kWave + m] = bk;
-            }
-            __syncthreads();
-            if ((bs & (kWave - 1)) == lane && gm[bs] == 0 && bm[bs] == 0) live &= ~(1u << (bs / kWave));
+            if (lane == 0) srec[off + int64_t(k) * kWave + m] = bk;
             if (m == 0) first = bk;
             open &= ~take;
             ++m;
