@@ -373,6 +373,23 @@ int crk_accel_energy_backward(crk_leaves* leaves, const crk_gas* gas, const void
                               hipStream_t stream);
 
 /*
+ * Adjoint of the viscous chain: volume -> corrections -> Extras (the velocity
+ * gradients dv, Sec. 5) -> forces with the artificial viscosity
+ * (crk_accel_energy_visc).  Same upstream adjoints and outputs as
+ * crk_accel_energy_backward (gx, gv, gu: dL/dx, dL/dv, dL/du in caller
+ * order), plus dv (the Extras pass's output the forward used, caller order,
+ * 9 per particle) and the viscosity constants of the forward.  The force
+ * adjoint also takes the viscosity's dependence on x, v, dv, rho and u; an
+ * Extras adjoint pass (timed as CRK_K_EXTRAS_ADJ) then carries dL/d dv to x,
+ * v, V and the corrections before the corrections, moments and volume
+ * adjoints.  corr.M (the forward's stored moment sums) is used when given.
+ */
+int crk_accel_energy_visc_backward(crk_leaves* leaves, const crk_gas* gas, const void* V, const void* rho,
+                                   const crk_corr* corr, const void* dv, const crk_visc* visc, double gamma,
+                                   const void* ga, const void* gdudt, crk_prec prec, void* gx, void* gv,
+                                   void* gu, hipStream_t stream);
+
+/*
  * Global time step (the paper's port reduces floating-point minima with atomic
  * fetch_min, Sec. 5.1): dt = min_i min(c_cfl 2h_i / (c_i + |v_i|),
  * c_acc sqrt(2h_i / |a_i|)), c_i = sqrt(gamma (gamma - 1) u_i), the second limit
@@ -455,7 +472,8 @@ enum {
     CRK_K_GRAVITY_ADJ = 10, /* short-range gravity adjoint */
     CRK_K_EXTRAS = 11,      /* Extras pass (CRK density, gradients of v and u) */
     CRK_K_ACCEL_VISC = 12,  /* acceleration/energy pair kernel with the artificial viscosity */
-    CRK_K_COUNT = 13
+    CRK_K_EXTRAS_ADJ = 13,  /* Extras adjoint pair kernel (viscous backward) */
+    CRK_K_COUNT = 14
 };
 int crk_timing(crk_leaves* leaves, int enable);
 int crk_kernel_times(crk_leaves* leaves, double* ms, int64_t* launches);

@@ -32,11 +32,12 @@ EXPORTS = ("crk_build_leaf_pairs", "crk_build_leaf_pairs_device", "crk_volume", 
            "crk_accel_energy", "crk_accel_energy_noalloc", "crk_extras", "crk_accel_energy_visc",
            "crk_accel_energy_compatible", "sr_gravity",
            "sr_gravity_backward", "sr_gravity_fit_poly", "crk_timestep", "crk_kick_drift",
-           "crk_queue_visits", "crk_accel_energy_backward", "crk_leaves_stats", "crk_leaves_perm",
+           "crk_queue_visits", "crk_accel_energy_backward", "crk_accel_energy_visc_backward",
+           "crk_leaves_stats", "crk_leaves_perm",
            "crk_get_tuning", "crk_set_tuning",
            "crk_timing", "crk_kernel_times", "crk_leaves_free", "crk_last_error")
 KERNEL_KINDS = ("cull", "volume", "moments", "accel", "gravity", "pack", "accel_adj",
-                "moments_adj", "volume_adj", "solve_adj", "gravity_adj", "extras", "accel_visc")
+                "moments_adj", "volume_adj", "solve_adj", "gravity_adj", "extras", "accel_visc", "extras_adj")
 
 
 class CrkError(RuntimeError):
@@ -114,6 +115,8 @@ def load_library(path=None):
                                                 ctypes.POINTER(Visc), D, D, I, P, P, P, P]
     lib.crk_accel_energy_backward.argtypes = [P, ctypes.POINTER(_Gas), P, P, ctypes.POINTER(_Corr), D,
                                               P, P, I, P, P, P, P]
+    lib.crk_accel_energy_visc_backward.argtypes = [P, ctypes.POINTER(_Gas), P, P, ctypes.POINTER(_Corr), P,
+                                                   ctypes.POINTER(Visc), D, P, P, I, P, P, P, P]
     lib.crk_leaves_stats.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
     lib.crk_leaves_perm.argtypes = [P, P, P]
     lib.crk_queue_visits.argtypes = [P, P, P]
@@ -461,6 +464,28 @@ def crk_accel_energy_compatible(leaves, gas, V, rho, corr, eps_u=0.1, dv=None, v
                                                       float(gamma), _PREC[prec], _ptr(a), _ptr(du), _ptr(tot),
                                                       _stream()))
     return a, du, tot
+
+
+def crk_accel_energy_visc_backward(leaves, gas, V, rho, corr, dv, ga, gdudt, gamma=5.0 / 3.0, prec="f32",
+                                   **visc):
+    """dL/dx [n,3], dL/dv [n,3], dL/du [n] through the viscous chain (volume,
+    corrections, Extras' velocity gradients dv, viscous forces) from
+    ga = dL/da and gdudt = dL/d(du/dt); corr as for crk_accel_energy_backward."""
+    g = _gas(gas, prec, ("vx", "vy", "vz", "u", "h", "m"))
+    dt, dev = _DTYPE[prec], gas["x"].device
+    for t in (V, rho, *corr[:4], dv, ga, gdudt):
+        _dev(t, dt)
+    c = _corr(corr)
+    q = Visc(**{**VISC_DEFAULT, **visc})
+    gx = torch.empty(g.n, 3, dtype=dt, device=dev)
+    gv = torch.empty(g.n, 3, dtype=dt, device=dev)
+    gu = torch.empty(g.n, dtype=dt, device=dev)
+    _check("crk_accel_energy_visc_backward",
+           load_library().crk_accel_energy_visc_backward(leaves.handle, ctypes.byref(g), _ptr(V), _ptr(rho),
+                                                         ctypes.byref(c), _ptr(dv), ctypes.byref(q), float(gamma),
+                                                         _ptr(ga), _ptr(gdudt), _PREC[prec], _ptr(gx), _ptr(gv),
+                                                         _ptr(gu), _stream()))
+    return gx, gv, gu
 
 
 def forward_visc(leaves, gas, gamma=5.0 / 3.0, prec="f32", **visc):

@@ -44,6 +44,38 @@ template <class R> struct alignas(128) RecBwd {
 static_assert(sizeof(RecBwd<float>) == 128, "f32 backward record is one line");
 static_assert(sizeof(RecBwd<double>) == 256, "f64 backward record is two lines");
 
+// The backward record with what the artificial viscosity needs (box units):
+// the velocity gradient dv[3a + c] = d_c v^a, h, the density and the sound speed.
+template <class R> struct alignas(16) RecBwdV {
+    uint32_t q[3];
+    R invH;
+    R V, P, A, dubar;
+    R cW, cF, cF2;
+    R B[3], dA[3], dB[9], v[3];
+    R abar[3];
+    R dv[9];
+    R h, rho, cs;
+};
+static_assert(sizeof(RecBwdV<float>) % 16 == 0 && sizeof(RecBwdV<double>) % 16 == 0, "whole 16-byte chunks");
+
+// Record of the extras adjoint: a particle's corrections, volume, velocity and
+// the adjoint of its velocity gradient dvb[3a + c] = dL/d(d_c v^a).
+template <class R> struct alignas(16) RecExA {
+    uint32_t q[3];
+    R invH;
+    R V, A, cW, cF, cF2;
+    R B[3], dA[3], dB[9], v[3];
+    R dvb[9];
+};
+static_assert(sizeof(RecExA<float>) % 16 == 0 && sizeof(RecExA<double>) % 16 == 0, "whole 16-byte chunks");
+static_assert(sizeof(RecExA<float>) <= sizeof(RecBwdV<float>) && sizeof(RecExA<double>) <= sizeof(RecBwdV<double>),
+              "the extras adjoint's records reuse the force adjoint's");
+
+// viscosity constants of a backward launch
+template <class R> struct ViscB {
+    R Cl, Cq, eps_q, g1;  // g1 = gamma (gamma - 1) / 2: d c / d u = g1 / c
+};
+
 // Wendland C4 shapes and the Hessian factor: W = cW w, grad W = cF f x,
 // grad (cF f) = cF2 f2 x.
 template <class R> __device__ __forceinline__ void shapes(R q, R& w, R& f, R& f2) {
@@ -64,7 +96,7 @@ template <class R> struct Side {
     R lin, t[3];
 };
 
-template <class R> __device__ __forceinline__ Side<R> side_terms(const RecBwd<R>& r, const R y[3]) {
+template <class R, class Rec> __device__ __forceinline__ Side<R> side_terms(const Rec& r, const R y[3]) {
     Side<R> s;
     s.lin = R(1) + r.B[0] * y[0] + r.B[1] * y[1] + r.B[2] * y[2];
 #pragma unroll
@@ -72,8 +104,8 @@ template <class R> __device__ __forceinline__ Side<R> side_terms(const RecBwd<R>
     return s;
 }
 
-template <class R>
-__device__ __forceinline__ void corr_grad(const RecBwd<R>& r, const Side<R>& s, R W, R F, const R y[3], R G[3]) {
+template <class R, class Rec>
+__device__ __forceinline__ void corr_grad(const Rec& r, const Side<R>& s, R W, R F, const R y[3], R G[3]) {
     const R LW = s.lin * W, AW = r.A * W, K = r.A * s.lin * F;
 #pragma unroll
     for (int c = 0; c < 3; ++c) G[c] = LW * r.dA[c] + AW * s.t[c] + K * y[c];
@@ -85,8 +117,8 @@ template <class R> struct Dots {
     R al, be, ga;
 };
 
-template <class R>
-__device__ __forceinline__ Dots<R> side_dots(const RecBwd<R>& r, const Side<R>& s, const R y[3], const R g[3]) {
+template <class R, class Rec>
+__device__ __forceinline__ Dots<R> side_dots(const Rec& r, const Side<R>& s, const R y[3], const R g[3]) {
     return Dots<R>{g[0] * r.dA[0] + g[1] * r.dA[1] + g[2] * r.dA[2],
                    g[0] * s.t[0] + g[1] * s.t[1] + g[2] * s.t[2],
                    g[0] * y[0] + g[1] * y[1] + g[2] * y[2]};
@@ -95,8 +127,8 @@ __device__ __forceinline__ Dots<R> side_dots(const RecBwd<R>& r, const Side<R>& 
 // out += (dG/dy)^T g, i.e. per component e
 //   W (al B^e + A (dB g)^e) + y^e (F (al lin + A be) + A lin F2 ga) + A F (ga B^e + lin g^e)
 // (F2: the gradient factor of F, grad F = F2 y).
-template <class R>
-__device__ __forceinline__ void corr_grad_dy(const RecBwd<R>& r, const Side<R>& s, const Dots<R>& d, R W, R F,
+template <class R, class Rec>
+__device__ __forceinline__ void corr_grad_dy(const Rec& r, const Side<R>& s, const Dots<R>& d, R W, R F,
                                              R F2, const R y[3], const R g[3], R out[3]) {
     const R AW = r.A * W, AF = r.A * F;
     const R KB = d.al * W + AF * d.ga;                                    // coefficient of B^e
@@ -112,8 +144,8 @@ __device__ __forceinline__ void corr_grad_dy(const RecBwd<R>& r, const Side<R>& 
 // adjoint of G with respect to (A, B, dA, dB), given g = Gbar:
 //   A: be W + lin F ga,  B^e: y^e (al W + A F ga) + A W g^e,
 //   dA^d: lin W g^d,  dB[a][d]: A W y^a g^d
-template <class R, class Acc>
-__device__ __forceinline__ void corr_grad_dC(const RecBwd<R>& r, const Side<R>& s, const Dots<R>& d, R W, R F,
+template <class R, class Rec, class Acc>
+__device__ __forceinline__ void corr_grad_dC(const Rec& r, const Side<R>& s, const Dots<R>& d, R W, R F,
                                              const R y[3], const R g[3], Acc& acc) {
     const R AW = r.A * W, LW = s.lin * W;
     const R KB = d.al * W + r.A * F * d.ga;
@@ -130,16 +162,18 @@ __device__ __forceinline__ void corr_grad_dC(const RecBwd<R>& r, const Side<R>& 
     }
 }
 
-template <class R>
+// Record of particle i (tree position s).  Viscous records (RecBwdV) also get
+// dv, h, rho and the sound speed c = sqrt(gamma (gamma - 1) u).
+template <class R, class Rec>
 __global__ void k_pack_bwd(int n, const int32_t* perm, const uint4* quant, const R* h, const R* u,
                            const R* vx, const R* vy, const R* vz, const R* m, const R* V,
                            const R* rho, const R* A, const R* B, const R* dA, const R* dB,
-                           const R* ga, const R* gdu, R gm1, RecBwd<R>* rec, R* aux) {
-    __shared__ uint4 buf[256 * (sizeof(RecBwd<R>) / 16)];
+                           const R* ga, const R* gdu, R gm1, const R* dv, Rec* rec, R* aux) {
+    __shared__ uint4 buf[256 * (sizeof(Rec) / 16)];
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = s < n;
     const int i = valid ? perm[s] : 0;
-    RecBwd<R> r;
+    Rec r;
     const uint4 q = quant[valid ? s : 0];
     r.q[0] = q.x; r.q[1] = q.y; r.q[2] = q.z;
     const R H = R(2) * h[i];
@@ -161,6 +195,12 @@ __global__ void k_pack_bwd(int n, const int32_t* perm, const uint4* quant, const
     }
     for (int k = 0; k < 9; ++k) r.dB[k] = dB[9 * i + k];
     r.v[0] = vx[i]; r.v[1] = vy[i]; r.v[2] = vz[i];
+    if constexpr (sizeof(Rec) != sizeof(RecBwd<R>)) {
+        for (int k = 0; k < 9; ++k) r.dv[k] = dv[9 * i + k];
+        r.h = h[i];
+        r.rho = rho[i];
+        r.cs = sqrt((gm1 + R(1)) * gm1 * u[i]);
+    }
     const int first = blockIdx.x * blockDim.x;
     store_records(rec, r, valid, first, min(int(blockDim.x), n - first), buf);
     if (valid) {
@@ -169,29 +209,113 @@ __global__ void k_pack_bwd(int n, const int32_t* perm, const uint4* quant, const
     }
 }
 
-// 1. force adjoint
-template <class R, bool kOff32>
+// Artificial viscosity of a pair (box units, x = x_i - x_j) and the pieces its
+// adjoint reuses: D_k = dv_k x, s_k = x.D_k, the van Leer limiter Phi, the
+// reconstructed velocity difference w and mu_k = min(0, h_k (w.x) / den_k),
+// den_k = r^2 + eps_q h_k^2; Q = sum_k rho_k (-C_l c_k mu_k + C_q mu_k^2).
+template <class R> struct ViscPair {
+    R Di[3], Dj[3], si, sj, phi, w[3], wx, deni, denj, mi, mj, Q;
+};
+
+template <class R, class Rec>
+__device__ __forceinline__ ViscPair<R> visc_pair(const Rec& ri, const Rec& rj, const R x[3], R r2,
+                                                 const ViscB<R>& vq) {
+    ViscPair<R> p;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        p.Di[a] = ri.dv[3 * a] * x[0] + ri.dv[3 * a + 1] * x[1] + ri.dv[3 * a + 2] * x[2];
+        p.Dj[a] = rj.dv[3 * a] * x[0] + rj.dv[3 * a + 1] * x[1] + rj.dv[3 * a + 2] * x[2];
+    }
+    p.si = x[0] * p.Di[0] + x[1] * p.Di[1] + x[2] * p.Di[2];
+    p.sj = x[0] * p.Dj[0] + x[1] * p.Dj[1] + x[2] * p.Dj[2];
+    const R sp = p.si * p.sj, ss = p.si + p.sj;
+    p.phi = sp > R(0) ? R(4) * sp / (ss * ss) : R(0);
+    p.wx = R(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        p.w[a] = (ri.v[a] - rj.v[a]) - R(0.5) * p.phi * (p.Di[a] + p.Dj[a]);
+        p.wx += p.w[a] * x[a];
+    }
+    p.deni = r2 + vq.eps_q * ri.h * ri.h;
+    p.denj = r2 + vq.eps_q * rj.h * rj.h;
+    p.mi = fmin(R(0), ri.h * p.wx / p.deni);
+    p.mj = fmin(R(0), rj.h * p.wx / p.denj);
+    p.Q = ri.rho * p.mi * (vq.Cq * p.mi - vq.Cl * ri.cs) + rj.rho * p.mj * (vq.Cq * p.mj - vq.Cl * rj.cs);
+    return p;
+}
+
+// Reverse of visc_pair for the lane's own inputs, given Qb = dL/dQ: adds to
+// xb (dL/dx_i), vb (dL/dv_i), dvb (dL/d dv_i), and returns dL/drho_i, dL/du_i.
+template <class R, class Rec>
+__device__ __forceinline__ void visc_pair_adj(const Rec& ri, const Rec& rj, const R x[3], const ViscPair<R>& p,
+                                              const ViscB<R>& vq, R Qb, R xb[3], R vb[3], R dvb[9], R& rhob,
+                                              R& ub) {
+    const R mbi = p.mi < R(0) ? Qb * ri.rho * (R(2) * vq.Cq * p.mi - vq.Cl * ri.cs) : R(0);
+    const R mbj = p.mj < R(0) ? Qb * rj.rho * (R(2) * vq.Cq * p.mj - vq.Cl * rj.cs) : R(0);
+    rhob = Qb * p.mi * (vq.Cq * p.mi - vq.Cl * ri.cs);
+    ub = ri.cs > R(0) ? -Qb * ri.rho * vq.Cl * p.mi * vq.g1 / ri.cs : R(0);
+    const R wxb = mbi * ri.h / p.deni + mbj * rj.h / p.denj;
+    const R r2b = -(mbi * p.mi / p.deni + mbj * p.mj / p.denj);
+    R phib = R(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const R wb = wxb * x[a];
+        vb[a] += wb;
+        xb[a] += wxb * p.w[a] + R(2) * r2b * x[a];
+        phib -= R(0.5) * wb * (p.Di[a] + p.Dj[a]);
+    }
+    const R sp = p.si * p.sj, ss = p.si + p.sj;
+    R sbi = R(0), sbj = R(0);
+    if (sp > R(0)) {
+        const R k = R(4) * phib / (ss * ss * ss);
+        sbi = k * p.sj * (p.sj - p.si);
+        sbj = k * p.si * (p.si - p.sj);
+    }
+    R Dbi[3], Dbj[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const R Db = -R(0.5) * p.phi * wxb * x[a];
+        Dbi[a] = Db + sbi * x[a];
+        Dbj[a] = Db + sbj * x[a];
+        xb[a] += sbi * p.Di[a] + sbj * p.Dj[a];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        xb[c] += Dbi[0] * ri.dv[c] + Dbi[1] * ri.dv[3 + c] + Dbi[2] * ri.dv[6 + c] + Dbj[0] * rj.dv[c] +
+                 Dbj[1] * rj.dv[3 + c] + Dbj[2] * rj.dv[6 + c];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dvb[3 * a + c] += Dbi[a] * x[c];
+    }
+}
+
+// 1. force adjoint (kVisc: with the artificial viscosity, whose Q joins
+// P_i + P_j; its adjoint also gives dL/d dv_i (dvbar) and dL/drho_i, dL/du_i
+// through Q (qbar), all in tree order)
+template <class R, bool kOff32, bool kVisc = false, class Rec = RecBwd<R>>
 __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
-                                                   const RecBwd<R>* __restrict__ rec, int chunk,
+                                                   const Rec* __restrict__ rec, int chunk,
                                                    R* __restrict__ cbar, R* __restrict__ vpbar,
-                                                   R* __restrict__ xbar, R* __restrict__ gv) {
-    constexpr int kStage = stage_stride<RecBwd<R>>();
+                                                   R* __restrict__ xbar, R* __restrict__ gv, ViscB<R> vq = {},
+                                                   R* __restrict__ dvbar = nullptr, R* __restrict__ qbar = nullptr) {
+    constexpr int kStage = stage_stride<Rec>();
     extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
     const int lane = lane_id();
     QState qs;
     for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
         const int s = w * kWave + lane;
         const bool valid = s < n;
-        const RecBwd<R> ri = rec[valid ? s : 0];
+        const Rec ri = rec[valid ? s : 0];
         const int cnt = valid ? L.cnt[s] : 0;
         const int len = L.len[w];
         ChunkSums<R, 16> cb;  // A, B[3], dA[3], dB[9]
         ChunkSums<R, 8> ob;   // Vbar, Pbar, xbar[3], vbar[3]
+        ChunkSums<R, kVisc ? 11 : 1> qb;  // dvbar[9], rhobar, ubar (through Q)
         cb.zero();
         ob.zero();
-        staged_list<RecBwd<R>, kOff32, false>(  // measured faster with fixed LDS addresses
+        qb.zero();
+        staged_list<Rec, kOff32, false>(  // measured faster with fixed LDS addresses
             L, w, cnt, len, rec, stage_buf + wave_in_block() * kStage,
-            [&](const RecBwd<R>& rj, int k) __attribute__((always_inline)) {
+            [&](const Rec& rj, int k) __attribute__((always_inline)) {
                 const R x[3] = {sep<R>(ri.q[0], rj.q[0]), sep<R>(ri.q[1], rj.q[1]), sep<R>(ri.q[2], rj.q[2])};
                 const R y[3] = {-x[0], -x[1], -x[2]};
                 const R r = dsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
@@ -205,7 +329,10 @@ __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, con
                 corr_grad(ri, si, Wi, Fi, x, Gi);
                 corr_grad(rj, sj, Wj, Fj, y, Gj);
                 const R D[3] = {Gi[0] - Gj[0], Gi[1] - Gj[1], Gi[2] - Gj[2]};
-                const R VV = ri.V * rj.V, PP = ri.P + rj.P;
+                const R VV = ri.V * rj.V;
+                ViscPair<R> vp{};
+                if constexpr (kVisc) vp = visc_pair(ri, rj, x, x[0] * x[0] + x[1] * x[1] + x[2] * x[2], vq);
+                const R PP = kVisc ? (ri.P + rj.P) + vp.Q : ri.P + rj.P;
                 const R coef = R(-0.5) * (VV * PP);
                 const R kap = ri.dubar + rj.dubar;
                 R Fb[3], s_ = R(0);
@@ -222,6 +349,20 @@ __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, con
                 const Dots<R> di = side_dots(ri, si, x, g), dj = side_dots(rj, sj, y, g);
                 corr_grad_dC(ri, si, di, Wi, Fi, x, g, cb);
                 R xb[3] = {R(0), R(0), R(0)};
+                if constexpr (kVisc) {
+                    // Q enters like P_i + P_j: dL/dQ = dL/dP_i of this pair
+                    R vb[3] = {R(0), R(0), R(0)}, dvb[9], rhob, ub;
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) dvb[e] = R(0);
+                    visc_pair_adj(ri, rj, x, vp, vq, R(-0.5) * VV * s_, xb, vb, dvb, rhob, ub);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) ob.add(5 + c, vb[c]);
+#pragma unroll
+                    for (int e = 0; e < 9; ++e) qb.add(e, dvb[e]);
+                    qb.add(9, rhob);
+                    qb.add(10, ub);
+                    qb.next(k, chunk);
+                }
                 corr_grad_dy(ri, si, di, Wi, Fi, F2i, x, g, xb);
                 corr_grad_dy(rj, sj, dj, Wj, Fj, F2j, y, g, xb);
 #pragma unroll
@@ -231,8 +372,15 @@ __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, con
             });
         cb.fold();
         ob.fold();
+        qb.fold();
         if (valid) {
             const int i = perm[s];
+            if constexpr (kVisc) {
+#pragma unroll
+                for (int e = 0; e < 9; ++e) dvbar[9 * s + e] = qb.get(e);
+                qbar[2 * s] = qb.get(9);
+                qbar[2 * s + 1] = qb.get(10);
+            }
 #pragma unroll
             for (int e = 0; e < 16; ++e) cbar[16 * s + e] = cb.get(e);
             vpbar[2 * s] = ob.get(0);
@@ -559,7 +707,7 @@ __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, c
                                                      const R* __restrict__ vpbar, const R* __restrict__ m,
                                                      const R* __restrict__ u, const R* __restrict__ rho, R gm1,
                                                      int chunk, R* __restrict__ xbar, RecVA<R>* __restrict__ varec,
-                                                     R* __restrict__ gu) {
+                                                     R* __restrict__ gu, const R* __restrict__ qbar = nullptr) {
     constexpr int kStage = stage_stride<RecMom<R>>();
     extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
     const int lane = lane_id();
@@ -603,16 +751,138 @@ __global__ __launch_bounds__(256) void k_moments_adj(Queue qu, int n, Lists L, c
             // j = i term of the own moments: V_i phi(0) = V_i W(0) P0
             const double Vbar = double(acc.get(0)) + double(ri.c[0]) + double(vpbar[2 * s]);
             const double Pbar = double(vpbar[2 * s + 1]);
-            const double rhobar = double(gm1) * double(u[i]) * Pbar;
+            // qbar: dL/drho and dL/du through the viscosity (tree order)
+            const double rhobar = double(gm1) * double(u[i]) * Pbar + (qbar ? double(qbar[2 * s]) : 0.0);
             const double Sbar = -Vbar * double(Vi) * double(Vi) + double(m[i]) * rhobar;
             RecVA<R> va{};
             va.q[0] = ri.q[0]; va.q[1] = ri.q[1]; va.q[2] = ri.q[2];
             va.invH = invHi;
             va.Sbar = R(Sbar);
             varec[s] = va;
-            gu[i] = R(double(gm1) * double(rho[i]) * Pbar);
+            gu[i] = R(double(gm1) * double(rho[i]) * Pbar + (qbar ? double(qbar[2 * s + 1]) : 0.0));
 #pragma unroll
             for (int c = 0; c < 3; ++c) xbar[4 * s + c] += acc.get(1 + c);
+        }
+    }
+}
+
+// Extras adjoint (viscous chain).  The velocity gradients
+//   dv_k[a][c] = sum_{j != k, r < H_k} V_j (v_j^a - v_k^a) G_kj^c
+// (G_kj the corrected kernel gradient of particle k at x_kj) enter the force
+// pass; given their adjoints dvb, each lane gathers the adjoints of its own
+// particle's inputs from its own sum (through G_ij: corrections and x_i; and
+// -v_i) and from every neighbour's sum that contains it (V_i, v_i, and x_i
+// through G_ji).  Beyond a support W, F and F2 vanish, so every pair of the
+// force list is taken whole.  Adds to cbar, vpbar (Vbar), xbar (tree order)
+// and gv (caller order).
+template <class R>
+__global__ void k_pack_exa(int n, const int32_t* perm, const uint4* quant, const R* h, const R* vx, const R* vy,
+                           const R* vz, const R* V, const R* A, const R* B, const R* dA, const R* dB,
+                           const R* dvbar, RecExA<R>* rec) {
+    __shared__ uint4 buf[256 * (sizeof(RecExA<R>) / 16)];
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = s < n;
+    const int i = valid ? perm[s] : 0;
+    const int sv = valid ? s : 0;
+    RecExA<R> r;
+    const uint4 q = quant[sv];
+    r.q[0] = q.x; r.q[1] = q.y; r.q[2] = q.z;
+    const R H = R(2) * h[i];
+    const R invH = R(1) / H;
+    r.invH = invH;
+    r.V = V[i];
+    r.A = A[i];
+    r.cW = norm_W(H);
+    r.cF = norm_F(H);
+    const R i2 = invH * invH;
+    r.cF2 = R(17325.0 / (2.0 * kPi)) * i2 * i2 * i2 * invH;
+    for (int a = 0; a < 3; ++a) {
+        r.B[a] = B[3 * i + a];
+        r.dA[a] = dA[3 * i + a];
+    }
+    for (int k = 0; k < 9; ++k) {
+        r.dB[k] = dB[9 * i + k];
+        r.dvb[k] = dvbar[9 * sv + k];
+    }
+    r.v[0] = vx[i]; r.v[1] = vy[i]; r.v[2] = vz[i];
+    const int first = blockIdx.x * blockDim.x;
+    store_records(rec, r, valid, first, min(int(blockDim.x), n - first), buf);
+}
+
+template <class R, bool kOff32>
+__global__ __launch_bounds__(256) void k_extras_adj(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
+                                                    const RecExA<R>* __restrict__ rec, int chunk,
+                                                    R* __restrict__ cbar, R* __restrict__ vpbar,
+                                                    R* __restrict__ xbar, R* __restrict__ gv) {
+    constexpr int kStage = stage_stride<RecExA<R>>();
+    extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
+    const int lane = lane_id();
+    QState qs;
+    for (int w = queue_start(qu, qs); w >= 0; w = queue_next(qu, qs)) {
+        const int s = w * kWave + lane;
+        const bool valid = s < n;
+        const RecExA<R> ri = rec[valid ? s : 0];
+        const int cnt = valid ? L.cnt[s] : 0;
+        const int len = L.len[w];
+        ChunkSums<R, 16> cb;  // A, B[3], dA[3], dB[9]
+        ChunkSums<R, 7> ob;   // Vbar, xbar[3], vbar[3]
+        cb.zero();
+        ob.zero();
+        staged_list<RecExA<R>, kOff32, false>(
+            L, w, cnt, len, rec, stage_buf + wave_in_block() * kStage,
+            [&](const RecExA<R>& rj, int k) __attribute__((always_inline)) {
+                const R x[3] = {sep<R>(ri.q[0], rj.q[0]), sep<R>(ri.q[1], rj.q[1]), sep<R>(ri.q[2], rj.q[2])};
+                const R y[3] = {-x[0], -x[1], -x[2]};
+                const R r = dsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+                R wi, fi, f2i, wj, fj, f2j;
+                shapes(r * ri.invH, wi, fi, f2i);
+                shapes(r * rj.invH, wj, fj, f2j);
+                const R Wi = ri.cW * wi, Fi = ri.cF * fi, F2i = ri.cF2 * f2i;
+                const R Wj = rj.cW * wj, Fj = rj.cF * fj, F2j = rj.cF2 * f2j;
+                const Side<R> si = side_terms(ri, x), sj = side_terms(rj, y);
+                R Gi[3], Gj[3];
+                corr_grad(ri, si, Wi, Fi, x, Gi);
+                corr_grad(rj, sj, Wj, Fj, y, Gj);
+                // own sum: V_j (v_j - v_i) (x) G_ij
+                R g[3], gp[3], e[3], Vb = R(0);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) e[a] = ri.v[a] - rj.v[a];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    g[c] = -rj.V * (ri.dvb[c] * e[0] + ri.dvb[3 + c] * e[1] + ri.dvb[6 + c] * e[2]);
+                    // the neighbour's sum: V_i (v_i - v_j) (x) G_ji, through x_ji = -x
+                    gp[c] = -ri.V * (rj.dvb[c] * e[0] + rj.dvb[3 + c] * e[1] + rj.dvb[6 + c] * e[2]);
+                }
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const R ti = ri.dvb[3 * a] * Gi[0] + ri.dvb[3 * a + 1] * Gi[1] + ri.dvb[3 * a + 2] * Gi[2];
+                    const R tj = rj.dvb[3 * a] * Gj[0] + rj.dvb[3 * a + 1] * Gj[1] + rj.dvb[3 * a + 2] * Gj[2];
+                    ob.add(4 + a, ri.V * tj - rj.V * ti);  // vbar_i
+                    Vb += e[a] * tj;
+                }
+                ob.add(0, Vb);
+                const Dots<R> di = side_dots(ri, si, x, g), dj = side_dots(rj, sj, y, gp);
+                corr_grad_dC(ri, si, di, Wi, Fi, x, g, cb);
+                R xb[3] = {R(0), R(0), R(0)};
+                corr_grad_dy(ri, si, di, Wi, Fi, F2i, x, g, xb);
+                corr_grad_dy(rj, sj, dj, Wj, Fj, F2j, y, gp, xb);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) ob.add(1 + c, xb[c]);
+                cb.next(k, chunk);
+                ob.next(k, chunk);
+            });
+        cb.fold();
+        ob.fold();
+        if (valid) {
+            const int i = perm[s];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) cbar[16 * s + e] += cb.get(e);
+            vpbar[2 * s] += ob.get(0);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                xbar[4 * s + c] += ob.get(1 + c);
+                gv[3 * i + c] += ob.get(4 + c);
+            }
         }
     }
 }
@@ -671,22 +941,33 @@ template <class T> T* carve(char*& p, size_t count) {
 }
 
 // scratch of one backward call: records and per-particle partial adjoints
-template <class R> size_t scratch_bytes(int64_t n) {
-    const size_t per = sizeof(RecBwd<R>) + sizeof(RecMom<R>) + sizeof(RecQV<R>) + sizeof(RecVA<R>) +
-                       sizeof(R) * (16 + 2 + 4 + 2);
-    return per * size_t(n) + 8 * 256;  // eight arrays, each on a 256-byte boundary
+// (visc: the larger force-adjoint records, reused by the extras adjoint, and
+// the adjoints of the velocity gradients, rho and u through the viscosity)
+template <class R> size_t scratch_bytes(int64_t n, bool visc) {
+    const size_t per = (visc ? sizeof(RecBwdV<R>) : sizeof(RecBwd<R>)) + sizeof(RecMom<R>) + sizeof(RecQV<R>) +
+                       sizeof(RecVA<R>) + sizeof(R) * (16 + 2 + 4 + 2 + (visc ? 9 + 2 : 0));
+    return per * size_t(n) + 10 * 256;  // ten arrays, each on a 256-byte boundary
 }
 
+// dv, q: the viscous chain (velocity gradients from the Extras pass and the
+// viscosity constants), else nullptr
 template <class R>
 int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, const crk_corr* C,
-                  double gamma, const R* ga, const R* gdu, R* gx, R* gv, R* gu, hipStream_t st) {
+                  double gamma, const R* ga, const R* gdu, R* gx, R* gv, R* gu, hipStream_t st,
+                  const R* dv = nullptr, const crk_visc* q_visc = nullptr) {
     const int n = int(L->n);
+    const bool visc = dv != nullptr;
     int rc = pack_positions<R>(L, g->x, g->y, g->z, static_cast<const R*>(g->h), st);
     if (rc) return rc;
     void* sp = nullptr;
-    if ((rc = pass_scratch(L, scratch_bytes<R>(n), &sp))) return rc;
+    if ((rc = pass_scratch(L, scratch_bytes<R>(n, visc), &sp))) return rc;
     char* p = static_cast<char*>(sp);
-    RecBwd<R>* rec = carve<RecBwd<R>>(p, n);
+    // the force adjoint's records; the extras adjoint's (viscous chain) reuse them
+    void* rec_any = visc ? static_cast<void*>(carve<RecBwdV<R>>(p, n)) : static_cast<void*>(carve<RecBwd<R>>(p, n));
+    RecBwd<R>* rec = static_cast<RecBwd<R>*>(rec_any);
+    RecBwdV<R>* recv = static_cast<RecBwdV<R>*>(rec_any);
+    R* dvbar = visc ? carve<R>(p, 9 * size_t(n)) : nullptr;
+    R* qbar = visc ? carve<R>(p, 2 * size_t(n)) : nullptr;
     R* aux = carve<R>(p, 2 * size_t(n));
     RecQV<R>* qv = carve<RecQV<R>>(p, n);
     R* cbar = carve<R>(p, 16 * size_t(n));
@@ -697,13 +978,18 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
     const R gm1 = R(gamma - 1.0);
     {
         TimeScope tp(L, st, CRK_K_PACK);
-        hipLaunchKernelGGL(k_pack_bwd<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, L->quant,
-                           static_cast<const R*>(g->h), static_cast<const R*>(g->u),
-                           static_cast<const R*>(g->vx), static_cast<const R*>(g->vy),
-                           static_cast<const R*>(g->vz), static_cast<const R*>(g->m), V, rho,
-                           static_cast<const R*>(C->A), static_cast<const R*>(C->B),
-                           static_cast<const R*>(C->dA), static_cast<const R*>(C->dB), ga, gdu, gm1,
-                           rec, aux);
+        const R *h = static_cast<const R*>(g->h), *u = static_cast<const R*>(g->u);
+        const R *vx = static_cast<const R*>(g->vx), *vy = static_cast<const R*>(g->vy),
+                *vz = static_cast<const R*>(g->vz), *m = static_cast<const R*>(g->m);
+        const R *A = static_cast<const R*>(C->A), *B = static_cast<const R*>(C->B),
+                *dA = static_cast<const R*>(C->dA), *dB = static_cast<const R*>(C->dB);
+        if (visc)
+            hipLaunchKernelGGL((k_pack_bwd<R, RecBwdV<R>>), dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm,
+                               L->quant, h, u, vx, vy, vz, m, V, rho, A, B, dA, dB, ga, gdu, gm1, dv, recv, aux);
+        else
+            hipLaunchKernelGGL((k_pack_bwd<R, RecBwd<R>>), dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm,
+                               L->quant, h, u, vx, vy, vz, m, V, rho, A, B, dA, dB, ga, gdu, gm1,
+                               static_cast<const R*>(nullptr), rec, aux);
         hipLaunchKernelGGL(k_pack_qv<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, L->quant, V, qv);
     }
     LAUNCH_CHECK("pack backward");
@@ -711,13 +997,40 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
     const dim3 grid(grid_nwave(L)), block(kWave * bw);
     const Queue q = make_queue(L, L->order_pair);
     reset_queue(L, st);
-    {
+    if (!visc) {
         TimeScope ts(L, st, CRK_K_ACCEL_ADJ);
         auto kern = off32<RecBwd<R>>(L) ? k_accel_adj<R, true> : k_accel_adj<R, false>;
         hipLaunchKernelGGL(kern, grid, block, stage_bytes<RecBwd<R>>(bw), st, q, n, lists(L),
-                           L->perm, rec, L->tune.kahan_chunk, cbar, vpbar, xbar, gv);
+                           L->perm, rec, L->tune.kahan_chunk, cbar, vpbar, xbar, gv, ViscB<R>{},
+                           static_cast<R*>(nullptr), static_cast<R*>(nullptr));
+    } else {
+        TimeScope ts(L, st, CRK_K_ACCEL_ADJ);
+        const ViscB<R> vq{R(q_visc->Cl), R(q_visc->Cq), R(q_visc->eps_q), R(0.5 * gamma * (gamma - 1.0))};
+        auto kern = off32<RecBwdV<R>>(L) ? k_accel_adj<R, true, true, RecBwdV<R>>
+                                         : k_accel_adj<R, false, true, RecBwdV<R>>;
+        hipLaunchKernelGGL(kern, grid, block, stage_bytes<RecBwdV<R>>(bw), st, q, n, lists(L), L->perm, recv,
+                           L->tune.kahan_chunk, cbar, vpbar, xbar, gv, vq, dvbar, qbar);
     }
     LAUNCH_CHECK("accel adjoint");
+    if (visc) {
+        // the Extras pass's velocity gradients: their adjoints, to the inputs
+        RecExA<R>* erec = reinterpret_cast<RecExA<R>*>(rec_any);
+        {
+            TimeScope tp(L, st, CRK_K_PACK);
+            hipLaunchKernelGGL(k_pack_exa<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm, L->quant,
+                               static_cast<const R*>(g->h), static_cast<const R*>(g->vx),
+                               static_cast<const R*>(g->vy), static_cast<const R*>(g->vz), V,
+                               static_cast<const R*>(C->A), static_cast<const R*>(C->B),
+                               static_cast<const R*>(C->dA), static_cast<const R*>(C->dB), dvbar, erec);
+        }
+        LAUNCH_CHECK("pack extras adjoint");
+        reset_queue(L, st);
+        TimeScope ts(L, st, CRK_K_EXTRAS_ADJ);
+        auto kern = off32<RecExA<R>>(L) ? k_extras_adj<R, true> : k_extras_adj<R, false>;
+        hipLaunchKernelGGL(kern, grid, block, stage_bytes<RecExA<R>>(bw), st, q, n, lists(L), L->perm, erec,
+                           L->tune.kahan_chunk, cbar, vpbar, xbar, gv);
+        LAUNCH_CHECK("extras adjoint");
+    }
     if (C->M) {
         TimeScope ts(L, st, CRK_K_SOLVE_ADJ);  // the forward's moment sums, stored
         hipLaunchKernelGGL(k_moments_bwd_stored<R>, dim3((n + 255) / 256), dim3(256), 0, st, n, L->perm,
@@ -737,7 +1050,7 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
         auto kern = off32<RecMom<R>>(L) ? k_moments_adj<R, true> : k_moments_adj<R, false>;
         hipLaunchKernelGGL(kern, grid, block, stage_bytes<RecMom<R>>(bw), st, q, n, lists(L),
                            L->perm, mrec, vpbar, static_cast<const R*>(g->m), static_cast<const R*>(g->u),
-                           rho, gm1, L->tune.kahan_chunk, xbar, varec, gu);
+                           rho, gm1, L->tune.kahan_chunk, xbar, varec, gu, static_cast<const R*>(qbar));
     }
     LAUNCH_CHECK("moments adjoint");
     reset_queue(L, st);
@@ -754,7 +1067,7 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
 }  // namespace
 
 size_t crk::backward_scratch_bytes(int64_t n, bool f64) {
-    return f64 ? scratch_bytes<double>(n) : scratch_bytes<float>(n);
+    return f64 ? scratch_bytes<double>(n, true) : scratch_bytes<float>(n, true);
 }
 
 extern "C" int crk_accel_energy_backward(crk_leaves* L, const crk_gas* g, const void* V,
@@ -773,5 +1086,28 @@ extern "C" int crk_accel_energy_backward(crk_leaves* L, const crk_gas* g, const 
         return backward_impl<double>(L, g, (const double*)V, (const double*)rho, C, gamma,
                                      (const double*)ga, (const double*)gdudt, (double*)gx, (double*)gv,
                                      (double*)gu, st);
+    return fail(CRK_EINVAL, "unknown precision");
+}
+
+extern "C" int crk_accel_energy_visc_backward(crk_leaves* L, const crk_gas* g, const void* V, const void* rho,
+                                              const crk_corr* C, const void* dv, const crk_visc* q, double gamma,
+                                              const void* ga, const void* gdudt, crk_prec prec, void* gx, void* gv,
+                                              void* gu, hipStream_t st) {
+    int rc = check_gas(L, g, true);
+    if (rc) return rc;
+    if (!q) return fail(CRK_EINVAL, "viscosity parameters are required");
+    if (!(q->Cl >= 0.0) || !(q->Cq >= 0.0) || !(q->eps_q > 0.0))
+        return fail(CRK_EINVAL, "viscosity needs Cl >= 0, Cq >= 0 and eps_q > 0");
+    if (!(gamma > 1.0)) return fail(CRK_EINVAL, "gamma must exceed 1 (the sound speed)");
+    if (L->n == 0) return CRK_OK;
+    if (!V || !rho || !C || !C->A || !C->B || !C->dA || !C->dB || !dv || !ga || !gdudt || !gx || !gv || !gu)
+        return fail(CRK_EINVAL, "V, rho, corrections, dv, upstream adjoints and all gradients are required");
+    if (prec == CRK_F32)
+        return backward_impl<float>(L, g, (const float*)V, (const float*)rho, C, gamma, (const float*)ga,
+                                    (const float*)gdudt, (float*)gx, (float*)gv, (float*)gu, st, (const float*)dv, q);
+    if (prec == CRK_F64)
+        return backward_impl<double>(L, g, (const double*)V, (const double*)rho, C, gamma, (const double*)ga,
+                                     (const double*)gdudt, (double*)gx, (double*)gv, (double*)gu, st,
+                                     (const double*)dv, q);
     return fail(CRK_EINVAL, "unknown precision");
 }
