@@ -554,6 +554,39 @@ def extras_viscosity(args, torch, crk, L, g32, cfg_t, G, F, config, table, f64=T
                      "flop_per_pair_oracle": flop, "units_per_launch": units}
     log(f"[bench] {config} extras {res['extras']['avg_ms']:.3f} ms, viscous force pass "
         f"{res['accel_visc']['avg_ms']:.3f} ms")
+
+    # the force pass with the compatible energy partition (inviscid), and the
+    # adjoint of the viscous chain (force adjoint with the viscosity, Extras adjoint)
+    w = torch.as_tensor(cfg_t["w"]).float().to(g32["x"].device)
+    c = torch.as_tensor(cfg_t["c"]).float().to(g32["x"].device)
+    rhoR, dv32, _ = crk.crk_extras(L, g32, o32["V"], c32, "f32")
+    av, _, _ = crk.crk_accel_energy_visc(L, g32, o32["V"], o32["rho"], c32, dv32, cfg_t["gamma"], "f32")
+    ga = (2.0 * w[:, None] * av).contiguous()
+
+    def compat_step():
+        crk.crk_accel_energy_compatible(L, g32, o32["V"], o32["rho"], c32, 0.1, gamma=cfg_t["gamma"], prec="f32")
+
+    def visc_bwd_step():
+        crk.crk_accel_energy_visc_backward(L, g32, o32["V"], o32["rho"], c32, dv32, ga, c, cfg_t["gamma"], "f32")
+
+    for name, fn, kinds in (("compatible", compat_step, (("accel", "accel_compat", F),)),
+                            ("visc_backward", visc_bwd_step,
+                             (("accel_adj", "accel_visc_adj", F), ("extras_adj", "extras_adj", G)))):
+        timed_steps(fn, 1, 1, torch)
+        L.timing(True)
+        ms_call = timed_steps(fn, reps, 0, torch)
+        kt = L.kernel_times()
+        L.timing(False)
+        sub = {"ms_per_call": round(ms_call, 4)}
+        for kind, fkey, units in kinds:
+            ms = kt[kind][0] / max(kt[kind][1], 1)
+            flop = table[fkey]
+            sub[kind] = {"avg_ms": round(ms, 4), "interactions_per_s": units / (ms * 1e-3),
+                         "tflops_algorithmic": round(flop * units / (ms * 1e-3) / 1e12, 3),
+                         "frac_fp32_peak": round(flop * units / (ms * 1e-3) / 1e12 / PEAK_FP32_VALU_TFLOPS, 4),
+                         "flop_per_pair_oracle": flop, "units_per_launch": units}
+        res[name] = sub
+        log(f"[bench] {config} {name}: {sub}")
     if f64:
         g64 = crk.gas_to_device(cfg_t, "f64")
         o64, c64 = run(g64, "f64")
@@ -564,8 +597,17 @@ def extras_viscosity(args, torch, crk, L, g32, cfg_t, G, F, config, table, f64=T
         err = {}
         for k, u, v in zip(("rhoR", "dv", "du", "a_visc", "dudt_visc"), e32 + a32[:2], e64 + a64[:2]):
             err[k] = float(f"{((u.double() - v).abs().max() / v.abs().max()).item():.3e}")
+        w64, c64w = w.double(), c.double()
+        b32 = crk.crk_accel_energy_visc_backward(L, g32, o32["V"], o32["rho"], c32, e32[1],
+                                                 (2.0 * w[:, None] * a64[0].float()).contiguous(), c,
+                                                 cfg_t["gamma"], "f32")
+        b64 = crk.crk_accel_energy_visc_backward(L, g64, o64["V"], o64["rho"], c64, e64[1],
+                                                 (2.0 * w64[:, None] * a64[0]).contiguous(), c64w,
+                                                 cfg_t["gamma"], "f64")
+        for k, u, v in zip(("gx_visc", "gv_visc", "gu_visc"), b32, b64):
+            err[k] = float(f"{((u.double() - v).abs().max() / v.abs().max()).item():.3e}")
         res["fp32_vs_fp64_normwise"] = err
-        del g64, o64, c64, e64, a64
+        del g64, o64, c64, e64, a64, b32, b64
     torch.cuda.empty_cache()
     return res
 

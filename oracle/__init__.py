@@ -419,7 +419,8 @@ def grad_coordinates(n, n_pos=32, n_vel=16, n_u=16, seed=19):
 
 
 FLOP_KINDS = ("volume", "moments", "accel", "gravity", "gravity_poly", "volume_adj", "moments_adj",
-              "accel_adj", "extras", "accel_visc", "gravity_adj", "gravity_adj_poly", "accel_compat")
+              "accel_adj", "extras", "accel_visc", "gravity_adj", "gravity_adj_poly", "accel_compat",
+              "accel_visc_adj", "extras_adj")
 
 
 def flops():

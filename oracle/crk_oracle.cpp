@@ -1005,6 +1005,67 @@ int64_t accel_visc(int nbrs) {
     return pair_flops({a[0], a[1], a[2], du});
 }
 
+// the viscous force pair's share of the loss, reversed for particle 0's
+// inputs (those of the inviscid form and its velocity gradient)
+int64_t accel_visc_adj(int nbrs) {
+    Setup s = make(nbrs);
+    std::vector<std::vector<Ops>> w(s.np);
+    std::vector<Ops> kap, dv;
+    for (int p = 0; p < s.np; ++p) {
+        for (int c = 0; c < 3; ++c) w[p].push_back(Ops::leaf(0.2 * (c + 1) - 0.1 * p, 1u << p));
+        kap.push_back(Ops::leaf(0.05 + 0.01 * p, 1u << p));
+        for (int k = 0; k < 9; ++k) dv.push_back(Ops::leaf(0.03 * (k + 1) - 0.02 * p, 1u << p));
+    }
+    Visc<Ops> q;
+    q.dv = dv.data();
+    const Ops Pi = Ops(5.0 / 3.0 - 1.0) * s.rho[0] * s.u[0];
+    Ops l(0.0);
+    for (int j = 1; j < s.np; ++j) {
+        Sep<Ops> sp = separation(s.g, 0, j);
+        Ops F[3], Fv;
+        accel_pair(s.g, s.V.data(), s.rho.data(), s.C.data(), 5.0 / 3.0, 0, j, sp,
+                   Pi + visc_pair(s.g, s.rho.data(), 5.0 / 3.0, q, 0, j, sp), F, Fv);
+        for (int c = 0; c < 3; ++c) l += F[c] * (w[0][c] - w[j][c]);
+        l -= (kap[0] + kap[j]) * Fv;
+    }
+    std::vector<Ops> wanted{s.x[0], s.y[0], s.z[0], s.vx[0], s.vy[0], s.vz[0], s.V[0], s.rho[0], s.u[0],
+                            s.C[0].A};
+    for (int a = 0; a < 3; ++a) {
+        wanted.push_back(s.C[0].B[a]);
+        wanted.push_back(s.C[0].dA[a]);
+        for (int c = 0; c < 3; ++c) wanted.push_back(s.C[0].dB[a][c]);
+    }
+    for (int k = 0; k < 9; ++k) wanted.push_back(dv[k]);
+    return pair_flops(reverse_sweep(l, wanted));
+}
+
+// l = dvb_0 . dv_0 + sum_j dvb_j . (particle 0's term in dv_j), reversed for
+// particle 0's position, velocity, volume and corrections
+int64_t extras_adj(int nbrs) {
+    Setup s = make(nbrs);
+    std::vector<std::vector<Ops>> b(s.np);
+    for (int p = 0; p < s.np; ++p)
+        for (int k = 0; k < 9; ++k) b[p].push_back(Ops::leaf(0.1 * (k + 1) - 0.07 * p, 1u << p));
+    Ops r, dv[3][3], du[3];
+    extras_one(s.g, s.V.data(), s.C.data(), 0, Cand{nullptr, s.np}, r, dv, du);
+    Ops l(0.0);
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) l += b[0][3 * a + c] * dv[a][c];
+    const int64_t zero = 0;
+    for (int j = 1; j < s.np; ++j) {
+        extras_one(s.g, s.V.data(), s.C.data(), j, Cand{&zero, 1}, r, dv, du);
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) l += b[j][3 * a + c] * dv[a][c];
+    }
+    std::vector<Ops> wanted{s.x[0], s.y[0], s.z[0], s.vx[0], s.vy[0], s.vz[0], s.V[0], s.C[0].A};
+    for (int a = 0; a < 3; ++a) {
+        wanted.push_back(s.C[0].B[a]);
+        wanted.push_back(s.C[0].dA[a]);
+        for (int c = 0; c < 3; ++c) wanted.push_back(s.C[0].dB[a][c]);
+    }
+    return pair_flops(reverse_sweep(l, wanted));
+}
+
 int64_t accel_compat(int nbrs) {
     Setup s = make(nbrs);
     Ops a[3], du;
@@ -1369,7 +1430,8 @@ int64_t oracle_count_pairs(int64_t n, const double* x, const double* y, const do
 // (see the flops namespace): [volume, moments, accel, gravity, gravity with the
 // polynomial term, volume adjoint, moments adjoint, force adjoint, extras, force
 // pass with the viscosity, gravity adjoint, gravity adjoint with the polynomial,
-// force pass with the compatible energy partition].
+// force pass with the compatible energy partition, viscous force adjoint, Extras
+// adjoint].
 void oracle_flops(double* out) {
     using namespace flops;
     out[0] = double(volume(2) - volume(1));
@@ -1385,6 +1447,8 @@ void oracle_flops(double* out) {
     out[10] = double(gravity_adj(2, false) - gravity_adj(1, false));
     out[11] = double(gravity_adj(2, true) - gravity_adj(1, true));
     out[12] = double(accel_compat(2) - accel_compat(1));
+    out[13] = double(accel_visc_adj(2) - accel_visc_adj(1));
+    out[14] = double(extras_adj(2) - extras_adj(1));
     op_reset();
 }
 
