@@ -80,6 +80,7 @@ def _load():
         lib.oracle_extras.argtypes = [I64] + [P] * 14 + [I64, P, P, P, P]
         lib.oracle_visc_listed.argtypes = [I64] + [P] * 9 + [D, D, D, D] + [P] * 15
         lib.oracle_accel_visc.argtypes = [I64] + [P] * 16 + [D, D, D, D, I64, P, P, P, P, P]
+        lib.oracle_compat_listed.argtypes = [I64] + [P] * 9 + [D, D] + [P] * 12
         lib.oracle_grad_visc.argtypes = [I64] + [P] * 9 + [D, D, D, D, P, P, I64, P, P, D, P, P]
         lib.oracle_accel_compat.argtypes = [I64] + [P] * 16 + [D, D, D, D, D, I64, P, P, P, P, P]
         lib.oracle_gravity_grad.argtypes = [I64, P, P, P, P, D, D, D, P, P, I64, P, P, D, P, P]
@@ -512,6 +513,22 @@ def visc_listed(g, off, idx, ref, Cl=1.0, Cq=2.0, eps_q=0.01):
                                _p(de), _p(a[0]), _p(a[1]), _p(a[2]), _p(du))
     a = a.T.copy()
     return dict(rhoR=rhoR, dv=dv, du=de, a=a, dudt=du, totals=totals(g, a, du))
+
+
+def compat_listed(g, off, idx, ref, eps_u=0.1):
+    """Forces with the compatible energy partition of all particles over
+    precomputed lists, from the oracle's own V, rho and corrections ``ref``.
+    With exact lists it equals accel_compat bit for bit."""
+    keys = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "m")
+    arr = [_c(g[k]) for k in keys]
+    n = arr[0].size
+    off, idx = _c(off, np.int64), _c(idx, np.int64)
+    a = np.empty((3, n))
+    du = np.empty(n)
+    _load().oracle_compat_listed(n, *[_p(v) for v in arr], float(g["gamma"]), float(eps_u), _p(off), _p(idx),
+                                 _p(_c(ref["V"])), _p(_c(ref["rho"])), _p(_c(ref["A"])), _p(_c(ref["B"])),
+                                 _p(_c(ref["dA"])), _p(_c(ref["dB"])), _p(a[0]), _p(a[1]), _p(a[2]), _p(du))
+    return a.T.copy(), du
 
 
 def neighbour_lists(g, margin=1e-9):

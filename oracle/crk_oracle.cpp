@@ -1635,6 +1635,34 @@ int oracle_visc_listed(int64_t n, const double* x, const double* y, const double
     return 0;
 }
 
+// Forces with the compatible energy partition (no viscosity) of all particles
+// over precomputed lists, from the oracle's own V, rho and corrections.  With
+// exact lists it equals oracle_accel_compat bit for bit.
+int oracle_compat_listed(int64_t n, const double* x, const double* y, const double* z, const double* vx,
+                         const double* vy, const double* vz, const double* u, const double* h, const double* m,
+                         double gamma, double eps_u, const int64_t* off, const int64_t* idx, const double* V,
+                         const double* rho, const double* A, const double* B, const double* dA, const double* dB,
+                         double* ax, double* ay, double* az, double* dudt) {
+    Gas<double> g = make_gas(n, x, y, z, vx, vy, vz, u, h, m);
+    auto cand = [&](int64_t i) { return Cand{idx + off[i], off[i + 1] - off[i]}; };
+    std::vector<Corr<double>> C(n);
+    for (int64_t i = 0; i < n; ++i) {
+        C[i].A = A[i];
+        for (int a = 0; a < 3; ++a) {
+            C[i].B[a] = B[3 * i + a];
+            C[i].dA[a] = dA[3 * i + a];
+            for (int c = 0; c < 3; ++c) C[i].dB[a][c] = dB[9 * i + 3 * a + c];
+        }
+    }
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        double a[3], du;
+        accel_one(g, V, rho, C.data(), gamma, i, cand(i), a, du, static_cast<Visc<double>*>(nullptr), &eps_u);
+        ax[i] = a[0]; ay[i] = a[1]; az[i] = a[2]; dudt[i] = du;
+    }
+    return 0;
+}
+
 // Kernel values for pinning: W(r, h) and F(r, h) at n radii.
 void oracle_kernel(int64_t n, const double* r, double h, double* W, double* F) {
     for (int64_t k = 0; k < n; ++k) {

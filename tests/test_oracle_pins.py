@@ -743,6 +743,16 @@ def test_compatible_partition_sends_heat_to_the_colder_particle(tiny, oracle_lib
     assert np.abs(du - du_dense).max() <= 1e-12 * np.abs(du_dense).max()
 
 
+def test_listed_compatible_partition_is_the_brute_force_one(oracle_lib):
+    """The compatible partition over exact lists equals the brute-force one bit for bit."""
+    g = synth.make_config("C2", n_side=10)
+    o = oracle_lib.hydro(g)
+    off, idx = oracle_lib.neighbour_lists(g)
+    a, du = oracle_lib.compat_listed(g, off, idx, o, eps_u=0.1)
+    ab, dub = oracle_lib.accel_compat(g, o["V"], o["rho"], (o["A"], o["B"], o["dA"], o["dB"]), eps_u=0.1)
+    assert np.array_equal(a, ab) and np.array_equal(du, dub)
+
+
 # ---------------------------------------------------------------- time step
 def test_timestep_closed_form(oracle_lib):
     """Three particles whose limits are known: the slowest-signal one sets the
