@@ -106,3 +106,31 @@ def test_compatible_partition_arguments(crk):
     a, du, T = crk.crk_accel_energy_compatible(L, g, V, rho, corr, eps_u=0.0, prec="f32")
     T = T.cpu().numpy()
     assert abs(T[3]) <= 2e-6 * T[5]
+
+
+_full = {}
+
+
+def test_compatible_partition_full_size_every_particle(crk):
+    """C2 at 128^3 (leaf 128, the benchmark's build): every particle's a and
+    du/dt against the oracle's chain over exact neighbour lists, FP64 and FP32."""
+    if "C2" not in _full:
+        cfg = synth.make_config("C2")
+        off, idx = oracle.neighbour_lists(cfg)
+        ref = oracle.hydro_listed(cfg, off, idx)
+        _full["C2"] = (cfg, oracle.compat_listed(cfg, off, idx, ref, eps_u=EPS_U))
+    cfg, (a_ref, du_ref) = _full["C2"]
+    for prec in ("f64", "f32"):
+        print(f"case C2 full n={cfg['n']} prec={prec}", flush=True)
+        g = crk.gas_to_device(cfg, prec)
+        L = crk.crk_build_leaf_pairs(g["x"], g["y"], g["z"], g["h"], leaf_max=128, prec=prec)
+        V, rho = crk.crk_volume(L, g, prec)
+        corr = crk.crk_corrections(L, g, V, prec)
+        a, du, T = crk.crk_accel_energy_compatible(L, g, V, rho, corr, eps_u=EPS_U, prec=prec)
+        ea = normwise(a.double().cpu().numpy(), a_ref)
+        ed = normwise(du.double().cpu().numpy(), du_ref)
+        print({"a": ea, "dudt": ed}, flush=True)
+        assert ea <= TOL[prec] and ed <= TOL[prec], (prec, ea, ed)
+        L.free()
+        del g, L, V, rho, corr, a, du
+        torch.cuda.empty_cache()

@@ -73,11 +73,11 @@ def reference(n_side):
     return _ref[n_side]
 
 
-@pytest.mark.parametrize("stored_sums", [False, True])
+@pytest.mark.parametrize("n_side,stored_sums", [(12, False), (12, True), (24, True)])
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-9), ("f32", 1e-4)])
-def test_viscous_gradients_against_oracle(crk, prec, tol, stored_sums):
-    cfg, parts, kinds, gd, gf = reference(12)
-    print(f"case C4 n_side=12 n={cfg['n']} prec={prec} stored_sums={stored_sums}", flush=True)
+def test_viscous_gradients_against_oracle(crk, prec, tol, n_side, stored_sums):
+    cfg, parts, kinds, gd, gf = reference(n_side)
+    print(f"case C4 n_side={n_side} n={cfg['n']} prec={prec} stored_sums={stored_sums}", flush=True)
     g = pick(*gpu_visc_gradients(crk, cfg, prec, stored_sums), parts, kinds)
     e_dual = rel_err(g, gd)
     e_fd = rel_err(g, gf)
