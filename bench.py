@@ -569,22 +569,26 @@ def extras_viscosity(args, torch, crk, L, g32, cfg_t, G, F, config, table, f64=T
     def visc_bwd_step():
         crk.crk_accel_energy_visc_backward(L, g32, o32["V"], o32["rho"], c32, dv32, ga, c, cfg_t["gamma"], "f32")
 
-    for name, fn, kinds in (("compatible", compat_step, (("accel", "accel_compat", F),)),
+    # kinds: (report name, kernel kinds whose launch times add up, FLOP key, units per launch)
+    for name, fn, kinds in (("compatible", compat_step, (("accel", ("accel",), "accel_compat", F),)),
                             ("visc_backward", visc_bwd_step,
-                             (("accel_adj", "accel_visc_adj", F), ("extras_adj", "extras_adj", G)))):
+                             (("visc_force_adjoint", ("accel_adj",), "accel_visc_adj", F),
+                              ("extras_adj", ("extras_adj",), "extras_adj", G)))):
         timed_steps(fn, 1, 1, torch)
         L.timing(True)
         ms_call = timed_steps(fn, reps, 0, torch)
         kt = L.kernel_times()
         L.timing(False)
         sub = {"ms_per_call": round(ms_call, 4)}
-        for kind, fkey, units in kinds:
-            ms = kt[kind][0] / max(kt[kind][1], 1)
+        for kind, parts, fkey, units in kinds:
+            ms = sum(kt[p][0] / max(kt[p][1], 1) for p in parts)
             flop = table[fkey]
             sub[kind] = {"avg_ms": round(ms, 4), "interactions_per_s": units / (ms * 1e-3),
                          "tflops_algorithmic": round(flop * units / (ms * 1e-3) / 1e12, 3),
                          "frac_fp32_peak": round(flop * units / (ms * 1e-3) / 1e12 / PEAK_FP32_VALU_TFLOPS, 4),
                          "flop_per_pair_oracle": flop, "units_per_launch": units}
+            if len(parts) > 1:
+                sub[kind]["kernels_ms"] = {p: round(kt[p][0] / max(kt[p][1], 1), 4) for p in parts}
         res[name] = sub
         log(f"[bench] {config} {name}: {sub}")
     if f64:

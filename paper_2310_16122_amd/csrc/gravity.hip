@@ -68,7 +68,8 @@ __device__ __forceinline__ void grav_phi(R r2, R eps2, const R pc[6], R& phi, R&
 //   kExPermute: the same walk, each candidate fetched by every lane with
 //              ds_bpermute (the select-from-group form).
 // The same candidates are evaluated in the same order with the compensated
-// fold after every kChunk of them, so the three give the same sums bit for bit.
+// fold after every kChunk of them (counted over the whole stream), so the
+// three give the same sums bit for bit.
 constexpr int kExLds = 0, kExSgpr = 1, kExPermute = 2;
 
 template <int kEx, class T> __device__ __forceinline__ T lane_value(T v, int k) {
@@ -114,9 +115,12 @@ template <int kEx, class Rec> __device__ __forceinline__ Rec lane_record(const R
 // stays beyond it; other tiles use the exact fixed-point separation.  In a
 // compact tile a candidate farther than r_c from the tile's bounding box
 // cannot interact with any lane and is dropped before it reaches LDS; the
-// survivors are compacted (ballot + mbcnt), padded with `pad` records (far
-// away, massless) to whole chunks, and evaluated in straight-line chunks of
-// kChunk with fold() after each chunk.
+// survivors are appended (ballot + mbcnt) to an LDS queue of up to 2 x 64
+// entries that carries over from block to block, whole chunks of kChunk are
+// evaluated in straight-line code with fold() after each once 64 are queued
+// (the remainder moves to the front), and the last partial chunk is padded
+// with `pad` records (far away, massless).  The chunks are thus the kept
+// candidates in stream order, eight at a time, whatever the block sizes.
 //   load(j): the candidate's record with its non-positional fields set;
 //   eval(rec, dx, dy, dz): one pair, x_ij = (dx, dy, dz).
 template <class R, class Rec, int kChunk, int kEx, class Load, class Eval, class Fold>
@@ -151,6 +155,30 @@ __device__ __forceinline__ void gravity_tile(int w, int n, const uint4* __restri
     uint4 nq = qo;
     Rec nrec = pad;
     if (r < r1 && lane < e - b) { nq = quant[b + lane]; nrec = load(b + lane); }
+    int done = 0;  // walk forms: candidates evaluated since the last fold
+    int have = 0;  // LDS form: candidates queued
+    // evaluates the first `count` queued entries (a multiple of kChunk)
+    auto eval_queued = [&](int count) __attribute__((always_inline)) {
+        if (compact) {
+            for (int j0 = 0; j0 < count; j0 += kChunk) {
+#pragma unroll
+                for (int u = 0; u < kChunk; ++u) {
+                    const Rec c = srec[j0 + u];
+                    eval(c, xi - c.x, yi - c.y, zi - c.z);
+                }
+                fold();
+            }
+        } else {
+            for (int j0 = 0; j0 < count; j0 += kChunk) {
+#pragma unroll
+                for (int u = 0; u < kChunk; ++u) {
+                    const uint4 c = sq[j0 + u];
+                    eval(srec[j0 + u], sep<R>(qi.x, c.x), sep<R>(qi.y, c.y), sep<R>(qi.z, c.z));
+                }
+                fold();
+            }
+        }
+    };
     while (r < r1) {
         const int mcnt = min(kWave, e - b);
         const uint4 qj = nq;
@@ -179,7 +207,6 @@ __device__ __forceinline__ void gravity_tile(int w, int n, const uint4* __restri
         if constexpr (kEx != kExLds) {
             // walk the kept lanes in lane order (the LDS form's compacted order)
             uint64_t left = mask;
-            int done = 0;
             while (left) {
                 const int k = __builtin_amdgcn_readfirstlane(int(__builtin_ctzll(left)));
                 left &= left - 1;
@@ -195,39 +222,39 @@ __device__ __forceinline__ void gravity_tile(int w, int n, const uint4* __restri
                     done = 0;
                 }
             }
-            if (done) fold();  // the LDS form pads the last chunk with zeros, then folds
             continue;
         }
         const int cnt = __popcll(mask);
-        const int padded = (cnt + kChunk - 1) / kChunk * kChunk;
         const int pos = __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32),
                                                   __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
-        __syncthreads();  // the previous block's entries have been read
-        if (keep) { srec[pos] = g; sq[pos] = qj; }
-        if (lane >= cnt && lane < padded) {
+        __syncthreads();  // queued entries moved by the previous step are in place
+        if (keep) { srec[have + pos] = g; sq[have + pos] = qj; }
+        have += cnt;  // < 2 x 64: fewer than 64 were queued before
+        __syncthreads();
+        if (have >= kWave) {
+            const int whole = have / kChunk * kChunk;
+            eval_queued(whole);
+            // the remainder (fewer than kChunk) to the front
+            const int rest = have - whole;
+            Rec tr = pad;
+            uint4 tq = qo;
+            if (lane < rest) { tr = srec[whole + lane]; tq = sq[whole + lane]; }
+            __syncthreads();
+            if (lane < rest) { srec[lane] = tr; sq[lane] = tq; }
+            have = rest;
+        }
+    }
+    if constexpr (kEx != kExLds) {
+        if (done) fold();  // the LDS form pads the last chunk with zeros, then folds
+    } else if (have > 0) {
+        const int padded = (have + kChunk - 1) / kChunk * kChunk;
+        __syncthreads();
+        if (lane >= have && lane < padded) {
             srec[lane] = pad;
             sq[lane] = qo;
         }
         __syncthreads();
-        if (compact) {
-            for (int j0 = 0; j0 < padded; j0 += kChunk) {
-#pragma unroll
-                for (int u = 0; u < kChunk; ++u) {
-                    const Rec c = srec[j0 + u];
-                    eval(c, xi - c.x, yi - c.y, zi - c.z);
-                }
-                fold();
-            }
-        } else {
-            for (int j0 = 0; j0 < padded; j0 += kChunk) {
-#pragma unroll
-                for (int u = 0; u < kChunk; ++u) {
-                    const uint4 c = sq[j0 + u];
-                    eval(srec[j0 + u], sep<R>(qi.x, c.x), sep<R>(qi.y, c.y), sep<R>(qi.z, c.z));
-                }
-                fold();
-            }
-        }
+        eval_queued(padded);
     }
 }
 
@@ -239,8 +266,8 @@ __global__ __launch_bounds__(64) void k_gravity(Queue qu, int n, const int32_t* 
                                                 const int2* __restrict__ rng, GravParams gp,
                                                 R* __restrict__ a_out) {
     constexpr bool kComp = sizeof(R) == 4;
-    __shared__ GravRec<R> srec[kWave];
-    __shared__ uint4 sq[kWave];
+    __shared__ GravRec<R> srec[2 * kWave];
+    __shared__ uint4 sq[2 * kWave];
     const int lane = lane_id();
     const R rc2 = R(gp.rc2), eps2 = R(gp.eps2);
     R pc[6];
@@ -292,8 +319,8 @@ __global__ __launch_bounds__(64) void k_gravity_adj(Queue qu, int n, const int32
                                                     const int2* __restrict__ rng, GravParams gp,
                                                     R* __restrict__ gx_out) {
     constexpr bool kComp = sizeof(R) == 4;
-    __shared__ GravAdjRec<R> srec[kWave];
-    __shared__ uint4 sq[kWave];
+    __shared__ GravAdjRec<R> srec[2 * kWave];
+    __shared__ uint4 sq[2 * kWave];
     const int lane = lane_id();
     const R rc2 = R(gp.rc2), eps2 = R(gp.eps2);
     R pc[6];
