@@ -441,8 +441,9 @@ def bench_hydro(args, torch, crk, config=None, tuning=None, autotune=True, rando
     # the Extras pass and the viscous force pass, and the device leaf build, on the headline workload only
     ev = extras_viscosity(args, torch, crk, L, g32, cfg_t, G, F, config, table, f64=f64) if config == "C2" else None
     dbuild = None
-    if config == "C2" and not args.no_device_build:
-        dbuild = device_build_leg(args, torch, crk, cfg, L.get_tuning(), backward, st)
+    if not args.no_device_build:
+        # C2: the build and the step over its order; C5: the build and its lists only
+        dbuild = device_build_leg(args, torch, crk, cfg, L.get_tuning(), backward, st, step=config == "C2")
     out = {
         "metric": METRIC, "value": inter / (ms32 * 1e-3), "unit": "interactions/s",
         "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": round(ms32, 4),
@@ -481,10 +482,11 @@ def bench_hydro(args, torch, crk, config=None, tuning=None, autotune=True, rando
     return out
 
 
-def device_build_leg(args, torch, crk, cfg, tuning, backward, host_stats):
+def device_build_leg(args, torch, crk, cfg, tuning, backward, host_stats, step=True):
     """The leaf build on the device (Morton octree; crk_build_leaf_pairs_device)
-    on the generated order: wall time, its list-build kernels; then the same
-    step as the headline one over particles in the device build's order."""
+    on the generated order: wall time, its list-build kernels, whether its
+    lists hold as many entries as the host build's; with step, the same step
+    as the headline one over particles in the device build's order."""
     import numpy as np
 
     g_rand = crk.gas_to_device(cfg, "f32")
@@ -494,9 +496,18 @@ def device_build_leg(args, torch, crk, cfg, tuning, backward, host_stats):
                                          leaf_max=args.leaf_max, prec="f32")
     build_ms = (time.perf_counter() - tb) * 1e3
     cull = Ld.kernel_times()["cull"]
+    std = Ld.stats()
     perm = Ld.perm().cpu().numpy()
     Ld.free()
     del g_rand, Ld
+    same = std["list_entries"] == host_stats["list_entries"] and std["pairs_force"] == host_stats["pairs_force"]
+    if not step:
+        log(f"[bench] device build {build_ms:.0f} ms (list build kernels {cull[0]:.2f} ms); same list "
+            f"entries as the host build: {same}")
+        torch.cuda.empty_cache()
+        return {"build_ms": round(build_ms, 1), "list_build_gpu_ms": round(cull[0], 3),
+                "list_entries": std["list_entries"], "same_lists_as_host_build": same,
+                "padded_slots": std["padded_slots"], "host_build_padded_slots": host_stats["padded_slots"]}
     cfg_t = {k: (v[perm] if isinstance(v, np.ndarray) and v.shape == (cfg["n"],) else v)
              for k, v in cfg.items()}
     g32 = crk.gas_to_device(cfg_t, "f32")
@@ -510,6 +521,7 @@ def device_build_leg(args, torch, crk, cfg, tuning, backward, host_stats):
     log(f"[bench] device build {build_ms:.0f} ms (list build kernels {cull[0]:.2f} ms); step over its "
         f"order {ms:.3f} ms; stats {st}")
     out = {"build_ms": round(build_ms, 1), "list_build_gpu_ms": round(cull[0], 3),
+           "same_lists_as_host_build": same,
            "ms_per_step": round(ms, 4), "identity_order": identity, "leaves": st["leaves"],
            "list_entries": st["list_entries"], "padded_slots": st["padded_slots"],
            "host_build_padded_slots": host_stats["padded_slots"],
@@ -707,7 +719,8 @@ def bench_gravity(args, torch, crk, tuning=None, leaf_max=None):
 def c5_summary(r):
     """The C5 leg of the default run, condensed into the headline line."""
     keys = ("ms_per_step", "value", "fp64_gpu_ms_per_step", "fp64_over_fp32_time", "fp32_vs_fp64_normwise",
-            "roofline", "roofline_forward_accel", "kernels", "build_ms", "list_build_gpu_ms", "generate_s")
+            "roofline", "roofline_forward_accel", "kernels", "build_ms", "list_build_gpu_ms", "generate_s",
+            "device_build")
     out = {k: r[k] for k in keys if k in r}
     out["workload"] = r["config"]["workload"]
     out["interactions_per_step"] = r["config"]["interactions_per_step"]
