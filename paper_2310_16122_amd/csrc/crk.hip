@@ -288,15 +288,28 @@ __device__ __forceinline__ unsigned long long readlane64(unsigned long long v, i
     return (static_cast<unsigned long long>(hi) << 32) | lo;
 }
 
-__global__ __launch_bounds__(64) void k_schedule(int n, const int32_t* __restrict__ cnt,
-                                                 const int32_t* __restrict__ cntg,
-                                                 const int64_t* __restrict__ ell_off,
-                                                 const int32_t* __restrict__ ell_len, uint32_t* __restrict__ nbr,
-                                                 uint32_t* __restrict__ srec, uint8_t* __restrict__ sidx,
-                                                 int32_t* __restrict__ scnt) {
+// One of the tile's distinct neighbours with the lanes that need it, in the
+// gather and the other part of their lists.
+struct SchedEntry {
+    unsigned long long gm, bm;
+    uint32_t key, pad;
+};
+
+// Phase 1, one wave per tile of a batch (tile0 + block): the tile's distinct
+// neighbours (an LDS hash table), compacted and written to tbl (kSchedHash
+// entries per tile of the batch), their number to tcnt.  A tile whose set
+// overflows the table gets the identity schedule here (tcnt = -1).
+__global__ __launch_bounds__(64) void k_sched_table(int n, int tile0, const int32_t* __restrict__ cnt,
+                                                    const int32_t* __restrict__ cntg,
+                                                    const int64_t* __restrict__ ell_off,
+                                                    const int32_t* __restrict__ ell_len,
+                                                    const uint32_t* __restrict__ nbr, uint32_t* __restrict__ srec,
+                                                    uint8_t* __restrict__ sidx, int32_t* __restrict__ scnt,
+                                                    SchedEntry* __restrict__ tbl, int32_t* __restrict__ tcnt) {
     __shared__ uint32_t key[kSchedHash];
     __shared__ unsigned long long gm[kSchedHash], bm[kSchedHash];  // lanes needing it: gather, other
-    const int w = blockIdx.x;
+    const int bt = blockIdx.x;
+    const int w = tile0 + bt;
     const int lane = int(threadIdx.x);
     const int s = w * kWave + lane;
     const bool valid = s < n;
@@ -304,7 +317,6 @@ __global__ __launch_bounds__(64) void k_schedule(int n, const int32_t* __restric
     const int cg = valid ? cntg[s] : 0;
     const int len = ell_len[w];
     const int64_t off = ell_off[w];
-    const uint32_t self = uint32_t(valid ? s : w * kWave);
     for (int t = lane; t < kSchedHash; t += kWave) {
         key[t] = kSchedEmpty;
         gm[t] = 0;
@@ -335,6 +347,7 @@ __global__ __launch_bounds__(64) void k_schedule(int n, const int32_t* __restric
             sidx[e] = uint8_t(lane);
             if (lane == 0) scnt[(off >> 6) + k] = kWave;
         }
+        if (lane == 0) tcnt[bt] = -1;
         return;
     }
     // compact the distinct neighbours to the front of the table (in place: an
@@ -356,19 +369,49 @@ __global__ __launch_bounds__(64) void k_schedule(int n, const int32_t* __restric
         nd += __popcll(lb);
     }
     __syncthreads();
-    const int nk = (nd + kWave - 1) / kWave;
-    uint32_t K[kSchedRegs];
-    unsigned long long GM[kSchedRegs], BM[kSchedRegs];
+    SchedEntry* out = tbl + int64_t(bt) * kSchedHash;
+    for (int t = lane; t < nd; t += kWave) out[t] = SchedEntry{gm[t], bm[t], key[t], 0u};
+    if (lane == 0) tcnt[bt] = nd;
+}
+
+// Phase 2, one wave per listed tile (list holds batch positions): the greedy
+// cover of every slot from the tile's neighbour table held in registers
+// (kRegs entries per lane at most: tiles are binned by their table size, so
+// that small tables run with fewer registers and more waves).
+template <int kRegs>
+__global__ __launch_bounds__(64) void k_sched_pick(int n, int tile0, const int32_t* __restrict__ list,
+                                                   const int32_t* __restrict__ cnt,
+                                                   const int32_t* __restrict__ cntg,
+                                                   const int64_t* __restrict__ ell_off,
+                                                   const int32_t* __restrict__ ell_len, uint32_t* __restrict__ nbr,
+                                                   uint32_t* __restrict__ srec, uint8_t* __restrict__ sidx,
+                                                   int32_t* __restrict__ scnt, const SchedEntry* __restrict__ tbl,
+                                                   const int32_t* __restrict__ tcnt) {
+    __shared__ uint32_t tmin[kWave];
+    const int bt = list[blockIdx.x];
+    const int w = tile0 + bt;
+    const int lane = int(threadIdx.x);
+    const int s = w * kWave + lane;
+    const bool valid = s < n;
+    const int c = valid ? cnt[s] : 0;
+    const int cg = valid ? cntg[s] : 0;
+    const int len = ell_len[w];
+    const int64_t off = ell_off[w];
+    const uint32_t self = uint32_t(valid ? s : w * kWave);
+    const int nd = tcnt[bt];
+    const int nk = (nd + kWave - 1) / kWave;  // <= kRegs (binned)
+    const SchedEntry* tab = tbl + int64_t(bt) * kSchedHash;
+    uint32_t K[kRegs];
+    unsigned long long GM[kRegs], BM[kRegs];
 #pragma unroll
-    for (int i = 0; i < kSchedRegs; ++i) {
+    for (int i = 0; i < kRegs; ++i) {
         const int t = lane + kWave * i;
         const bool ok = i < nk && t < nd;
-        K[i] = ok ? key[t] : kSchedEmpty;
-        GM[i] = ok ? gm[t] : 0ull;
-        BM[i] = ok ? bm[t] : 0ull;
+        const SchedEntry e = ok ? tab[t] : SchedEntry{0ull, 0ull, kSchedEmpty, 0u};
+        K[i] = e.key;
+        GM[i] = e.gm;
+        BM[i] = e.bm;
     }
-    __syncthreads();
-    uint32_t* tmin = key;  // the table is in registers now: its first words hold per-lane minima
     int remg = cg, remb = c - cg;
     const unsigned long long bit = 1ull << lane;
     for (int k = 0; k < len; ++k) {
@@ -382,7 +425,7 @@ __global__ __launch_bounds__(64) void k_schedule(int n, const int32_t* __restric
             int bc = 0;
             uint32_t bk = kSchedEmpty;
 #pragma unroll
-            for (int i = 0; i < kSchedRegs; ++i) {
+            for (int i = 0; i < kRegs; ++i) {
                 if (i >= nk) continue;
                 const int cv = __popcll(((GM[i] & gph) | (BM[i] & ~gph)) & open);
                 if (cv > bc || (cv == bc && K[i] < bk)) {
@@ -407,7 +450,7 @@ __global__ __launch_bounds__(64) void k_schedule(int n, const int32_t* __restric
                 tmin[lane] = kSchedEmpty;
                 __syncthreads();
 #pragma unroll
-                for (int i = 0; i < kSchedRegs; ++i) {
+                for (int i = 0; i < kRegs; ++i) {
                     if (i >= nk) continue;
                     const unsigned long long want = ((GM[i] & gph) | (BM[i] & ~gph)) & open;
                     if (want) atomicMin(&tmin[__builtin_ctzll(want)], K[i]);
@@ -418,7 +461,7 @@ __global__ __launch_bounds__(64) void k_schedule(int n, const int32_t* __restric
                 int rank = 0;
                 for (int l = 0; l < kWave; ++l) rank += ((open >> l) & 1ull) && tmin[l] < mk;
 #pragma unroll
-                for (int i = 0; i < kSchedRegs; ++i) {
+                for (int i = 0; i < kRegs; ++i) {
                     if (i >= nk) continue;
                     const unsigned long long want = ((GM[i] & gph) | (BM[i] & ~gph)) & open;
                     if (want && tmin[__builtin_ctzll(want)] == K[i]) {
@@ -444,7 +487,7 @@ __global__ __launch_bounds__(64) void k_schedule(int n, const int32_t* __restric
             unsigned long long take = 0;
             bool owner = false;
 #pragma unroll
-            for (int i = 0; i < kSchedRegs; ++i) {
+            for (int i = 0; i < kRegs; ++i) {
                 if (i >= nk) continue;
                 if (K[i] == bk) {
                     owner = true;
@@ -471,6 +514,18 @@ __global__ __launch_bounds__(64) void k_schedule(int n, const int32_t* __restric
         if (lane >= m) srec[e] = m > 0 ? first : self;  // past the set: any valid index
         if (lane == 0) scnt[(off >> 6) + k] = m > 0 ? m : 1;
     }
+}
+
+// Tiles of a batch by the register table they need: up to 16 entries per lane
+// (list16) or up to 32 (list32); counts[0..1] their numbers (zeroed before).
+__global__ void k_sched_bins(int nb, const int32_t* __restrict__ tcnt, int32_t* __restrict__ list16,
+                             int32_t* __restrict__ list32, int32_t* __restrict__ counts) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const int nd = tcnt[b];
+    if (nd < 0) return;  // identity schedule, already written
+    if (nd <= 16 * kWave) list16[atomicAdd(&counts[0], 1)] = b;
+    else list32[atomicAdd(&counts[1], 1)] = b;
 }
 
 // Exact FP64 interaction counts over the lists: r < H_i and r < max(H_i, H_j).
@@ -1268,6 +1323,8 @@ void carve_part_a(crk_leaves* L, Carver& c, int64_t n, int64_t nt) {
                                            size_t(n) * sizeof(RecAcc<double>))
                                 : size_t(n) * 4 * sizeof(double);  // masses and adjoints (gravity)
     if (L->dev_tree) L->scratch_bytes = std::max(L->scratch_bytes, crk::devtree_scratch_bytes(n, nt));
+    // the list schedule's neighbour tables (at least one tile at a time)
+    if (L->hydro) L->scratch_bytes = std::max(L->scratch_bytes, sizeof(SchedEntry) * kSchedHash + 8192);
     L->scratch = c.take<char>(L->scratch_bytes);
 }
 
@@ -1314,11 +1371,44 @@ int fill_lists(crk_leaves* L, const std::vector<int32_t>& len, hipStream_t strea
         return fail(CRK_EHIP, "list build failed");
     if (mismatched)
         return fail(CRK_EHIP, "neighbour lists: count and fill passes disagree on %d particles", mismatched);
-    // shared-record slots: reorder the lists, name each slot's particles
+    // shared-record slots: reorder the lists, name each slot's particles; in
+    // batches of tiles whose neighbour tables fit the per-pass scratch
+    const size_t per_tile = sizeof(SchedEntry) * kSchedHash + 3 * sizeof(int32_t) + 16;
+    const int64_t batch = std::min<int64_t>(nt, int64_t((L->scratch_bytes - 4096) / per_tile));
+    if (batch < 1) return fail(CRK_EHIP, "list schedule: per-pass scratch of %zu bytes too small", L->scratch_bytes);
     {
-        TimeScope ts(L, stream, CRK_K_CULL);
-        hipLaunchKernelGGL(k_schedule, dim3(unsigned(nt)), dim3(kWave), 0, stream, int(n), L->cnt,
-                           L->cnt_gather, L->ell_off, L->ell_len, L->nbr, L->srec, L->sidx, L->scnt);
+        Carver cv(static_cast<char*>(L->scratch));
+        SchedEntry* tbl = cv.take<SchedEntry>(size_t(batch) * kSchedHash);
+        int32_t* tcnt = cv.take<int32_t>(size_t(batch));
+        int32_t* list16 = cv.take<int32_t>(size_t(batch));
+        int32_t* list32 = cv.take<int32_t>(size_t(batch));
+        int32_t* counts = cv.take<int32_t>(kMaxGroups);  // k_reset clears kMaxGroups
+        for (int64_t t0 = 0; t0 < nt; t0 += batch) {
+            const int nb = int(std::min<int64_t>(batch, nt - t0));
+            int32_t hc[2] = {0, 0};
+            {
+                TimeScope ts(L, stream, CRK_K_CULL);
+                hipLaunchKernelGGL(k_sched_table, dim3(unsigned(nb)), dim3(kWave), 0, stream, int(n), int(t0),
+                                   L->cnt, L->cnt_gather, L->ell_off, L->ell_len, L->nbr, L->srec, L->sidx,
+                                   L->scnt, tbl, tcnt);
+                hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, counts);
+                hipLaunchKernelGGL(k_sched_bins, dim3((nb + 255) / 256), dim3(256), 0, stream, nb, tcnt, list16,
+                                   list32, counts);
+            }
+            if (hipGetLastError() != hipSuccess ||
+                hipMemcpyAsync(hc, counts, sizeof hc, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+                hipStreamSynchronize(stream) != hipSuccess)
+                return fail(CRK_EHIP, "list schedule (tables) failed");
+            TimeScope ts(L, stream, CRK_K_CULL);
+            if (hc[0] > 0)
+                hipLaunchKernelGGL(k_sched_pick<16>, dim3(unsigned(hc[0])), dim3(kWave), 0, stream, int(n),
+                                   int(t0), list16, L->cnt, L->cnt_gather, L->ell_off, L->ell_len, L->nbr,
+                                   L->srec, L->sidx, L->scnt, tbl, tcnt);
+            if (hc[1] > 0)
+                hipLaunchKernelGGL(k_sched_pick<kSchedRegs>, dim3(unsigned(hc[1])), dim3(kWave), 0, stream,
+                                   int(n), int(t0), list32, L->cnt, L->cnt_gather, L->ell_off, L->ell_len, L->nbr,
+                                   L->srec, L->sidx, L->scnt, tbl, tcnt);
+        }
     }
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(stream) != hipSuccess)
         return fail(CRK_EHIP, "list schedule failed");
