@@ -292,11 +292,10 @@ __device__ __forceinline__ void visc_pair_adj(const Rec& ri, const Rec& rj, cons
 // P_i + P_j; its adjoint also gives dL/d dv_i (dvbar) and dL/drho_i, dL/du_i
 // through Q (qbar), all in tree order)
 template <class R, bool kOff32, bool kVisc = false, class Rec = RecBwd<R>>
-__global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
-                                                   const Rec* __restrict__ rec, int chunk,
-                                                   R* __restrict__ cbar, R* __restrict__ vpbar,
-                                                   R* __restrict__ xbar, R* __restrict__ gv, ViscB<R> vq = {},
-                                                   R* __restrict__ dvbar = nullptr, R* __restrict__ qbar = nullptr) {
+__device__ __forceinline__ void accel_adj_body(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
+                                               const Rec* __restrict__ rec, int chunk, R* __restrict__ cbar,
+                                               R* __restrict__ vpbar, R* __restrict__ xbar, R* __restrict__ gv,
+                                               ViscB<R> vq, R* __restrict__ dvbar, R* __restrict__ qbar) {
     constexpr int kStage = stage_stride<Rec>();
     extern __shared__ uint4 stage_buf[];  // kStage per wave (stage_bytes)
     const int lane = lane_id();
@@ -309,7 +308,9 @@ __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, con
         const int len = L.len[w];
         ChunkSums<R, 16> cb;  // A, B[3], dA[3], dB[9]
         ChunkSums<R, 8> ob;   // Vbar, Pbar, xbar[3], vbar[3]
-        ChunkSums<R, kVisc ? 11 : 1> qb;  // dvbar[9], rhobar, ubar (through Q)
+        // dvbar[9], rhobar, ubar (through Q): the viscosity's own adjoints, summed
+        // plainly in FP32 (their compensation's registers would halve the occupancy)
+        PlainSums<R, kVisc ? 11 : 1> qb;
         cb.zero();
         ob.zero();
         qb.zero();
@@ -392,6 +393,24 @@ __global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, con
             }
         }
     }
+}
+
+template <class R, bool kOff32>
+__global__ __launch_bounds__(256) void k_accel_adj(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
+                                                   const RecBwd<R>* __restrict__ rec, int chunk,
+                                                   R* __restrict__ cbar, R* __restrict__ vpbar,
+                                                   R* __restrict__ xbar, R* __restrict__ gv) {
+    accel_adj_body<R, kOff32>(qu, n, L, perm, rec, chunk, cbar, vpbar, xbar, gv, ViscB<R>{}, nullptr, nullptr);
+}
+
+// the viscous form, held to two waves per SIMD (FP32: a few registers spill)
+template <class R, bool kOff32>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 2 : 1)))
+void k_accel_adj_visc(Queue qu, int n, Lists L, const int32_t* __restrict__ perm,
+                      const RecBwdV<R>* __restrict__ rec, int chunk, R* __restrict__ cbar, R* __restrict__ vpbar,
+                      R* __restrict__ xbar, R* __restrict__ gv, ViscB<R> vq, R* __restrict__ dvbar,
+                      R* __restrict__ qbar) {
+    accel_adj_body<R, kOff32, true, RecBwdV<R>>(qu, n, L, perm, rec, chunk, cbar, vpbar, xbar, gv, vq, dvbar, qbar);
 }
 
 // Reverse of the FP64 solve (solve_moments) for one particle: corrections
@@ -1001,13 +1020,11 @@ int backward_impl(crk_leaves* L, const crk_gas* g, const R* V, const R* rho, con
         TimeScope ts(L, st, CRK_K_ACCEL_ADJ);
         auto kern = off32<RecBwd<R>>(L) ? k_accel_adj<R, true> : k_accel_adj<R, false>;
         hipLaunchKernelGGL(kern, grid, block, stage_bytes<RecBwd<R>>(bw), st, q, n, lists(L),
-                           L->perm, rec, L->tune.kahan_chunk, cbar, vpbar, xbar, gv, ViscB<R>{},
-                           static_cast<R*>(nullptr), static_cast<R*>(nullptr));
+                           L->perm, rec, L->tune.kahan_chunk, cbar, vpbar, xbar, gv);
     } else {
         TimeScope ts(L, st, CRK_K_ACCEL_ADJ);
         const ViscB<R> vq{R(q_visc->Cl), R(q_visc->Cq), R(q_visc->eps_q), R(0.5 * gamma * (gamma - 1.0))};
-        auto kern = off32<RecBwdV<R>>(L) ? k_accel_adj<R, true, true, RecBwdV<R>>
-                                         : k_accel_adj<R, false, true, RecBwdV<R>>;
+        auto kern = off32<RecBwdV<R>>(L) ? k_accel_adj_visc<R, true> : k_accel_adj_visc<R, false>;
         hipLaunchKernelGGL(kern, grid, block, stage_bytes<RecBwdV<R>>(bw), st, q, n, lists(L), L->perm, recv,
                            L->tune.kahan_chunk, cbar, vpbar, xbar, gv, vq, dvbar, qbar);
     }

@@ -478,6 +478,20 @@ template <class R, int N> struct ChunkSums {
     __device__ R get(int e) const { return sizeof(R) == 4 ? s[e] - c[e] : p[e]; }
 };
 
+// The same interface with plain sums (one register per value), for small
+// secondary terms where the compensation's registers would cost occupancy.
+template <class R, int N> struct PlainSums {
+    R p[N];
+    __device__ void zero() {
+#pragma unroll
+        for (int e = 0; e < N; ++e) p[e] = R(0);
+    }
+    __device__ void add(int e, R t) { p[e] += t; }
+    __device__ void fold() {}
+    __device__ void next(int, int) {}
+    __device__ R get(int e) const { return p[e]; }
+};
+
 // ------------------------------------------------------------------ moments
 
 // The correction moments of the lane's particle, as 29 independent FP64 sums
