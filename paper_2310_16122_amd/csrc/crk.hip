@@ -604,7 +604,7 @@ __global__ __launch_bounds__(256) void k_volume(Queue qu, int n, Lists L, const 
         const int i = valid ? perm[s] : 0;
         const uint4 qi = valid ? quant[s] : make_uint4(0, 0, 0, 0);
         const R H = valid ? R(2) * h[i] : R(1);
-        const R invH = R(1) / H;
+        const R invHg = (R(1) / H) * R(kInvGrid);  // q from separations in grid units
         const int cnt = valid ? L.cnt[s] : 0;
         const int len = L.len[w];
         ChunkSums<R, 1> S;
@@ -613,11 +613,11 @@ __global__ __launch_bounds__(256) void k_volume(Queue qu, int n, Lists L, const 
         list_loop<uint4, kOff32, kStage16>(
             L, w, cnt, len, quant, stage_buf + wave_in_block() * kStage,
             [&](const uint4& qj, int k) __attribute__((always_inline)) {
-                const R dx = sep<R>(qi.x, qj.x), dy = sep<R>(qi.y, qj.y), dz = sep<R>(qi.z, qj.z);
+                const R dx = grid_sep<R>(qi.x, qj.x), dy = grid_sep<R>(qi.y, qj.y), dz = grid_sep<R>(qi.z, qj.z);
                 const R r = dsqrt(dx * dx + dy * dy + dz * dz);
                 R wq, fq;
-                wendland(r * invH, wq, fq);
-                S.add(0, wq);
+                wendland(r * invHg, wq, fq);
+                S.add(0, k < cnt ? wq : R(0));  // past the count: adds zero
                 S.next(k, chunk);
             });
         S.fold();

@@ -192,37 +192,74 @@ struct Lists {
 
 
 
+// a pointer the caller knows to be wave-uniform, moved to scalar registers
+template <class T> __device__ __forceinline__ const T* uniform_ptr(const T* p) {
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(a));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(a >> 32));
+    return reinterpret_cast<const T*>((uint64_t(hi) << 32) | lo);
+}
+
 // Neighbour-list loop of one lane with software-pipelined loads: the data of
-// entries k+2 and k+3 and the list indices of entries k+4 and k+5 are
-// requested before entries k and k+1 are processed, so the two dependent
-// memory round trips per neighbour overlap two entries' arithmetic.  The loop
-// is unrolled by two and every load is unconditional: slots past a lane's
-// count hold a valid index (the list build pads them with the lane's own
-// particle) and slot numbers are clamped to the tile's last slot.  lst points
-// at the lane's slot 0 (slot k at lst[64 k]); len is the tile's longest list;
-// load(j) fetches neighbour j's data; body(d, k) runs for k < cnt.
-template <class D, class Load, class Body>
-__device__ __forceinline__ void pipelined_list(const uint32_t* __restrict__ lst, int cnt, int len,
-                                               Load load, Body body) {
+// entry k+kD and the list index of entry k+kD+kI are requested before entry k
+// is processed.  A wave's loads complete in issue order, so every wait covers
+// all loads issued before the one it needs, among them index rows that miss to
+// HBM (the rows stream once per pass and are the bulk of its traffic): both
+// lookaheads must be deep for those round trips to hide behind other work.
+// The loop is unrolled by eight over rings of registers (no copies between
+// iterations); the slot counter stays in scalar registers and the rows are
+// read through a buffer descriptor at a scalar offset (no address arithmetic
+// per index load).  Every load is unconditional: slots past a lane's count
+// hold a valid index (the list build pads them) and slot numbers are clamped
+// to the tile's last slot.  row0 is the tile's slot-0 row (lane l of slot k at
+// row0[64 k + l]); len is the tile's longest list; load(j) fetches neighbour
+// j's data.  body(d, k) runs on every lane for every k < len: a lane past its
+// own count must add nothing, by selection rather than a branch, which keeps
+// the loop free of divergent control flow.
+template <class D, int kD = 6, class Load, class Body>
+__device__ __forceinline__ void pipelined_list(const uint32_t* __restrict__ row0, int len, Load load, Body body) {
+    constexpr int kI = 8;   // indices requested kI entries ahead of their data
+    constexpr int kRD = 8;  // data ring
+    constexpr int kU = 8;   // unroll: a whole turn of both rings
+    static_assert(kU % kI == 0 && kU % kRD == 0 && kD < kRD, "ring sizes");
     len = __builtin_amdgcn_readfirstlane(len);  // the tile's: a scalar slot loop
     if (len <= 0) return;
     const int last = len - 1;
+    const __amdgpu_buffer_rsrc_t rows = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t*>(uniform_ptr(row0)), 0, len * kWave * 4, 0x00020000);
+    const int vo = lane_id() * 4;
     auto slot = [&](int k) __attribute__((always_inline)) {
-        return lst[int64_t(k < last ? k : last) * kWave];
+        return uint32_t(__builtin_amdgcn_raw_buffer_load_b32(rows, vo, (k < last ? k : last) * (kWave * 4), 0));
     };
-    D dA = load(slot(0)), dB = load(slot(1));
-    uint32_t jC = slot(2), jD = slot(3);
-    for (int k = 0; k < len; k += 2) {
-        const uint32_t jE = slot(k + 4), jF = slot(k + 5);
-        const D dC = load(jC);
-        if (k < cnt) body(dA, k);
-        const D dD = load(jD);
-        if (k + 1 < cnt) body(dB, k + 1);
-        dA = dC;
-        dB = dD;
-        jC = jE;
-        jD = jF;
+    D d[kRD];        // entry e's data in d[e % kRD]
+    uint32_t j[kI];  // entry e's index in j[e % kI]
+    // The first entries' loads are issued in entry order (the scheduler
+    // would otherwise put entry 0's data last, and the loop's waits, which
+    // must hold on entry as on the back edge, would shrink to that).
+    uint32_t j0[kD];
+#pragma unroll
+    for (int e = 0; e < kD; ++e) j0[e] = slot(e);
+#pragma unroll
+    for (int e = 0; e < kD; ++e) {
+        d[e] = load(j0[e]);
+        __builtin_amdgcn_sched_barrier(0);
     }
+#pragma unroll
+    for (int e = kD; e < kD + kI; ++e) j[e % kI] = slot(e);
+    auto turn = [&](int k) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int a = u + kD;
+            d[a % kRD] = load(j[a % kI]);
+            j[a % kI] = slot(k + a + kI);
+            if (u == 0 || k + u < len) body(d[u % kRD], k + u);
+        }
+    };
+    // The first turn is peeled: the loop is then entered with as many loads in
+    // flight as its back edge carries, and its waits (one static count for
+    // both ways in) keep the full depth.
+    turn(0);
+    for (int k = kU; k < len; k += kU) turn(k);
 }
 
 // Neighbour-list loop for large per-particle records (NCH 16-byte chunks),
@@ -253,14 +290,6 @@ template <int NCH> __device__ __forceinline__ int stage_swz(int r) {
 // index of the calling wave within its workgroup, in a scalar register
 __device__ __forceinline__ int wave_in_block() {
     return __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-}
-
-// a pointer the caller knows to be wave-uniform, moved to scalar registers
-template <class T> __device__ __forceinline__ const T* uniform_ptr(const T* p) {
-    const uint64_t a = reinterpret_cast<uint64_t>(p);
-    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(a));
-    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(a >> 32));
-    return reinterpret_cast<const T*>((uint64_t(hi) << 32) | lo);
 }
 
 // Byte offset of record j in the 32-bit form: a shift for power-of-two record
@@ -440,14 +469,27 @@ template <class D, bool kStage16 = false> inline size_t stage_bytes(int block_wa
 // 16-byte records are gathered lane by lane, with the loads software-pipelined
 // (kStage16 = false), or staged through LDS like the larger ones: each slot's
 // distinct particles fetched once (about 14 of 64 on the clustered gas), so a
-// slot touches that many cache lines instead of one per lane.
+// slot touches that many cache lines instead of one per lane.  The staged form
+// calls body(d, k) for k < cnt only, the gathered one on every lane (see
+// pipelined_list): a body used with both adds nothing where k >= cnt.
 template <class D, bool kOff32, bool kStage16 = false, class Body>
 __device__ __forceinline__ void list_loop(const Lists& L, int w, int cnt, int len,
                                           const D* __restrict__ recs, uint4* __restrict__ lds, Body body) {
     if constexpr (!staged<D, kStage16>()) {
+        static_assert(sizeof(D) == 16, "gathered records are 16 bytes");
+        // the records as a buffer (the 32-bit form spans at most 4 GiB): one
+        // shift per load for its offset
+        const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<D*>(uniform_ptr(recs)), 0, int(0xffffffffu), 0x00020000);
         pipelined_list<D>(
-            L.nbr + L.off[w] + lane_id(), cnt, len,
-            [&](uint32_t j) __attribute__((always_inline)) { return recs[j]; }, body);
+            L.nbr + L.off[w], len,
+            [&](uint32_t j) __attribute__((always_inline)) {
+                if constexpr (kOff32)
+                    return __builtin_bit_cast(D, __builtin_amdgcn_raw_buffer_load_b128(rb, int(j * 16u), 0, 0));
+                else
+                    return recs[j];
+            },
+            body);
     } else {
         staged_list<D, kOff32>(L, w, cnt, len, recs, lds, body);
     }
@@ -513,7 +555,10 @@ __device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, con
     const int lane = lane_id();
     const RecQV<R> self = qv[valid ? s : 0];
     const uint4 qi = make_uint4(self.q[0], self.q[1], self.q[2], 0u);
-    const R invH = R(1) / H;
+    // separations in grid units (2^32 per box length): the sums of pairs with
+    // g powers of x are 2^(32 g) times the physical ones (exact power-of-two
+    // factors, removed in FP64 at the end)
+    const R invHg = (R(1) / H) * R(kInvGrid);
     const R cW = norm_W(H), cF = norm_F(H);
     const int cnt = valid ? L.cnt[s] : 0;
     const int len = L.len[w];
@@ -524,15 +569,16 @@ __device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, con
     list_loop<RecQV<R>, kOff32, kStage16>(
         L, w, cnt, len, qv, lds,
         [&](const RecQV<R>& d, int k) __attribute__((always_inline)) {
+            const bool act = k < cnt;  // past the count: the pair adds zeros
             const R Vj = d.V;
-            const R x[3] = {sep<R>(qi.x, d.q[0]), sep<R>(qi.y, d.q[1]), sep<R>(qi.z, d.q[2])};
+            const R x[3] = {grid_sep<R>(qi.x, d.q[0]), grid_sep<R>(qi.y, d.q[1]), grid_sep<R>(qi.z, d.q[2])};
             const R r = dsqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
-            const R q = r * invH;
+            const R q = r * invHg;
             R wq, fq;
             wendland(q, wq, fq);
-            nnb += q < R(1);
-            const R wv = cW * wq * Vj;
-            const R fv = cF * fq * Vj;
+            nnb += (act && q < R(1)) ? 1 : 0;
+            const R wv = act ? cW * wq * Vj : R(0);
+            const R fv = act ? cF * fq * Vj : R(0);
             R xx[6], x3[10];
             xx[0] = x[0] * x[0]; xx[1] = x[0] * x[1]; xx[2] = x[0] * x[2];
             xx[3] = x[1] * x[1]; xx[4] = x[1] * x[2]; xx[5] = x[2] * x[2];
@@ -559,11 +605,15 @@ __device__ inline void moment_sums(int w, int s, bool valid, const Lists& L, con
         });
 #pragma unroll
     for (int e = 0; e < kN; ++e) {
+        // power of x in sum e: m0 0, m1 1, m2 2, g0 1, t1 2, t3 3
+        const int g = e == 0 ? 0 : e < 4 ? 1 : e < 10 ? 2 : e < 13 ? 1 : e < 19 ? 2 : 3;
+        const double unit = g == 0 ? 1.0 : g == 1 ? kInvGrid : g == 2 ? kInvGrid * kInvGrid
+                                                                   : kInvGrid * kInvGrid * kInvGrid;
         if (kComp) {
             kadd(sm[e], cm[e], p[e]);
-            S[e] = double(sm[e]) - double(cm[e]);
+            S[e] = (double(sm[e]) - double(cm[e])) * unit;
         } else {
-            S[e] = double(p[e]);
+            S[e] = double(p[e]) * unit;
         }
     }
     if (valid) S[0] += double(cW) * double(self.V);  // j = i
