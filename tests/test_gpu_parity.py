@@ -495,6 +495,32 @@ def test_empty_and_tiny_inputs(crk):
             assert int(got["n_fallback"][0]) == ref["n_fallback"]
 
 
+def short_list_case(lo, hi, seed):
+    """209 random particles (three full tiles and a ragged one) with h for lo..hi
+    neighbours: tiles whose longest list lies below, at and just past the gathered
+    loop's unroll of eight (and lanes with no gather neighbour at lo = 0)."""
+    rng = np.random.default_rng(seed)
+    n = 3 * 64 + 17
+    x, y, z = (synth.grid_round(rng.random(n)) for _ in range(3))
+    H = synth.knn_support(x, y, z, rng.integers(lo, hi + 1, n))
+    return dict(n=n, x=x, y=y, z=z, h=synth.f32(0.5 * H), m=synth.f32(rng.uniform(0.5, 1.5, n) / n),
+                vx=synth.f32(rng.normal(0, 0.1, n)), vy=synth.f32(rng.normal(0, 0.1, n)),
+                vz=synth.f32(rng.normal(0, 0.1, n)), u=synth.f32(np.exp(0.5 * rng.normal(size=n))),
+                gamma=5.0 / 3.0)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("lo,hi", [(0, 3), (5, 9), (14, 18)])
+def test_short_lists_around_the_loop_unroll(crk, prec, lo, hi):
+    cfg = short_list_case(lo, hi, seed=40 + lo)
+    ref = oracle.hydro(cfg)
+    got, L = run_gpu(crk, cfg, prec, leaf_max=64)
+    print(f"case short lists {lo}..{hi} prec={prec} n={cfg['n']}", flush=True)
+    assert int(got["n_fallback"][0]) == ref["n_fallback"]
+    for k in KEYS:
+        assert normwise(got[k], ref[k]) <= TOL[prec], k
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("case", [fallback_case, planar_case])
 def test_singular_moment_fallback(crk, prec, case):
