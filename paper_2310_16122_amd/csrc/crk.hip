@@ -998,7 +998,9 @@ template <class R> int volume_impl(crk_leaves* L, const crk_gas* g, R* V, R* rho
     reset_queue(L, st);
     TimeScope ts(L, st, CRK_K_VOLUME);
     const bool st16 = L->tune.stage16 != 0, o32 = off32<uint4>(L);
-    auto kern = st16 ? (o32 ? k_volume<R, true, true> : k_volume<R, true, false>) : k_volume<R, false, true>;
+    // both forms take 32-bit record offsets only where the positions span at most 4 GiB
+    auto kern = st16 ? (o32 ? k_volume<R, true, true> : k_volume<R, true, false>)
+                     : (o32 ? k_volume<R, false, true> : k_volume<R, false, false>);
     const int bw = L->tune.block_waves;
     const size_t lds = st16 ? stage_bytes<uint4, true>(bw) : size_t(0);
     hipLaunchKernelGGL(kern, dim3(grid_nwave(L)), dim3(kWave * bw), lds, st,
