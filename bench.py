@@ -622,6 +622,17 @@ def extras_viscosity(args, torch, crk, L, g32, cfg_t, G, F, config, table, f64=T
                                                  cfg_t["gamma"], "f64")
         for k, u, v in zip(("gx_visc", "gv_visc", "gu_visc"), b32, b64):
             err[k] = float(f"{((u.double() - v).abs().max() / v.abs().max()).item():.3e}")
+        # the viscous chain's gradient jumps where a pair's viscosity switches on,
+        # so the end-to-end figures above include the jumps the FP32 forward
+        # crosses; against the FP64 backward at the FP32 forward's own state
+        # (V, rho, corrections, dv) they measure the FP32 backward's arithmetic
+        d = lambda t: t.double().contiguous()
+        bs = crk.crk_accel_energy_visc_backward(L, g64, d(o32["V"]), d(o32["rho"]), tuple(d(t) for t in c32),
+                                                d(e32[1]), (2.0 * w64[:, None] * a64[0]).contiguous(), c64w,
+                                                cfg_t["gamma"], "f64")
+        for k, u, v in zip(("gx_visc_same_state", "gv_visc_same_state", "gu_visc_same_state"), b32, bs):
+            err[k] = float(f"{((u.double() - v).abs().max() / v.abs().max()).item():.3e}")
+        del bs
         res["fp32_vs_fp64_normwise"] = err
         del g64, o64, c64, e64, a64, b32, b64
     torch.cuda.empty_cache()
