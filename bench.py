@@ -238,6 +238,35 @@ def measured_counters(config, kind):
     return max(hits, key=lambda v: v.get("dispatches", 0)) if hits else None
 
 
+def profiled_setup(config):
+    """(tuning, leaf size) the committed counter profile of `config` was taken
+    with (from its command line), when it matches the current kernel sources;
+    else None.  The timed launches then use it, so that the counters, the
+    executed FLOP and the launch times in the roofline describe the same
+    launches (the autotuner's own pick, within noise of it, is reported beside)."""
+    import re
+
+    from paper_2310_16122_amd import profiling
+
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILES.get(config, ""))
+    if not os.path.isfile(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_digest") != profiling.source_digest():
+        return None
+    cmd = rec.get("command", "")
+    flag, leaf_flag, leaf = (("--gravity-tuning", "--gravity-leaf-max", None) if config == "C3"
+                             else ("--tuning", "--leaf-max", 128))
+    m = re.search(re.escape(flag) + r" '(\{[^']*\})'", cmd)
+    if not m:
+        return None
+    m2 = re.search(re.escape(leaf_flag) + r" (\d+)", cmd)
+    if m2:
+        leaf = int(m2.group(1))
+    return json.loads(m.group(1)), leaf
+
+
 def flop_per_unit(kind, units, config, table):
     """(FLOP per pair used for the algorithmic rate, oracle count, executed
     count per pair or None).  The algorithmic count is the oracle's, unless the
@@ -397,8 +426,14 @@ def bench_hydro(args, torch, crk, config=None, tuning=None, autotune=True, rando
 
         best, best_ms, tried = tune.autotune(L, step32, repeats=2)
         L_rand.set_tuning(**best)
-        tuned = {"tried": len(tried), "best_ms": round(best_ms, 3)}
+        tuned = {"tried": len(tried), "best": best, "best_ms": round(best_ms, 3)}
         log(f"[bench] autotuned over {len(tried)} settings: {best} ({best_ms:.3f} ms)")
+        prof = profiled_setup(config)
+        if prof is not None and prof[1] == args.leaf_max:
+            L.set_tuning(**prof[0])
+            L_rand.set_tuning(**prof[0])
+            tuned["timed"] = "the committed profile's tuning"
+            log(f"[bench] timing with the committed profile's tuning {prof[0]}")
     L.timing(False)
     timed_steps(step32, 2, args.warmup, torch)
     L.timing(True)
@@ -678,8 +713,16 @@ def bench_gravity(args, torch, crk, tuning=None, leaf_max=None):
             lambda lm: build(lm, x, y, z), make_step, leaf_values=(128, 256, 512), log=log, repeats=2,
             space=tune.GRAVITY_SPACE)
         tuned = {"leaf_max": leaf, "ms_by_leaf": {str(k): round(v, 3) for k, v in per_leaf.items()},
-                 "best_ms": round(best_ms, 3)}
+                 "best": tun, "best_ms": round(best_ms, 3)}
         log(f"[bench] autotuned gravity: leaf {leaf}, {tun} ({best_ms:.3f} ms)")
+        prof = profiled_setup("C3")
+        if prof is not None and prof[1] is not None:
+            if prof[1] != leaf:
+                L.free()
+                L = build(prof[1], x, y, z)
+            L.set_tuning(**prof[0])
+            tuned["timed"] = f"the committed profile's tree (leaf {prof[1]}) and tuning"
+            log(f"[bench] timing gravity with the committed profile's leaf {prof[1]} and tuning {prof[0]}")
     st = L.stats()
     step = make_step(L)
 
